@@ -5,15 +5,19 @@ TEST INFRASTRUCTURE ONLY (see the oracle package docstring).
 * ``segment``: Section 4.1.2 builds an affinity U U^T from the top left singular
   vectors of Z, embeds the points spectrally into k dimensions and runs k-means.
   The paper does not fix the number of vectors, the Laplacian, the k-means
-  initialisation or tie breaking; the readings used here are: numerical rank
-  #sigma > 1e-6 sigma_1, affinity |U U^T|, symmetric normalisation
-  D^-1/2 W D^-1/2, the k leading eigenvectors with unit rows, Lloyd's k-means
-  with k-means++ seeding from a fixed seed, 10 restarts, lowest inertia, ties to
-  the lowest index, labels renumbered by first appearance.  The routine is
-  deterministic in Z, so running it on two Z's tests the Z's, not the clustering.
+  initialisation, tie breaking, or what happens to outlier columns; the readings
+  used here are: numerical rank #sigma > 1e-6 sigma_1, affinity |U U^T| over the
+  points not marked as outliers (an outlier column is represented by itself, so
+  each one is a separate component of the affinity graph and the k leading
+  eigenvectors would not be determined), symmetric normalisation D^-1/2 W D^-1/2,
+  the k leading eigenvectors with unit rows, Lloyd's k-means started from a
+  deterministic farthest-point seeding, labels renumbered by first appearance,
+  -1 for the excluded points.  The routine is deterministic and continuous away
+  from exact ties, so running it on two Z's tests the Z's, not the clustering.
 * ``segmentation_accuracy``: each cluster takes the majority ground-truth label of
   its members; the score is the mean over classes of the fraction of that class
-  labelled correctly (Section 4.1.2).  Columns with ground truth -1 are skipped.
+  labelled correctly (Section 4.1.2).  Columns labelled -1 (either side) are
+  skipped.
 * ``oracle_constraints``: the success test of Section 4.1.1 -- the oracle
   constraints of the appendix (column space of Z inside the row space of the
   clean data, outlier estimate supported on the outlier columns) within a
@@ -27,39 +31,32 @@ import scipy.linalg as sla
 __all__ = ["segment", "segmentation_accuracy", "oracle_constraints", "kmeans"]
 
 
-def kmeans(Y: np.ndarray, k: int, seed: int = 0, restarts: int = 10, max_iter: int = 300):
-    """Lloyd's k-means with k-means++ seeding; returns (labels, inertia)."""
-    rng = np.random.default_rng(seed)
-    npts = Y.shape[0]
-    best_lab, best_in = None, np.inf
-    for _ in range(restarts):
-        centers = np.empty((k, Y.shape[1]))
-        centers[0] = Y[rng.integers(npts)]
-        d2 = np.sum((Y - centers[0]) ** 2, axis=1)
-        for c in range(1, k):
-            tot = d2.sum()
-            if tot <= 0:
-                idx = int(rng.integers(npts))
-            else:
-                idx = int(np.searchsorted(np.cumsum(d2), rng.uniform(0, tot)))
-                idx = min(idx, npts - 1)
-            centers[c] = Y[idx]
-            d2 = np.minimum(d2, np.sum((Y - centers[c]) ** 2, axis=1))
-        lab = None
-        for _it in range(max_iter):
-            dist = np.sum((Y[:, None, :] - centers[None, :, :]) ** 2, axis=2)
-            new = np.argmin(dist, axis=1)          # ties -> lowest centre index
-            if lab is not None and np.array_equal(new, lab):
-                break
-            lab = new
-            for c in range(k):
-                mem = Y[lab == c]
-                if len(mem):
-                    centers[c] = mem.mean(axis=0)
-        inertia = float(np.sum((Y - centers[lab]) ** 2))
-        if inertia < best_in - 1e-12:
-            best_in, best_lab = inertia, lab.copy()
-    return best_lab, best_in
+def kmeans(Y: np.ndarray, k: int, max_iter: int = 300):
+    """Lloyd's k-means from a farthest-point seeding; returns (labels, inertia).
+
+    Seeding: the point farthest from the centroid, then repeatedly the point
+    farthest from the chosen ones (ties to the lowest index).  Assignment ties go
+    to the lowest centre index."""
+    c0 = int(np.argmax(np.sum((Y - Y.mean(axis=0)) ** 2, axis=1)))
+    chosen = [c0]
+    d2 = np.sum((Y - Y[c0]) ** 2, axis=1)
+    for _ in range(1, k):
+        j = int(np.argmax(d2))
+        chosen.append(j)
+        d2 = np.minimum(d2, np.sum((Y - Y[j]) ** 2, axis=1))
+    centers = Y[chosen].copy()
+    lab = None
+    for _it in range(max_iter):
+        dist = np.sum((Y[:, None, :] - centers[None, :, :]) ** 2, axis=2)
+        new = np.argmin(dist, axis=1)
+        if lab is not None and np.array_equal(new, lab):
+            break
+        lab = new
+        for c in range(k):
+            mem = Y[lab == c]
+            if len(mem):
+                centers[c] = mem.mean(axis=0)
+    return lab, float(np.sum((Y - centers[lab]) ** 2))
 
 
 def _canonical(labels: np.ndarray) -> np.ndarray:
@@ -72,12 +69,16 @@ def _canonical(labels: np.ndarray) -> np.ndarray:
     return out
 
 
-def segment(Z: np.ndarray, k: int, seed: int = 0, rank_tol: float = 1e-6) -> np.ndarray:
-    """Labels 0..k-1 for the n points from Z (n x n), Section 4.1.2 pipeline."""
+def segment(Z: np.ndarray, k: int, exclude: np.ndarray | None = None,
+            rank_tol: float = 1e-6) -> np.ndarray:
+    """Labels 0..k-1 for the n points from Z (n x n), Section 4.1.2 pipeline;
+    points with exclude[j] True get -1 and stay out of the affinity."""
+    n = Z.shape[0]
     U, s, _ = sla.svd(Z, full_matrices=False, lapack_driver="gesdd")
     r = int(np.sum(s > rank_tol * s[0])) if s.size and s[0] > 0 else 0
     r = max(r, 1)
-    Ur = U[:, :r]
+    keep = np.ones(n, dtype=bool) if exclude is None else ~np.asarray(exclude, dtype=bool)
+    Ur = U[keep, :r]
     W = np.abs(Ur @ Ur.T)
     d = W.sum(axis=1)
     d[d <= 0] = 1.0
@@ -88,13 +89,15 @@ def segment(Z: np.ndarray, k: int, seed: int = 0, rank_tol: float = 1e-6) -> np.
     nrm = np.linalg.norm(emb, axis=1, keepdims=True)
     nrm[nrm == 0] = 1.0
     emb = emb / nrm
-    lab, _ = kmeans(emb, k, seed=seed)
-    return _canonical(lab)
+    lab, _ = kmeans(emb, k)
+    out = -np.ones(n, dtype=np.int64)
+    out[keep] = _canonical(lab)
+    return out
 
 
 def segmentation_accuracy(pred: np.ndarray, truth: np.ndarray) -> float:
     """Majority-vote cluster labels, then mean per-class recall (-1 ignored)."""
-    keep = truth >= 0
+    keep = (truth >= 0) & (pred >= 0)
     pred, truth = pred[keep], truth[keep]
     assign = {}
     for c in np.unique(pred):
