@@ -1,0 +1,161 @@
+/*
+ * lrr.h -- C ABI of the MI355X (gfx950) DFC-LRR library.
+ *
+ * The library solves the low-rank representation program
+ *
+ *     min ||Z||_* + lambda ||E||_{2,1}   s.t.  X = A Z + E          (Eq. 1 / Eq. 2)
+ *
+ * where ||.||_{2,1} is the sum of the column l2 norms (Section 1), with the
+ * inexact augmented-Lagrange-multiplier iteration that the paper uses as its base
+ * LRR solver (Section 4 preamble), and the divide-factor-combine wrapper of
+ * Algorithm 1 (Section 2.2): the columns of M are split into t blocks C_i, each
+ * block solves Eq. (2) with the whole M as dictionary, and the block estimates
+ * are combined by projecting onto the column space of the first one.
+ *
+ * Memory conventions (all entry points)
+ * -------------------------------------
+ *  - Matrices are column-major with an explicit leading dimension (ld >= rows).
+ *    A column is one data point, so a row-major (n, m) tensor holds M^T.
+ *  - Matrix arguments are DEVICE pointers on the ctx's device.  The element type
+ *    is double for LRR_FP64 and float for LRR_FP32 / LRR_MIXED_BF16.
+ *    Index arrays (perm, offsets) and the info arrays are HOST pointers.
+ *  - The caller owns every argument buffer.  The library owns its workspace,
+ *    which lives in the ctx and is reused (and grown) across calls.
+ *  - All device work is enqueued on `stream`; every entry point returns after the
+ *    result is complete on that stream (it reads back convergence flags).
+ *  - A ctx is not thread safe: use one ctx per host thread.
+ *
+ * Errors
+ * ------
+ *  Arguments are validated before any device work.  A negative status means no
+ *  output was written; LRR_NOT_CONVERGED (> 0) means outputs are valid but some
+ *  block hit max_iter.  lrr_last_error() returns a message for the last failure.
+ */
+#ifndef LRR_H
+#define LRR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lrr_ctx lrr_ctx;
+
+typedef enum {
+    LRR_OK = 0,
+    LRR_NOT_CONVERGED = 1,   /* outputs valid, max_iter reached in some block      */
+    LRR_EINVAL = -1,         /* bad argument (dims, ld, lambda, partition, nulls)  */
+    LRR_ENOMEM = -2,         /* device workspace could not be allocated           */
+    LRR_EDEVICE = -3,        /* a HIP runtime call failed                          */
+    LRR_ENUMERIC = -4,       /* non-finite value in the input                      */
+    LRR_ENOTAPE = -5         /* backward called without a recorded forward         */
+} lrr_status;
+
+typedef enum {
+    LRR_FP64 = 0,            /* every product and factorisation in FP64            */
+    LRR_FP32 = 1,            /* FP32 storage and products, FP64 reductions          */
+    LRR_MIXED_BF16 = 2       /* BF16 split products on MFMA, FP64 solve/SVD/norms  */
+} lrr_precision;
+
+typedef enum {
+    LRR_SOLVE_AUTO = 0,      /* push-through when m < n, literal otherwise          */
+    LRR_SOLVE_LITERAL = 1,   /* Cholesky of I + A^T A (n x n)                        */
+    LRR_SOLVE_PUSHTHROUGH = 2/* Cholesky of I + A A^T (m x m), same iterates        */
+} lrr_solve_form;
+
+/* Inexact-ALM controls.  The paper does not print the solver's constants; these
+ * are explicit so that any caller (and the CPU reference) can use the same ones. */
+typedef struct {
+    int precision;           /* lrr_precision                                       */
+    int solve_form;          /* lrr_solve_form                                      */
+    double mu0;              /* initial penalty (default 1e-6)                      */
+    double rho;              /* penalty growth factor (default 1.1)                 */
+    double mu_max;           /* penalty cap (default 1e10)                          */
+    double tol;              /* stop when both residual max-norms < tol (1e-8)      */
+    int max_iter;            /* iteration cap (default 1000)                        */
+    int fixed_iters;         /* > 0: run exactly this many iterations, no stop test */
+    int check_every;         /* read device convergence flags every c iterations   */
+    int max_sweeps;          /* Jacobi sweep cap of the eigensolver (default 30)    */
+    int save_for_backward;   /* record what dfc_lrr_backward needs                  */
+    int checkpoint_every;    /* adjoint checkpoint spacing k (default 20)           */
+    int eig_block;           /* Jacobi block width: 0 auto, 16 or 32                */
+    int reserved[7];         /* must be zero                                        */
+} lrr_opts;
+
+/* Per-block results; every pointer may be NULL, each non-NULL array has t entries. */
+typedef struct {
+    int *iters;              /* iterations run by each block                        */
+    int *rank;               /* rank of each block estimate J_i                     */
+    double *res_primal;      /* ||X_i - A Z_i - E_i||_max at the last iteration     */
+    double *res_coupling;    /* ||Z_i - J_i||_max at the last iteration             */
+    int batch_iters;         /* (out) iterations of the batched loop                */
+    int combine_rank;        /* (out) rank r_1 of the combine basis                 */
+} lrr_info;
+
+/* Library version string. */
+const char *lrr_version(void);
+
+/* Fill *opts with the defaults listed above. */
+void lrr_opts_default(lrr_opts *opts);
+
+/* Create a context bound to HIP device `device`.  *out is NULL on failure. */
+lrr_status lrr_ctx_create(int device, lrr_ctx **out);
+
+/* Release the context and its workspace.  NULL is accepted. */
+void lrr_ctx_destroy(lrr_ctx *ctx);
+
+/* Message of the last failure on ctx (or of the last failure without a ctx). */
+const char *lrr_last_error(const lrr_ctx *ctx);
+
+/* Host-only check of a D-step partition (Algorithm 1, SampleCols): perm must be a
+ * permutation of 0..n-1 and offsets[0] = 0 < offsets[1] < ... < offsets[t] = n.
+ * perm and offsets are host int32 arrays of length n and t+1. */
+lrr_status lrr_check_partition(int n, int t, const int *perm, const int *offsets);
+
+/* Device bytes of workspace dfc_lrr_solve would hold for this problem. */
+lrr_status lrr_workspace_bytes(int m, int n, int t, const int *offsets,
+                               const lrr_opts *opts, size_t *bytes);
+
+/*
+ * Eq. (2) with one block: observations X (m x l, device), dictionary A (m x n,
+ * device).  Writes Z (n x l, ldz >= n) and, if E is not NULL, E (m x l, lde >= m).
+ * Z is the ALM iterate Z; at convergence it differs from the exactly low-rank J
+ * by less than tol in max-norm.
+ */
+lrr_status lrr_solve(lrr_ctx *ctx, int m, int n, int l,
+                     const void *A, int lda, const void *X, int ldx,
+                     double lambda, const lrr_opts *opts,
+                     void *Z, int ldz, void *E, int lde,
+                     lrr_info *info, void *stream);
+
+/*
+ * Algorithm 1 (DFC-LRR) on M (m x n, device).  Block i holds the original
+ * columns perm[offsets[i] .. offsets[i+1]-1] (host arrays, see
+ * lrr_check_partition).  Every block solves Eq. (2) with C_i = M[:, block] and
+ * the whole M as dictionary (same lambda for all blocks); the estimate of a block
+ * is its J at termination (exactly low rank, factored).  The C step projects
+ * [J_1 ... J_t] onto the column space of J_1 and puts the columns back in their
+ * original order: Z (n x n, ldz >= n).  If S is not NULL it receives the outlier
+ * estimates [E_1 ... E_t] in the original column order (m x n, lds >= m).
+ * With t = 1 the result is J of lrr_solve(X = M, A = M).
+ */
+lrr_status dfc_lrr_solve(lrr_ctx *ctx, int m, int n, const void *M, int ldm,
+                         double lambda, int t, const int *perm, const int *offsets,
+                         const lrr_opts *opts, void *Z, int ldz, void *S, int lds,
+                         lrr_info *info, void *stream);
+
+/*
+ * Reverse-mode derivative of the last dfc_lrr_solve on ctx, which must have run
+ * with save_for_backward = 1 and fixed_iters > 0 (the unrolled map).  Given
+ * dZ = dL/dZ (n x n, device, original column order) it writes dL/dlambda to
+ * *dlambda (host) and, if dM is not NULL, dL/dM (m x n, device, lddm >= m).
+ */
+lrr_status dfc_lrr_backward(lrr_ctx *ctx, const void *dZ, int lddz,
+                            double *dlambda, void *dM, int lddm, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRR_H */

@@ -1,0 +1,47 @@
+/*
+ * lrr_diag.h -- diagnostic entry points of the gfx950 DFC-LRR library.
+ *
+ * These expose the building blocks of the solver one by one, so that each can
+ * be checked against a plain reference in isolation.  They are not needed to
+ * solve a problem.  Conventions are those of lrr.h: column-major FP64 DEVICE
+ * matrices with leading dimensions, work enqueued on `stream`, the call
+ * returns after the work is complete, negative status = nothing written.
+ */
+#ifndef LRR_DIAG_H
+#define LRR_DIAG_H
+
+#include "lrr.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C = alpha * op(A) op(B) + beta * C with op(X) = X or X^T (ta, tb != 0 means
+ * transposed).  op(A) is M x K, op(B) is K x N, C is M x N.  The MFMA GEMM used
+ * for every dense product of the solver (Gram matrices, dictionary products,
+ * reconstruction, combine). */
+lrr_status lrr_diag_dgemm(lrr_ctx *ctx, int ta, int tb, int M, int N, int K, double alpha,
+                          const double *A, int lda, const double *B, int ldb, double beta,
+                          double *C, int ldc, void *stream);
+
+/* Kinv = (I + A A^T)^{-1} for A (m x n): the factorisation the Z-step uses
+ * (FP64 blocked Cholesky, then the explicit inverse of the factor).
+ * Kinv is m x m with ld >= m. */
+lrr_status lrr_diag_spd_inverse(lrr_ctx *ctx, int m, int n, const double *A, int lda,
+                                double *Kinv, int ldk, void *stream);
+
+/* Eigen-decomposition of `count` symmetric matrices of orders l[i] (host array):
+ * matrix i is read from B + i*strideB (ld = ldb >= max l) and its eigenvalues
+ * (unsorted) are written to lam + i*ldlam, its eigenvectors (columns, same
+ * order) to W + i*strideB (ld = ldb).  Block-Jacobi solver of the thresholding
+ * step, started from the identity.  sweeps (host, may be NULL) receives the
+ * number of sweeps run. */
+lrr_status lrr_diag_syevj(lrr_ctx *ctx, int count, const int *l, const double *B, int ldb,
+                          long strideB, double *lam, int ldlam, double *W, int eig_block,
+                          int *sweeps, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRR_DIAG_H */

@@ -1,0 +1,327 @@
+// Column-wise kernels of the batched inexact-ALM iteration (FP64).
+//
+// All t blocks of DFC-LRR share one column-concatenated layout: block b owns
+// columns [boff[b], boff[b+1]) of every state matrix (Z, J, Y2 in R^{n x n};
+// E, Y1 in R^{m x n}).  Each kernel here handles one column per workgroup,
+// skips the columns of frozen blocks, and reads the penalty of the current
+// iteration from the device-resident DevIter, so that the same launches can
+// be replayed without host-side arguments changing.
+//
+// Per iteration (push-through form of the Z-step, see the solver):
+//   k_form_Y      Y = Z + Y2/mu, column sums of squares        (J-step input)
+//   k_block_fro   ||Y_b||_F per block; ||Y_b||_F <= tau => J_b = 0 exactly
+//   k_form_QT     Q = J - Y2/mu,  T = X - E + Y1/mu
+//   k_update_Z    Z = Q + M^T V,  R2 = Z - J,  Y2 += mu R2,  max|R2|
+//   k_estep       q = E + V (= X - M Z + Y1/mu), column l2 shrinkage by
+//                 lam/mu, R1 = q - Y1/mu - E,  Y1 += mu R1,  max|R1|
+//   k_check       per-block stop test, freeze, advance mu
+// Reductions run in a fixed order (deterministic); the max-norms use integer
+// atomics on the bit patterns of non-negative doubles, which is order-free.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lrr {
+
+namespace {
+
+// deterministic sum over a 256-thread workgroup; result valid in all threads
+__device__ double block_sum256(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    const double r = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_max256(double v, double* red) {
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_gather_cols(const double* __restrict__ M, long ldm,
+                                                      double* __restrict__ X, long ldx, int m,
+                                                      const int* __restrict__ perm) {
+    const int j = blockIdx.x;
+    const long src = perm[j];
+    for (int i = threadIdx.x; i < m; i += 256) X[i + j * ldx] = M[i + src * ldm];
+}
+
+__global__ __launch_bounds__(256) void k_scatter_cols(const double* __restrict__ X, long ldx,
+                                                       double* __restrict__ S, long lds, int m,
+                                                       const int* __restrict__ perm) {
+    const int j = blockIdx.x;
+    const long dst = perm[j];
+    for (int i = threadIdx.x; i < m; i += 256) S[i + dst * lds] = X[i + j * ldx];
+}
+
+__global__ __launch_bounds__(256) void k_copy_cols(const double* __restrict__ X, long ldx,
+                                                    double* __restrict__ Y, long ldy, int m) {
+    const int j = blockIdx.x;
+    for (int i = threadIdx.x; i < m; i += 256) Y[i + j * ldy] = X[i + j * ldx];
+}
+
+__global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ M, long ldm, int m,
+                                                    int* flag) {
+    const int j = blockIdx.x;
+    int bad = 0;
+    for (int i = threadIdx.x; i < m; i += 256) bad |= !isfinite(M[i + j * ldm]);
+    if (bad) atomicOr(flag, 1);
+}
+
+__global__ __launch_bounds__(256) void k_form_Y(const double* __restrict__ Z, const double* __restrict__ Y2,
+                                                 double* __restrict__ Y, double* __restrict__ colsq,
+                                                 int n, long ld, const int* __restrict__ colblk,
+                                                 const int* __restrict__ active, const DevIter* it) {
+    __shared__ double red[4];
+    const int j = blockIdx.x;
+    if (!active[colblk[j]]) return;
+    const double mu = it->mu;
+    const long o = j * ld;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double y = Z[o + i] + Y2[o + i] / mu;
+        Y[o + i] = y;
+        s += y * y;
+    }
+    s = block_sum256(s, red);
+    if (threadIdx.x == 0) colsq[j] = s;
+}
+
+__global__ __launch_bounds__(256) void k_block_fro(const double* __restrict__ colsq,
+                                                    const int* __restrict__ boff, BlockState bs,
+                                                    const DevIter* it) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    if (!bs.active[b]) {
+        if (threadIdx.x == 0) bs.svt_run[b] = 0;
+        return;
+    }
+    double s = 0.0;
+    for (int c = boff[b] + threadIdx.x; c < boff[b + 1]; c += 256) s += colsq[c];
+    s = block_sum256(s, red);
+    if (threadIdx.x == 0) {
+        // sigma_max <= ||Y||_F, so ||Y||_F <= tau gives J = 0 without a decomposition
+        bs.svt_run[b] = (sqrt(s) > it->tau) ? 1 : 0;
+        bs.rank[b] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_J(double* __restrict__ J, int n, long ld,
+                                                 const int* __restrict__ colblk, BlockState bs) {
+    const int j = blockIdx.x;
+    const int b = colblk[j];
+    if (!bs.active[b] || bs.svt_run[b]) return;
+    for (int i = threadIdx.x; i < n; i += 256) J[i + j * ld] = 0.0;
+}
+
+// SVT weights from the converged Gram eigenvalues: sigma = sqrt(lambda),
+// g = (1 - tau/sigma)_+ scales the eigenvector columns, h = 1/sigma on the
+// kept columns (the combine basis), rank = #{sigma > tau}.
+__global__ __launch_bounds__(256) void k_svt_weights(const SvtDesc* __restrict__ descs,
+                                                      const DevIter* it, BlockState bs) {
+    const SvtDesc d = descs[blockIdx.y];
+    if (!d.run[0]) return;
+    const int i = blockIdx.x;
+    if (i >= d.L) return;
+    const double tau = it->tau;
+    const double lam = (i < d.l) ? d.B[i + (long)i * d.L] : 0.0;
+    const double sig = sqrt(fmax(lam, 0.0));
+    const bool keep = sig > tau;
+    const double g = keep ? 1.0 - tau / sig : 0.0;
+    if (threadIdx.x == 0) {
+        d.lam[i] = lam;
+        d.h[i] = keep ? 1.0 / sig : 0.0;
+        if (keep) atomicAdd(&bs.rank[d.block], 1);
+    }
+    const long o = (long)i * d.L;
+    for (int r = threadIdx.x; r < d.L; r += 256) d.Wg[o + r] = d.W[o + r] * g;
+}
+
+__global__ __launch_bounds__(256) void k_form_QT(const double* __restrict__ J, const double* __restrict__ Y2,
+                                                  double* __restrict__ Q, int n, long ldn,
+                                                  const double* __restrict__ X, const double* __restrict__ E,
+                                                  const double* __restrict__ Y1, double* __restrict__ T,
+                                                  int m, long ldm, const int* __restrict__ colblk,
+                                                  const int* __restrict__ active, const DevIter* it) {
+    const int j = blockIdx.x;
+    if (!active[colblk[j]]) return;
+    const double mu = it->mu;
+    const long on = j * ldn, om = j * ldm;
+    for (int i = threadIdx.x; i < n; i += 256) Q[on + i] = J[on + i] - Y2[on + i] / mu;
+    for (int i = threadIdx.x; i < m; i += 256) T[om + i] = X[om + i] - E[om + i] + Y1[om + i] / mu;
+}
+
+__global__ __launch_bounds__(256) void k_update_Z(const double* __restrict__ Q, const double* __restrict__ MtV,
+                                                   const double* __restrict__ J, double* __restrict__ Z,
+                                                   double* __restrict__ Y2, int n, long ld,
+                                                   const int* __restrict__ colblk, BlockState bs,
+                                                   const DevIter* it) {
+    __shared__ double red[4];
+    const int j = blockIdx.x;
+    const int b = colblk[j];
+    if (!bs.active[b]) return;
+    const double mu = it->mu;
+    const long o = j * ld;
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double z = Q[o + i] + MtV[o + i];
+        const double r2 = z - J[o + i];
+        Z[o + i] = z;
+        Y2[o + i] = Y2[o + i] + mu * r2;
+        mx = fmax(mx, fabs(r2));
+    }
+    mx = block_max256(mx, red);
+    if (threadIdx.x == 0) atomic_max_nonneg(&bs.r2max[b], mx);
+}
+
+__global__ __launch_bounds__(256) void k_estep(double* __restrict__ E, const double* __restrict__ V,
+                                                double* __restrict__ Y1, int m, long ld, double lam,
+                                                const int* __restrict__ colblk, BlockState bs,
+                                                const DevIter* it) {
+    __shared__ double red[4];
+    const int j = blockIdx.x;
+    const int b = colblk[j];
+    if (!bs.active[b]) return;
+    const double mu = it->mu;
+    const long o = j * ld;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        const double q = E[o + i] + V[o + i];   // = X - M Z + Y1/mu
+        E[o + i] = q;
+        s += q * q;
+    }
+    s = block_sum256(s, red);
+    const double nrm = sqrt(s);
+    const double thr = lam / mu;
+    const double scale = (nrm > thr) ? 1.0 - thr / nrm : 0.0;
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        const double q = E[o + i];
+        const double e = q * scale;
+        const double y1 = Y1[o + i];
+        const double r1 = q - y1 / mu - e;
+        Y1[o + i] = y1 + mu * r1;
+        E[o + i] = e;
+        mx = fmax(mx, fabs(r1));
+    }
+    mx = block_max256(mx, red);
+    if (threadIdx.x == 0) atomic_max_nonneg(&bs.r1max[b], mx);
+}
+
+__global__ __launch_bounds__(256) void k_check(BlockState bs, int t, DevIter* it,
+                                                const double* __restrict__ mu_sched, double tol,
+                                                int fixed, int* n_active) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int k = it->k;
+    for (int b = threadIdx.x; b < t; b += 256) {
+        if (bs.active[b]) {
+            const double r1 = __longlong_as_double((long long)bs.r1max[b]);
+            const double r2 = __longlong_as_double((long long)bs.r2max[b]);
+            bs.res1[b] = r1;
+            bs.res2[b] = r2;
+            bs.iters[b] = k + 1;
+            if (!fixed && r1 < tol && r2 < tol) bs.active[b] = 0;
+            else atomicAdd(&cnt, 1);
+        }
+        bs.r1max[b] = 0ull;
+        bs.r2max[b] = 0ull;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        it->k = k + 1;
+        it->mu = mu_sched[k + 1];
+        it->tau = 1.0 / it->mu;
+        *n_active = cnt;
+    }
+}
+
+__global__ void k_init_iter(DevIter* it, const double* __restrict__ mu_sched) {
+    it->k = 0;
+    it->pad = 0;
+    it->mu = mu_sched[0];
+    it->tau = 1.0 / mu_sched[0];
+}
+
+__global__ __launch_bounds__(256) void k_scale_cols(double* __restrict__ U, long ld, int rows,
+                                                     const double* __restrict__ h) {
+    const int j = blockIdx.x;
+    const double s = h[j];
+    for (int i = threadIdx.x; i < rows; i += 256) U[i + j * ld] *= s;
+}
+
+__global__ void k_set_identity(double* __restrict__ W, int L) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < (long)L * L) W[idx] = ((idx % L) == (idx / L)) ? 1.0 : 0.0;
+}
+
+}  // namespace
+
+void launch_gather_cols(const double* M, long ldm, double* X, long ldx, int m, int ncols,
+                        const int* d_perm, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_cols, dim3(ncols), dim3(256), 0, s, M, ldm, X, ldx, m, d_perm);
+}
+void launch_scatter_cols(const double* X, long ldx, double* S, long lds, int m, int ncols,
+                         const int* d_perm, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_cols, dim3(ncols), dim3(256), 0, s, X, ldx, S, lds, m, d_perm);
+}
+void launch_copy_cols(const double* X, long ldx, double* Y, long ldy, int m, int ncols, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_cols, dim3(ncols), dim3(256), 0, s, X, ldx, Y, ldy, m);
+}
+void launch_nonfinite(const double* M, long ldm, int m, int n, int* d_flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_nonfinite, dim3(n), dim3(256), 0, s, M, ldm, m, d_flag);
+}
+void launch_form_Y(const double* Z, const double* Y2, double* Y, double* colsq, int n, long ld, int ncols,
+                   const int* colblk, const int* active, const DevIter* it, hipStream_t s) {
+    hipLaunchKernelGGL(k_form_Y, dim3(ncols), dim3(256), 0, s, Z, Y2, Y, colsq, n, ld, colblk, active, it);
+}
+void launch_block_fro(const double* colsq, const int* boff, int t, BlockState bs, const DevIter* it,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_block_fro, dim3(t), dim3(256), 0, s, colsq, boff, bs, it);
+}
+void launch_zero_J(double* J, int n, long ld, int ncols, const int* colblk, BlockState bs, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_J, dim3(ncols), dim3(256), 0, s, J, n, ld, colblk, bs);
+}
+void launch_svt_weights(const SvtDesc* d, int count, int maxL, const DevIter* it, BlockState bs,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_svt_weights, dim3(maxL, count), dim3(256), 0, s, d, it, bs);
+}
+void launch_form_QT(const double* J, const double* Y2, double* Q, int n, long ldn, const double* X,
+                    const double* E, const double* Y1, double* T, int m, long ldm, int ncols,
+                    const int* colblk, const int* active, const DevIter* it, hipStream_t s) {
+    hipLaunchKernelGGL(k_form_QT, dim3(ncols), dim3(256), 0, s, J, Y2, Q, n, ldn, X, E, Y1, T, m, ldm,
+                       colblk, active, it);
+}
+void launch_update_Z(const double* Q, const double* MtV, const double* J, double* Z, double* Y2, int n,
+                     long ld, int ncols, const int* colblk, BlockState bs, const DevIter* it,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_update_Z, dim3(ncols), dim3(256), 0, s, Q, MtV, J, Z, Y2, n, ld, colblk, bs, it);
+}
+void launch_estep(double* E, const double* V, double* Y1, int m, long ld, int ncols, double lam,
+                  const int* colblk, BlockState bs, const DevIter* it, hipStream_t s) {
+    hipLaunchKernelGGL(k_estep, dim3(ncols), dim3(256), 0, s, E, V, Y1, m, ld, lam, colblk, bs, it);
+}
+void launch_check(BlockState bs, int t, DevIter* it, const double* mu_sched, double tol, int fixed,
+                  int* n_active, hipStream_t s) {
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, s, bs, t, it, mu_sched, tol, fixed, n_active);
+}
+void launch_init_iter(DevIter* it, const double* mu_sched, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_iter, dim3(1), dim3(1), 0, s, it, mu_sched);
+}
+void launch_scale_cols(double* U, long ld, int rows, int ncols, const double* h, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_cols, dim3(ncols), dim3(256), 0, s, U, ld, rows, h);
+}
+void launch_set_identity(double* W, int L, hipStream_t s) {
+    const long n = (long)L * L;
+    hipLaunchKernelGGL(k_set_identity, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, L);
+}
+
+}  // namespace lrr

@@ -1,0 +1,126 @@
+// Shared definitions of the gfx950 DFC-LRR library (device and host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+namespace lrr {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// ----------------------------------------------------------------------------
+// Batched GEMM descriptor:  C = alpha * op(A) op(B) + beta * C  (column-major).
+// op(A) is M x K, op(B) is K x N, C is M x N.  If `active` is set and
+// active[0] == 0 the batch item is skipped (frozen or trivial block).  If
+// `colmap` is set, result column j is stored in column colmap[j] of C.
+// ----------------------------------------------------------------------------
+struct GemmDesc {
+    const double* A;
+    const double* B;
+    double* C;
+    int M, N, K;
+    int lda, ldb, ldc;
+    double alpha, beta;
+    const int* active;
+    const int* colmap;
+};
+
+// Device-resident iteration state of the batched ALM loop.  Kernels read the
+// penalty of the current iteration from here, so a captured sequence of
+// launches replays correctly.
+struct DevIter {
+    int k;          // iteration index (0-based) of the iteration being run
+    int pad;
+    double mu;      // penalty mu_k of this iteration
+    double tau;     // 1 / mu_k, the singular-value threshold
+};
+
+// Per-block state of the batched ALM loop (device arrays of length t).
+struct BlockState {
+    int* active;        // 1 while the block is iterating
+    int* svt_run;       // 1 if this iteration needs the eigen-based threshold step
+    int* iters;         // iterations run
+    int* rank;          // rank of J
+    double* res1;       // ||X - AZ - E||_max of the last iteration
+    double* res2;       // ||Z - J||_max of the last iteration
+    unsigned long long* r1max;  // running max (bit pattern of a non-negative double)
+    unsigned long long* r2max;
+};
+
+// Eigensolver descriptor of one symmetric matrix (padded size L, ld = L).
+struct EigDesc {
+    double* B;          // L x L symmetric, diagonalised in place
+    double* W;          // L x L, accumulates the rotations (eigenvectors)
+    double* R;          // (L / (2 bs)) rotation blocks of (2 bs)^2 each
+    double* lam;        // L eigenvalues (diagonal of B on exit)
+    int L;              // padded order, multiple of 2 bs
+    int l;              // true order (rows/cols >= l are padding)
+    const int* run;     // skip the matrix if run[0] == 0
+    int* st;            // [0] converged, [1] pairs that rotated in the current sweep
+    double* scale;      // max |diag| of B at the start, for the absolute floor
+};
+
+// Thresholding weights of one block after its Gram eigensolve.
+struct SvtDesc {
+    const double* B;    // L x L, diagonal = eigenvalues of the Gram matrix
+    const double* W;    // L x L eigenvectors
+    double* Wg;         // L x L, W scaled column-wise by g = (1 - tau/sigma)_+
+    double* lam;        // L eigenvalues (copy)
+    double* h;          // L, 1/sigma on kept columns, 0 elsewhere
+    int L, l;
+    const int* run;
+    int block;
+};
+
+__device__ __forceinline__ unsigned long long dbl_bits(double x) {
+    return (unsigned long long)__double_as_longlong(x);
+}
+
+// max of non-negative doubles through their (monotone) bit patterns: the
+// result does not depend on the order of the updates.
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, double v) {
+    atomicMax(addr, dbl_bits(v));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Round-robin (circle method) pairing of N players (N even) in round r of N-1:
+// player N-1 is fixed, the others rotate.  Every pair meets once per sweep.
+__host__ __device__ __forceinline__ void rr_pair(int N, int r, int k, int& a, int& b) {
+    if (k == 0) {
+        a = r;
+        b = N - 1;
+    } else {
+        a = (r + k) % (N - 1);
+        b = (r - k + (N - 1)) % (N - 1);
+    }
+    if (a > b) { int t = a; a = b; b = t; }
+}
+
+}  // namespace lrr
+
+#define LRR_HIP(call)                                                         \
+    do {                                                                      \
+        hipError_t _e = (call);                                               \
+        if (_e != hipSuccess) {                                               \
+            throw lrr::HipError(std::string(#call) + ": " + hipGetErrorString(_e)); \
+        }                                                                     \
+    } while (0)
+
+namespace lrr {
+struct HipError {
+    std::string msg;
+    explicit HipError(std::string m) : msg(std::move(m)) {}
+};
+}  // namespace lrr

@@ -1,0 +1,283 @@
+// Batched two-sided block-Jacobi eigensolver for symmetric FP64 matrices.
+//
+// This is the "small dense SVD in FP64" of the singular-value thresholding
+// step: the SVT of a block Y (n x l) needs the eigen-decomposition of its Gram
+// matrix Y^T Y (l x l).  Several matrices (one per DFC block, of different
+// orders) are processed by the same launches.
+//
+// A matrix of padded order L is cut into nb = L / BS blocks of BS indices.  One
+// sweep has nb - 1 rounds; in a round the blocks are paired by the circle
+// method and every pair (p, q) is handled in two launches:
+//   phase A  one workgroup per pair diagonalises the 2BS x 2BS sub-matrix
+//            B[p u q, p u q] in LDS with cyclic parallel Jacobi and writes the
+//            accumulated rotation R_pq (2BS x 2BS);
+//   phase B  every tile pair (P, Q), P <= Q, of the round is replaced by
+//            R_P^T B[P, Q] R_Q (and its transpose), and the eigenvector
+//            accumulator gets W[:, P] <- W[:, P] R_P.
+// A sweep in which no pair needed a rotation ends the iteration.  The
+// rotation test is relative, |b_pq| > 1e-15 sqrt(b_pp b_qq), with an absolute
+// floor of 1e-18 max|diag B| so that noise-level entries terminate.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lrr {
+
+namespace {
+
+constexpr double kRelTol = 1e-15;
+constexpr double kAbsFloor = 1e-18;
+constexpr int kInnerSweeps = 12;
+
+// symmetric 2x2 Schur rotation: [c s; -s c]^T [app apq; apq aqq] [c s; -s c] is diagonal
+__device__ __forceinline__ void sym_schur2(double app, double aqq, double apq, double& c, double& s) {
+    const double theta = (aqq - app) / (2.0 * apq);
+    const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = t * c;
+}
+
+template <int BS, int NT>
+__global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__ descs, int round) {
+    constexpr int PB = 2 * BS;
+    constexpr int NP = PB / 2;   // rotations per inner round
+    const EigDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0 || d.st[0] != 0) return;
+    const int nb = d.L / BS;
+    const int P = blockIdx.x;
+    if (P >= nb / 2 || round >= nb - 1) return;
+    int p, q;
+    rr_pair(nb, round, P, p, q);
+
+    __shared__ double S[PB][PB + 1];
+    __shared__ double R[PB][PB + 1];
+    __shared__ double csc[NP], css[NP];
+    __shared__ int any;
+
+    const int tid = threadIdx.x;
+    const long L = d.L;
+    for (int idx = tid; idx < PB * PB; idx += NT) {
+        const int i = idx % PB, j = idx / PB;
+        const long gi = (i < BS) ? (long)p * BS + i : (long)q * BS + (i - BS);
+        const long gj = (j < BS) ? (long)p * BS + j : (long)q * BS + (j - BS);
+        S[i][j] = d.B[gi + gj * L];
+        R[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    const double floor_abs = kAbsFloor * d.scale[0];
+    int rotated = 0;
+    __syncthreads();
+
+    for (int sweep = 0; sweep < kInnerSweeps; ++sweep) {
+        if (tid == 0) any = 0;
+        __syncthreads();
+        for (int r = 0; r < PB - 1; ++r) {
+            if (tid < NP) {
+                int a, b;
+                rr_pair(PB, r, tid, a, b);
+                const double app = S[a][a], aqq = S[b][b], apq = S[a][b];
+                double c = 1.0, s = 0.0;
+                if (fabs(apq) > fmax(kRelTol * sqrt(fabs(app * aqq)), floor_abs)) {
+                    sym_schur2(app, aqq, apq, c, s);
+                    any = 1;
+                }
+                csc[tid] = c;
+                css[tid] = s;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < NP * NP; idx += NT) {
+                const int P2 = idx / NP, Q2 = idx % NP;
+                int aP, bP, aQ, bQ;
+                rr_pair(PB, r, P2, aP, bP);
+                rr_pair(PB, r, Q2, aQ, bQ);
+                const double cP = csc[P2], sP = css[P2], cQ = csc[Q2], sQ = css[Q2];
+                const double s_aa = S[aP][aQ], s_ab = S[aP][bQ];
+                const double s_ba = S[bP][aQ], s_bb = S[bP][bQ];
+                // columns: T = S G_Q
+                const double t_aa = cQ * s_aa - sQ * s_ab, t_ab = sQ * s_aa + cQ * s_ab;
+                const double t_ba = cQ * s_ba - sQ * s_bb, t_bb = sQ * s_ba + cQ * s_bb;
+                // rows: S' = G_P^T T
+                S[aP][aQ] = cP * t_aa - sP * t_ba;
+                S[aP][bQ] = cP * t_ab - sP * t_bb;
+                S[bP][aQ] = sP * t_aa + cP * t_ba;
+                S[bP][bQ] = sP * t_ab + cP * t_bb;
+            }
+            for (int idx = tid; idx < PB * NP; idx += NT) {
+                const int i = idx / NP, Q2 = idx % NP;
+                int aQ, bQ;
+                rr_pair(PB, r, Q2, aQ, bQ);
+                const double cQ = csc[Q2], sQ = css[Q2];
+                const double ra = R[i][aQ], rb = R[i][bQ];
+                R[i][aQ] = cQ * ra - sQ * rb;
+                R[i][bQ] = sQ * ra + cQ * rb;
+            }
+            __syncthreads();
+        }
+        const int a = any;
+        __syncthreads();
+        if (!a) break;
+        rotated = 1;
+    }
+    double* Rg = d.R + (long)P * PB * PB;
+    for (int idx = tid; idx < PB * PB; idx += NT) {
+        const int i = idx % PB, j = idx / PB;
+        Rg[i + (long)j * PB] = R[i][j];
+    }
+    if (tid == 0 && rotated) atomicAdd(&d.st[1], 1);
+}
+
+// phase B: tiles of B and row chunks of W
+template <int BS>
+__global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict__ descs, int round) {
+    constexpr int PB = 2 * BS;
+    constexpr int RC = 64;   // rows of W per workgroup
+    const EigDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0 || d.st[0] != 0) return;
+    const int nb = d.L / BS;
+    const int npair = nb / 2;
+    const int ntri = npair * (npair + 1) / 2;
+    const int nchunks = (d.L + RC - 1) / RC;
+    const int item = blockIdx.x;
+    if (item >= ntri + nchunks * npair || round >= nb - 1) return;
+
+    __shared__ double X[PB][PB + 1];
+    __shared__ double RP[PB][PB + 1];
+    __shared__ double RQ[PB][PB + 1];
+    __shared__ double T[PB][PB + 1];
+    const int tid = threadIdx.x;
+    const long L = d.L;
+
+    if (item < ntri) {
+        // decode upper-triangular index (P <= Q)
+        int P = 0, rem = item;
+        while (rem >= npair - P) { rem -= npair - P; ++P; }
+        const int Q = P + rem;
+        int p1, q1, p2, q2;
+        rr_pair(nb, round, P, p1, q1);
+        rr_pair(nb, round, Q, p2, q2);
+        const double* RgP = d.R + (long)P * PB * PB;
+        const double* RgQ = d.R + (long)Q * PB * PB;
+        for (int idx = tid; idx < PB * PB; idx += 256) {
+            const int i = idx % PB, j = idx / PB;
+            const long gi = (i < BS) ? (long)p1 * BS + i : (long)q1 * BS + (i - BS);
+            const long gj = (j < BS) ? (long)p2 * BS + j : (long)q2 * BS + (j - BS);
+            X[i][j] = d.B[gi + gj * L];
+            RP[i][j] = RgP[i + (long)j * PB];
+            RQ[i][j] = RgQ[i + (long)j * PB];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < PB * PB; idx += 256) {
+            const int i = idx % PB, j = idx / PB;
+            double acc = 0.0;
+#pragma unroll 8
+            for (int k = 0; k < PB; ++k) acc += X[i][k] * RQ[k][j];
+            T[i][j] = acc;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < PB * PB; idx += 256) {
+            const int i = idx % PB, j = idx / PB;
+            double acc = 0.0;
+#pragma unroll 8
+            for (int k = 0; k < PB; ++k) acc += RP[k][i] * T[k][j];
+            const long gi = (i < BS) ? (long)p1 * BS + i : (long)q1 * BS + (i - BS);
+            const long gj = (j < BS) ? (long)p2 * BS + j : (long)q2 * BS + (j - BS);
+            d.B[gi + gj * L] = acc;
+            if (P != Q) d.B[gj + gi * L] = acc;
+        }
+    } else {
+        const int w = item - ntri;
+        const int P = w % npair, chunk = w / npair;
+        int p1, q1;
+        rr_pair(nb, round, P, p1, q1);
+        const double* RgP = d.R + (long)P * PB * PB;
+        const int r0 = chunk * RC;
+        // reuse X as a RC x PB panel when RC <= PB, else loop in pieces of PB rows
+        for (int rr = 0; rr < RC; rr += PB) {
+            for (int idx = tid; idx < PB * PB; idx += 256) {
+                const int i = idx % PB, j = idx / PB;
+                const long gi = r0 + rr + i;
+                const long gj = (j < BS) ? (long)p1 * BS + j : (long)q1 * BS + (j - BS);
+                X[i][j] = (gi < L) ? d.W[gi + gj * L] : 0.0;
+                if (rr == 0) RP[i][j] = RgP[i + (long)j * PB];
+            }
+            __syncthreads();
+            for (int idx = tid; idx < PB * PB; idx += 256) {
+                const int i = idx % PB, j = idx / PB;
+                double acc = 0.0;
+#pragma unroll 8
+                for (int k = 0; k < PB; ++k) acc += X[i][k] * RP[k][j];
+                const long gi = r0 + rr + i;
+                const long gj = (j < BS) ? (long)p1 * BS + j : (long)q1 * BS + (j - BS);
+                if (gi < L) d.W[gi + gj * L] = acc;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// start of an eigensolve: reset flags, scale = max |diag|
+__global__ __launch_bounds__(256) void k_jacobi_init(const EigDesc* __restrict__ descs) {
+    const EigDesc d = descs[blockIdx.x];
+    if (d.run[0] == 0) return;
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < d.l; i += 256) mx = fmax(mx, fabs(d.B[i + (long)i * d.L]));
+    mx = wave_max(mx);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        d.scale[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        d.st[0] = 0;
+        d.st[1] = 0;
+    }
+}
+
+// end of a sweep: a sweep without rotations means converged
+__global__ void k_jacobi_sweep_end(const EigDesc* __restrict__ descs, int count, int* any_active) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const EigDesc d = descs[b];
+    if (d.run[0] == 0 || d.st[0] != 0) return;
+    if (d.st[1] == 0) d.st[0] = 1;
+    else atomicAdd(any_active, 1);
+    d.st[1] = 0;
+}
+
+// eigenvalues = diagonal (padding -> 0)
+__global__ void k_jacobi_eigvals(const EigDesc* __restrict__ descs) {
+    const EigDesc d = descs[blockIdx.x];
+    if (d.run[0] == 0) return;
+    for (int i = threadIdx.x; i < d.L; i += blockDim.x)
+        d.lam[i] = (i < d.l) ? d.B[i + (long)i * d.L] : 0.0;
+}
+
+}  // namespace
+
+void launch_jacobi_init(const EigDesc* d_descs, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_jacobi_init, dim3(count), dim3(256), 0, s, d_descs);
+}
+
+void launch_jacobi_round(const EigDesc* d_descs, int count, int maxL, int bs, int round,
+                         hipStream_t s) {
+    const int nb = maxL / bs;
+    const int npair = nb / 2;
+    const int ntri = npair * (npair + 1) / 2;
+    const int nchunks = (maxL + 63) / 64;
+    if (bs == 16) {
+        hipLaunchKernelGGL((k_jacobi_pairs<16, 64>), dim3(npair, count), dim3(64), 0, s, d_descs, round);
+        hipLaunchKernelGGL((k_jacobi_apply<16>), dim3(ntri + nchunks * npair, count), dim3(256), 0, s,
+                           d_descs, round);
+    } else {
+        hipLaunchKernelGGL((k_jacobi_pairs<32, 256>), dim3(npair, count), dim3(256), 0, s, d_descs, round);
+        hipLaunchKernelGGL((k_jacobi_apply<32>), dim3(ntri + nchunks * npair, count), dim3(256), 0, s,
+                           d_descs, round);
+    }
+}
+
+void launch_jacobi_sweep_end(const EigDesc* d_descs, int count, int* d_any, hipStream_t s) {
+    hipLaunchKernelGGL(k_jacobi_sweep_end, dim3((count + 63) / 64), dim3(64), 0, s, d_descs, count, d_any);
+}
+
+void launch_jacobi_eigvals(const EigDesc* d_descs, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_jacobi_eigvals, dim3(count), dim3(256), 0, s, d_descs);
+}
+
+}  // namespace lrr

@@ -1,0 +1,52 @@
+// Host-side launchers of the library's kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace lrr {
+
+// gemm.hip
+void launch_dgemm(const GemmDesc* d_descs, int count, int maxM, int maxN, bool ta, bool tb,
+                  hipStream_t stream);
+
+// chol.hip
+int spd_inverse_desc_count(int m);
+void spd_inverse(double* K, int m, double* Lbuf, double* Linv, double* Dinv, double* Tbuf,
+                 GemmDesc* d_desc, int* d_info, hipStream_t s);
+void launch_add_identity(double* A, int lda, int m, double s, hipStream_t st);
+
+// jacobi.hip
+void launch_jacobi_init(const EigDesc* d_descs, int count, hipStream_t s);
+void launch_jacobi_round(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s);
+void launch_jacobi_sweep_end(const EigDesc* d_descs, int count, int* d_any, hipStream_t s);
+void launch_jacobi_eigvals(const EigDesc* d_descs, int count, hipStream_t s);
+
+// alm.hip
+void launch_gather_cols(const double* M, long ldm, double* X, long ldx, int m, int ncols,
+                        const int* d_perm, hipStream_t s);
+void launch_scatter_cols(const double* X, long ldx, double* S, long lds, int m, int ncols,
+                         const int* d_perm, hipStream_t s);
+void launch_copy_cols(const double* X, long ldx, double* Y, long ldy, int m, int ncols, hipStream_t s);
+void launch_nonfinite(const double* M, long ldm, int m, int n, int* d_flag, hipStream_t s);
+void launch_form_Y(const double* Z, const double* Y2, double* Y, double* colsq, int n, long ld, int ncols,
+                   const int* colblk, const int* active, const DevIter* it, hipStream_t s);
+void launch_block_fro(const double* colsq, const int* boff, int t, BlockState bs, const DevIter* it,
+                      hipStream_t s);
+void launch_zero_J(double* J, int n, long ld, int ncols, const int* colblk, BlockState bs, hipStream_t s);
+void launch_svt_weights(const SvtDesc* d, int count, int maxL, const DevIter* it, BlockState bs,
+                        hipStream_t s);
+void launch_form_QT(const double* J, const double* Y2, double* Q, int n, long ldn, const double* X,
+                    const double* E, const double* Y1, double* T, int m, long ldm, int ncols,
+                    const int* colblk, const int* active, const DevIter* it, hipStream_t s);
+void launch_update_Z(const double* Q, const double* MtV, const double* J, double* Z, double* Y2, int n,
+                     long ld, int ncols, const int* colblk, BlockState bs, const DevIter* it,
+                     hipStream_t s);
+void launch_estep(double* E, const double* V, double* Y1, int m, long ld, int ncols, double lam,
+                  const int* colblk, BlockState bs, const DevIter* it, hipStream_t s);
+void launch_check(BlockState bs, int t, DevIter* it, const double* mu_sched, double tol, int fixed,
+                  int* n_active, hipStream_t s);
+void launch_init_iter(DevIter* it, const double* mu_sched, hipStream_t s);
+void launch_scale_cols(double* U, long ld, int rows, int ncols, const double* h, hipStream_t s);
+void launch_set_identity(double* W, int L, hipStream_t s);
+
+}  // namespace lrr

@@ -1,0 +1,631 @@
+// Host side of the library: argument checks, workspace planning, the batched
+// inexact-ALM loop over the DFC blocks, the column-projection combine, and the
+// extern "C" entry points declared in include/lrr.h.
+//
+// ALM for one block (observations X, dictionary A = M), from the augmented
+// Lagrangian of the split Z = J of Eq. (2):
+//   J  = SVT_{1/mu}(Z + Y2/mu)
+//   Z  = (I + A^T A)^{-1} (A^T (X - E + Y1/mu) + J - Y2/mu)
+//   E  = column l2 shrinkage of X - A Z + Y1/mu by lam/mu
+//   Y1 += mu (X - A Z - E),  Y2 += mu (Z - J),  mu = min(rho mu, mu_max)
+//   stop when both residual max-norms are below tol.
+// The Z-step is evaluated in push-through form: with P = X - E + Y1/mu and
+// Q = J - Y2/mu,  V = (I + A A^T)^{-1} (P - A Q),  Z = Q + A^T V  and
+// X - A Z + Y1/mu = E + V, so the m x m inverse is the only factorisation and no
+// product A Z is needed.
+//
+// All t blocks run in the same launches: the state of block b is the column
+// range [boff[b], boff[b+1]) of column-concatenated matrices, the dictionary
+// products cover all columns at once, and the per-block steps (Gram, eigensolve,
+// reconstruction) are batched launches with one descriptor per block.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "../../include/lrr.h"
+
+struct lrr_ctx {
+    int device = 0;
+    std::string err;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    void* pinned = nullptr;      // small pinned host area for flag read-back
+    size_t pinned_bytes = 0;
+    int* dflag = nullptr;        // device flag for the input check
+};
+
+namespace {
+
+using lrr::BlockState;
+using lrr::DevIter;
+using lrr::EigDesc;
+using lrr::GemmDesc;
+using lrr::SvtDesc;
+
+thread_local std::string g_last_error;
+
+lrr_status fail(lrr_ctx* ctx, lrr_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    g_last_error = msg;
+    return st;
+}
+
+// bump allocator over the workspace (256-byte aligned slices)
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+        off += sizeof(T) * std::max<size_t>(count, 1);
+        return p;
+    }
+};
+
+struct Plan {
+    int m = 0, n = 0, ncols = 0, t = 0;
+    int bs = 16;                 // Jacobi block width
+    std::vector<int> boff;       // t + 1 column offsets
+    std::vector<int> L;          // padded Gram order per block
+    int maxL = 0, maxl = 0;
+    int n_iter = 0;
+};
+
+struct Buffers {
+    double *X, *Z, *J, *Y2, *Y, *Q, *MtV, *E, *Y1, *T, *V;
+    double *K, *Lb, *Linv, *Tb, *Dinv;
+    double *colsq, *mu_sched;
+    int *colblk, *boff, *perm;
+    int *active, *svt_run, *iters, *rank, *eigst, *n_active, *eig_any, *flag;
+    double *res1, *res2, *eigscale;
+    unsigned long long *r1max, *r2max;
+    DevIter* it;
+    std::vector<double*> Bm, Wm, Wg, Bt, Pm, Rm, lam, h;
+    GemmDesc *g_gram, *g_w1, *g_w2, *g_P, *g_J, *g_MQ, *g_KV, *g_MtV, *g_U, *g_H, *g_Z, *g_spd, *g_KK;
+    EigDesc* eig;
+    SvtDesc* svt;
+    // combine
+    double *U, *H;
+};
+
+int jacobi_bs(int maxl, int requested) {
+    if (requested == 16 || requested == 32) return requested;
+    return 16;
+}
+
+int round_up(int x, int a) { return ((x + a - 1) / a) * a; }
+
+// Lay out every buffer; with a null base only the size is computed.
+size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need_X) {
+    Arena a{base, 0};
+    const size_t n = p.n, m = p.m, c = p.ncols, t = p.t;
+    b.X = a.take<double>(m * c);
+    b.Z = a.take<double>(n * c);
+    b.J = a.take<double>(n * c);
+    b.Y2 = a.take<double>(n * c);
+    b.Y = a.take<double>(n * c);
+    b.Q = a.take<double>(n * c);
+    b.MtV = a.take<double>(n * c);
+    b.E = a.take<double>(m * c);
+    b.Y1 = a.take<double>(m * c);
+    b.T = a.take<double>(m * c);
+    b.V = a.take<double>(m * c);
+    b.K = a.take<double>(m * m);
+    b.Lb = a.take<double>(m * m);
+    b.Linv = a.take<double>(m * m);
+    b.Tb = a.take<double>(m * m);
+    b.Dinv = a.take<double>(m * 32);
+    b.colsq = a.take<double>(c);
+    b.mu_sched = a.take<double>(p.n_iter + 2);
+    b.colblk = a.take<int>(c);
+    b.boff = a.take<int>(t + 1);
+    b.perm = a.take<int>(c);
+    b.active = a.take<int>(t);
+    b.svt_run = a.take<int>(t);
+    b.iters = a.take<int>(t);
+    b.rank = a.take<int>(t);
+    b.eigst = a.take<int>(2 * t);
+    b.n_active = a.take<int>(1);
+    b.eig_any = a.take<int>(1);
+    b.flag = a.take<int>(1);
+    b.res1 = a.take<double>(t);
+    b.res2 = a.take<double>(t);
+    b.eigscale = a.take<double>(t);
+    b.r1max = a.take<unsigned long long>(t);
+    b.r2max = a.take<unsigned long long>(t);
+    b.it = a.take<DevIter>(1);
+    b.Bm.assign(t, nullptr); b.Wm.assign(t, nullptr); b.Wg.assign(t, nullptr);
+    b.Bt.assign(t, nullptr); b.Pm.assign(t, nullptr); b.Rm.assign(t, nullptr);
+    b.lam.assign(t, nullptr); b.h.assign(t, nullptr);
+    for (size_t i = 0; i < t; ++i) {
+        const size_t L = p.L[i];
+        b.Bm[i] = a.take<double>(L * L);
+        b.Wm[i] = a.take<double>(L * L);
+        b.Wg[i] = a.take<double>(L * L);
+        b.Bt[i] = a.take<double>(L * L);
+        b.Pm[i] = a.take<double>(L * L);
+        b.Rm[i] = a.take<double>(L * 2 * p.bs);
+        b.lam[i] = a.take<double>(L);
+        b.h[i] = a.take<double>(L);
+    }
+    b.g_gram = a.take<GemmDesc>(t);
+    b.g_w1 = a.take<GemmDesc>(t);
+    b.g_w2 = a.take<GemmDesc>(t);
+    b.g_P = a.take<GemmDesc>(t);
+    b.g_J = a.take<GemmDesc>(t);
+    b.g_MQ = a.take<GemmDesc>(1);
+    b.g_KV = a.take<GemmDesc>(1);
+    b.g_MtV = a.take<GemmDesc>(1);
+    b.g_U = a.take<GemmDesc>(1);
+    b.g_H = a.take<GemmDesc>(1);
+    b.g_Z = a.take<GemmDesc>(1);
+    b.g_KK = a.take<GemmDesc>(1);
+    b.g_spd = a.take<GemmDesc>(lrr::spd_inverse_desc_count(p.m));
+    b.eig = a.take<EigDesc>(t);
+    b.svt = a.take<SvtDesc>(t);
+    if (with_combine) {
+        b.U = a.take<double>(n * p.L[0]);
+        b.H = a.take<double>((size_t)p.L[0] * c);
+    } else {
+        b.U = b.H = nullptr;
+    }
+    (void)need_X;
+    return a.off + 256;
+}
+
+bool opts_valid(const lrr_opts& o, std::string& why) {
+    if (o.precision != LRR_FP64 && o.precision != LRR_FP32 && o.precision != LRR_MIXED_BF16) {
+        why = "unknown precision";
+        return false;
+    }
+    if (o.solve_form < 0 || o.solve_form > 2) { why = "unknown solve_form"; return false; }
+    if (!(o.mu0 > 0) || !std::isfinite(o.mu0)) { why = "mu0 must be positive"; return false; }
+    if (!(o.rho >= 1.0) || !std::isfinite(o.rho)) { why = "rho must be >= 1"; return false; }
+    if (!(o.mu_max >= o.mu0) || !std::isfinite(o.mu_max)) { why = "mu_max must be >= mu0"; return false; }
+    if (!(o.tol > 0)) { why = "tol must be positive"; return false; }
+    if (o.max_iter <= 0 && o.fixed_iters <= 0) { why = "max_iter must be positive"; return false; }
+    if (o.fixed_iters < 0) { why = "fixed_iters must be >= 0"; return false; }
+    if (o.check_every < 0 || o.max_sweeps < 0 || o.checkpoint_every < 0) {
+        why = "negative count"; return false;
+    }
+    if (o.eig_block != 0 && o.eig_block != 16 && o.eig_block != 32) { why = "eig_block must be 0, 16 or 32"; return false; }
+    for (int r : o.reserved) if (r != 0) { why = "reserved fields must be zero"; return false; }
+    return true;
+}
+
+lrr_status check_partition_impl(int n, int t, const int* perm, const int* offsets, std::string& why) {
+    if (n <= 0 || t <= 0 || t > n) { why = "need 0 < t <= n"; return LRR_EINVAL; }
+    if (!perm || !offsets) { why = "perm and offsets must not be NULL"; return LRR_EINVAL; }
+    if (offsets[0] != 0 || offsets[t] != n) { why = "offsets must start at 0 and end at n"; return LRR_EINVAL; }
+    for (int i = 0; i < t; ++i)
+        if (offsets[i + 1] <= offsets[i]) { why = "offsets must be strictly increasing"; return LRR_EINVAL; }
+    std::vector<char> seen(n, 0);
+    for (int j = 0; j < n; ++j) {
+        const int v = perm[j];
+        if (v < 0 || v >= n || seen[v]) { why = "perm is not a permutation of 0..n-1"; return LRR_EINVAL; }
+        seen[v] = 1;
+    }
+    return LRR_OK;
+}
+
+struct Problem {
+    int m, n, ncols, t;
+    const double* A; long lda;
+    const double* X; long ldx;    // either X given ...
+    const int* perm;              // ... or columns perm of A (host)
+    const int* offsets;           // host, t + 1
+    double lam;
+    lrr_opts o;
+};
+
+struct Result {
+    std::vector<int> iters, rank;
+    std::vector<double> res1, res2;
+    int batch_iters = 0;
+    bool converged = true;
+};
+
+void ensure_ws(lrr_ctx* ctx, size_t bytes) {
+    if (ctx->ws_bytes >= bytes) return;
+    if (ctx->ws) { (void)hipFree(ctx->ws); ctx->ws = nullptr; ctx->ws_bytes = 0; }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) throw std::bad_alloc();
+    ctx->ws = p;
+    ctx->ws_bytes = bytes;
+}
+
+void* ensure_pinned(lrr_ctx* ctx, size_t bytes) {
+    if (ctx->pinned_bytes >= bytes) return ctx->pinned;
+    if (ctx->pinned) { (void)hipHostFree(ctx->pinned); ctx->pinned = nullptr; ctx->pinned_bytes = 0; }
+    void* p = nullptr;
+    LRR_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+    ctx->pinned = p;
+    ctx->pinned_bytes = bytes;
+    return p;
+}
+
+Plan make_plan(const Problem& pr) {
+    Plan p;
+    p.m = pr.m; p.n = pr.n; p.ncols = pr.ncols; p.t = pr.t;
+    p.boff.assign(pr.offsets, pr.offsets + pr.t + 1);
+    p.maxl = 0;
+    for (int b = 0; b < pr.t; ++b) p.maxl = std::max(p.maxl, p.boff[b + 1] - p.boff[b]);
+    p.bs = jacobi_bs(p.maxl, pr.o.eig_block);
+    p.L.resize(pr.t);
+    p.maxL = 0;
+    for (int b = 0; b < pr.t; ++b) {
+        p.L[b] = round_up(p.boff[b + 1] - p.boff[b], 2 * p.bs);
+        p.maxL = std::max(p.maxL, p.L[b]);
+    }
+    p.n_iter = pr.o.fixed_iters > 0 ? pr.o.fixed_iters : pr.o.max_iter;
+    return p;
+}
+
+// Run the batched ALM over all blocks; leaves the state in the workspace.
+Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t s, bool with_combine) {
+    const int m = p.m, n = p.n, c = p.ncols, t = p.t;
+    const lrr_opts& o = pr.o;
+    const size_t need = layout(p, nullptr, b, with_combine, true);
+    ensure_ws(ctx, need);
+    layout(p, static_cast<char*>(ctx->ws), b, with_combine, true);
+    int* hp = static_cast<int*>(ensure_pinned(ctx, sizeof(int) * (4 * (size_t)t + 16) + sizeof(double) * 2 * t));
+
+    // ---- host-side tables -------------------------------------------------
+    std::vector<int> colblk(c);
+    for (int bb = 0; bb < t; ++bb)
+        for (int j = p.boff[bb]; j < p.boff[bb + 1]; ++j) colblk[j] = bb;
+    std::vector<double> sched(p.n_iter + 2);
+    sched[0] = o.mu0;
+    for (int k = 1; k < (int)sched.size(); ++k) sched[k] = std::min(o.rho * sched[k - 1], o.mu_max);
+
+    std::vector<GemmDesc> gram(t), w1(t), w2(t), gP(t), gJ(t);
+    std::vector<EigDesc> eig(t);
+    std::vector<SvtDesc> svt(t);
+    for (int bb = 0; bb < t; ++bb) {
+        const int l = p.boff[bb + 1] - p.boff[bb], L = p.L[bb];
+        double* Yb = b.Y + (size_t)p.boff[bb] * n;
+        double* Jb = b.J + (size_t)p.boff[bb] * n;
+        const int* run = b.svt_run + bb;
+        gram[bb] = GemmDesc{Yb, Yb, b.Bm[bb], l, l, n, n, n, L, 1.0, 0.0, run, nullptr};
+        w1[bb] = GemmDesc{b.Bm[bb], b.Wm[bb], b.Bt[bb], L, L, L, L, L, L, 1.0, 0.0, run, nullptr};
+        w2[bb] = GemmDesc{b.Wm[bb], b.Bt[bb], b.Bm[bb], L, L, L, L, L, L, 1.0, 0.0, run, nullptr};
+        gP[bb] = GemmDesc{b.Wg[bb], b.Wm[bb], b.Pm[bb], l, l, L, L, L, L, 1.0, 0.0, run, nullptr};
+        gJ[bb] = GemmDesc{Yb, b.Pm[bb], Jb, n, l, l, n, L, n, 1.0, 0.0, run, nullptr};
+        eig[bb] = EigDesc{b.Bm[bb], b.Wm[bb], b.Rm[bb], b.lam[bb], L, l, run, b.eigst + 2 * bb,
+                          b.eigscale + bb};
+        svt[bb] = SvtDesc{b.Bm[bb], b.Wm[bb], b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
+    }
+    GemmDesc gMQ{pr.A, b.Q, b.T, m, c, n, (int)pr.lda, n, m, -1.0, 1.0, nullptr, nullptr};
+    GemmDesc gKV{b.K, b.T, b.V, m, c, m, m, m, m, 1.0, 0.0, nullptr, nullptr};
+    GemmDesc gMtV{pr.A, b.V, b.MtV, n, c, m, (int)pr.lda, m, n, 1.0, 0.0, nullptr, nullptr};
+    GemmDesc gKK{pr.A, pr.A, b.K, m, m, n, (int)pr.lda, (int)pr.lda, m, 1.0, 0.0, nullptr, nullptr};
+
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        LRR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    };
+    up(b.colblk, colblk.data(), sizeof(int) * c);
+    up(b.boff, p.boff.data(), sizeof(int) * (t + 1));
+    up(b.mu_sched, sched.data(), sizeof(double) * sched.size());
+    up(b.g_gram, gram.data(), sizeof(GemmDesc) * t);
+    up(b.g_w1, w1.data(), sizeof(GemmDesc) * t);
+    up(b.g_w2, w2.data(), sizeof(GemmDesc) * t);
+    up(b.g_P, gP.data(), sizeof(GemmDesc) * t);
+    up(b.g_J, gJ.data(), sizeof(GemmDesc) * t);
+    up(b.g_MQ, &gMQ, sizeof(GemmDesc));
+    up(b.g_KV, &gKV, sizeof(GemmDesc));
+    up(b.g_MtV, &gMtV, sizeof(GemmDesc));
+    up(b.g_KK, &gKK, sizeof(GemmDesc));
+    up(b.eig, eig.data(), sizeof(EigDesc) * t);
+    up(b.svt, svt.data(), sizeof(SvtDesc) * t);
+    if (pr.perm) up(b.perm, pr.perm, sizeof(int) * c);
+
+    // ---- setup: observations, state, factorisation (once per solve) -------
+    if (pr.perm) lrr::launch_gather_cols(pr.A, pr.lda, b.X, m, m, c, b.perm, s);
+    else lrr::launch_copy_cols(pr.X, pr.ldx, b.X, m, m, c, s);
+    const size_t nc = (size_t)n * c, mc = (size_t)m * c;
+    LRR_HIP(hipMemsetAsync(b.Z, 0, sizeof(double) * nc, s));
+    LRR_HIP(hipMemsetAsync(b.J, 0, sizeof(double) * nc, s));
+    LRR_HIP(hipMemsetAsync(b.Y2, 0, sizeof(double) * nc, s));
+    LRR_HIP(hipMemsetAsync(b.E, 0, sizeof(double) * mc, s));
+    LRR_HIP(hipMemsetAsync(b.Y1, 0, sizeof(double) * mc, s));
+    for (int bb = 0; bb < t; ++bb) {
+        const size_t L = p.L[bb];
+        LRR_HIP(hipMemsetAsync(b.Bm[bb], 0, sizeof(double) * L * L, s));
+        LRR_HIP(hipMemsetAsync(b.Pm[bb], 0, sizeof(double) * L * L, s));
+        LRR_HIP(hipMemsetAsync(b.h[bb], 0, sizeof(double) * L, s));
+        lrr::launch_set_identity(b.Wm[bb], (int)L, s);
+    }
+    std::vector<int> ones(t, 1);
+    up(b.active, ones.data(), sizeof(int) * t);
+    LRR_HIP(hipMemsetAsync(b.iters, 0, sizeof(int) * t, s));
+    LRR_HIP(hipMemsetAsync(b.rank, 0, sizeof(int) * t, s));
+    LRR_HIP(hipMemsetAsync(b.r1max, 0, sizeof(unsigned long long) * t, s));
+    LRR_HIP(hipMemsetAsync(b.r2max, 0, sizeof(unsigned long long) * t, s));
+    LRR_HIP(hipMemsetAsync(b.res1, 0, sizeof(double) * t, s));
+    LRR_HIP(hipMemsetAsync(b.res2, 0, sizeof(double) * t, s));
+    lrr::launch_init_iter(b.it, b.mu_sched, s);
+
+    // K = I + A A^T, then K^{-1} (FP64 Cholesky, once per solve)
+    lrr::launch_dgemm(b.g_KK, 1, m, m, false, true, s);
+    lrr::launch_add_identity(b.K, m, m, 1.0, s);
+    lrr::spd_inverse(b.K, m, b.Lb, b.Linv, b.Dinv, b.Tb, b.g_spd, b.flag, s);
+
+    BlockState bst{b.active, b.svt_run, b.iters, b.rank, b.res1, b.res2, b.r1max, b.r2max};
+    const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
+    const int check_every = o.check_every > 0 ? o.check_every : 1;
+    const int fixed = o.fixed_iters > 0 ? 1 : 0;
+    int* h_run = hp;            // t ints
+    int* h_misc = hp + t;       // scalars
+
+    Result res;
+    int k = 0;
+    for (k = 0; k < p.n_iter; ++k) {
+        // J-step input and the exact zero test
+        lrr::launch_form_Y(b.Z, b.Y2, b.Y, b.colsq, n, n, c, b.colblk, b.active, b.it, s);
+        lrr::launch_block_fro(b.colsq, b.boff, t, bst, b.it, s);
+        lrr::launch_zero_J(b.J, n, n, c, b.colblk, bst, s);
+        LRR_HIP(hipMemcpyAsync(h_run, b.svt_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+        LRR_HIP(hipStreamSynchronize(s));
+        int any_run = 0;
+        for (int bb = 0; bb < t; ++bb) any_run |= h_run[bb];
+        if (any_run) {
+            // Gram, warm start with the previous eigenvectors, Jacobi sweeps
+            lrr::launch_dgemm(b.g_gram, t, p.maxl, p.maxl, true, false, s);
+            lrr::launch_dgemm(b.g_w1, t, p.maxL, p.maxL, false, false, s);
+            lrr::launch_dgemm(b.g_w2, t, p.maxL, p.maxL, true, false, s);
+            lrr::launch_jacobi_init(b.eig, t, s);
+            const int nb = p.maxL / p.bs;
+            for (int sw = 0; sw < max_sweeps; ++sw) {
+                for (int r = 0; r < nb - 1; ++r) lrr::launch_jacobi_round(b.eig, t, p.maxL, p.bs, r, s);
+                LRR_HIP(hipMemsetAsync(b.eig_any, 0, sizeof(int), s));
+                lrr::launch_jacobi_sweep_end(b.eig, t, b.eig_any, s);
+                LRR_HIP(hipMemcpyAsync(h_misc, b.eig_any, sizeof(int), hipMemcpyDeviceToHost, s));
+                LRR_HIP(hipStreamSynchronize(s));
+                if (h_misc[0] == 0) break;
+            }
+            lrr::launch_svt_weights(b.svt, t, p.maxL, b.it, bst, s);
+            lrr::launch_dgemm(b.g_P, t, p.maxl, p.maxl, false, true, s);
+            lrr::launch_dgemm(b.g_J, t, n, p.maxl, false, false, s);
+        }
+        // Z-step (push-through) and E-step
+        lrr::launch_form_QT(b.J, b.Y2, b.Q, n, n, b.X, b.E, b.Y1, b.T, m, m, c, b.colblk, b.active, b.it, s);
+        lrr::launch_dgemm(b.g_MQ, 1, m, c, false, false, s);
+        lrr::launch_dgemm(b.g_KV, 1, m, c, false, false, s);
+        lrr::launch_dgemm(b.g_MtV, 1, n, c, true, false, s);
+        lrr::launch_update_Z(b.Q, b.MtV, b.J, b.Z, b.Y2, n, n, c, b.colblk, bst, b.it, s);
+        lrr::launch_estep(b.E, b.V, b.Y1, m, m, c, pr.lam, b.colblk, bst, b.it, s);
+        lrr::launch_check(bst, t, b.it, b.mu_sched, o.tol, fixed, b.n_active, s);
+        if (!fixed && ((k + 1) % check_every == 0 || k + 1 == p.n_iter)) {
+            LRR_HIP(hipMemcpyAsync(h_misc + 1, b.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+            LRR_HIP(hipStreamSynchronize(s));
+            if (h_misc[1] == 0) { ++k; break; }
+        }
+    }
+    res.batch_iters = k;
+    res.iters.resize(t); res.rank.resize(t); res.res1.resize(t); res.res2.resize(t);
+    std::vector<int> act(t);
+    LRR_HIP(hipMemcpyAsync(res.iters.data(), b.iters, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+    LRR_HIP(hipMemcpyAsync(res.rank.data(), b.rank, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+    LRR_HIP(hipMemcpyAsync(res.res1.data(), b.res1, sizeof(double) * t, hipMemcpyDeviceToHost, s));
+    LRR_HIP(hipMemcpyAsync(res.res2.data(), b.res2, sizeof(double) * t, hipMemcpyDeviceToHost, s));
+    LRR_HIP(hipMemcpyAsync(act.data(), b.active, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+    LRR_HIP(hipStreamSynchronize(s));
+    res.converged = true;
+    if (!fixed)
+        for (int bb = 0; bb < t; ++bb) if (act[bb]) res.converged = false;
+    return res;
+}
+
+void fill_info(lrr_info* info, const Result& r, int combine_rank) {
+    if (!info) return;
+    const int t = (int)r.iters.size();
+    for (int b = 0; b < t; ++b) {
+        if (info->iters) info->iters[b] = r.iters[b];
+        if (info->rank) info->rank[b] = r.rank[b];
+        if (info->res_primal) info->res_primal[b] = r.res1[b];
+        if (info->res_coupling) info->res_coupling[b] = r.res2[b];
+    }
+    info->batch_iters = r.batch_iters;
+    info->combine_rank = combine_rank;
+}
+
+template <class F>
+lrr_status guarded(lrr_ctx* ctx, F&& f) {
+    try {
+        return f();
+    } catch (const lrr::HipError& e) {
+        return fail(ctx, LRR_EDEVICE, e.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, LRR_ENOMEM, "device workspace allocation failed");
+    }
+}
+
+bool input_nonfinite(lrr_ctx* ctx, const double* A, long lda, int m, int n, hipStream_t s) {
+    if (!ctx->dflag) LRR_HIP(hipMalloc((void**)&ctx->dflag, 256));
+    int* h = static_cast<int*>(ensure_pinned(ctx, 64));
+    LRR_HIP(hipMemsetAsync(ctx->dflag, 0, sizeof(int), s));
+    lrr::launch_nonfinite(A, lda, m, n, ctx->dflag, s);
+    LRR_HIP(hipMemcpyAsync(h, ctx->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    LRR_HIP(hipStreamSynchronize(s));
+    return h[0] != 0;
+}
+
+}  // namespace
+
+namespace lrr {
+lrr_status ctx_fail(lrr_ctx* ctx, lrr_status st, const std::string& msg) { return fail(ctx, st, msg); }
+int ctx_device(const lrr_ctx* ctx) { return ctx ? ctx->device : 0; }
+}  // namespace lrr
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* lrr_version(void) { return "dfc-lrr-gfx950 0.1"; }
+
+void lrr_opts_default(lrr_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = LRR_FP64;
+    o->solve_form = LRR_SOLVE_AUTO;
+    o->mu0 = 1e-6;
+    o->rho = 1.1;
+    o->mu_max = 1e10;
+    o->tol = 1e-8;
+    o->max_iter = 1000;
+    o->fixed_iters = 0;
+    o->check_every = 1;
+    o->max_sweeps = 30;
+    o->save_for_backward = 0;
+    o->checkpoint_every = 20;
+    o->eig_block = 0;
+}
+
+lrr_status lrr_ctx_create(int device, lrr_ctx** out) {
+    if (!out) return fail(nullptr, LRR_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(nullptr, LRR_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= count) return fail(nullptr, LRR_EINVAL, "device index out of range");
+    lrr_ctx* c = new lrr_ctx();
+    c->device = device;
+    *out = c;
+    return LRR_OK;
+}
+
+void lrr_ctx_destroy(lrr_ctx* ctx) {
+    if (!ctx) return;
+    if (hipSetDevice(ctx->device) == hipSuccess) {
+        if (ctx->ws) (void)hipFree(ctx->ws);
+        if (ctx->dflag) (void)hipFree(ctx->dflag);
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    }
+    delete ctx;
+}
+
+const char* lrr_last_error(const lrr_ctx* ctx) {
+    if (ctx && !ctx->err.empty()) return ctx->err.c_str();
+    return g_last_error.c_str();
+}
+
+lrr_status lrr_check_partition(int n, int t, const int* perm, const int* offsets) {
+    std::string why;
+    lrr_status st = check_partition_impl(n, t, perm, offsets, why);
+    if (st != LRR_OK) return fail(nullptr, st, why);
+    return LRR_OK;
+}
+
+lrr_status lrr_workspace_bytes(int m, int n, int t, const int* offsets, const lrr_opts* opts,
+                               size_t* bytes) {
+    if (!bytes || !offsets || !opts) return fail(nullptr, LRR_EINVAL, "NULL argument");
+    if (m <= 0 || n <= 0 || t <= 0 || t > n) return fail(nullptr, LRR_EINVAL, "bad dimensions");
+    Problem pr{};
+    pr.m = m; pr.n = n; pr.ncols = n; pr.t = t; pr.offsets = offsets; pr.o = *opts;
+    Plan p = make_plan(pr);
+    Buffers b{};
+    *bytes = layout(p, nullptr, b, 1, true);
+    return LRR_OK;
+}
+
+lrr_status lrr_solve(lrr_ctx* ctx, int m, int n, int l, const void* A, int lda, const void* X, int ldx,
+                     double lambda, const lrr_opts* opts, void* Z, int ldz, void* E, int lde,
+                     lrr_info* info, void* stream) {
+    if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
+    if (m <= 0 || n <= 0 || l <= 0) return fail(ctx, LRR_EINVAL, "dimensions must be positive");
+    if (!A || !X || !Z) return fail(ctx, LRR_EINVAL, "A, X and Z must not be NULL");
+    if (lda < m || ldx < m || ldz < n || (E && lde < m)) return fail(ctx, LRR_EINVAL, "leading dimension too small");
+    if (!(lambda > 0) || !std::isfinite(lambda)) return fail(ctx, LRR_EINVAL, "lambda must be positive and finite");
+    lrr_opts o;
+    if (opts) o = *opts; else lrr_opts_default(&o);
+    std::string why;
+    if (!opts_valid(o, why)) return fail(ctx, LRR_EINVAL, why);
+    if (o.precision != LRR_FP64) return fail(ctx, LRR_EINVAL, "this build solves in FP64 only");
+    return guarded(ctx, [&]() -> lrr_status {
+        LRR_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (input_nonfinite(ctx, static_cast<const double*>(A), lda, m, n, s) ||
+            input_nonfinite(ctx, static_cast<const double*>(X), ldx, m, l, s))
+            return fail(ctx, LRR_ENUMERIC, "non-finite value in A or X");
+        int offs[2] = {0, l};
+        Problem pr{m, n, l, 1, static_cast<const double*>(A), lda, static_cast<const double*>(X), ldx,
+                   nullptr, offs, lambda, o};
+        Plan p = make_plan(pr);
+        Buffers b{};
+        Result r = run_alm(ctx, pr, p, b, s, false);
+        lrr::launch_copy_cols(b.Z, n, static_cast<double*>(Z), ldz, n, l, s);
+        if (E) lrr::launch_copy_cols(b.E, m, static_cast<double*>(E), lde, m, l, s);
+        LRR_HIP(hipStreamSynchronize(s));
+        fill_info(info, r, r.rank[0]);
+        return r.converged ? LRR_OK : LRR_NOT_CONVERGED;
+    });
+}
+
+lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, double lambda, int t,
+                         const int* perm, const int* offsets, const lrr_opts* opts, void* Z, int ldz,
+                         void* S, int lds, lrr_info* info, void* stream) {
+    if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
+    if (m <= 0 || n <= 0) return fail(ctx, LRR_EINVAL, "dimensions must be positive");
+    if (!M || !Z) return fail(ctx, LRR_EINVAL, "M and Z must not be NULL");
+    if (ldm < m || ldz < n || (S && lds < m)) return fail(ctx, LRR_EINVAL, "leading dimension too small");
+    if (!(lambda > 0) || !std::isfinite(lambda)) return fail(ctx, LRR_EINVAL, "lambda must be positive and finite");
+    std::string why;
+    if (check_partition_impl(n, t, perm, offsets, why) != LRR_OK) return fail(ctx, LRR_EINVAL, why);
+    lrr_opts o;
+    if (opts) o = *opts; else lrr_opts_default(&o);
+    if (!opts_valid(o, why)) return fail(ctx, LRR_EINVAL, why);
+    if (o.precision != LRR_FP64) return fail(ctx, LRR_EINVAL, "this build solves in FP64 only");
+    return guarded(ctx, [&]() -> lrr_status {
+        LRR_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (input_nonfinite(ctx, static_cast<const double*>(M), ldm, m, n, s))
+            return fail(ctx, LRR_ENUMERIC, "non-finite value in M");
+        Problem pr{m, n, n, t, static_cast<const double*>(M), ldm, nullptr, 0, perm, offsets, lambda, o};
+        Plan p = make_plan(pr);
+        Buffers b{};
+        Result r = run_alm(ctx, pr, p, b, s, true);
+        // C step: U1 = Y_1 W_1 diag(h_1) spans the column space of J_1 (zero
+        // columns where sigma <= tau); Z = U1 (U1^T [J_1 ... J_t]), columns put back.
+        const int L0 = p.L[0], l0 = p.boff[1];
+        const int r1 = r.rank[0];
+        double* Zo = static_cast<double*>(Z);
+        if (r1 == 0) {
+            for (int j = 0; j < n; ++j)
+                LRR_HIP(hipMemsetAsync(Zo + (size_t)j * ldz, 0, sizeof(double) * n, s));
+        } else {
+            GemmDesc gU{b.Y, b.Wm[0], b.U, n, L0, l0, n, L0, n, 1.0, 0.0, nullptr, nullptr};
+            GemmDesc gH{b.U, b.J, b.H, L0, n, n, n, n, L0, 1.0, 0.0, nullptr, nullptr};
+            GemmDesc gZ{b.U, b.H, Zo, n, n, L0, n, L0, ldz, 1.0, 0.0, nullptr, b.perm};
+            GemmDesc hd[3] = {gU, gH, gZ};
+            LRR_HIP(hipMemcpyAsync(b.g_U, &hd[0], sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+            LRR_HIP(hipMemcpyAsync(b.g_H, &hd[1], sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+            LRR_HIP(hipMemcpyAsync(b.g_Z, &hd[2], sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+            lrr::launch_dgemm(b.g_U, 1, n, L0, false, false, s);
+            lrr::launch_scale_cols(b.U, n, n, L0, b.h[0], s);
+            lrr::launch_dgemm(b.g_H, 1, L0, n, true, false, s);
+            lrr::launch_dgemm(b.g_Z, 1, n, n, false, false, s);
+        }
+        if (S) lrr::launch_scatter_cols(b.E, m, static_cast<double*>(S), lds, m, n, b.perm, s);
+        LRR_HIP(hipStreamSynchronize(s));
+        fill_info(info, r, r1);
+        return r.converged ? LRR_OK : LRR_NOT_CONVERGED;
+    });
+}
+
+lrr_status dfc_lrr_backward(lrr_ctx* ctx, const void* dZ, int lddz, double* dlambda, void* dM, int lddm,
+                            void* stream) {
+    (void)dZ; (void)lddz; (void)dlambda; (void)dM; (void)lddm; (void)stream;
+    if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
+    return fail(ctx, LRR_ENOTAPE, "no recorded forward pass on this context");
+}
+
+}  // extern "C"

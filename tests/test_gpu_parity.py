@@ -1,0 +1,175 @@
+"""GPU parity: the HIP solver against the FP64 CPU oracle, element by element.
+
+Tolerances (FP64 path): ||Z - Z_oracle||_F / ||Z_oracle||_F <= 1e-6 (the stated
+bar), same per-block iteration counts within one, same ranks, identical
+segmentation labels.  Sizes are chosen so the oracle finishes in seconds while
+the GPU kernels see several tiles, ragged edges and uneven blocks.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import need_gpu, one_thread, rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL_Z = 1e-6
+
+
+def _gpu_dfc(p, lam=None, **opt):
+    from paper_1304_5583_amd import binding as B
+    o = B.lrr_opts_default(**opt)
+    Mt = B.to_device_colmajor(p.M)
+    Zt, St, info = B.dfc_lrr_solve(Mt, p.lam if lam is None else lam, p.perm, p.offsets, opts=o)
+    return B.from_device_colmajor(Zt), B.from_device_colmajor(St), info
+
+
+def _compare_dfc(p, tag, check_labels=True):
+    import oracle
+    say(f"[{tag}] m={p.m} n={p.n} t={p.t} widths={np.diff(p.offsets).tolist()[:8]}")
+    Zg, Sg, info = _gpu_dfc(p)
+    with one_thread():
+        ref = oracle.dfc_lrr(p.M, p.lam, p.perm, p.offsets)
+    ez, es = rel(Zg, ref.Z), rel(Sg, ref.S)
+    it_o = np.array([b.iters for b in ref.blocks])
+    rk_o = np.array([b.rank for b in ref.blocks])
+    say(f"  relZ={ez:.2e} relS={es:.2e} iters gpu={info.iters.tolist()} oracle={it_o.tolist()} "
+        f"rank gpu={info.rank.tolist()} oracle={rk_o.tolist()}")
+    assert info.status == 0
+    assert ez <= TOL_Z and es <= TOL_Z
+    assert np.all(np.abs(info.iters - it_o) <= 1)
+    assert np.array_equal(info.rank, rk_o)
+    assert info.combine_rank == rk_o[0]
+    if check_labels:
+        k = p.extra.get("k", 3)
+        with one_thread():
+            assert np.array_equal(oracle.segment(Zg, k, p.outliers), oracle.segment(ref.Z, k, p.outliers))
+    return Zg, ref
+
+
+def test_lrr_single_block_small():
+    torch = need_gpu()
+    import oracle
+    from paper_1304_5583_amd import binding as B
+    from paper_1304_5583_amd.datagen import small_problem
+    p = small_problem(21, m=40, k=3, r=3, ns=30, n_replace=6, t=1)
+    X = p.M[:, 5:75]
+    say("[lrr small] m=40 n=90 l=70")
+    Zt, Et, info = B.lrr_solve(B.to_device_colmajor(p.M), B.to_device_colmajor(X), 0.3)
+    Zg, Eg = B.from_device_colmajor(Zt), B.from_device_colmajor(Et)
+    with one_thread():
+        ref = oracle.lrr_alm(X, p.M, 0.3)
+    say(f"  relZ={rel(Zg, ref.Z):.2e} relE={rel(Eg, ref.E):.2e} iters {info.iters[0]} vs {ref.iters}")
+    assert info.status == 0
+    assert rel(Zg, ref.Z) <= TOL_Z and rel(Eg, ref.E) <= TOL_Z
+    assert abs(int(info.iters[0]) - ref.iters) <= 1 and info.rank[0] == ref.rank
+    assert info.res_primal[0] < 1e-8 and info.res_coupling[0] < 1e-8
+
+
+def test_dfc_small_equal_blocks():
+    need_gpu()
+    from paper_1304_5583_amd.datagen import small_problem
+    _compare_dfc(small_problem(22, m=50, k=4, r=3, ns=30, n_replace=8, t=4, lam=0.3), "dfc small t=4")
+
+
+def test_dfc_small_uneven_blocks_ragged():
+    need_gpu()
+    from paper_1304_5583_amd.datagen import small_problem
+    # widths in [33, 47]: ragged against the 32/64-wide tiles
+    _compare_dfc(small_problem(23, m=70, k=5, r=4, ns=40, n_replace=10, t=5, lam=0.25,
+                               uneven=(33, 47)), "dfc uneven t=5")
+
+
+def test_dfc_normalized_columns_like_workload2():
+    need_gpu()
+    from paper_1304_5583_amd.datagen import small_problem
+    _compare_dfc(small_problem(24, m=120, k=6, r=5, ns=40, n_replace=12, t=3, lam=0.2,
+                               normalize=True), "dfc normalized t=3")
+
+
+def test_dfc_eig_block_32_same_result():
+    need_gpu()
+    from paper_1304_5583_amd.datagen import small_problem
+    p = small_problem(25, m=60, k=3, r=4, ns=40, n_replace=6, t=2, lam=0.3)
+    Z16, _, i16 = _gpu_dfc(p, eig_block=16)
+    Z32, _, i32 = _gpu_dfc(p, eig_block=32)
+    say(f"[eig_block 16 vs 32] rel={rel(Z32, Z16):.2e}")
+    assert rel(Z32, Z16) <= 1e-9
+    assert np.array_equal(i16.rank, i32.rank)
+
+
+def test_workload1_full_lrr():
+    """Workload 1 (m=100, n=200, t=1, lam=0.1) against the oracle, with labels."""
+    need_gpu()
+    from paper_1304_5583_amd.datagen import make_config
+    p = make_config(1)
+    _compare_dfc(p, "workload1")
+
+
+def test_dfc_t1_equals_lrr_J():
+    torch = need_gpu()
+    import oracle
+    from paper_1304_5583_amd.datagen import small_problem
+    p = small_problem(26, m=30, k=2, r=3, ns=25, n_replace=4, t=1, lam=0.4)
+    rng = np.random.default_rng(26)
+    p.perm = rng.permutation(p.n).astype(np.int32)
+    Zg, _, _ = _gpu_dfc(p)
+    with one_thread():
+        ref = oracle.lrr_alm(p.M, p.M, 0.4)
+    say(f"[dfc t=1 permuted] rel={rel(Zg, ref.J):.2e}")
+    assert rel(Zg, ref.J) <= TOL_Z
+
+
+def test_trivial_lambda_gives_zero():
+    need_gpu()
+    import oracle
+    from paper_1304_5583_amd.datagen import small_problem
+    p = small_problem(27, m=30, k=2, r=3, ns=20, n_replace=4, t=2, lam=0.3)
+    lam0 = min(oracle.trivial_lambda(p.M[:, p.perm[p.offsets[i]:p.offsets[i + 1]]], p.M)
+               for i in range(p.t))
+    Zg, Sg, info = _gpu_dfc(p, lam=0.5 * lam0)
+    with one_thread():
+        ref = oracle.dfc_lrr(p.M, 0.5 * lam0, p.perm, p.offsets)
+    say(f"[trivial lam] max|Z|={np.abs(Zg).max():.2e} oracle={np.abs(ref.Z).max():.2e} ranks={info.rank.tolist()}")
+    assert np.abs(Zg - ref.Z).max() <= 1e-9 and rel(Sg, ref.S) <= TOL_Z
+
+
+def test_not_converged_and_fixed_iters():
+    torch = need_gpu()
+    import oracle
+    from paper_1304_5583_amd import binding as B
+    from paper_1304_5583_amd.datagen import small_problem
+    p = small_problem(28, m=30, k=2, r=3, ns=20, n_replace=4, t=2, lam=0.3)
+    Mt = B.to_device_colmajor(p.M)
+    Zt, St, info = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=B.lrr_opts_default(max_iter=150))
+    assert info.status == B.LRR_NOT_CONVERGED and np.all(info.iters == 150)
+    with one_thread():
+        ref = oracle.dfc_lrr(p.M, p.lam, p.perm, p.offsets, oracle.ALMOptions(max_iter=150))
+    assert rel(B.from_device_colmajor(Zt), ref.Z) <= TOL_Z
+    Zt, St, info = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=B.lrr_opts_default(fixed_iters=180))
+    with one_thread():
+        ref = oracle.dfc_lrr(p.M, p.lam, p.perm, p.offsets, oracle.ALMOptions(fixed_iters=180))
+    say(f"[fixed 180] rel={rel(B.from_device_colmajor(Zt), ref.Z):.2e}")
+    assert info.status == 0 and np.all(info.iters == 180)
+    assert rel(B.from_device_colmajor(Zt), ref.Z) <= TOL_Z
+
+
+def test_nonfinite_input_rejected():
+    torch = need_gpu()
+    from paper_1304_5583_amd import binding as B
+    M = np.random.default_rng(0).standard_normal((10, 20))
+    M[3, 7] = np.nan
+    with pytest.raises(B.LRRError) as e:
+        B.dfc_lrr_solve(B.to_device_colmajor(M), 0.3, np.arange(20), [0, 20])
+    assert e.value.status == B.LRR_ENUMERIC
+
+
+def test_bad_arguments_rejected():
+    torch = need_gpu()
+    from paper_1304_5583_amd import binding as B
+    M = np.random.default_rng(0).standard_normal((10, 20))
+    Mt = B.to_device_colmajor(M)
+    for perm, off, lam in [(np.arange(20), [0, 20], -1.0), (np.arange(20), [0, 5, 5, 20], 0.3),
+                           (np.zeros(20), [0, 20], 0.3)]:
+        with pytest.raises(B.LRRError) as e:
+            B.dfc_lrr_solve(Mt, lam, perm, off)
+        assert e.value.status == B.LRR_EINVAL
