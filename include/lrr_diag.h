@@ -40,6 +40,19 @@ lrr_status lrr_diag_syevj(lrr_ctx *ctx, int count, const int *l, const double *B
                           long strideB, double *lam, int ldlam, double *W, int eig_block,
                           int *sweeps, void *stream);
 
+/* Per-kernel timing of the solver's own launches.  When enabled, every kernel
+ * launch of lrr_solve / dfc_lrr_solve is bracketed by HIP events recorded on the
+ * solve's stream; durations are accumulated per kernel name together with the
+ * algorithmic flops (GEMMs: 2 M N K per active product) and algorithmic HBM
+ * bytes (column kernels: every matrix element read or written once) of each
+ * launch.  lrr_prof_enable also clears the table. */
+lrr_status lrr_prof_enable(lrr_ctx *ctx, int on);
+int lrr_prof_count(const lrr_ctx *ctx);
+/* Entry idx (0 <= idx < lrr_prof_count): name (owned by ctx), total ms, number
+ * of launches, total algorithmic flops and bytes. */
+lrr_status lrr_prof_entry(const lrr_ctx *ctx, int idx, const char **name, double *ms,
+                          long long *launches, double *flops, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

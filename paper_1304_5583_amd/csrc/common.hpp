@@ -61,6 +61,7 @@ struct EigDesc {
     const int* run;     // skip the matrix if run[0] == 0
     int* st;            // [0] converged, [1] pairs that rotated in the current sweep
     double* scale;      // max |diag| of B at the start, for the absolute floor
+    int* prot;          // per pair of the current round: 1 if it rotated
 };
 
 // Thresholding weights of one block after its Gram eigensolve.

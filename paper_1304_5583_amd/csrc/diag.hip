@@ -125,7 +125,7 @@ lrr_status lrr_diag_syevj(lrr_ctx* ctx, int count, const int* l, const double* B
         hipStream_t s = static_cast<hipStream_t>(stream);
         const size_t LL = (size_t)L * L;
         double *Bp, *Wp, *Rp, *lamp, *scale;
-        int *st, *run_on, *ls, *any;
+        int *st, *run_on, *ls, *any, *prot;
         lrr::EigDesc* dd;
         LRR_HIP(hipMalloc((void**)&Bp, sizeof(double) * LL * count));
         LRR_HIP(hipMalloc((void**)&Wp, sizeof(double) * LL * count));
@@ -136,12 +136,14 @@ lrr_status lrr_diag_syevj(lrr_ctx* ctx, int count, const int* l, const double* B
         LRR_HIP(hipMalloc((void**)&run_on, sizeof(int) * count));
         LRR_HIP(hipMalloc((void**)&ls, sizeof(int) * count));
         LRR_HIP(hipMalloc((void**)&any, sizeof(int)));
+        const int npair = L / (2 * bs);
+        LRR_HIP(hipMalloc((void**)&prot, sizeof(int) * npair * count));
         LRR_HIP(hipMalloc((void**)&dd, sizeof(lrr::EigDesc) * count));
         std::vector<lrr::EigDesc> hd(count);
         std::vector<int> ones(count, 1);
         for (int i = 0; i < count; ++i)
             hd[i] = lrr::EigDesc{Bp + LL * i, Wp + LL * i, Rp + (size_t)L * 2 * bs * i, lamp + (size_t)L * i,
-                                 L, l[i], run_on + i, st + 2 * i, scale + i};
+                                 L, l[i], run_on + i, st + 2 * i, scale + i, prot + npair * i};
         LRR_HIP(hipMemcpy(dd, hd.data(), sizeof(lrr::EigDesc) * count, hipMemcpyHostToDevice));
         LRR_HIP(hipMemcpy(run_on, ones.data(), sizeof(int) * count, hipMemcpyHostToDevice));
         LRR_HIP(hipMemcpy(ls, l, sizeof(int) * count, hipMemcpyHostToDevice));
@@ -151,12 +153,13 @@ lrr_status lrr_diag_syevj(lrr_ctx* ctx, int count, const int* l, const double* B
         lrr::launch_jacobi_init(dd, count, s);
         const int nb = L / bs;
         int sw = 0, h_any = 1;
-        for (sw = 0; sw < 60 && h_any; ++sw) {
-            for (int r = 0; r < nb - 1; ++r) lrr::launch_jacobi_round(dd, count, L, bs, r, s);
+        for (sw = 0; sw <= 60; ++sw) {
             LRR_HIP(hipMemsetAsync(any, 0, sizeof(int), s));
-            lrr::launch_jacobi_sweep_end(dd, count, any, s);
+            lrr::launch_jacobi_check(dd, count, L, any, s);
             LRR_HIP(hipMemcpyAsync(&h_any, any, sizeof(int), hipMemcpyDeviceToHost, s));
             LRR_HIP(hipStreamSynchronize(s));
+            if (h_any == 0 || sw == 60) break;
+            for (int r = 0; r < nb - 1; ++r) lrr::launch_jacobi_round(dd, count, L, bs, r, s);
         }
         lrr::launch_jacobi_eigvals(dd, count, s);
         hipLaunchKernelGGL(k_unpad, dim3((unsigned)((LL + 255) / 256), count), dim3(256), 0, s, Wp, L, W, ldb,
@@ -165,6 +168,7 @@ lrr_status lrr_diag_syevj(lrr_ctx* ctx, int count, const int* l, const double* B
         if (sweeps) *sweeps = sw;
         (void)hipFree(Bp); (void)hipFree(Wp); (void)hipFree(Rp); (void)hipFree(lamp); (void)hipFree(scale);
         (void)hipFree(st); (void)hipFree(run_on); (void)hipFree(ls); (void)hipFree(any); (void)hipFree(dd);
+        (void)hipFree(prot);
         return LRR_OK;
     });
 }

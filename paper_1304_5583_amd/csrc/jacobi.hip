@@ -14,9 +14,13 @@
 //   phase B  every tile pair (P, Q), P <= Q, of the round is replaced by
 //            R_P^T B[P, Q] R_Q (and its transpose), and the eigenvector
 //            accumulator gets W[:, P] <- W[:, P] R_P.
-// A sweep in which no pair needed a rotation ends the iteration.  The
-// rotation test is relative, |b_pq| > 1e-15 sqrt(b_pp b_qq), with an absolute
-// floor of 1e-18 max|diag B| so that noise-level entries terminate.
+// Convergence: an off-diagonal entry needs a rotation when
+// |b_pq| > max(1e-15 sqrt(|b_pp b_qq|), 1e-14 max|diag B|).  The absolute floor
+// sits at the rounding level of the matrix: a Gram matrix of a rank-deficient
+// block has exactly-zero eigenvalues whose coupling entries are pure rounding
+// noise, and rotating them only regenerates noise.  Before each sweep one
+// launch checks every off-diagonal entry; pairs whose sub-matrix is already
+// diagonal skip their work, and so do the tiles they touch.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -25,7 +29,7 @@ namespace lrr {
 namespace {
 
 constexpr double kRelTol = 1e-15;
-constexpr double kAbsFloor = 1e-18;
+constexpr double kAbsFloor = 1e-14;
 constexpr int kInnerSweeps = 12;
 
 // symmetric 2x2 Schur rotation: [c s; -s c]^T [app apq; apq aqq] [c s; -s c] is diagonal
@@ -50,7 +54,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
 
     __shared__ double S[PB][PB + 1];
     __shared__ double R[PB][PB + 1];
-    __shared__ double csc[NP], css[NP];
+    __shared__ double csc[NP], css[NP], cst[NP], csd[NP], cse[NP];
     __shared__ int any;
 
     const int tid = threadIdx.x;
@@ -67,26 +71,47 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
     __syncthreads();
 
     for (int sweep = 0; sweep < kInnerSweeps; ++sweep) {
+        // parallel convergence test of the whole sub-matrix
         if (tid == 0) any = 0;
         __syncthreads();
+        for (int idx = tid; idx < PB * PB; idx += NT) {
+            const int i = idx % PB, j = idx / PB;
+            if (i < j && fabs(S[i][j]) > fmax(kRelTol * sqrt(fabs(S[i][i] * S[j][j])), floor_abs)) any = 1;
+        }
+        __syncthreads();
+        if (!any) break;
+        rotated = 1;
         for (int r = 0; r < PB - 1; ++r) {
             if (tid < NP) {
                 int a, b;
                 rr_pair(PB, r, tid, a, b);
                 const double app = S[a][a], aqq = S[b][b], apq = S[a][b];
-                double c = 1.0, s = 0.0;
+                double c = 1.0, s = 0.0, t = 0.0;
                 if (fabs(apq) > fmax(kRelTol * sqrt(fabs(app * aqq)), floor_abs)) {
                     sym_schur2(app, aqq, apq, c, s);
-                    any = 1;
+                    t = s / c;
                 }
                 csc[tid] = c;
                 css[tid] = s;
+                cst[tid] = t;
+                csd[tid] = app - t * apq;   // rotated diagonal, closed form
+                cse[tid] = aqq + t * apq;
             }
             __syncthreads();
             for (int idx = tid; idx < NP * NP; idx += NT) {
                 const int P2 = idx / NP, Q2 = idx % NP;
                 int aP, bP, aQ, bQ;
                 rr_pair(PB, r, P2, aP, bP);
+                if (P2 == Q2) {
+                    // the rotated pair itself: exact zero off the diagonal
+                    if (cst[P2] != 0.0) {
+                        S[aP][aP] = csd[P2];
+                        S[bP][bP] = cse[P2];
+                        S[aP][bP] = 0.0;
+                        S[bP][aP] = 0.0;
+                    }
+                    continue;
+                }
                 rr_pair(PB, r, Q2, aQ, bQ);
                 const double cP = csc[P2], sP = css[P2], cQ = csc[Q2], sQ = css[Q2];
                 const double s_aa = S[aP][aQ], s_ab = S[aP][bQ];
@@ -111,17 +136,17 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
             }
             __syncthreads();
         }
-        const int a = any;
-        __syncthreads();
-        if (!a) break;
-        rotated = 1;
+    }
+    if (!rotated) {
+        if (tid == 0) d.prot[P] = 0;
+        return;
     }
     double* Rg = d.R + (long)P * PB * PB;
     for (int idx = tid; idx < PB * PB; idx += NT) {
         const int i = idx % PB, j = idx / PB;
         Rg[i + (long)j * PB] = R[i][j];
     }
-    if (tid == 0 && rotated) atomicAdd(&d.st[1], 1);
+    if (tid == 0) d.prot[P] = rotated;
 }
 
 // phase B: tiles of B and row chunks of W
@@ -150,6 +175,7 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
         int P = 0, rem = item;
         while (rem >= npair - P) { rem -= npair - P; ++P; }
         const int Q = P + rem;
+        if (!d.prot[P] && !d.prot[Q]) return;
         int p1, q1, p2, q2;
         rr_pair(nb, round, P, p1, q1);
         rr_pair(nb, round, Q, p2, q2);
@@ -160,8 +186,9 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
             const long gi = (i < BS) ? (long)p1 * BS + i : (long)q1 * BS + (i - BS);
             const long gj = (j < BS) ? (long)p2 * BS + j : (long)q2 * BS + (j - BS);
             X[i][j] = d.B[gi + gj * L];
-            RP[i][j] = RgP[i + (long)j * PB];
-            RQ[i][j] = RgQ[i + (long)j * PB];
+            // a pair that did not rotate has R = I (its R block was not written)
+            RP[i][j] = d.prot[P] ? RgP[i + (long)j * PB] : (i == j ? 1.0 : 0.0);
+            RQ[i][j] = d.prot[Q] ? RgQ[i + (long)j * PB] : (i == j ? 1.0 : 0.0);
         }
         __syncthreads();
         for (int idx = tid; idx < PB * PB; idx += 256) {
@@ -185,6 +212,7 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
     } else {
         const int w = item - ntri;
         const int P = w % npair, chunk = w / npair;
+        if (!d.prot[P]) return;
         int p1, q1;
         rr_pair(nb, round, P, p1, q1);
         const double* RgP = d.R + (long)P * PB * PB;
@@ -230,6 +258,40 @@ __global__ __launch_bounds__(256) void k_jacobi_init(const EigDesc* __restrict__
     }
 }
 
+// one launch per sweep: does any off-diagonal entry still need a rotation?
+__global__ __launch_bounds__(256) void k_jacobi_offcheck(const EigDesc* __restrict__ descs, int* n_open) {
+    const EigDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0 || d.st[0] != 0) return;
+    const long L = d.L;
+    const long total = (long)d.l * d.l;
+    const double floor_abs = kAbsFloor * d.scale[0];
+    int need = 0;
+    for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long)gridDim.x * 256) {
+        const int i = (int)(idx % d.l), j = (int)(idx / d.l);
+        if (i < j) {
+            const double a = d.B[i + j * L];
+            if (fabs(a) > fmax(kRelTol * sqrt(fabs(d.B[i + i * L] * d.B[j + j * L])), floor_abs)) need = 1;
+        }
+    }
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    if (need) any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && any) atomicOr(&d.st[1], 1);
+}
+
+// after the check: a matrix with nothing left to rotate is converged
+__global__ void k_jacobi_close(const EigDesc* __restrict__ descs, int count, int* n_open) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const EigDesc d = descs[b];
+    if (d.run[0] == 0 || d.st[0] != 0) return;
+    if (d.st[1] == 0) d.st[0] = 1;
+    else atomicAdd(n_open, 1);
+    d.st[1] = 0;
+}
+
 // end of a sweep: a sweep without rotations means converged
 __global__ void k_jacobi_sweep_end(const EigDesc* __restrict__ descs, int count, int* any_active) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -255,21 +317,35 @@ void launch_jacobi_init(const EigDesc* d_descs, int count, hipStream_t s) {
     hipLaunchKernelGGL(k_jacobi_init, dim3(count), dim3(256), 0, s, d_descs);
 }
 
-void launch_jacobi_round(const EigDesc* d_descs, int count, int maxL, int bs, int round,
-                         hipStream_t s) {
-    const int nb = maxL / bs;
-    const int npair = nb / 2;
+void launch_jacobi_pairs(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s) {
+    const int npair = maxL / bs / 2;
+    if (bs == 16)
+        hipLaunchKernelGGL((k_jacobi_pairs<16, 64>), dim3(npair, count), dim3(64), 0, s, d_descs, round);
+    else
+        hipLaunchKernelGGL((k_jacobi_pairs<32, 256>), dim3(npair, count), dim3(256), 0, s, d_descs, round);
+}
+
+void launch_jacobi_apply(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s) {
+    const int npair = maxL / bs / 2;
     const int ntri = npair * (npair + 1) / 2;
     const int nchunks = (maxL + 63) / 64;
-    if (bs == 16) {
-        hipLaunchKernelGGL((k_jacobi_pairs<16, 64>), dim3(npair, count), dim3(64), 0, s, d_descs, round);
+    if (bs == 16)
         hipLaunchKernelGGL((k_jacobi_apply<16>), dim3(ntri + nchunks * npair, count), dim3(256), 0, s,
                            d_descs, round);
-    } else {
-        hipLaunchKernelGGL((k_jacobi_pairs<32, 256>), dim3(npair, count), dim3(256), 0, s, d_descs, round);
+    else
         hipLaunchKernelGGL((k_jacobi_apply<32>), dim3(ntri + nchunks * npair, count), dim3(256), 0, s,
                            d_descs, round);
-    }
+}
+
+void launch_jacobi_round(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s) {
+    launch_jacobi_pairs(d_descs, count, maxL, bs, round, s);
+    launch_jacobi_apply(d_descs, count, maxL, bs, round, s);
+}
+
+void launch_jacobi_check(const EigDesc* d_descs, int count, int maxL, int* d_open, hipStream_t s) {
+    const int blocks = (maxL * maxL + 255) / 256 < 64 ? (maxL * maxL + 255) / 256 : 64;
+    hipLaunchKernelGGL(k_jacobi_offcheck, dim3(blocks, count), dim3(256), 0, s, d_descs, d_open);
+    hipLaunchKernelGGL(k_jacobi_close, dim3((count + 63) / 64), dim3(64), 0, s, d_descs, count, d_open);
 }
 
 void launch_jacobi_sweep_end(const EigDesc* d_descs, int count, int* d_any, hipStream_t s) {

@@ -18,6 +18,9 @@ void launch_add_identity(double* A, int lda, int m, double s, hipStream_t st);
 // jacobi.hip
 void launch_jacobi_init(const EigDesc* d_descs, int count, hipStream_t s);
 void launch_jacobi_round(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s);
+void launch_jacobi_pairs(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s);
+void launch_jacobi_apply(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s);
+void launch_jacobi_check(const EigDesc* d_descs, int count, int maxL, int* d_open, hipStream_t s);
 void launch_jacobi_sweep_end(const EigDesc* d_descs, int count, int* d_any, hipStream_t s);
 void launch_jacobi_eigvals(const EigDesc* d_descs, int count, hipStream_t s);
 

@@ -30,8 +30,76 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "../../include/lrr.h"
+#include "../../include/lrr_diag.h"
+
+// Opt-in per-kernel timing with HIP events on the solve's stream.
+struct LrrProf {
+    struct Entry {
+        std::string name;
+        double ms = 0.0;
+        long long launches = 0;
+        double flops = 0.0, bytes = 0.0;
+    };
+    struct Pending {
+        int idx;
+        hipEvent_t a, b;
+        double flops, bytes;
+    };
+    bool on = false;
+    std::vector<Entry> entries;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+
+    int index(const char* name) {
+        for (size_t i = 0; i < entries.size(); ++i)
+            if (entries[i].name == name) return (int)i;
+        entries.push_back(Entry{name});
+        return (int)entries.size() - 1;
+    }
+    hipEvent_t get() {
+        if (pool.empty()) {
+            hipEvent_t e;
+            LRR_HIP(hipEventCreate(&e));
+            return e;
+        }
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    template <class F>
+    void run(hipStream_t s, const char* name, double flops, double bytes, F&& f) {
+        if (!on) { f(); return; }
+        hipEvent_t a = get(), b = get();
+        LRR_HIP(hipEventRecord(a, s));
+        f();
+        LRR_HIP(hipEventRecord(b, s));
+        pending.push_back(Pending{index(name), a, b, flops, bytes});
+    }
+    // call after the stream has been synchronised
+    void flush() {
+        for (const Pending& p : pending) {
+            float ms = 0.f;
+            LRR_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+            Entry& e = entries[p.idx];
+            e.ms += ms;
+            e.launches += 1;
+            e.flops += p.flops;
+            e.bytes += p.bytes;
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+    }
+    void release() {
+        for (const Pending& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pending.clear();
+        pool.clear();
+    }
+};
 
 struct lrr_ctx {
+    LrrProf prof;
     int device = 0;
     std::string err;
     void* ws = nullptr;
@@ -85,6 +153,7 @@ struct Buffers {
     double *colsq, *mu_sched;
     int *colblk, *boff, *perm;
     int *active, *svt_run, *iters, *rank, *eigst, *n_active, *eig_any, *flag;
+    std::vector<int*> prot;
     double *res1, *res2, *eigscale;
     unsigned long long *r1max, *r2max;
     DevIter* it;
@@ -144,7 +213,7 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.it = a.take<DevIter>(1);
     b.Bm.assign(t, nullptr); b.Wm.assign(t, nullptr); b.Wg.assign(t, nullptr);
     b.Bt.assign(t, nullptr); b.Pm.assign(t, nullptr); b.Rm.assign(t, nullptr);
-    b.lam.assign(t, nullptr); b.h.assign(t, nullptr);
+    b.lam.assign(t, nullptr); b.h.assign(t, nullptr); b.prot.assign(t, nullptr);
     for (size_t i = 0; i < t; ++i) {
         const size_t L = p.L[i];
         b.Bm[i] = a.take<double>(L * L);
@@ -155,6 +224,7 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
         b.Rm[i] = a.take<double>(L * 2 * p.bs);
         b.lam[i] = a.take<double>(L);
         b.h[i] = a.take<double>(L);
+        b.prot[i] = a.take<int>(L / (2 * p.bs) + 1);
     }
     b.g_gram = a.take<GemmDesc>(t);
     b.g_w1 = a.take<GemmDesc>(t);
@@ -300,7 +370,7 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         gP[bb] = GemmDesc{b.Wg[bb], b.Wm[bb], b.Pm[bb], l, l, L, L, L, L, 1.0, 0.0, run, nullptr};
         gJ[bb] = GemmDesc{Yb, b.Pm[bb], Jb, n, l, l, n, L, n, 1.0, 0.0, run, nullptr};
         eig[bb] = EigDesc{b.Bm[bb], b.Wm[bb], b.Rm[bb], b.lam[bb], L, l, run, b.eigst + 2 * bb,
-                          b.eigscale + bb};
+                          b.eigscale + bb, b.prot[bb]};
         svt[bb] = SvtDesc{b.Bm[bb], b.Wm[bb], b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
     }
     GemmDesc gMQ{pr.A, b.Q, b.T, m, c, n, (int)pr.lda, n, m, -1.0, 1.0, nullptr, nullptr};
@@ -366,46 +436,104 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     int* h_misc = hp + t;       // scalars
 
     Result res;
+    LrrProf& prof = ctx->prof;
+    auto timed = [&](const char* name, double flops, double bytes, auto&& f) {
+        prof.run(s, name, flops, bytes, f);
+    };
+    auto sync = [&]() {
+        LRR_HIP(hipStreamSynchronize(s));
+        if (prof.on) prof.flush();
+    };
+    std::vector<int> h_act(t, 1);
+    const double D = sizeof(double);
     int k = 0;
     for (k = 0; k < p.n_iter; ++k) {
+        double cact = 0.0;   // columns of blocks still iterating
+        for (int bb = 0; bb < t; ++bb) if (h_act[bb]) cact += p.boff[bb + 1] - p.boff[bb];
         // J-step input and the exact zero test
-        lrr::launch_form_Y(b.Z, b.Y2, b.Y, b.colsq, n, n, c, b.colblk, b.active, b.it, s);
-        lrr::launch_block_fro(b.colsq, b.boff, t, bst, b.it, s);
-        lrr::launch_zero_J(b.J, n, n, c, b.colblk, bst, s);
+        timed("k_form_Y", 0.0, 3.0 * n * cact * D, [&] {
+            lrr::launch_form_Y(b.Z, b.Y2, b.Y, b.colsq, n, n, c, b.colblk, b.active, b.it, s);
+        });
+        timed("k_block_fro", 0.0, cact * D, [&] { lrr::launch_block_fro(b.colsq, b.boff, t, bst, b.it, s); });
+        timed("k_zero_J", 0.0, 0.0, [&] { lrr::launch_zero_J(b.J, n, n, c, b.colblk, bst, s); });
         LRR_HIP(hipMemcpyAsync(h_run, b.svt_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
-        LRR_HIP(hipStreamSynchronize(s));
+        sync();
         int any_run = 0;
-        for (int bb = 0; bb < t; ++bb) any_run |= h_run[bb];
+        double f_gram = 0, f_warm = 0, f_P = 0, f_J = 0;
+        for (int bb = 0; bb < t; ++bb) {
+            if (!h_run[bb]) continue;
+            any_run = 1;
+            const double l = p.boff[bb + 1] - p.boff[bb], L = p.L[bb];
+            f_gram += 2.0 * l * l * n;
+            f_warm += 2.0 * L * L * L;
+            f_P += 2.0 * l * l * L;
+            f_J += 2.0 * n * l * l;
+        }
         if (any_run) {
             // Gram, warm start with the previous eigenvectors, Jacobi sweeps
-            lrr::launch_dgemm(b.g_gram, t, p.maxl, p.maxl, true, false, s);
-            lrr::launch_dgemm(b.g_w1, t, p.maxL, p.maxL, false, false, s);
-            lrr::launch_dgemm(b.g_w2, t, p.maxL, p.maxL, true, false, s);
-            lrr::launch_jacobi_init(b.eig, t, s);
+            timed("k_dgemm<true, false>", f_gram, 0.0, [&] {
+                lrr::launch_dgemm(b.g_gram, t, p.maxl, p.maxl, true, false, s);
+            });
+            timed("k_dgemm<false, false>", f_warm, 0.0, [&] {
+                lrr::launch_dgemm(b.g_w1, t, p.maxL, p.maxL, false, false, s);
+            });
+            timed("k_dgemm<true, false>", f_warm, 0.0, [&] {
+                lrr::launch_dgemm(b.g_w2, t, p.maxL, p.maxL, true, false, s);
+            });
+            timed("k_jacobi_init", 0.0, 0.0, [&] { lrr::launch_jacobi_init(b.eig, t, s); });
             const int nb = p.maxL / p.bs;
-            for (int sw = 0; sw < max_sweeps; ++sw) {
-                for (int r = 0; r < nb - 1; ++r) lrr::launch_jacobi_round(b.eig, t, p.maxL, p.bs, r, s);
+            for (int sw = 0; sw <= max_sweeps; ++sw) {
+                // converged matrices are closed here; the loop ends when none is open
                 LRR_HIP(hipMemsetAsync(b.eig_any, 0, sizeof(int), s));
-                lrr::launch_jacobi_sweep_end(b.eig, t, b.eig_any, s);
+                timed("k_jacobi_offcheck", 0.0, 0.0, [&] {
+                    lrr::launch_jacobi_check(b.eig, t, p.maxL, b.eig_any, s);
+                });
                 LRR_HIP(hipMemcpyAsync(h_misc, b.eig_any, sizeof(int), hipMemcpyDeviceToHost, s));
-                LRR_HIP(hipStreamSynchronize(s));
-                if (h_misc[0] == 0) break;
+                sync();
+                if (h_misc[0] == 0 || sw == max_sweeps) break;
+                for (int r = 0; r < nb - 1; ++r) {
+                    timed(p.bs == 16 ? "k_jacobi_pairs<16, 64>" : "k_jacobi_pairs<32, 256>", 0.0, 0.0, [&] {
+                        lrr::launch_jacobi_pairs(b.eig, t, p.maxL, p.bs, r, s);
+                    });
+                    timed(p.bs == 16 ? "k_jacobi_apply<16>" : "k_jacobi_apply<32>", 0.0, 0.0, [&] {
+                        lrr::launch_jacobi_apply(b.eig, t, p.maxL, p.bs, r, s);
+                    });
+                }
             }
-            lrr::launch_svt_weights(b.svt, t, p.maxL, b.it, bst, s);
-            lrr::launch_dgemm(b.g_P, t, p.maxl, p.maxl, false, true, s);
-            lrr::launch_dgemm(b.g_J, t, n, p.maxl, false, false, s);
+            timed("k_svt_weights", 0.0, 0.0, [&] { lrr::launch_svt_weights(b.svt, t, p.maxL, b.it, bst, s); });
+            timed("k_dgemm<false, true>", f_P, 0.0, [&] {
+                lrr::launch_dgemm(b.g_P, t, p.maxl, p.maxl, false, true, s);
+            });
+            timed("k_dgemm<false, false>", f_J, 0.0, [&] {
+                lrr::launch_dgemm(b.g_J, t, n, p.maxl, false, false, s);
+            });
         }
         // Z-step (push-through) and E-step
-        lrr::launch_form_QT(b.J, b.Y2, b.Q, n, n, b.X, b.E, b.Y1, b.T, m, m, c, b.colblk, b.active, b.it, s);
-        lrr::launch_dgemm(b.g_MQ, 1, m, c, false, false, s);
-        lrr::launch_dgemm(b.g_KV, 1, m, c, false, false, s);
-        lrr::launch_dgemm(b.g_MtV, 1, n, c, true, false, s);
-        lrr::launch_update_Z(b.Q, b.MtV, b.J, b.Z, b.Y2, n, n, c, b.colblk, bst, b.it, s);
-        lrr::launch_estep(b.E, b.V, b.Y1, m, m, c, pr.lam, b.colblk, bst, b.it, s);
-        lrr::launch_check(bst, t, b.it, b.mu_sched, o.tol, fixed, b.n_active, s);
+        timed("k_form_QT", 0.0, (3.0 * n + 4.0 * m) * cact * D, [&] {
+            lrr::launch_form_QT(b.J, b.Y2, b.Q, n, n, b.X, b.E, b.Y1, b.T, m, m, c, b.colblk, b.active, b.it, s);
+        });
+        timed("k_dgemm<false, false>", 2.0 * m * n * cact, 0.0, [&] {
+            lrr::launch_dgemm(b.g_MQ, 1, m, c, false, false, s);
+        });
+        timed("k_dgemm<false, false>", 2.0 * m * m * cact, 0.0, [&] {
+            lrr::launch_dgemm(b.g_KV, 1, m, c, false, false, s);
+        });
+        timed("k_dgemm<true, false>", 2.0 * n * m * cact, 0.0, [&] {
+            lrr::launch_dgemm(b.g_MtV, 1, n, c, true, false, s);
+        });
+        timed("k_update_Z", 0.0, 6.0 * n * cact * D, [&] {
+            lrr::launch_update_Z(b.Q, b.MtV, b.J, b.Z, b.Y2, n, n, c, b.colblk, bst, b.it, s);
+        });
+        timed("k_estep", 0.0, 5.0 * m * cact * D, [&] {
+            lrr::launch_estep(b.E, b.V, b.Y1, m, m, c, pr.lam, b.colblk, bst, b.it, s);
+        });
+        timed("k_check", 0.0, 0.0, [&] {
+            lrr::launch_check(bst, t, b.it, b.mu_sched, o.tol, fixed, b.n_active, s);
+        });
         if (!fixed && ((k + 1) % check_every == 0 || k + 1 == p.n_iter)) {
             LRR_HIP(hipMemcpyAsync(h_misc + 1, b.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-            LRR_HIP(hipStreamSynchronize(s));
+            LRR_HIP(hipMemcpyAsync(h_act.data(), b.active, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+            sync();
             if (h_misc[1] == 0) { ++k; break; }
         }
     }
@@ -506,6 +634,7 @@ lrr_status lrr_ctx_create(int device, lrr_ctx** out) {
 void lrr_ctx_destroy(lrr_ctx* ctx) {
     if (!ctx) return;
     if (hipSetDevice(ctx->device) == hipSuccess) {
+        ctx->prof.release();
         if (ctx->ws) (void)hipFree(ctx->ws);
         if (ctx->dflag) (void)hipFree(ctx->dflag);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -609,16 +738,44 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
             LRR_HIP(hipMemcpyAsync(b.g_U, &hd[0], sizeof(GemmDesc), hipMemcpyHostToDevice, s));
             LRR_HIP(hipMemcpyAsync(b.g_H, &hd[1], sizeof(GemmDesc), hipMemcpyHostToDevice, s));
             LRR_HIP(hipMemcpyAsync(b.g_Z, &hd[2], sizeof(GemmDesc), hipMemcpyHostToDevice, s));
-            lrr::launch_dgemm(b.g_U, 1, n, L0, false, false, s);
-            lrr::launch_scale_cols(b.U, n, n, L0, b.h[0], s);
-            lrr::launch_dgemm(b.g_H, 1, L0, n, true, false, s);
-            lrr::launch_dgemm(b.g_Z, 1, n, n, false, false, s);
+            LrrProf& prof = ctx->prof;
+            prof.run(s, "k_dgemm<false, false>", 2.0 * n * L0 * l0, 0.0,
+                     [&] { lrr::launch_dgemm(b.g_U, 1, n, L0, false, false, s); });
+            prof.run(s, "k_scale_cols", 0.0, 2.0 * n * L0 * sizeof(double),
+                     [&] { lrr::launch_scale_cols(b.U, n, n, L0, b.h[0], s); });
+            prof.run(s, "k_dgemm<true, false>", 2.0 * L0 * n * n, 0.0,
+                     [&] { lrr::launch_dgemm(b.g_H, 1, L0, n, true, false, s); });
+            prof.run(s, "k_dgemm<false, false>", 2.0 * n * n * L0, 0.0,
+                     [&] { lrr::launch_dgemm(b.g_Z, 1, n, n, false, false, s); });
         }
         if (S) lrr::launch_scatter_cols(b.E, m, static_cast<double*>(S), lds, m, n, b.perm, s);
         LRR_HIP(hipStreamSynchronize(s));
+        if (ctx->prof.on) ctx->prof.flush();
         fill_info(info, r, r1);
         return r.converged ? LRR_OK : LRR_NOT_CONVERGED;
     });
+}
+
+lrr_status lrr_prof_enable(lrr_ctx* ctx, int on) {
+    if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
+    ctx->prof.flush();
+    ctx->prof.entries.clear();
+    ctx->prof.on = on != 0;
+    return LRR_OK;
+}
+
+int lrr_prof_count(const lrr_ctx* ctx) { return ctx ? (int)ctx->prof.entries.size() : 0; }
+
+lrr_status lrr_prof_entry(const lrr_ctx* ctx, int idx, const char** name, double* ms, long long* launches,
+                          double* flops, double* bytes) {
+    if (!ctx || idx < 0 || idx >= (int)ctx->prof.entries.size()) return LRR_EINVAL;
+    const LrrProf::Entry& e = ctx->prof.entries[idx];
+    if (name) *name = e.name.c_str();
+    if (ms) *ms = e.ms;
+    if (launches) *launches = e.launches;
+    if (flops) *flops = e.flops;
+    if (bytes) *bytes = e.bytes;
+    return LRR_OK;
 }
 
 lrr_status dfc_lrr_backward(lrr_ctx* ctx, const void* dZ, int lddz, double* dlambda, void* dM, int lddm,
