@@ -62,6 +62,25 @@ struct EigDesc {
     int* st;            // [0] converged, [1] pairs that rotated in the current sweep
     double* scale;      // max |diag| of B at the start, for the absolute floor
     int* prot;          // per pair of the current round: 1 if it rotated
+    int* lo;            // per index: Gershgorin disc below tau^2 (pairs of two such are skipped)
+};
+
+// Warm-started eigenvector refinement of one Gram matrix (see refsyev.hip).
+struct RefDesc {
+    const double* B;    // L x L Gram matrix
+    double* X;          // L x L eigenvector estimate (right half of the [T | X] buffer)
+    double* SG;         // L x 2L: [S | G] = X^T [B X | X]
+    double* E;          // L x L correction
+    double* XE;         // L x L product X E
+    double* lam;        // L Rayleigh quotients
+    int* lo;            // L Gershgorin flags
+    double* scale;      // max |diag B|
+    unsigned long long* emax;  // largest resolvable correction of the step (bits)
+    int* unres;         // couplings left for the Jacobi sweeps
+    double* eprev;      // previous step's largest correction
+    int* run;           // refinement step applied to this matrix
+    int* cont;          // refinement continues after this step
+    int L, l, block;
 };
 
 // Thresholding weights of one block after its Gram eigensolve.

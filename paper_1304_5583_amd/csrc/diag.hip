@@ -125,7 +125,7 @@ lrr_status lrr_diag_syevj(lrr_ctx* ctx, int count, const int* l, const double* B
         hipStream_t s = static_cast<hipStream_t>(stream);
         const size_t LL = (size_t)L * L;
         double *Bp, *Wp, *Rp, *lamp, *scale;
-        int *st, *run_on, *ls, *any, *prot;
+        int *st, *run_on, *ls, *any, *prot, *lo;
         lrr::EigDesc* dd;
         LRR_HIP(hipMalloc((void**)&Bp, sizeof(double) * LL * count));
         LRR_HIP(hipMalloc((void**)&Wp, sizeof(double) * LL * count));
@@ -138,12 +138,16 @@ lrr_status lrr_diag_syevj(lrr_ctx* ctx, int count, const int* l, const double* B
         LRR_HIP(hipMalloc((void**)&any, sizeof(int)));
         const int npair = L / (2 * bs);
         LRR_HIP(hipMalloc((void**)&prot, sizeof(int) * npair * count));
+        // no threshold here: every pair of indices is resolved
+        LRR_HIP(hipMalloc((void**)&lo, sizeof(int) * (size_t)L * count));
+        LRR_HIP(hipMemsetAsync(lo, 0, sizeof(int) * (size_t)L * count, s));
         LRR_HIP(hipMalloc((void**)&dd, sizeof(lrr::EigDesc) * count));
         std::vector<lrr::EigDesc> hd(count);
         std::vector<int> ones(count, 1);
         for (int i = 0; i < count; ++i)
             hd[i] = lrr::EigDesc{Bp + LL * i, Wp + LL * i, Rp + (size_t)L * 2 * bs * i, lamp + (size_t)L * i,
-                                 L, l[i], run_on + i, st + 2 * i, scale + i, prot + npair * i};
+                                 L, l[i], run_on + i, st + 2 * i, scale + i, prot + npair * i,
+                                 lo + (size_t)L * i};
         LRR_HIP(hipMemcpy(dd, hd.data(), sizeof(lrr::EigDesc) * count, hipMemcpyHostToDevice));
         LRR_HIP(hipMemcpy(run_on, ones.data(), sizeof(int) * count, hipMemcpyHostToDevice));
         LRR_HIP(hipMemcpy(ls, l, sizeof(int) * count, hipMemcpyHostToDevice));
@@ -169,6 +173,7 @@ lrr_status lrr_diag_syevj(lrr_ctx* ctx, int count, const int* l, const double* B
         (void)hipFree(Bp); (void)hipFree(Wp); (void)hipFree(Rp); (void)hipFree(lamp); (void)hipFree(scale);
         (void)hipFree(st); (void)hipFree(run_on); (void)hipFree(ls); (void)hipFree(any); (void)hipFree(dd);
         (void)hipFree(prot);
+        (void)hipFree(lo);
         return LRR_OK;
     });
 }

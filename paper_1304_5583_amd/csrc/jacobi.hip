@@ -14,6 +14,9 @@
 //   phase B  every tile pair (P, Q), P <= Q, of the round is replaced by
 //            R_P^T B[P, Q] R_Q (and its transpose), and the eigenvector
 //            accumulator gets W[:, P] <- W[:, P] R_P.
+// Pairs of indices whose Gershgorin discs both lie below tau^2 are never
+// rotated: the thresholding step discards every eigenvalue of that cluster, so
+// only the subspace it spans matters, not a basis of it.
 // Convergence: an off-diagonal entry needs a rotation when
 // |b_pq| > max(1e-15 sqrt(|b_pp b_qq|), 1e-14 max|diag B|).  The absolute floor
 // sits at the rounding level of the matrix: a Gram matrix of a rank-deficient
@@ -56,6 +59,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
     __shared__ double R[PB][PB + 1];
     __shared__ double csc[NP], css[NP], cst[NP], csd[NP], cse[NP];
     __shared__ int any;
+    __shared__ int LO[PB];
 
     const int tid = threadIdx.x;
     const long L = d.L;
@@ -65,6 +69,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
         const long gj = (j < BS) ? (long)p * BS + j : (long)q * BS + (j - BS);
         S[i][j] = d.B[gi + gj * L];
         R[i][j] = (i == j) ? 1.0 : 0.0;
+        if (j == 0) LO[i] = d.lo[gi];
     }
     const double floor_abs = kAbsFloor * d.scale[0];
     int rotated = 0;
@@ -76,7 +81,9 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
         __syncthreads();
         for (int idx = tid; idx < PB * PB; idx += NT) {
             const int i = idx % PB, j = idx / PB;
-            if (i < j && fabs(S[i][j]) > fmax(kRelTol * sqrt(fabs(S[i][i] * S[j][j])), floor_abs)) any = 1;
+            if (i < j && !(LO[i] && LO[j]) &&
+                fabs(S[i][j]) > fmax(kRelTol * sqrt(fabs(S[i][i] * S[j][j])), floor_abs))
+                any = 1;
         }
         __syncthreads();
         if (!any) break;
@@ -87,7 +94,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
                 rr_pair(PB, r, tid, a, b);
                 const double app = S[a][a], aqq = S[b][b], apq = S[a][b];
                 double c = 1.0, s = 0.0, t = 0.0;
-                if (fabs(apq) > fmax(kRelTol * sqrt(fabs(app * aqq)), floor_abs)) {
+                if (!(LO[a] && LO[b]) && fabs(apq) > fmax(kRelTol * sqrt(fabs(app * aqq)), floor_abs)) {
                     sym_schur2(app, aqq, apq, c, s);
                     t = s / c;
                 }
@@ -268,7 +275,7 @@ __global__ __launch_bounds__(256) void k_jacobi_offcheck(const EigDesc* __restri
     int need = 0;
     for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long)gridDim.x * 256) {
         const int i = (int)(idx % d.l), j = (int)(idx / d.l);
-        if (i < j) {
+        if (i < j && !(d.lo[i] && d.lo[j])) {
             const double a = d.B[i + j * L];
             if (fabs(a) > fmax(kRelTol * sqrt(fabs(d.B[i + i * L] * d.B[j + j * L])), floor_abs)) need = 1;
         }
@@ -320,7 +327,7 @@ void launch_jacobi_init(const EigDesc* d_descs, int count, hipStream_t s) {
 void launch_jacobi_pairs(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s) {
     const int npair = maxL / bs / 2;
     if (bs == 16)
-        hipLaunchKernelGGL((k_jacobi_pairs<16, 64>), dim3(npair, count), dim3(64), 0, s, d_descs, round);
+        hipLaunchKernelGGL((k_jacobi_pairs<16, 256>), dim3(npair, count), dim3(256), 0, s, d_descs, round);
     else
         hipLaunchKernelGGL((k_jacobi_pairs<32, 256>), dim3(npair, count), dim3(256), 0, s, d_descs, round);
 }

@@ -24,6 +24,19 @@ void launch_jacobi_check(const EigDesc* d_descs, int count, int maxL, int* d_ope
 void launch_jacobi_sweep_end(const EigDesc* d_descs, int count, int* d_any, hipStream_t s);
 void launch_jacobi_eigvals(const EigDesc* d_descs, int count, hipStream_t s);
 
+// refsyev.hip
+void launch_ref_begin(const RefDesc* d, int count, const int* svt_run, const int* warm, hipStream_t s);
+void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, hipStream_t s);
+void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s);
+void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s);
+void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, int* n_open, hipStream_t s);
+void launch_ref_next(const RefDesc* d, int count, hipStream_t s);
+void launch_orth_guard(const RefDesc* d, int count, int maxL, hipStream_t s);
+void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hipStream_t s);
+void launch_orth_E(const RefDesc* d, int count, int maxL, hipStream_t s);
+void launch_ref_set_run(const RefDesc* d, int count, const int* svt_run, hipStream_t s);
+void launch_mark_warm(const int* svt_run, int* warm, int t, hipStream_t s);
+
 // alm.hip
 void launch_gather_cols(const double* M, long ldm, double* X, long ldx, int m, int ncols,
                         const int* d_perm, hipStream_t s);
@@ -51,5 +64,6 @@ void launch_check(BlockState bs, int t, DevIter* it, const double* mu_sched, dou
 void launch_init_iter(DevIter* it, const double* mu_sched, hipStream_t s);
 void launch_scale_cols(double* U, long ld, int rows, int ncols, const double* h, hipStream_t s);
 void launch_set_identity(double* W, int L, hipStream_t s);
+
 
 }  // namespace lrr

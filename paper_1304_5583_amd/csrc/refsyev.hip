@@ -1,0 +1,287 @@
+// Warm-started refinement of a symmetric eigen-decomposition (FP64).
+//
+// The thresholding step of iteration k needs the eigenvectors of the Gram
+// matrix B_k = Y_k^T Y_k, and B_k is close to B_{k-1}.  Starting from the
+// eigenvectors X of the previous iteration, each refinement step is the
+// Newton-type update of Ogita and Aishima (Japan J. Indust. Appl. Math., 2018):
+//   G = X^T X,  S = X^T B X,  lambda_i = s_ii / g_ii,  R = I - G,
+//   E_ij = (s_ij + lambda_j r_ij) / (lambda_j - lambda_i)   (i != j, resolvable)
+//   E_ij = r_ij / 2                                          (otherwise)
+//   X <- X + X E
+// which converges quadratically once the off-diagonal coupling is small
+// against the eigenvalue gaps.  Built entirely from the MFMA GEMM plus two
+// element-wise kernels, so a step is a handful of launches whatever the order.
+//
+// A pair (i, j) is resolvable when |s_ij + lambda_j r_ij| <= 0.1 |lambda_j -
+// lambda_i| (inside the linear regime of the update) and the two Gershgorin
+// discs of S are not both below tau^2: every eigenvalue whose disc lies below
+// tau^2 is discarded by the threshold step, so rotations among such indices
+// cannot change the result.  Couplings that stay unresolvable are left to the
+// block-Jacobi sweeps that follow.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lrr {
+
+namespace {
+
+constexpr double kLinCap = 0.1;
+constexpr double kFirstStepCap = 0.1;    // largest correction accepted in the first step
+constexpr double kOrthTol = 1e-6;         // |I - X^T X| above this after one step: restart cold
+constexpr double kRelTol = 1e-15;
+constexpr double kAbsFloor = 1e-14;
+
+// row pass: lambda_i, Gershgorin flag lo_i of S (padding: lambda 0, lo 1)
+__global__ __launch_bounds__(256) void k_ref_rows(const RefDesc* __restrict__ descs, const DevIter* it) {
+    const RefDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0) return;
+    const int i = blockIdx.x;
+    if (i >= d.L) return;
+    const long L = d.L;
+    const double* S = d.SG;
+    const double* G = d.SG + L * L;
+    __shared__ double red[4];
+    double rs = 0.0;
+    for (int j = threadIdx.x; j < d.l; j += 256)
+        if (j != i) rs += fabs(S[i + j * L]);
+    rs = wave_sum(rs);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rs;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double r = (red[0] + red[1]) + (red[2] + red[3]);
+        const double tau = it->tau;
+        if (i < d.l) {
+            const double sii = S[i + i * L];
+            d.lam[i] = sii / G[i + i * L];
+            d.lo[i] = (sii + r < tau * tau * (1.0 - 1e-9)) ? 1 : 0;
+        } else {
+            d.lam[i] = 0.0;
+            d.lo[i] = 1;
+        }
+    }
+}
+
+// correction matrix E and per-matrix statistics
+__global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs) {
+    const RefDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0) return;
+    const long L = d.L;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    double emax = 0.0;
+    int unres = 0;
+    if (idx < L * L) {
+        const int i = (int)(idx % L), j = (int)(idx / L);
+        const double* S = d.SG;
+        const double* G = d.SG + L * L;
+        const double gij = G[i + j * L];
+        double e;
+        if (i == j) {
+            e = 0.5 * (1.0 - gij);
+        } else {
+            const double rij = -gij;
+            const double sij = S[i + j * L];
+            const double li = d.lam[i], lj = d.lam[j];
+            const double num = sij + lj * rij;
+            const double dl = lj - li;
+            const bool both_lo = d.lo[i] && d.lo[j];
+            const bool ok = !both_lo && dl != 0.0 && fabs(num) <= kLinCap * fabs(dl);
+            if (ok) {
+                e = num / dl;
+                emax = fabs(e);
+            } else {
+                e = 0.5 * rij;
+                if (!both_lo && i < j && i < d.l && j < d.l) {
+                    const double sii = S[i + i * L], sjj = S[j + j * L];
+                    if (fabs(sij) > fmax(kRelTol * sqrt(fabs(sii * sjj)), kAbsFloor * d.scale[0])) unres = 1;
+                }
+            }
+        }
+        d.E[idx] = e;
+    }
+    emax = wave_max(emax);
+    int u = unres;
+    for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
+    if ((threadIdx.x & 63) == 0) {
+        if (emax > 0.0) atomic_max_nonneg(d.emax, emax);
+        if (u) atomicAdd(d.unres, u);
+    }
+}
+
+// X += XE
+__global__ __launch_bounds__(256) void k_ref_add(const RefDesc* __restrict__ descs) {
+    const RefDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0) return;
+    const long L = d.L;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx < L * L) d.X[idx] += d.XE[idx];
+}
+
+// after E is formed and before it is applied: apply the step only while the
+// corrections do not grow; stop (without applying) otherwise
+__global__ void k_ref_update(const RefDesc* __restrict__ descs, int count, int step, int max_steps,
+                             int* n_open) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const RefDesc d = descs[b];
+    if (d.run[0] == 0) return;
+    const double e = __longlong_as_double((long long)d.emax[0]);
+    const double limit = (step == 0) ? kFirstStepCap : d.eprev[0];
+    const bool apply = (e <= limit);
+    const bool cont = apply && e >= 1e-13 && step + 1 < max_steps;
+    d.eprev[0] = e;
+    d.emax[0] = 0ull;
+    d.unres[0] = 0;
+    d.run[0] = apply ? 1 : 0;
+    d.cont[0] = cont ? 1 : 0;
+    if (cont) atomicAdd(n_open, 1);
+}
+
+// after the step is applied: continue only where the update asked for it
+__global__ void k_ref_next(const RefDesc* __restrict__ descs, int count) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const RefDesc d = descs[b];
+    d.run[0] = d.cont[0];
+}
+
+// start of a refinement: per-matrix flags and the scale of S
+__global__ void k_ref_begin(const RefDesc* __restrict__ descs, int count, const int* __restrict__ svt_run,
+                            const int* __restrict__ warm) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const RefDesc d = descs[b];
+    d.run[0] = (svt_run[d.block] && warm[d.block]) ? 1 : 0;
+    d.cont[0] = 0;
+    d.eprev[0] = 1.0;
+    d.emax[0] = 0ull;
+    d.unres[0] = 0;
+}
+
+// max |diag| of the Gram matrix (scale of the absolute floor)
+__global__ __launch_bounds__(256) void k_ref_scale(const RefDesc* __restrict__ descs) {
+    const RefDesc d = descs[blockIdx.x];
+    if (d.run[0] == 0) return;
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < d.l; i += 256) mx = fmax(mx, fabs(d.B[i + (long)i * d.L]));
+    mx = wave_max(mx);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) d.scale[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// Gershgorin flags of the Jacobi matrix (for the cleanup sweeps)
+__global__ __launch_bounds__(256) void k_lo_rows(const EigDesc* __restrict__ descs, const DevIter* it) {
+    const EigDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0 || d.st[0] != 0) return;
+    const int i = blockIdx.x;
+    if (i >= d.L) return;
+    const long L = d.L;
+    __shared__ double red[4];
+    double rs = 0.0;
+    for (int j = threadIdx.x; j < d.l; j += 256)
+        if (j != i) rs += fabs(d.B[i + j * L]);
+    rs = wave_sum(rs);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rs;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double r = (red[0] + red[1]) + (red[2] + red[3]);
+        const double tau = it->tau;
+        d.lo[i] = (i >= d.l) ? 1 : ((d.B[i + i * L] + r < tau * tau * (1.0 - 1e-9)) ? 1 : 0);
+    }
+}
+
+// orthogonalisation step (Newton-Schulz for the polar factor): E = (I - G)/2,
+// and the largest |I - G| of the matrix
+__global__ __launch_bounds__(256) void k_orth_E(const RefDesc* __restrict__ descs) {
+    const RefDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0) return;
+    const long L = d.L;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    double dev = 0.0;
+    if (idx < L * L) {
+        const int i = (int)(idx % L), j = (int)(idx / L);
+        const double g = d.SG[L * L + idx];
+        const double e = (i == j) ? 0.5 * (1.0 - g) : -0.5 * g;
+        d.E[idx] = e;
+        dev = 2.0 * fabs(e);
+    }
+    dev = wave_max(dev);
+    if ((threadIdx.x & 63) == 0 && dev > 0.0) atomic_max_nonneg(d.emax, dev);
+}
+
+// a matrix whose estimate lost orthogonality restarts from the identity
+__global__ __launch_bounds__(256) void k_orth_guard(const RefDesc* __restrict__ descs) {
+    const RefDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0) return;
+    const double dev = __longlong_as_double((long long)d.emax[0]);
+    if (!(dev <= kOrthTol)) {
+        const long L = d.L;
+        const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+        if (idx < L * L) d.X[idx] = ((idx % L) == (idx / L)) ? 1.0 : 0.0;
+    }
+}
+
+__global__ void k_orth_reset(const RefDesc* __restrict__ descs, int count) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    descs[b].emax[0] = 0ull;
+}
+
+// the steps after the refinement run on every matrix that needs a decomposition
+__global__ void k_ref_set_run(const RefDesc* __restrict__ descs, int count, const int* __restrict__ svt_run) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const RefDesc d = descs[b];
+    d.run[0] = svt_run[d.block];
+}
+
+__global__ void k_mark_warm(const int* __restrict__ svt_run, int* __restrict__ warm, int t) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < t && svt_run[b]) warm[b] = 1;
+}
+
+}  // namespace
+
+void launch_orth_E(const RefDesc* d, int count, int maxL, hipStream_t s) {
+    const long n = (long)maxL * maxL;
+    hipLaunchKernelGGL(k_orth_reset, dim3((count + 63) / 64), dim3(64), 0, s, d, count);
+    hipLaunchKernelGGL(k_orth_E, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d);
+}
+void launch_orth_guard(const RefDesc* d, int count, int maxL, hipStream_t s) {
+    const long n = (long)maxL * maxL;
+    hipLaunchKernelGGL(k_orth_guard, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d);
+}
+void launch_ref_next(const RefDesc* d, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_ref_next, dim3((count + 63) / 64), dim3(64), 0, s, d, count);
+}
+void launch_ref_set_run(const RefDesc* d, int count, const int* svt_run, hipStream_t s) {
+    hipLaunchKernelGGL(k_ref_set_run, dim3((count + 63) / 64), dim3(64), 0, s, d, count, svt_run);
+}
+void launch_mark_warm(const int* svt_run, int* warm, int t, hipStream_t s) {
+    hipLaunchKernelGGL(k_mark_warm, dim3((t + 63) / 64), dim3(64), 0, s, svt_run, warm, t);
+}
+
+void launch_ref_begin(const RefDesc* d, int count, const int* svt_run, const int* warm, hipStream_t s) {
+    hipLaunchKernelGGL(k_ref_begin, dim3((count + 63) / 64), dim3(64), 0, s, d, count, svt_run, warm);
+    hipLaunchKernelGGL(k_ref_scale, dim3(count), dim3(256), 0, s, d);
+}
+void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, hipStream_t s) {
+    hipLaunchKernelGGL(k_ref_rows, dim3(maxL, count), dim3(256), 0, s, d, it);
+}
+void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s) {
+    const long n = (long)maxL * maxL;
+    hipLaunchKernelGGL(k_ref_E, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d);
+}
+void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s) {
+    const long n = (long)maxL * maxL;
+    hipLaunchKernelGGL(k_ref_add, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d);
+}
+void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, int* n_open, hipStream_t s) {
+    hipLaunchKernelGGL(k_ref_update, dim3((count + 63) / 64), dim3(64), 0, s, d, count, step, max_steps, n_open);
+}
+void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hipStream_t s) {
+    hipLaunchKernelGGL(k_lo_rows, dim3(maxL, count), dim3(256), 0, s, d, it);
+}
+
+}  // namespace lrr

@@ -116,6 +116,7 @@ using lrr::DevIter;
 using lrr::EigDesc;
 using lrr::GemmDesc;
 using lrr::SvtDesc;
+using lrr::RefDesc;
 
 thread_local std::string g_last_error;
 
@@ -157,13 +158,21 @@ struct Buffers {
     double *res1, *res2, *eigscale;
     unsigned long long *r1max, *r2max;
     DevIter* it;
-    std::vector<double*> Bm, Wm, Wg, Bt, Pm, Rm, lam, h;
-    GemmDesc *g_gram, *g_w1, *g_w2, *g_P, *g_J, *g_MQ, *g_KV, *g_MtV, *g_U, *g_H, *g_Z, *g_spd, *g_KK;
+    std::vector<double*> Bm, Wm, Wg, Pm, Rm, lam, h, TX, SG, Eb, XE, Bq;
+    std::vector<int*> lo;
+    int *warm, *ref_run, *ref_unres, *ref_cont;
+    double *ref_eprev, *ref_scale;
+    unsigned long long* ref_emax;
+    GemmDesc *g_gram, *g_refT, *g_refSG, *g_refXE, *g_orthG, *g_Bq, *g_P, *g_J, *g_MQ, *g_KV, *g_MtV, *g_U, *g_H,
+        *g_Z, *g_spd, *g_KK;
+    RefDesc* ref;
     EigDesc* eig;
     SvtDesc* svt;
     // combine
     double *U, *H;
 };
+
+constexpr int kRefSteps = 8;   // cap on refinement steps per thresholding step
 
 int jacobi_bs(int maxl, int requested) {
     if (requested == 16 || requested == 32) return requested;
@@ -211,24 +220,41 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.r1max = a.take<unsigned long long>(t);
     b.r2max = a.take<unsigned long long>(t);
     b.it = a.take<DevIter>(1);
-    b.Bm.assign(t, nullptr); b.Wm.assign(t, nullptr); b.Wg.assign(t, nullptr);
-    b.Bt.assign(t, nullptr); b.Pm.assign(t, nullptr); b.Rm.assign(t, nullptr);
-    b.lam.assign(t, nullptr); b.h.assign(t, nullptr); b.prot.assign(t, nullptr);
+    for (auto* v : {&b.Bm, &b.Wm, &b.Wg, &b.Pm, &b.Rm, &b.lam, &b.h, &b.TX, &b.SG, &b.Eb, &b.XE, &b.Bq})
+        v->assign(t, nullptr);
+    b.prot.assign(t, nullptr);
+    b.lo.assign(t, nullptr);
     for (size_t i = 0; i < t; ++i) {
         const size_t L = p.L[i];
         b.Bm[i] = a.take<double>(L * L);
-        b.Wm[i] = a.take<double>(L * L);
+        b.TX[i] = a.take<double>(2 * L * L);
+        b.Wm[i] = b.TX[i] + L * L;          // eigenvector estimate X = right half of [T | X]
+        b.SG[i] = a.take<double>(2 * L * L);
+        b.Eb[i] = a.take<double>(L * L);
+        b.XE[i] = a.take<double>(L * L);
+        b.Bq[i] = a.take<double>(L * L);
         b.Wg[i] = a.take<double>(L * L);
-        b.Bt[i] = a.take<double>(L * L);
         b.Pm[i] = a.take<double>(L * L);
         b.Rm[i] = a.take<double>(L * 2 * p.bs);
         b.lam[i] = a.take<double>(L);
         b.h[i] = a.take<double>(L);
+        b.lo[i] = a.take<int>(L);
         b.prot[i] = a.take<int>(L / (2 * p.bs) + 1);
     }
+    b.warm = a.take<int>(t);
+    b.ref_run = a.take<int>(t);
+    b.ref_cont = a.take<int>(t);
+    b.ref_unres = a.take<int>(t);
+    b.ref_eprev = a.take<double>(t);
+    b.ref_scale = a.take<double>(t);
+    b.ref_emax = a.take<unsigned long long>(t);
     b.g_gram = a.take<GemmDesc>(t);
-    b.g_w1 = a.take<GemmDesc>(t);
-    b.g_w2 = a.take<GemmDesc>(t);
+    b.g_refT = a.take<GemmDesc>(t);
+    b.g_refSG = a.take<GemmDesc>(t);
+    b.g_refXE = a.take<GemmDesc>(t);
+    b.g_orthG = a.take<GemmDesc>(t);
+    b.g_Bq = a.take<GemmDesc>(t);
+    b.ref = a.take<RefDesc>(t);
     b.g_P = a.take<GemmDesc>(t);
     b.g_J = a.take<GemmDesc>(t);
     b.g_MQ = a.take<GemmDesc>(1);
@@ -356,22 +382,35 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     sched[0] = o.mu0;
     for (int k = 1; k < (int)sched.size(); ++k) sched[k] = std::min(o.rho * sched[k - 1], o.mu_max);
 
-    std::vector<GemmDesc> gram(t), w1(t), w2(t), gP(t), gJ(t);
+    std::vector<GemmDesc> gram(t), gRT(t), gRSG(t), gRXE(t), gOG(t), gBq(t), gP(t), gJ(t);
     std::vector<EigDesc> eig(t);
     std::vector<SvtDesc> svt(t);
+    std::vector<RefDesc> ref(t);
     for (int bb = 0; bb < t; ++bb) {
         const int l = p.boff[bb + 1] - p.boff[bb], L = p.L[bb];
+        const size_t LL = (size_t)L * L;
         double* Yb = b.Y + (size_t)p.boff[bb] * n;
         double* Jb = b.J + (size_t)p.boff[bb] * n;
         const int* run = b.svt_run + bb;
+        const int* rrun = b.ref_run + bb;
+        double* X = b.Wm[bb];
+        double* T = b.TX[bb];
         gram[bb] = GemmDesc{Yb, Yb, b.Bm[bb], l, l, n, n, n, L, 1.0, 0.0, run, nullptr};
-        w1[bb] = GemmDesc{b.Bm[bb], b.Wm[bb], b.Bt[bb], L, L, L, L, L, L, 1.0, 0.0, run, nullptr};
-        w2[bb] = GemmDesc{b.Wm[bb], b.Bt[bb], b.Bm[bb], L, L, L, L, L, L, 1.0, 0.0, run, nullptr};
-        gP[bb] = GemmDesc{b.Wg[bb], b.Wm[bb], b.Pm[bb], l, l, L, L, L, L, 1.0, 0.0, run, nullptr};
+        // refinement: T = B X, [S | G] = X^T [T | X], XE = X E
+        gRT[bb] = GemmDesc{b.Bm[bb], X, T, L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
+        gRSG[bb] = GemmDesc{X, T, b.SG[bb], L, 2 * L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
+        gRXE[bb] = GemmDesc{X, b.Eb[bb], b.XE[bb], L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
+        // orthogonalisation: G = X^T X;  Jacobi matrix Bq = X^T (B X)
+        gOG[bb] = GemmDesc{X, X, b.SG[bb] + LL, L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
+        gBq[bb] = GemmDesc{X, T, b.Bq[bb], L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
+        gP[bb] = GemmDesc{b.Wg[bb], X, b.Pm[bb], l, l, L, L, L, L, 1.0, 0.0, run, nullptr};
         gJ[bb] = GemmDesc{Yb, b.Pm[bb], Jb, n, l, l, n, L, n, 1.0, 0.0, run, nullptr};
-        eig[bb] = EigDesc{b.Bm[bb], b.Wm[bb], b.Rm[bb], b.lam[bb], L, l, run, b.eigst + 2 * bb,
-                          b.eigscale + bb, b.prot[bb]};
-        svt[bb] = SvtDesc{b.Bm[bb], b.Wm[bb], b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
+        eig[bb] = EigDesc{b.Bq[bb], X, b.Rm[bb], b.lam[bb], L, l, run, b.eigst + 2 * bb,
+                          b.eigscale + bb, b.prot[bb], b.lo[bb]};
+        svt[bb] = SvtDesc{b.Bq[bb], X, b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
+        ref[bb] = RefDesc{b.Bm[bb], X, b.SG[bb], b.Eb[bb], b.XE[bb], b.lam[bb], b.lo[bb], b.ref_scale + bb,
+                          b.ref_emax + bb, b.ref_unres + bb, b.ref_eprev + bb, b.ref_run + bb,
+                          b.ref_cont + bb, L, l, bb};
     }
     GemmDesc gMQ{pr.A, b.Q, b.T, m, c, n, (int)pr.lda, n, m, -1.0, 1.0, nullptr, nullptr};
     GemmDesc gKV{b.K, b.T, b.V, m, c, m, m, m, m, 1.0, 0.0, nullptr, nullptr};
@@ -385,8 +424,12 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     up(b.boff, p.boff.data(), sizeof(int) * (t + 1));
     up(b.mu_sched, sched.data(), sizeof(double) * sched.size());
     up(b.g_gram, gram.data(), sizeof(GemmDesc) * t);
-    up(b.g_w1, w1.data(), sizeof(GemmDesc) * t);
-    up(b.g_w2, w2.data(), sizeof(GemmDesc) * t);
+    up(b.g_refT, gRT.data(), sizeof(GemmDesc) * t);
+    up(b.g_refSG, gRSG.data(), sizeof(GemmDesc) * t);
+    up(b.g_refXE, gRXE.data(), sizeof(GemmDesc) * t);
+    up(b.g_orthG, gOG.data(), sizeof(GemmDesc) * t);
+    up(b.g_Bq, gBq.data(), sizeof(GemmDesc) * t);
+    up(b.ref, ref.data(), sizeof(RefDesc) * t);
     up(b.g_P, gP.data(), sizeof(GemmDesc) * t);
     up(b.g_J, gJ.data(), sizeof(GemmDesc) * t);
     up(b.g_MQ, &gMQ, sizeof(GemmDesc));
@@ -409,6 +452,8 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     for (int bb = 0; bb < t; ++bb) {
         const size_t L = p.L[bb];
         LRR_HIP(hipMemsetAsync(b.Bm[bb], 0, sizeof(double) * L * L, s));
+        LRR_HIP(hipMemsetAsync(b.TX[bb], 0, sizeof(double) * L * L, s));
+        LRR_HIP(hipMemsetAsync(b.Bq[bb], 0, sizeof(double) * L * L, s));
         LRR_HIP(hipMemsetAsync(b.Pm[bb], 0, sizeof(double) * L * L, s));
         LRR_HIP(hipMemsetAsync(b.h[bb], 0, sizeof(double) * L, s));
         lrr::launch_set_identity(b.Wm[bb], (int)L, s);
@@ -416,6 +461,7 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     std::vector<int> ones(t, 1);
     up(b.active, ones.data(), sizeof(int) * t);
     LRR_HIP(hipMemsetAsync(b.iters, 0, sizeof(int) * t, s));
+    LRR_HIP(hipMemsetAsync(b.warm, 0, sizeof(int) * t, s));
     LRR_HIP(hipMemsetAsync(b.rank, 0, sizeof(int) * t, s));
     LRR_HIP(hipMemsetAsync(b.r1max, 0, sizeof(unsigned long long) * t, s));
     LRR_HIP(hipMemsetAsync(b.r2max, 0, sizeof(unsigned long long) * t, s));
@@ -445,6 +491,7 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         if (prof.on) prof.flush();
     };
     std::vector<int> h_act(t, 1);
+    long long sweeps_total = 0;
     const double D = sizeof(double);
     int k = 0;
     for (k = 0; k < p.n_iter; ++k) {
@@ -459,31 +506,82 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         LRR_HIP(hipMemcpyAsync(h_run, b.svt_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
         sync();
         int any_run = 0;
-        double f_gram = 0, f_warm = 0, f_P = 0, f_J = 0;
+        double f_gram = 0, f_P = 0, f_J = 0;
         for (int bb = 0; bb < t; ++bb) {
             if (!h_run[bb]) continue;
             any_run = 1;
             const double l = p.boff[bb + 1] - p.boff[bb], L = p.L[bb];
             f_gram += 2.0 * l * l * n;
-            f_warm += 2.0 * L * L * L;
             f_P += 2.0 * l * l * L;
             f_J += 2.0 * n * l * l;
         }
         if (any_run) {
-            // Gram, warm start with the previous eigenvectors, Jacobi sweeps
+            // Gram matrix of each block that needs a decomposition
             timed("k_dgemm<true, false>", f_gram, 0.0, [&] {
                 lrr::launch_dgemm(b.g_gram, t, p.maxl, p.maxl, true, false, s);
             });
-            timed("k_dgemm<false, false>", f_warm, 0.0, [&] {
-                lrr::launch_dgemm(b.g_w1, t, p.maxL, p.maxL, false, false, s);
+            // Newton refinement of the previous iteration's eigenvectors
+            timed("k_ref_begin", 0.0, 0.0, [&] { lrr::launch_ref_begin(b.ref, t, b.svt_run, b.warm, s); });
+            std::vector<int> h_ref(t, 0);
+            LRR_HIP(hipMemcpyAsync(h_ref.data(), b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+            sync();
+            for (int step = 0; step < kRefSteps; ++step) {
+                double fl = 0.0;
+                int nref = 0;
+                for (int bb = 0; bb < t; ++bb)
+                    if (h_ref[bb]) { fl += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb]; ++nref; }
+                if (nref == 0) break;
+                timed("k_dgemm<false, false>", fl, 0.0, [&] {
+                    lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, s);
+                });
+                timed("k_dgemm<true, false>", 2.0 * fl, 0.0, [&] {
+                    lrr::launch_dgemm(b.g_refSG, t, p.maxL, 2 * p.maxL, true, false, s);
+                });
+                timed("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, s); });
+                timed("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, s); });
+                // decide before applying: only quadratically shrinking corrections
+                LRR_HIP(hipMemsetAsync(b.eig_any, 0, sizeof(int), s));
+                timed("k_ref_update", 0.0, 0.0, [&] {
+                    lrr::launch_ref_update(b.ref, t, step, kRefSteps, b.eig_any, s);
+                });
+                timed("k_dgemm<false, false>", fl, 0.0, [&] {
+                    lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, s);
+                });
+                timed("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, s); });
+                timed("k_ref_next", 0.0, 0.0, [&] { lrr::launch_ref_next(b.ref, t, s); });
+                LRR_HIP(hipMemcpyAsync(h_ref.data(), b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+                sync();
+            }
+            // two Newton-Schulz steps X <- X (I + (I - X^T X)/2); an estimate that is
+            // still far from orthonormal before the second step restarts from I
+            double f_L3 = 0.0;
+            for (int bb = 0; bb < t; ++bb)
+                if (h_run[bb]) f_L3 += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
+            timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run(b.ref, t, b.svt_run, s); });
+            for (int ns = 0; ns < 2; ++ns) {
+                timed("k_dgemm<true, false>", f_L3, 0.0, [&] {
+                    lrr::launch_dgemm(b.g_orthG, t, p.maxL, p.maxL, true, false, s);
+                });
+                timed("k_orth_E", 0.0, 0.0, [&] { lrr::launch_orth_E(b.ref, t, p.maxL, s); });
+                timed("k_dgemm<false, false>", f_L3, 0.0, [&] {
+                    lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, s);
+                });
+                timed("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, s); });
+            }
+            timed("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, s); });
+            timed("k_dgemm<false, false>", f_L3, 0.0, [&] {
+                lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, s);
             });
-            timed("k_dgemm<true, false>", f_warm, 0.0, [&] {
-                lrr::launch_dgemm(b.g_w2, t, p.maxL, p.maxL, true, false, s);
+            timed("k_dgemm<true, false>", f_L3, 0.0, [&] {
+                lrr::launch_dgemm(b.g_Bq, t, p.maxL, p.maxL, true, false, s);
             });
+            // block-Jacobi sweeps for the couplings the refinement left (the
+            // whole decomposition on a block's first thresholding step)
             timed("k_jacobi_init", 0.0, 0.0, [&] { lrr::launch_jacobi_init(b.eig, t, s); });
             const int nb = p.maxL / p.bs;
             for (int sw = 0; sw <= max_sweeps; ++sw) {
                 // converged matrices are closed here; the loop ends when none is open
+                timed("k_lo_rows", 0.0, 0.0, [&] { lrr::launch_lo_rows(b.eig, t, p.maxL, b.it, s); });
                 LRR_HIP(hipMemsetAsync(b.eig_any, 0, sizeof(int), s));
                 timed("k_jacobi_offcheck", 0.0, 0.0, [&] {
                     lrr::launch_jacobi_check(b.eig, t, p.maxL, b.eig_any, s);
@@ -491,8 +589,9 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
                 LRR_HIP(hipMemcpyAsync(h_misc, b.eig_any, sizeof(int), hipMemcpyDeviceToHost, s));
                 sync();
                 if (h_misc[0] == 0 || sw == max_sweeps) break;
+                ++sweeps_total;
                 for (int r = 0; r < nb - 1; ++r) {
-                    timed(p.bs == 16 ? "k_jacobi_pairs<16, 64>" : "k_jacobi_pairs<32, 256>", 0.0, 0.0, [&] {
+                    timed(p.bs == 16 ? "k_jacobi_pairs<16, 256>" : "k_jacobi_pairs<32, 256>", 0.0, 0.0, [&] {
                         lrr::launch_jacobi_pairs(b.eig, t, p.maxL, p.bs, r, s);
                     });
                     timed(p.bs == 16 ? "k_jacobi_apply<16>" : "k_jacobi_apply<32>", 0.0, 0.0, [&] {
@@ -507,6 +606,7 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
             timed("k_dgemm<false, false>", f_J, 0.0, [&] {
                 lrr::launch_dgemm(b.g_J, t, n, p.maxl, false, false, s);
             });
+            timed("k_mark_warm", 0.0, 0.0, [&] { lrr::launch_mark_warm(b.svt_run, b.warm, t, s); });
         }
         // Z-step (push-through) and E-step
         timed("k_form_QT", 0.0, (3.0 * n + 4.0 * m) * cact * D, [&] {

@@ -173,3 +173,40 @@ def test_bad_arguments_rejected():
         with pytest.raises(B.LRRError) as e:
             B.dfc_lrr_solve(Mt, lam, perm, off)
         assert e.value.status == B.LRR_EINVAL
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_full_size_workload_vs_oracle_fingerprint(cfg):
+    """Full-size workload in the benchmark's launch configuration against the
+    stored oracle fingerprint (written by tests/golden/make_golden.py from the
+    oracle only): Z w for two seeded probes and Z at 512 seeded positions within
+    1e-6 relative, per-block iteration counts within one, identical ranks and
+    identical segmentation labels."""
+    import json
+    import os
+    torch = need_gpu()
+    import oracle
+    from paper_1304_5583_amd.datagen import make_config
+    path = os.path.join(os.path.dirname(__file__), "golden", f"workload{cfg}_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("fingerprint not generated")
+    g = json.load(open(path))
+    p = make_config(cfg)
+    say(f"[workload {cfg} full] m={p.m} n={p.n} t={p.t}")
+    Zg, Sg, info = _gpu_dfc(p)
+    rng = np.random.default_rng(4242)
+    W = rng.standard_normal((p.n, 2))
+    idx = rng.integers(0, p.n, size=(512, 2))
+    ezw = rel((Zg @ W).T, np.array(g["Zw"]))
+    zat = np.array([Zg[i, j] for i, j in idx])
+    ezat = float(np.abs(zat - np.array(g["Z_at"])).max() / np.abs(Zg).max())
+    say(f"  relZw={ezw:.2e} maxZat={ezat:.2e} iters gpu={info.iters.tolist()} oracle={g['iters']}")
+    assert info.status == 0
+    assert ezw <= TOL_Z and ezat <= TOL_Z
+    assert abs(np.linalg.norm(Zg) - g["Z_fro"]) <= TOL_Z * g["Z_fro"]
+    assert abs(np.linalg.norm(Sg) - g["S_fro"]) <= TOL_Z * g["S_fro"]
+    assert np.all(np.abs(info.iters - np.array(g["iters"])) <= 1)
+    assert info.rank.tolist() == g["rank"]
+    with one_thread():
+        lab = oracle.segment(Zg, p.extra["k"], p.outliers)
+    assert lab.tolist() == g["labels"]
