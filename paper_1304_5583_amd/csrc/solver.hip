@@ -172,7 +172,7 @@ struct Buffers {
     double *U, *H;
 };
 
-constexpr int kRefSteps = 8;   // cap on refinement steps per thresholding step
+constexpr int kRefSteps = 10;  // cap on refinement steps per thresholding step
 
 int jacobi_bs(int maxl, int requested) {
     if (requested == 16 || requested == 32) return requested;

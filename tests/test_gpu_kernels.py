@@ -79,7 +79,7 @@ def test_syevj_batched_uneven(eig_block):
     lam, W, sweeps = B.lrr_diag_syevj(torch.from_numpy(Bs).cuda(), orders, eig_block=eig_block)
     lam, W = lam.cpu().numpy(), W.cpu().numpy()
     say(f"  sweeps={sweeps}")
-    assert sweeps < 30
+    assert sweeps < 40
     for i, l in enumerate(orders):
         Wi = W[i].T[:l, :l]               # column-major storage -> columns are eigenvectors
         li = lam[i, :l]
