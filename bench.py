@@ -52,21 +52,26 @@ def prof_enable(B, ctx, on):
 
 
 def roofline_of(row, traffic=None):
+    """Roofline entry of one kernel from its event-timed launches.
+
+    GEMMs are priced against the FP64 matrix peak; the Jacobi kernels, whose
+    FP64 operations are counted on the device, against the FP64 vector peak;
+    column kernels by their algorithmic HBM bytes."""
     avg_ms = row["ms"] / max(row["launches"], 1)
+    base = {"kernel": row["name"], "traffic": traffic, "avg_launch_us": round(avg_ms * 1e3, 2),
+            "launches": row["launches"]}
     if row["flops"] > 0:
         ach = row["flops"] / row["launches"] / (avg_ms * 1e-3) / 1e12
-        return {"kernel": row["name"], "bound": "mfma", "achieved": round(ach, 3),
-                "peak": PEAK["mfma_f64"], "unit": "TFLOP/s", "frac": round(ach / PEAK["mfma_f64"], 4),
-                "traffic": traffic, "avg_launch_us": round(avg_ms * 1e3, 2),
-                "launches": row["launches"]}
+        mfma = row["name"].startswith("k_dgemm")
+        peak = PEAK["mfma_f64"] if mfma else PEAK["alu_f64"]
+        return {**base, "bound": "mfma" if mfma else "alu", "achieved": round(ach, 4), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(ach / peak, 5)}
     if row["bytes"] > 0:
         ach = row["bytes"] / row["launches"] / (avg_ms * 1e-3) / 1e9
-        return {"kernel": row["name"], "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm"],
-                "unit": "GB/s", "frac": round(ach / PEAK["hbm"], 4), "traffic": traffic,
-                "avg_launch_us": round(avg_ms * 1e3, 2), "launches": row["launches"]}
-    return {"kernel": row["name"], "bound": "alu", "achieved": None, "peak": PEAK["alu_f64"],
-            "unit": "TFLOP/s", "frac": None, "traffic": traffic,
-            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": row["launches"]}
+        return {**base, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm"], "unit": "GB/s",
+                "frac": round(ach / PEAK["hbm"], 4)}
+    return {**base, "bound": "alu", "achieved": None, "peak": PEAK["alu_f64"], "unit": "TFLOP/s",
+            "frac": None}
 
 
 def oracle_error(p, Z, golden_path):
@@ -118,6 +123,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eig-block", type=int, default=0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 512 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the DFC blocks would "
@@ -161,8 +168,18 @@ def main():
     rows = prof_table(B, ctx)
     prof_enable(B, ctx, 0)
     print(f"bench: {args.steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
-    for r in rows[:12]:
-        print(f"bench:   {r['name']:28s} {r['ms']:10.2f} ms  {r['launches']:7d} launches", file=sys.stderr)
+    for r in rows[:14]:
+        rf = roofline_of(r)
+        rate = f"{rf['achieved']} {rf['unit']}" if rf["achieved"] is not None else "-"
+        print(f"bench:   {r['name']:28s} {r['ms']:10.2f} ms  {r['launches']:7d} launches  "
+              f"avg {rf['avg_launch_us']:8.1f} us  {rate}", file=sys.stderr)
+    if args.calib_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)   # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("bench: calibration copy 512 MiB x 3 done", file=sys.stderr)
 
     Z = Zt.cpu().numpy().T
     err = oracle_error(p, Z, os.path.join(ROOT, "tests", "golden", f"workload{args.workload}_oracle.json"))

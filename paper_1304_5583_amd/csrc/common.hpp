@@ -63,6 +63,7 @@ struct EigDesc {
     double* scale;      // max |diag| of B at the start, for the absolute floor
     int* prot;          // per pair of the current round: 1 if it rotated
     int* lo;            // per index: Gershgorin disc below tau^2 (pairs of two such are skipped)
+    unsigned long long* work;  // [0] FP64 operations of the pair solves, [1] of the tile updates
 };
 
 // Warm-started eigenvector refinement of one Gram matrix (see refsyev.hip).

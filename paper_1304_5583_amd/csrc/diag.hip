@@ -147,7 +147,7 @@ lrr_status lrr_diag_syevj(lrr_ctx* ctx, int count, const int* l, const double* B
         for (int i = 0; i < count; ++i)
             hd[i] = lrr::EigDesc{Bp + LL * i, Wp + LL * i, Rp + (size_t)L * 2 * bs * i, lamp + (size_t)L * i,
                                  L, l[i], run_on + i, st + 2 * i, scale + i, prot + npair * i,
-                                 lo + (size_t)L * i};
+                                 lo + (size_t)L * i, nullptr};
         LRR_HIP(hipMemcpy(dd, hd.data(), sizeof(lrr::EigDesc) * count, hipMemcpyHostToDevice));
         LRR_HIP(hipMemcpy(run_on, ones.data(), sizeof(int) * count, hipMemcpyHostToDevice));
         LRR_HIP(hipMemcpy(ls, l, sizeof(int) * count, hipMemcpyHostToDevice));

@@ -149,6 +149,11 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
         if (tid == 0) d.prot[P] = 0;
         return;
     }
+    if (tid == 0 && d.work) {
+        // per round: NP angles (~30 operations), (NP^2 - NP) 2x2 updates (24), PB*NP rotations of R (6)
+        const unsigned long long per_round = 30ull * NP + 24ull * (NP * NP - NP) + 6ull * PB * NP;
+        atomicAdd(&d.work[0], per_round * (PB - 1));
+    }
     double* Rg = d.R + (long)P * PB * PB;
     for (int idx = tid; idx < PB * PB; idx += NT) {
         const int i = idx % PB, j = idx / PB;
@@ -184,6 +189,7 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
         while (rem >= npair - P) { rem -= npair - P; ++P; }
         const int Q = P + rem;
         if (!d.prot[P] && !d.prot[Q]) return;
+        if (tid == 0 && d.work) atomicAdd(&d.work[1], 4ull * PB * PB * PB);   // two PB^3 products
         int p1, q1, p2, q2;
         rr_pair(nb, round, P, p1, q1);
         rr_pair(nb, round, Q, p2, q2);
@@ -221,6 +227,7 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
         const int w = item - ntri;
         const int P = w % npair, chunk = w / npair;
         if (!d.prot[P]) return;
+        if (tid == 0 && d.work) atomicAdd(&d.work[1], 2ull * RC * PB * PB);   // RC x PB times PB x PB
         int p1, q1;
         rr_pair(nb, round, P, p1, q1);
         const double* RgP = d.R + (long)P * PB * PB;

@@ -67,6 +67,7 @@ __global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs
     if (d.run[0] == 0) return;
     const long L = d.L;
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if ((long)blockIdx.x * 256 >= L * L) return;   // whole workgroup past the matrix
     double emax = 0.0;
     int unres = 0;
     if (idx < L * L) {
@@ -98,12 +99,22 @@ __global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs
         }
         d.E[idx] = e;
     }
+    // one atomic per workgroup (per-wave atomics on one address serialise)
     emax = wave_max(emax);
     int u = unres;
     for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
+    __shared__ double wmax[4];
+    __shared__ int wsum[4];
     if ((threadIdx.x & 63) == 0) {
-        if (emax > 0.0) atomic_max_nonneg(d.emax, emax);
-        if (u) atomicAdd(d.unres, u);
+        wmax[threadIdx.x >> 6] = emax;
+        wsum[threadIdx.x >> 6] = u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double e4 = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+        const int u4 = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (e4 > 0.0) atomic_max_nonneg(d.emax, e4);
+        if (u4) atomicAdd(d.unres, u4);
     }
 }
 
@@ -199,6 +210,7 @@ __global__ __launch_bounds__(256) void k_orth_E(const RefDesc* __restrict__ desc
     if (d.run[0] == 0) return;
     const long L = d.L;
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if ((long)blockIdx.x * 256 >= L * L) return;   // whole workgroup past the matrix
     double dev = 0.0;
     if (idx < L * L) {
         const int i = (int)(idx % L), j = (int)(idx / L);
@@ -208,7 +220,13 @@ __global__ __launch_bounds__(256) void k_orth_E(const RefDesc* __restrict__ desc
         dev = 2.0 * fabs(e);
     }
     dev = wave_max(dev);
-    if ((threadIdx.x & 63) == 0 && dev > 0.0) atomic_max_nonneg(d.emax, dev);
+    __shared__ double wmax[4];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = dev;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double d4 = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+        if (d4 > 0.0) atomic_max_nonneg(d.emax, d4);
+    }
 }
 
 // a matrix whose estimate lost orthogonality restarts from the identity

@@ -107,6 +107,7 @@ struct lrr_ctx {
     void* pinned = nullptr;      // small pinned host area for flag read-back
     size_t pinned_bytes = 0;
     int* dflag = nullptr;        // device flag for the input check
+    unsigned long long* dwork = nullptr;   // operation counters of the Jacobi kernels
 };
 
 namespace {
@@ -371,6 +372,8 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     const lrr_opts& o = pr.o;
     const size_t need = layout(p, nullptr, b, with_combine, true);
     ensure_ws(ctx, need);
+    if (!ctx->dwork) LRR_HIP(hipMalloc((void**)&ctx->dwork, 256));
+    LRR_HIP(hipMemsetAsync(ctx->dwork, 0, 2 * sizeof(unsigned long long), s));
     layout(p, static_cast<char*>(ctx->ws), b, with_combine, true);
     int* hp = static_cast<int*>(ensure_pinned(ctx, sizeof(int) * (4 * (size_t)t + 16) + sizeof(double) * 2 * t));
 
@@ -406,7 +409,7 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         gP[bb] = GemmDesc{b.Wg[bb], X, b.Pm[bb], l, l, L, L, L, L, 1.0, 0.0, run, nullptr};
         gJ[bb] = GemmDesc{Yb, b.Pm[bb], Jb, n, l, l, n, L, n, 1.0, 0.0, run, nullptr};
         eig[bb] = EigDesc{b.Bq[bb], X, b.Rm[bb], b.lam[bb], L, l, run, b.eigst + 2 * bb,
-                          b.eigscale + bb, b.prot[bb], b.lo[bb]};
+                          b.eigscale + bb, b.prot[bb], b.lo[bb], ctx->dwork};
         svt[bb] = SvtDesc{b.Bq[bb], X, b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
         ref[bb] = RefDesc{b.Bm[bb], X, b.SG[bb], b.Eb[bb], b.XE[bb], b.lam[bb], b.lo[bb], b.ref_scale + bb,
                           b.ref_emax + bb, b.ref_unres + bb, b.ref_eprev + bb, b.ref_run + bb,
@@ -637,6 +640,17 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
             if (h_misc[1] == 0) { ++k; break; }
         }
     }
+    if (prof.on) {
+        // operations counted on the device by the Jacobi kernels over this solve
+        unsigned long long hw[2] = {0, 0};
+        LRR_HIP(hipMemcpyAsync(hw, ctx->dwork, sizeof(hw), hipMemcpyDeviceToHost, s));
+        sync();
+        const std::string sfx = p.bs == 16 ? "<16" : "<32";
+        for (auto& e : prof.entries) {
+            if (e.name.rfind("k_jacobi_pairs" + sfx, 0) == 0) e.flops += (double)hw[0];
+            if (e.name.rfind("k_jacobi_apply" + sfx, 0) == 0) e.flops += (double)hw[1];
+        }
+    }
     res.batch_iters = k;
     res.iters.resize(t); res.rank.resize(t); res.res1.resize(t); res.res2.resize(t);
     std::vector<int> act(t);
@@ -737,6 +751,7 @@ void lrr_ctx_destroy(lrr_ctx* ctx) {
         ctx->prof.release();
         if (ctx->ws) (void)hipFree(ctx->ws);
         if (ctx->dflag) (void)hipFree(ctx->dflag);
+        if (ctx->dwork) (void)hipFree(ctx->dwork);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     }
     delete ctx;
