@@ -16,8 +16,9 @@
  * -------------------------------------
  *  - Matrices are column-major with an explicit leading dimension (ld >= rows).
  *    A column is one data point, so a row-major (n, m) tensor holds M^T.
- *  - Matrix arguments are DEVICE pointers on the ctx's device.  The element type
- *    is double for LRR_FP64 and float for LRR_FP32 / LRR_MIXED_BF16.
+ *  - Matrix arguments are DEVICE pointers on the ctx's device, element type
+ *    double in every precision form (the form selects the arithmetic of the
+ *    large products, not the storage).
  *    Index arrays (perm, offsets) and the info arrays are HOST pointers.
  *  - The caller owns every argument buffer.  The library owns its workspace,
  *    which lives in the ctx and is reused (and grown) across calls.
@@ -52,10 +53,19 @@ typedef enum {
     LRR_ENOTAPE = -5         /* backward called without a recorded forward         */
 } lrr_status;
 
+/* Precision forms.  FP64 state in every form.  The reduced forms run the two
+ * dictionary products of the Z-step (M Q and M^T V) and the last two products
+ * of the combine on the FP32 or BF16 matrix cores with FP32 accumulation; the
+ * Gram matrix, the reconstruction J = Y P, the Cholesky factorisation and its
+ * application, the eigen-decomposition and every residual norm stay FP64.  M Q
+ * is carried as a running sum of products of the changes of Q, re-formed in
+ * FP64 every 16 iterations, so that its rounding error shrinks as the
+ * iteration converges and the FP64 stopping tolerance stays reachable. */
 typedef enum {
-    LRR_FP64 = 0,            /* every product and factorisation in FP64            */
-    LRR_FP32 = 1,            /* FP32 storage and products, FP64 reductions          */
-    LRR_MIXED_BF16 = 2       /* BF16 split products on MFMA, FP64 solve/SVD/norms  */
+    LRR_FP64 = 0,            /* every product in FP64                              */
+    LRR_FP32 = 1,            /* operands rounded to FP32, FP32 MFMA                */
+    LRR_MIXED_BF16 = 2       /* operands split x = hi + lo in BF16, three BF16     */
+                             /* MFMA products (hi hi + hi lo + lo hi), FP32 accum. */
 } lrr_precision;
 
 typedef enum {

@@ -24,6 +24,16 @@ lrr_status lrr_diag_dgemm(lrr_ctx *ctx, int ta, int tb, int M, int N, int K, dou
                           const double *A, int lda, const double *B, int ldb, double beta,
                           double *C, int ldc, void *stream);
 
+/* The same product with the arithmetic of a precision form (lrr_precision):
+ * LRR_FP64 as lrr_diag_dgemm; LRR_FP32 rounds the operands to FP32 and
+ * accumulates in FP32 on the matrix cores; LRR_MIXED_BF16 splits each operand
+ * into two BF16 numbers (hi + lo) and sums hi*hi + hi*lo + lo*hi in FP32.
+ * Operands and result are FP64 in memory in every form; an unknown precision
+ * is LRR_EINVAL. */
+lrr_status lrr_diag_gemm(lrr_ctx *ctx, int precision, int ta, int tb, int M, int N, int K,
+                         double alpha, const double *A, int lda, const double *B, int ldb,
+                         double beta, double *C, int ldc, void *stream);
+
 /* Kinv = (I + A A^T)^{-1} for A (m x n): the factorisation the Z-step uses
  * (FP64 blocked Cholesky, then the explicit inverse of the factor).
  * Kinv is m x m with ld >= m. */

@@ -88,6 +88,8 @@ def load_library(path: str = LIB_PATH):
     lib.dfc_lrr_backward.restype = i
     lib.lrr_diag_dgemm.argtypes = [vp, i, i, i, i, i, d, vp, i, vp, i, d, vp, i, vp]
     lib.lrr_diag_dgemm.restype = i
+    lib.lrr_diag_gemm.argtypes = [vp, i, i, i, i, i, i, d, vp, i, vp, i, d, vp, i, vp]
+    lib.lrr_diag_gemm.restype = i
     lib.lrr_diag_spd_inverse.argtypes = [vp, i, i, vp, i, vp, i, vp]
     lib.lrr_diag_spd_inverse.restype = i
     lib.lrr_diag_syevj.argtypes = [vp, i, ip, vp, i, C.c_long, vp, i, vp, i, ip, vp]
@@ -271,6 +273,17 @@ def lrr_diag_dgemm(ta: bool, tb: bool, A, B, Cm, M: int, N: int, K: int, lda: in
                                        C.c_void_p(A.data_ptr()), lda, C.c_void_p(B.data_ptr()), ldb,
                                        float(beta), C.c_void_p(Cm.data_ptr()), ldc,
                                        _stream(torch, A.device))
+    _check(st, ctx, allow_nc=False)
+
+
+def lrr_diag_gemm(precision: int, ta: bool, tb: bool, A, B, Cm, M: int, N: int, K: int, lda: int, ldb: int,
+                  ldc: int, alpha: float = 1.0, beta: float = 0.0, ctx: Context | None = None):
+    import torch
+    ctx = ctx or get_context(A.device.index or 0)
+    st = load_library().lrr_diag_gemm(ctx.handle, int(precision), int(ta), int(tb), M, N, K, float(alpha),
+                                      C.c_void_p(A.data_ptr()), lda, C.c_void_p(B.data_ptr()), ldb,
+                                      float(beta), C.c_void_p(Cm.data_ptr()), ldc,
+                                      _stream(torch, A.device))
     _check(st, ctx, allow_nc=False)
 
 

@@ -11,6 +11,8 @@
 //   k_form_Y      Y = Z + Y2/mu, column sums of squares        (J-step input)
 //   k_block_fro   ||Y_b||_F per block; ||Y_b||_F <= tau => J_b = 0 exactly
 //   k_form_QT     Q = J - Y2/mu,  T = X - E + Y1/mu
+//                 (reduced-precision products: also dQ = Q - Q_prev, and
+//                 T -= M Q is carried as T -= sum of M dQ, see k_sub_cols)
 //   k_update_Z    Z = Q + M^T V,  R2 = Z - J,  Y2 += mu R2,  max|R2|
 //   k_estep       q = E + V (= X - M Z + Y1/mu), column l2 shrinkage by
 //                 lam/mu, R1 = q - Y1/mu - E,  Y1 += mu R1,  max|R1|
@@ -144,18 +146,38 @@ __global__ __launch_bounds__(256) void k_svt_weights(const SvtDesc* __restrict__
     for (int r = threadIdx.x; r < d.L; r += 256) d.Wg[o + r] = d.W[o + r] * g;
 }
 
+// With dQ set (difference form), dQ = Q_new - Q_old is written as well.
 __global__ __launch_bounds__(256) void k_form_QT(const double* __restrict__ J, const double* __restrict__ Y2,
-                                                  double* __restrict__ Q, int n, long ldn,
-                                                  const double* __restrict__ X, const double* __restrict__ E,
-                                                  const double* __restrict__ Y1, double* __restrict__ T,
-                                                  int m, long ldm, const int* __restrict__ colblk,
-                                                  const int* __restrict__ active, const DevIter* it) {
+                                                  double* __restrict__ Q, double* __restrict__ dQ, int n,
+                                                  long ldn, const double* __restrict__ X,
+                                                  const double* __restrict__ E, const double* __restrict__ Y1,
+                                                  double* __restrict__ T, int m, long ldm,
+                                                  const int* __restrict__ colblk, const int* __restrict__ active,
+                                                  const DevIter* it) {
     const int j = blockIdx.x;
     if (!active[colblk[j]]) return;
     const double mu = it->mu;
     const long on = j * ldn, om = j * ldm;
-    for (int i = threadIdx.x; i < n; i += 256) Q[on + i] = J[on + i] - Y2[on + i] / mu;
+    if (dQ) {
+        for (int i = threadIdx.x; i < n; i += 256) {
+            const double q = J[on + i] - Y2[on + i] / mu;
+            dQ[on + i] = q - Q[on + i];
+            Q[on + i] = q;
+        }
+    } else {
+        for (int i = threadIdx.x; i < n; i += 256) Q[on + i] = J[on + i] - Y2[on + i] / mu;
+    }
     for (int i = threadIdx.x; i < m; i += 256) T[om + i] = X[om + i] - E[om + i] + Y1[om + i] / mu;
+}
+
+// T -= A on the columns of active blocks
+__global__ __launch_bounds__(256) void k_sub_cols(double* __restrict__ T, const double* __restrict__ A, int m,
+                                                   long ld, const int* __restrict__ colblk,
+                                                   const int* __restrict__ active) {
+    const int j = blockIdx.x;
+    if (!active[colblk[j]]) return;
+    const long o = j * ld;
+    for (int i = threadIdx.x; i < m; i += 256) T[o + i] -= A[o + i];
 }
 
 __global__ __launch_bounds__(256) void k_update_Z(const double* __restrict__ Q, const double* __restrict__ MtV,
@@ -294,11 +316,15 @@ void launch_svt_weights(const SvtDesc* d, int count, int maxL, const DevIter* it
                         hipStream_t s) {
     hipLaunchKernelGGL(k_svt_weights, dim3(maxL, count), dim3(256), 0, s, d, it, bs);
 }
-void launch_form_QT(const double* J, const double* Y2, double* Q, int n, long ldn, const double* X,
-                    const double* E, const double* Y1, double* T, int m, long ldm, int ncols,
+void launch_form_QT(const double* J, const double* Y2, double* Q, double* dQ, int n, long ldn,
+                    const double* X, const double* E, const double* Y1, double* T, int m, long ldm, int ncols,
                     const int* colblk, const int* active, const DevIter* it, hipStream_t s) {
-    hipLaunchKernelGGL(k_form_QT, dim3(ncols), dim3(256), 0, s, J, Y2, Q, n, ldn, X, E, Y1, T, m, ldm,
+    hipLaunchKernelGGL(k_form_QT, dim3(ncols), dim3(256), 0, s, J, Y2, Q, dQ, n, ldn, X, E, Y1, T, m, ldm,
                        colblk, active, it);
+}
+void launch_sub_cols(double* T, const double* A, int m, long ld, int ncols, const int* colblk,
+                     const int* active, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub_cols, dim3(ncols), dim3(256), 0, s, T, A, m, ld, colblk, active);
 }
 void launch_update_Z(const double* Q, const double* MtV, const double* J, double* Z, double* Y2, int n,
                      long ld, int ncols, const int* colblk, BlockState bs, const DevIter* it,

@@ -28,6 +28,13 @@ struct GemmDesc {
     const int* colmap;
 };
 
+// Arithmetic of a product (operands and result are FP64 in memory in all modes).
+enum GemmMode {
+    kGemmFP64 = 0,     // FP64 matrix cores, FP64 accumulation
+    kGemmFP32 = 1,     // operands rounded to FP32, FP32 matrix cores and accumulation
+    kGemmBF16X3 = 2    // operands split into BF16 hi + lo, three BF16 products, FP32 accumulation
+};
+
 // Device-resident iteration state of the batched ALM loop.  Kernels read the
 // penalty of the current iteration from here, so a captured sequence of
 // launches replays correctly.

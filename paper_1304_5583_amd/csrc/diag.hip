@@ -58,7 +58,15 @@ extern "C" {
 
 lrr_status lrr_diag_dgemm(lrr_ctx* ctx, int ta, int tb, int M, int N, int K, double alpha, const double* A,
                           int lda, const double* B, int ldb, double beta, double* C, int ldc, void* stream) {
+    return lrr_diag_gemm(ctx, LRR_FP64, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+}
+
+lrr_status lrr_diag_gemm(lrr_ctx* ctx, int precision, int ta, int tb, int M, int N, int K, double alpha,
+                         const double* A, int lda, const double* B, int ldb, double beta, double* C, int ldc,
+                         void* stream) {
     if (!ctx) return lrr::ctx_fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
+    if (precision != LRR_FP64 && precision != LRR_FP32 && precision != LRR_MIXED_BF16)
+        return lrr::ctx_fail(ctx, LRR_EINVAL, "unknown precision");
     if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !C) return lrr::ctx_fail(ctx, LRR_EINVAL, "bad GEMM arguments");
     if (lda < (ta ? K : M) || ldb < (tb ? N : K) || ldc < M) return lrr::ctx_fail(ctx, LRR_EINVAL, "leading dimension too small");
     return run(ctx, [&]() -> lrr_status {
@@ -67,7 +75,9 @@ lrr_status lrr_diag_dgemm(lrr_ctx* ctx, int ta, int tb, int M, int N, int K, dou
         lrr::GemmDesc* d = nullptr;
         LRR_HIP(hipMalloc((void**)&d, sizeof(h)));
         LRR_HIP(hipMemcpy(d, &h, sizeof(h), hipMemcpyHostToDevice));
-        lrr::launch_dgemm(d, 1, M, N, ta != 0, tb != 0, s);
+        const int mode = precision == LRR_FP32 ? lrr::kGemmFP32
+                         : precision == LRR_MIXED_BF16 ? lrr::kGemmBF16X3 : lrr::kGemmFP64;
+        lrr::launch_xgemm(d, 1, M, N, ta != 0, tb != 0, mode, s);
         LRR_HIP(hipStreamSynchronize(s));
         LRR_HIP(hipFree(d));
         return LRR_OK;

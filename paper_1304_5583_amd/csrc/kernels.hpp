@@ -9,6 +9,11 @@ namespace lrr {
 void launch_dgemm(const GemmDesc* d_descs, int count, int maxM, int maxN, bool ta, bool tb,
                   hipStream_t stream);
 
+// xgemm.hip: the same contract with the arithmetic chosen by `mode` (GemmMode)
+void launch_xgemm(const GemmDesc* d_descs, int count, int maxM, int maxN, bool ta, bool tb, int mode,
+                  hipStream_t stream);
+const char* xgemm_name(int mode, bool ta, bool tb);
+
 // chol.hip
 int spd_inverse_desc_count(int m);
 void spd_inverse(double* K, int m, double* Lbuf, double* Linv, double* Dinv, double* Tbuf,
@@ -51,9 +56,11 @@ void launch_block_fro(const double* colsq, const int* boff, int t, BlockState bs
 void launch_zero_J(double* J, int n, long ld, int ncols, const int* colblk, BlockState bs, hipStream_t s);
 void launch_svt_weights(const SvtDesc* d, int count, int maxL, const DevIter* it, BlockState bs,
                         hipStream_t s);
-void launch_form_QT(const double* J, const double* Y2, double* Q, int n, long ldn, const double* X,
-                    const double* E, const double* Y1, double* T, int m, long ldm, int ncols,
+void launch_form_QT(const double* J, const double* Y2, double* Q, double* dQ, int n, long ldn,
+                    const double* X, const double* E, const double* Y1, double* T, int m, long ldm, int ncols,
                     const int* colblk, const int* active, const DevIter* it, hipStream_t s);
+void launch_sub_cols(double* T, const double* A, int m, long ld, int ncols, const int* colblk,
+                     const int* active, hipStream_t s);
 void launch_update_Z(const double* Q, const double* MtV, const double* J, double* Z, double* Y2, int n,
                      long ld, int ncols, const int* colblk, BlockState bs, const DevIter* it,
                      hipStream_t s);

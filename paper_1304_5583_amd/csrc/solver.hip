@@ -140,6 +140,15 @@ struct Arena {
     }
 };
 
+// Arithmetic (GemmMode) of each large product of an iteration, and whether the
+// product is carried in difference form (reduced precision only).
+struct ProductModes {
+    int MQ = 0;         // M Q of the Z-step
+    int MtV = 0;        // M^T V
+    int comb = 0;       // U1^T J and U1 H of the combine
+    bool dMQ = false;   // M Q carried as a sum of M dQ
+};
+
 struct Plan {
     int m = 0, n = 0, ncols = 0, t = 0;
     int bs = 16;                 // Jacobi block width
@@ -147,12 +156,14 @@ struct Plan {
     std::vector<int> L;          // padded Gram order per block
     int maxL = 0, maxl = 0;
     int n_iter = 0;
+    ProductModes pm;             // arithmetic of each large product
 };
 
 struct Buffers {
     double *X, *Z, *J, *Y2, *Y, *Q, *MtV, *E, *Y1, *T, *V;
     double *K, *Lb, *Linv, *Tb, *Dinv;
     double *colsq, *mu_sched;
+    double *Dn, *MQacc;          // difference form of M Q only
     int *colblk, *boff, *perm;
     int *active, *svt_run, *iters, *rank, *eigst, *n_active, *eig_any, *flag;
     std::vector<int*> prot;
@@ -164,7 +175,7 @@ struct Buffers {
     int *warm, *ref_run, *ref_unres, *ref_cont;
     double *ref_eprev, *ref_scale;
     unsigned long long* ref_emax;
-    GemmDesc *g_gram, *g_refT, *g_refSG, *g_refXE, *g_orthG, *g_Bq, *g_P, *g_J, *g_MQ, *g_KV, *g_MtV, *g_U, *g_H,
+    GemmDesc *g_gram, *g_refT, *g_refSG, *g_refXE, *g_orthG, *g_Bq, *g_P, *g_J, *g_MQ, *g_MQa, *g_KV, *g_MtV, *g_U, *g_H,
         *g_Z, *g_spd, *g_KK;
     RefDesc* ref;
     EigDesc* eig;
@@ -174,6 +185,7 @@ struct Buffers {
 };
 
 constexpr int kRefSteps = 10;  // cap on refinement steps per thresholding step
+constexpr int kAnchorEvery = 16;   // FP64 re-anchoring period of the carried product M Q
 
 int jacobi_bs(int maxl, int requested) {
     if (requested == 16 || requested == 32) return requested;
@@ -202,6 +214,8 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.Linv = a.take<double>(m * m);
     b.Tb = a.take<double>(m * m);
     b.Dinv = a.take<double>(m * 32);
+    b.Dn = p.pm.dMQ ? a.take<double>(n * c) : nullptr;
+    b.MQacc = p.pm.dMQ ? a.take<double>(m * c) : nullptr;
     b.colsq = a.take<double>(c);
     b.mu_sched = a.take<double>(p.n_iter + 2);
     b.colblk = a.take<int>(c);
@@ -258,9 +272,11 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.ref = a.take<RefDesc>(t);
     b.g_P = a.take<GemmDesc>(t);
     b.g_J = a.take<GemmDesc>(t);
-    b.g_MQ = a.take<GemmDesc>(1);
-    b.g_KV = a.take<GemmDesc>(1);
-    b.g_MtV = a.take<GemmDesc>(1);
+    b.g_MQ = a.take<GemmDesc>(t);
+    b.g_MQa = a.take<GemmDesc>(t);
+    b.g_KV = a.take<GemmDesc>(t);
+    b.g_MtV = a.take<GemmDesc>(t);
+
     b.g_U = a.take<GemmDesc>(1);
     b.g_H = a.take<GemmDesc>(1);
     b.g_Z = a.take<GemmDesc>(1);
@@ -276,6 +292,40 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     }
     (void)need_X;
     return a.off + 256;
+}
+
+// Arithmetic of the large products (Gram, reconstruction, dictionary
+// products, combine) for a precision form.  The Cholesky factorisation, the
+// eigen-decomposition of the Gram matrix and every residual stay in FP64.
+int gemm_mode(int precision) {
+    if (precision == LRR_FP32) return lrr::kGemmFP32;
+    if (precision == LRR_MIXED_BF16) return lrr::kGemmBF16X3;
+    return lrr::kGemmFP64;
+}
+
+// Products of each precision form.  Only the two dictionary products of the
+// Z-step (M Q and M^T V, 4 m n l of the iteration's flops) and the last two
+// products of the combine run in reduced precision.  FP64 stays where rounding
+// is amplified:
+//  - the Gram matrix Y^T Y, whose eigenvalues are thresholded at tau^2, far
+//    below FP32 resolution once mu is large;
+//  - the reconstruction J = Y P, whose rounding error lands in the directions
+//    the thresholding has just removed, where the multipliers accumulate it;
+//  - K^{-1} T, whose entries cancel heavily when M is ill-conditioned;
+//  - the combine basis U1 = Y W diag(1/sigma), which divides by sigma ~ tau;
+//  - the Cholesky factorisation, the eigen-decomposition and every residual.
+// M Q, whose operand does not vanish at convergence, is carried as a sum of
+// products of the changes of Q, so that its rounding error vanishes as the
+// iteration converges; M^T V acts on V -> 0 and is formed directly.
+ProductModes product_modes(int precision) {
+    ProductModes m;
+    const int g = gemm_mode(precision);
+    if (g == lrr::kGemmFP64) return m;
+    m.MQ = g;
+    m.MtV = g;
+    m.comb = g;
+    m.dMQ = true;
+    return m;
 }
 
 bool opts_valid(const lrr_opts& o, std::string& why) {
@@ -363,6 +413,7 @@ Plan make_plan(const Problem& pr) {
         p.maxL = std::max(p.maxL, p.L[b]);
     }
     p.n_iter = pr.o.fixed_iters > 0 ? pr.o.fixed_iters : pr.o.max_iter;
+    p.pm = product_modes(pr.o.precision);
     return p;
 }
 
@@ -386,6 +437,7 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     for (int k = 1; k < (int)sched.size(); ++k) sched[k] = std::min(o.rho * sched[k - 1], o.mu_max);
 
     std::vector<GemmDesc> gram(t), gRT(t), gRSG(t), gRXE(t), gOG(t), gBq(t), gP(t), gJ(t);
+    std::vector<GemmDesc> gMQ(t), gMQa(t), gKV(t), gMtV(t);
     std::vector<EigDesc> eig(t);
     std::vector<SvtDesc> svt(t);
     std::vector<RefDesc> ref(t);
@@ -408,6 +460,19 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         gBq[bb] = GemmDesc{X, T, b.Bq[bb], L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
         gP[bb] = GemmDesc{b.Wg[bb], X, b.Pm[bb], l, l, L, L, L, L, 1.0, 0.0, run, nullptr};
         gJ[bb] = GemmDesc{Yb, b.Pm[bb], Jb, n, l, l, n, L, n, 1.0, 0.0, run, nullptr};
+        const int* act = b.active + bb;
+        const size_t o_n = (size_t)p.boff[bb] * n, o_m = (size_t)p.boff[bb] * m;
+        if (p.pm.dMQ) {
+            gMQ[bb] = GemmDesc{pr.A, b.Dn + o_n, b.MQacc + o_m, m, l, n, (int)pr.lda, n, m, 1.0, 1.0, act,
+                               nullptr};
+            // re-anchoring: the carried product replaced by an FP64 M Q
+            gMQa[bb] = GemmDesc{pr.A, b.Q + o_n, b.MQacc + o_m, m, l, n, (int)pr.lda, n, m, 1.0, 0.0, act,
+                                nullptr};
+        }
+        else
+            gMQ[bb] = GemmDesc{pr.A, b.Q + o_n, b.T + o_m, m, l, n, (int)pr.lda, n, m, -1.0, 1.0, act, nullptr};
+        gKV[bb] = GemmDesc{b.K, b.T + o_m, b.V + o_m, m, l, m, m, m, m, 1.0, 0.0, act, nullptr};
+        gMtV[bb] = GemmDesc{pr.A, b.V + o_m, b.MtV + o_n, n, l, m, (int)pr.lda, m, n, 1.0, 0.0, act, nullptr};
         eig[bb] = EigDesc{b.Bq[bb], X, b.Rm[bb], b.lam[bb], L, l, run, b.eigst + 2 * bb,
                           b.eigscale + bb, b.prot[bb], b.lo[bb], ctx->dwork};
         svt[bb] = SvtDesc{b.Bq[bb], X, b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
@@ -415,9 +480,6 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
                           b.ref_emax + bb, b.ref_unres + bb, b.ref_eprev + bb, b.ref_run + bb,
                           b.ref_cont + bb, L, l, bb};
     }
-    GemmDesc gMQ{pr.A, b.Q, b.T, m, c, n, (int)pr.lda, n, m, -1.0, 1.0, nullptr, nullptr};
-    GemmDesc gKV{b.K, b.T, b.V, m, c, m, m, m, m, 1.0, 0.0, nullptr, nullptr};
-    GemmDesc gMtV{pr.A, b.V, b.MtV, n, c, m, (int)pr.lda, m, n, 1.0, 0.0, nullptr, nullptr};
     GemmDesc gKK{pr.A, pr.A, b.K, m, m, n, (int)pr.lda, (int)pr.lda, m, 1.0, 0.0, nullptr, nullptr};
 
     auto up = [&](void* dst, const void* src, size_t bytes) {
@@ -435,9 +497,11 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     up(b.ref, ref.data(), sizeof(RefDesc) * t);
     up(b.g_P, gP.data(), sizeof(GemmDesc) * t);
     up(b.g_J, gJ.data(), sizeof(GemmDesc) * t);
-    up(b.g_MQ, &gMQ, sizeof(GemmDesc));
-    up(b.g_KV, &gKV, sizeof(GemmDesc));
-    up(b.g_MtV, &gMtV, sizeof(GemmDesc));
+    up(b.g_MQ, gMQ.data(), sizeof(GemmDesc) * t);
+    up(b.g_MQa, gMQa.data(), sizeof(GemmDesc) * t);
+    up(b.g_KV, gKV.data(), sizeof(GemmDesc) * t);
+    up(b.g_MtV, gMtV.data(), sizeof(GemmDesc) * t);
+
     up(b.g_KK, &gKK, sizeof(GemmDesc));
     up(b.eig, eig.data(), sizeof(EigDesc) * t);
     up(b.svt, svt.data(), sizeof(SvtDesc) * t);
@@ -452,6 +516,11 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     LRR_HIP(hipMemsetAsync(b.Y2, 0, sizeof(double) * nc, s));
     LRR_HIP(hipMemsetAsync(b.E, 0, sizeof(double) * mc, s));
     LRR_HIP(hipMemsetAsync(b.Y1, 0, sizeof(double) * mc, s));
+    // the carried product M Q starts from Q = 0
+    if (p.pm.dMQ) {
+        LRR_HIP(hipMemsetAsync(b.Q, 0, sizeof(double) * nc, s));
+        LRR_HIP(hipMemsetAsync(b.MQacc, 0, sizeof(double) * mc, s));
+    }
     for (int bb = 0; bb < t; ++bb) {
         const size_t L = p.L[bb];
         LRR_HIP(hipMemsetAsync(b.Bm[bb], 0, sizeof(double) * L * L, s));
@@ -478,6 +547,7 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     lrr::spd_inverse(b.K, m, b.Lb, b.Linv, b.Dinv, b.Tb, b.g_spd, b.flag, s);
 
     BlockState bst{b.active, b.svt_run, b.iters, b.rank, b.res1, b.res2, b.r1max, b.r2max};
+    const ProductModes& pm = p.pm;
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
     const int check_every = o.check_every > 0 ? o.check_every : 1;
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
@@ -519,7 +589,8 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
             f_J += 2.0 * n * l * l;
         }
         if (any_run) {
-            // Gram matrix of each block that needs a decomposition
+            // Gram matrix of each block that needs a decomposition (FP64 in every
+            // precision form)
             timed("k_dgemm<true, false>", f_gram, 0.0, [&] {
                 lrr::launch_dgemm(b.g_gram, t, p.maxl, p.maxl, true, false, s);
             });
@@ -612,17 +683,31 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
             timed("k_mark_warm", 0.0, 0.0, [&] { lrr::launch_mark_warm(b.svt_run, b.warm, t, s); });
         }
         // Z-step (push-through) and E-step
-        timed("k_form_QT", 0.0, (3.0 * n + 4.0 * m) * cact * D, [&] {
-            lrr::launch_form_QT(b.J, b.Y2, b.Q, n, n, b.X, b.E, b.Y1, b.T, m, m, c, b.colblk, b.active, b.it, s);
+        timed("k_form_QT", 0.0, ((pm.dMQ ? 5.0 : 3.0) * n + 4.0 * m) * cact * D, [&] {
+            lrr::launch_form_QT(b.J, b.Y2, b.Q, pm.dMQ ? b.Dn : nullptr, n, n, b.X, b.E, b.Y1, b.T, m, m, c,
+                                b.colblk, b.active, b.it, s);
         });
-        timed("k_dgemm<false, false>", 2.0 * m * n * cact, 0.0, [&] {
-            lrr::launch_dgemm(b.g_MQ, 1, m, c, false, false, s);
-        });
+        // T = P - M Q; the difference form carries M Q as a sum of products M dQ
+        if (pm.dMQ && k > 0 && k % kAnchorEvery == 0) {
+            // every kAnchorEvery iterations the rounding carried in the sum of
+            // products is dropped: M Q is formed once in FP64
+            timed("k_dgemm<false, false>", 2.0 * m * n * cact, 0.0, [&] {
+                lrr::launch_dgemm(b.g_MQa, t, m, p.maxl, false, false, s);
+            });
+        } else {
+            timed(lrr::xgemm_name(pm.MQ, false, false), 2.0 * m * n * cact, 0.0, [&] {
+                lrr::launch_xgemm(b.g_MQ, t, m, p.maxl, false, false, pm.MQ, s);
+            });
+        }
+        if (pm.dMQ)
+            timed("k_sub_cols", 0.0, 3.0 * m * cact * D, [&] {
+                lrr::launch_sub_cols(b.T, b.MQacc, m, m, c, b.colblk, b.active, s);
+            });
         timed("k_dgemm<false, false>", 2.0 * m * m * cact, 0.0, [&] {
-            lrr::launch_dgemm(b.g_KV, 1, m, c, false, false, s);
+            lrr::launch_dgemm(b.g_KV, t, m, p.maxl, false, false, s);
         });
-        timed("k_dgemm<true, false>", 2.0 * n * m * cact, 0.0, [&] {
-            lrr::launch_dgemm(b.g_MtV, 1, n, c, true, false, s);
+        timed(lrr::xgemm_name(pm.MtV, true, false), 2.0 * n * m * cact, 0.0, [&] {
+            lrr::launch_xgemm(b.g_MtV, t, n, p.maxl, true, false, pm.MtV, s);
         });
         timed("k_update_Z", 0.0, 6.0 * n * cact * D, [&] {
             lrr::launch_update_Z(b.Q, b.MtV, b.J, b.Z, b.Y2, n, n, c, b.colblk, bst, b.it, s);
@@ -793,7 +878,6 @@ lrr_status lrr_solve(lrr_ctx* ctx, int m, int n, int l, const void* A, int lda, 
     if (opts) o = *opts; else lrr_opts_default(&o);
     std::string why;
     if (!opts_valid(o, why)) return fail(ctx, LRR_EINVAL, why);
-    if (o.precision != LRR_FP64) return fail(ctx, LRR_EINVAL, "this build solves in FP64 only");
     return guarded(ctx, [&]() -> lrr_status {
         LRR_HIP(hipSetDevice(ctx->device));
         hipStream_t s = static_cast<hipStream_t>(stream);
@@ -827,7 +911,6 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
     lrr_opts o;
     if (opts) o = *opts; else lrr_opts_default(&o);
     if (!opts_valid(o, why)) return fail(ctx, LRR_EINVAL, why);
-    if (o.precision != LRR_FP64) return fail(ctx, LRR_EINVAL, "this build solves in FP64 only");
     return guarded(ctx, [&]() -> lrr_status {
         LRR_HIP(hipSetDevice(ctx->device));
         hipStream_t s = static_cast<hipStream_t>(stream);
@@ -854,14 +937,15 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
             LRR_HIP(hipMemcpyAsync(b.g_H, &hd[1], sizeof(GemmDesc), hipMemcpyHostToDevice, s));
             LRR_HIP(hipMemcpyAsync(b.g_Z, &hd[2], sizeof(GemmDesc), hipMemcpyHostToDevice, s));
             LrrProf& prof = ctx->prof;
+            const int gm = p.pm.comb;
             prof.run(s, "k_dgemm<false, false>", 2.0 * n * L0 * l0, 0.0,
                      [&] { lrr::launch_dgemm(b.g_U, 1, n, L0, false, false, s); });
             prof.run(s, "k_scale_cols", 0.0, 2.0 * n * L0 * sizeof(double),
                      [&] { lrr::launch_scale_cols(b.U, n, n, L0, b.h[0], s); });
-            prof.run(s, "k_dgemm<true, false>", 2.0 * L0 * n * n, 0.0,
-                     [&] { lrr::launch_dgemm(b.g_H, 1, L0, n, true, false, s); });
-            prof.run(s, "k_dgemm<false, false>", 2.0 * n * n * L0, 0.0,
-                     [&] { lrr::launch_dgemm(b.g_Z, 1, n, n, false, false, s); });
+            prof.run(s, lrr::xgemm_name(gm, true, false), 2.0 * L0 * n * n, 0.0,
+                     [&] { lrr::launch_xgemm(b.g_H, 1, L0, n, true, false, gm, s); });
+            prof.run(s, lrr::xgemm_name(gm, false, false), 2.0 * n * n * L0, 0.0,
+                     [&] { lrr::launch_xgemm(b.g_Z, 1, n, n, false, false, gm, s); });
         }
         if (S) lrr::launch_scatter_cols(b.E, m, static_cast<double*>(S), lds, m, n, b.perm, s);
         LRR_HIP(hipStreamSynchronize(s));

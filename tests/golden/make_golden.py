@@ -7,6 +7,11 @@ positions, ||Z||_F, ||S||_F and the segmentation labels -- enough to check a
 full-size GPU solve element by element where the oracle can compute it once.
 
     python tests/golden/make_golden.py 2 [3 ...]
+    python tests/golden/make_golden.py 4b1      # block 1 of workload 4 only
+
+Workload 4 is too large for the oracle's DFC run (40 blocks, n = 20000); its
+fingerprint covers the first block, solved as one LRR problem with the whole M
+as dictionary (Eq. 2), in the push-through form of the Z-step.
 """
 from __future__ import annotations
 
@@ -31,8 +36,35 @@ def probes(n: int, seed: int = 4242):
     return W, idx
 
 
+def block_fingerprint(cfg: int, block: int):
+    p = make_config(cfg)
+    cols = p.perm[p.offsets[block - 1]:p.offsets[block]]
+    X = p.M[:, cols]
+    t0 = time.time()
+    r = oracle.lrr_alm(X, p.M, p.lam, oracle.ALMOptions(solve_form="pushthrough"))
+    el = time.time() - t0
+    rng = np.random.default_rng(4243)
+    W = rng.standard_normal((X.shape[1], 2))
+    idx = np.stack([rng.integers(0, p.n, 512), rng.integers(0, X.shape[1], 512)], axis=1)
+    out = {
+        "workload": p.name, "config": cfg, "block": block, "m": p.m, "n": p.n, "l": int(X.shape[1]),
+        "lam": p.lam, "oracle_seconds": el, "iters": r.iters, "rank": r.rank, "res1": r.res1,
+        "res2": r.res2, "Zw": (r.Z @ W).T.tolist(), "probe_idx": idx.tolist(),
+        "Z_at": [float(r.Z[i, j]) for i, j in idx], "Z_fro": float(np.linalg.norm(r.Z)),
+        "E_fro": float(np.linalg.norm(r.E)), "s_top": r.s[:8].tolist(),
+    }
+    path = os.path.join(HERE, f"workload{cfg}_block{block}_oracle.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print(f"workload {cfg} block {block}: {el:.1f}s iters={r.iters} rank={r.rank} -> {path}", flush=True)
+
+
 def main(cfgs):
     for cfg in cfgs:
+        if isinstance(cfg, str):
+            c, b = cfg.split("b")
+            block_fingerprint(int(c), int(b))
+            continue
         p = make_config(cfg)
         t0 = time.time()
         d = oracle.dfc_lrr(p.M, p.lam, p.perm, p.offsets)
@@ -49,6 +81,8 @@ def main(cfgs):
             "Z_at": [float(d.Z[i, j]) for i, j in idx],
             "Z_fro": float(np.linalg.norm(d.Z)), "S_fro": float(np.linalg.norm(d.S)),
             "labels": labels.tolist(),
+            # segmentation with the rank cut above the reduced forms' error level
+            "labels_rank_tol_1e-3": oracle.segment(d.Z, k, p.outliers, rank_tol=1e-3).tolist(),
             "accuracy": oracle.segmentation_accuracy(labels, p.labels),
         }
         path = os.path.join(HERE, f"workload{cfg}_oracle.json")
@@ -58,4 +92,4 @@ def main(cfgs):
 
 
 if __name__ == "__main__":
-    main([int(a) for a in sys.argv[1:]] or [2])
+    main([a if "b" in a else int(a) for a in sys.argv[1:]] or [2])

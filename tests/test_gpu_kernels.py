@@ -89,3 +89,45 @@ def test_syevj_batched_uneven(eig_block):
         assert np.abs((Wi * li) @ Wi.T - Mx).max() <= 1e-13 * nrm * l
         ref = np.linalg.eigvalsh(Mx)
         assert np.abs(np.sort(li) - ref).max() <= 1e-13 * nrm * l
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("M,N,K", [(64, 64, 16), (77, 131, 45), (200, 9, 300), (130, 70, 1001)])
+def test_reduced_precision_gemm_error_bound(prec, ta, tb, M, N, K):
+    """FP32 and BF16x3 products against FP64 with the a-priori elementwise bound.
+
+    FP32: each operand rounded once (u = 2^-24) and K-term FP32 accumulation,
+    |C - AB| <= (K + 2) u (|A||B|).  BF16x3: x = hi + lo represents x to 2^-18
+    relative, the dropped lo*lo term is below 2^-18 |a b|, and the 3K exact
+    BF16 products are summed in FP32: |C - AB| <= (3 2^-18 + (3K + 2) u)(|A||B|).
+    The product must also differ from the FP64 one (the reduced path ran)."""
+    torch = need_gpu()
+    from paper_1304_5583_amd import binding as B
+    say(f"gemm prec={prec} ta={ta} tb={tb} M={M} N={N} K={K}")
+    rng = np.random.default_rng(M * 7 + N * 3 + K + prec)
+    opA = rng.standard_normal((M, K)) * np.exp(rng.uniform(-3, 3, (M, 1)))
+    opB = rng.standard_normal((K, N))
+    C0 = rng.standard_normal((M, N))
+    A = opA.T if ta else opA
+    Bm = opB.T if tb else opB
+    dA, dB, dC = (torch.from_numpy(np.ascontiguousarray(X.T)).cuda() for X in (A, Bm, C0))
+    B.lrr_diag_gemm(prec, bool(ta), bool(tb), dA, dB, dC, M, N, K, A.shape[0], Bm.shape[0], M,
+                    alpha=0.75, beta=-0.5)
+    got = dC.cpu().numpy().T
+    ref = 0.75 * opA @ opB - 0.5 * C0
+    scale = 0.75 * np.abs(opA) @ np.abs(opB)
+    u = 2.0 ** -24
+    bound = (K + 2) * u if prec == 1 else 3 * 2.0 ** -18 + (3 * K + 2) * u
+    err = np.abs(got - ref)
+    assert np.all(err <= bound * scale + 1e-15 * np.abs(ref))
+    assert err.max() > 1e-13 * scale.max()
+
+
+def test_reduced_precision_gemm_rejects_unknown_precision():
+    torch = need_gpu()
+    from paper_1304_5583_amd import binding as B
+    X = torch.ones((4, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.LRRError) as e:
+        B.lrr_diag_gemm(7, False, False, X, X, X, 4, 4, 4, 4, 4, 4)
+    assert e.value.status == B.LRR_EINVAL
