@@ -266,11 +266,11 @@ __global__ __launch_bounds__(256) void k_check(BlockState bs, int t, DevIter* it
     }
 }
 
-__global__ void k_init_iter(DevIter* it, const double* __restrict__ mu_sched) {
-    it->k = 0;
-    it->pad = 0;
-    it->mu = mu_sched[0];
-    it->tau = 1.0 / mu_sched[0];
+__global__ void k_init_iter(DevIter* it, const double* __restrict__ mu_sched, int k, int full) {
+    it->k = k;
+    it->full = full;
+    it->mu = mu_sched[k];
+    it->tau = 1.0 / mu_sched[k];
 }
 
 __global__ __launch_bounds__(256) void k_scale_cols(double* __restrict__ U, long ld, int rows,
@@ -339,8 +339,8 @@ void launch_check(BlockState bs, int t, DevIter* it, const double* mu_sched, dou
                   int* n_active, hipStream_t s) {
     hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, s, bs, t, it, mu_sched, tol, fixed, n_active);
 }
-void launch_init_iter(DevIter* it, const double* mu_sched, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_iter, dim3(1), dim3(1), 0, s, it, mu_sched);
+void launch_init_iter(DevIter* it, const double* mu_sched, int k, hipStream_t s, int full) {
+    hipLaunchKernelGGL(k_init_iter, dim3(1), dim3(1), 0, s, it, mu_sched, k, full);
 }
 void launch_scale_cols(double* U, long ld, int rows, int ncols, const double* h, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_cols, dim3(ncols), dim3(256), 0, s, U, ld, rows, h);

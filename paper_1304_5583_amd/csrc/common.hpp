@@ -40,7 +40,8 @@ enum GemmMode {
 // launches replays correctly.
 struct DevIter {
     int k;          // iteration index (0-based) of the iteration being run
-    int pad;
+    int full;       // nonzero: the eigensolver resolves every eigenpair, also
+                    // those below tau^2 (reverse-mode replay needs them)
     double mu;      // penalty mu_k of this iteration
     double tau;     // 1 / mu_k, the singular-value threshold
 };
@@ -89,6 +90,18 @@ struct RefDesc {
     int* run;           // refinement step applied to this matrix
     int* cont;          // refinement continues after this step
     int L, l, block;
+};
+
+// One block's small matrices in the reverse sweep of the thresholding step.
+struct BwDesc {
+    const double* W;    // L x L eigenvectors of the Gram matrix (recorded)
+    const double* lam;  // L eigenvalues (recorded; zero beyond l)
+    double* Wg;         // L x L  W diag(g(lam))
+    double* S;          // L x L scratch
+    double* C;          // L x L scratch
+    double* N;          // L x L scratch
+    int L, l;
+    const int* run;     // thresholding step taken by this block in the recorded iteration
 };
 
 // Thresholding weights of one block after its Gram eigensolve.

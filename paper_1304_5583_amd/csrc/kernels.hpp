@@ -68,9 +68,30 @@ void launch_estep(double* E, const double* V, double* Y1, int m, long ld, int nc
                   const int* colblk, BlockState bs, const DevIter* it, hipStream_t s);
 void launch_check(BlockState bs, int t, DevIter* it, const double* mu_sched, double tol, int fixed,
                   int* n_active, hipStream_t s);
-void launch_init_iter(DevIter* it, const double* mu_sched, hipStream_t s);
+void launch_init_iter(DevIter* it, const double* mu_sched, int k, hipStream_t s, int full = 0);
 void launch_scale_cols(double* U, long ld, int rows, int ncols, const double* h, hipStream_t s);
 void launch_set_identity(double* W, int L, hipStream_t s);
 
+// adjoint.hip
+void launch_bw_estep(const double* E0, const double* V, double* cE, const double* cY1, double* Vb,
+                     double* lamcol, int m, long ld, int ncols, const int* colblk, const int* active,
+                     const DevIter* it, double lam, hipStream_t s);
+void launch_bw_zt(const double* cZ, const double* cY2, const double* cJ, double* Zt, double* Jt, int n, long ld,
+                  int ncols, const int* colblk, const int* active, const DevIter* it, hipStream_t s);
+void launch_bw_mid(const double* Qb, double* Jt, double* cY2, const double* Wb, double* Xbar, double* cE,
+                   double* cY1, int n, long ldn, int m, long ldm, int ncols, const int* colblk,
+                   const int* active, const DevIter* it, hipStream_t s);
+void launch_bw_final(const double* Yb, double* cY2, int n, long ld, int ncols, const int* colblk,
+                     const int* active, const DevIter* it, hipStream_t s);
+void launch_zero_norun(double* A, int n, long ld, int ncols, const int* colblk, const int* run, const int* active,
+                       hipStream_t s);
+void launch_bw_wg(const BwDesc* d, int count, int maxL, const DevIter* it, hipStream_t s);
+void launch_bw_sym(const BwDesc* d, int count, int maxL, hipStream_t s);
+void launch_bw_phi(const BwDesc* d, int count, int maxL, const DevIter* it, hipStream_t s);
+void launch_bw_rdiag(const double* W, const double* lam, double* Wr, int L, int l, const DevIter* it,
+                     hipStream_t s);
+void launch_scatter_add(const double* Xb, long ldx, double* Mb, long ldm, int m, int ncols, const int* perm,
+                        hipStream_t s);
+void launch_add_cols(double* A, long lda, const double* B, long ldb, int rows, int ncols, hipStream_t s);
 
 }  // namespace lrr

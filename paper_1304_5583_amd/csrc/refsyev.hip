@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void k_ref_rows(const RefDesc* __restrict__ de
         if (i < d.l) {
             const double sii = S[i + i * L];
             d.lam[i] = sii / G[i + i * L];
-            d.lo[i] = (sii + r < tau * tau * (1.0 - 1e-9)) ? 1 : 0;
+            d.lo[i] = (!it->full && sii + r < tau * tau * (1.0 - 1e-9)) ? 1 : 0;
         } else {
             d.lam[i] = 0.0;
             d.lo[i] = 1;
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_lo_rows(const EigDesc* __restrict__ des
     if (threadIdx.x == 0) {
         const double r = (red[0] + red[1]) + (red[2] + red[3]);
         const double tau = it->tau;
-        d.lo[i] = (i >= d.l) ? 1 : ((d.B[i + i * L] + r < tau * tau * (1.0 - 1e-9)) ? 1 : 0);
+        d.lo[i] = (i >= d.l) ? 1 : ((!it->full && d.B[i + i * L] + r < tau * tau * (1.0 - 1e-9)) ? 1 : 0);
     }
 }
 

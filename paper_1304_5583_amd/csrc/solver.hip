@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -98,6 +99,8 @@ struct LrrProf {
     }
 };
 
+struct Tape;   // record of the last dfc_lrr_solve for dfc_lrr_backward
+
 struct lrr_ctx {
     LrrProf prof;
     int device = 0;
@@ -108,6 +111,7 @@ struct lrr_ctx {
     size_t pinned_bytes = 0;
     int* dflag = nullptr;        // device flag for the input check
     unsigned long long* dwork = nullptr;   // operation counters of the Jacobi kernels
+    Tape* tape = nullptr;
 };
 
 namespace {
@@ -417,8 +421,9 @@ Plan make_plan(const Problem& pr) {
     return p;
 }
 
-// Run the batched ALM over all blocks; leaves the state in the workspace.
-Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t s, bool with_combine) {
+// Lay out the workspace, upload the descriptors, gather the observations,
+// zero the state and factor K = I + A A^T (once per solve).
+void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t s, bool with_combine) {
     const int m = p.m, n = p.n, c = p.ncols, t = p.t;
     const lrr_opts& o = pr.o;
     const size_t need = layout(p, nullptr, b, with_combine, true);
@@ -426,7 +431,7 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     if (!ctx->dwork) LRR_HIP(hipMalloc((void**)&ctx->dwork, 256));
     LRR_HIP(hipMemsetAsync(ctx->dwork, 0, 2 * sizeof(unsigned long long), s));
     layout(p, static_cast<char*>(ctx->ws), b, with_combine, true);
-    int* hp = static_cast<int*>(ensure_pinned(ctx, sizeof(int) * (4 * (size_t)t + 16) + sizeof(double) * 2 * t));
+    ensure_pinned(ctx, sizeof(int) * (4 * (size_t)t + 16) + sizeof(double) * 2 * t);
 
     // ---- host-side tables -------------------------------------------------
     std::vector<int> colblk(c);
@@ -539,13 +544,28 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     LRR_HIP(hipMemsetAsync(b.r2max, 0, sizeof(unsigned long long) * t, s));
     LRR_HIP(hipMemsetAsync(b.res1, 0, sizeof(double) * t, s));
     LRR_HIP(hipMemsetAsync(b.res2, 0, sizeof(double) * t, s));
-    lrr::launch_init_iter(b.it, b.mu_sched, s);
+    lrr::launch_init_iter(b.it, b.mu_sched, 0, s);
 
     // K = I + A A^T, then K^{-1} (FP64 Cholesky, once per solve)
     lrr::launch_dgemm(b.g_KK, 1, m, m, false, true, s);
     lrr::launch_add_identity(b.K, m, m, 1.0, s);
     lrr::spd_inverse(b.K, m, b.Lb, b.Linv, b.Dinv, b.Tb, b.g_spd, b.flag, s);
+}
 
+// Hooks of iterate_alm: called before iteration k starts and after it ends
+// (the stream is not synchronised in between).
+struct IterHooks {
+    std::function<void(int)> begin;
+    std::function<void(int)> end;
+};
+
+// Iterations [k0, k1) of the batched ALM over all blocks, from the state in the
+// workspace (DevIter must hold iteration k0); leaves the state there.
+Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t s, int k0, int k1,
+                   const IterHooks* hooks = nullptr) {
+    const int m = p.m, n = p.n, c = p.ncols, t = p.t;
+    const lrr_opts& o = pr.o;
+    int* hp = static_cast<int*>(ctx->pinned);
     BlockState bst{b.active, b.svt_run, b.iters, b.rank, b.res1, b.res2, b.r1max, b.r2max};
     const ProductModes& pm = p.pm;
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
@@ -566,8 +586,9 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     std::vector<int> h_act(t, 1);
     long long sweeps_total = 0;
     const double D = sizeof(double);
-    int k = 0;
-    for (k = 0; k < p.n_iter; ++k) {
+    int k = k0;
+    for (k = k0; k < k1; ++k) {
+        if (hooks && hooks->begin) hooks->begin(k);
         double cact = 0.0;   // columns of blocks still iterating
         for (int bb = 0; bb < t; ++bb) if (h_act[bb]) cact += p.boff[bb + 1] - p.boff[bb];
         // J-step input and the exact zero test
@@ -718,6 +739,7 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         timed("k_check", 0.0, 0.0, [&] {
             lrr::launch_check(bst, t, b.it, b.mu_sched, o.tol, fixed, b.n_active, s);
         });
+        if (hooks && hooks->end) hooks->end(k);
         if (!fixed && ((k + 1) % check_every == 0 || k + 1 == p.n_iter)) {
             LRR_HIP(hipMemcpyAsync(h_misc + 1, b.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
             LRR_HIP(hipMemcpyAsync(h_act.data(), b.active, sizeof(int) * t, hipMemcpyDeviceToHost, s));
@@ -736,7 +758,7 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
             if (e.name.rfind("k_jacobi_apply" + sfx, 0) == 0) e.flops += (double)hw[1];
         }
     }
-    res.batch_iters = k;
+    res.batch_iters = k - k0;
     res.iters.resize(t); res.rank.resize(t); res.res1.resize(t); res.res2.resize(t);
     std::vector<int> act(t);
     LRR_HIP(hipMemcpyAsync(res.iters.data(), b.iters, sizeof(int) * t, hipMemcpyDeviceToHost, s));
@@ -749,6 +771,13 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     if (!fixed)
         for (int bb = 0; bb < t; ++bb) if (act[bb]) res.converged = false;
     return res;
+}
+
+// Run the batched ALM over all blocks; leaves the state in the workspace.
+Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t s, bool with_combine,
+               const IterHooks* hooks = nullptr) {
+    setup_alm(ctx, pr, p, b, s, with_combine);
+    return iterate_alm(ctx, pr, p, b, s, 0, p.n_iter, hooks);
 }
 
 void fill_info(lrr_info* info, const Result& r, int combine_rank) {
@@ -785,6 +814,338 @@ bool input_nonfinite(lrr_ctx* ctx, const double* A, long lda, int m, int n, hipS
     return h[0] != 0;
 }
 
+}  // namespace
+
+// ============================================================================
+// Reverse mode (dfc_lrr_backward): the state of the unrolled iteration is
+// checkpointed every `every` iterations during the forward solve; the reverse
+// sweep replays one segment at a time from its checkpoint, recording every
+// state and the eigen-decomposition of every thresholding step of the segment,
+// and then runs the per-iteration reverse steps (adjoint.hip) backwards
+// through it.  dM collects both roles of M (dictionary and the blocks' columns).
+// ============================================================================
+struct Tape {
+    bool valid = false;
+    Problem pr{};
+    lrr_opts o{};
+    std::vector<int> perm, offsets;
+    Plan p;
+    Buffers b{};
+    int K = 0, every = 0, nck = 0, rank0 = 0;
+    // host tables
+    std::vector<size_t> woff, loff;     // per-block offsets into the packed L x L / L arrays
+    size_t sumLL = 0, sumL = 0;
+    // device memory
+    void* mem = nullptr;
+    size_t bytes = 0;
+    double *ck = nullptr, *ckW = nullptr;   // checkpoints: states and warm-start eigenvectors
+    int* ckWarm = nullptr;
+    double *seg = nullptr, *segW = nullptr, *segLam = nullptr;   // the replayed segment
+    int* segRun = nullptr;
+    double *cZ, *cE, *cY1, *cY2, *cJ, *Zt, *Jt, *Vb, *Wb, *Gm, *Mbar, *Xbar, *lamcol;
+    double *Sb, *Cb, *Nb;                   // per-block L x L scratch (packed)
+    double *B1, *A1, *A2, *F;               // combine reverse, n x l_1 each
+    lrr::BwDesc* bwd = nullptr;
+    GemmDesc* gd = nullptr;                 // backward GEMM descriptors
+    size_t state_doubles() const { return (size_t)(2 * p.n + 2 * p.m) * p.ncols; }
+};
+
+enum BwG {   // indices of the single (all-column) backward GEMM descriptors
+    G_MQ64, G_VBMZ, G_MBVZ, G_WB, G_ZTMW, G_MBWQ, G_G1, G_G2, G_MBGM,
+    G_H, G_CJ, G_R1, G_B1, G_A1, G_A2, G_F1, G_F2, G_FP, G_F3, G_COUNT
+};
+enum BwGb { GB_S, GB_C1, GB_C2, GB_T1, GB_T2, GB_Y1, GB_Y2, GB_COUNT };   // per block, t each
+
+static void tape_free(Tape* tp) {
+    if (tp && tp->mem) (void)hipFree(tp->mem);
+    if (tp) { tp->mem = nullptr; tp->bytes = 0; tp->valid = false; }
+}
+
+// Lay out (base == nullptr: size only) the tape memory of plan p.
+static size_t tape_layout(Tape& tp, char* base) {
+    Arena a{base, 0};
+    const Plan& p = tp.p;
+    const size_t n = p.n, m = p.m, c = p.ncols, t = p.t;
+    const size_t st = tp.state_doubles();
+    tp.ck = a.take<double>(st * tp.nck);
+    tp.ckW = a.take<double>(tp.sumLL * tp.nck);
+    tp.ckWarm = a.take<int>(t * tp.nck);
+    tp.seg = a.take<double>(st * tp.every);
+    tp.segW = a.take<double>(tp.sumLL * tp.every);
+    tp.segLam = a.take<double>(tp.sumL * tp.every);
+    tp.segRun = a.take<int>(t * tp.every);
+    tp.cZ = a.take<double>(n * c);
+    tp.cY2 = a.take<double>(n * c);
+    tp.cJ = a.take<double>(n * c);
+    tp.Zt = a.take<double>(n * c);
+    tp.Jt = a.take<double>(n * c);
+    tp.cE = a.take<double>(m * c);
+    tp.cY1 = a.take<double>(m * c);
+    tp.Vb = a.take<double>(m * c);
+    tp.Wb = a.take<double>(m * c);
+    tp.Xbar = a.take<double>(m * c);
+    tp.Gm = a.take<double>(m * m);
+    tp.Mbar = a.take<double>(m * n);
+    tp.lamcol = a.take<double>(c);
+    tp.Sb = a.take<double>(tp.sumLL);
+    tp.Cb = a.take<double>(tp.sumLL);
+    tp.Nb = a.take<double>(tp.sumLL);
+    const size_t l1 = p.boff[1];
+    tp.B1 = a.take<double>(std::max(n, (size_t)p.L[0]) * l1);   // also holds U1^T F (L_1 x l_1)
+    tp.A1 = a.take<double>(n * l1);
+    tp.A2 = a.take<double>(n * l1);
+    tp.F = a.take<double>(n * l1);
+    tp.bwd = a.take<lrr::BwDesc>(t);
+    tp.gd = a.take<GemmDesc>(G_COUNT + GB_COUNT * t);
+    return a.off + 256;
+}
+
+// Prepare the tape before a recorded forward solve (allocates its memory).
+static void tape_begin(lrr_ctx* ctx, const Problem& pr, const Plan& p) {
+    if (!ctx->tape) ctx->tape = new Tape();
+    Tape& tp = *ctx->tape;
+    tp.valid = false;
+    tp.o = pr.o;
+    tp.perm.assign(pr.perm, pr.perm + pr.ncols);
+    tp.offsets.assign(pr.offsets, pr.offsets + pr.t + 1);
+    tp.pr = pr;
+    tp.pr.o = tp.o;
+    tp.pr.perm = tp.perm.data();
+    tp.pr.offsets = tp.offsets.data();
+    tp.p = p;
+    tp.K = pr.o.fixed_iters;
+    tp.every = pr.o.checkpoint_every > 0 ? pr.o.checkpoint_every : 20;
+    tp.every = std::min(tp.every, tp.K);
+    tp.nck = (tp.K + tp.every - 1) / tp.every;
+    tp.woff.assign(p.t, 0);
+    tp.loff.assign(p.t, 0);
+    tp.sumLL = tp.sumL = 0;
+    for (int bb = 0; bb < p.t; ++bb) {
+        tp.woff[bb] = tp.sumLL;
+        tp.loff[bb] = tp.sumL;
+        tp.sumLL += (size_t)p.L[bb] * p.L[bb];
+        tp.sumL += p.L[bb];
+    }
+    const size_t need = tape_layout(tp, nullptr);
+    if (need > tp.bytes) {
+        tape_free(&tp);
+        if (hipMalloc(&tp.mem, need) != hipSuccess) {
+            tp.mem = nullptr;
+            throw std::bad_alloc();
+        }
+        tp.bytes = need;
+    }
+    tape_layout(tp, static_cast<char*>(tp.mem));
+}
+
+// Copy the ALM state (Z, E, Y1, Y2) between the workspace and a packed slot.
+static void state_copy(const Tape& tp, const Buffers& b, double* slot, bool save, hipStream_t s) {
+    const size_t nc = (size_t)tp.p.n * tp.p.ncols, mc = (size_t)tp.p.m * tp.p.ncols;
+    double* parts[4] = {b.Z, b.E, b.Y1, b.Y2};
+    const size_t len[4] = {nc, mc, mc, nc};
+    size_t off = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (save) LRR_HIP(hipMemcpyAsync(slot + off, parts[i], sizeof(double) * len[i], hipMemcpyDeviceToDevice, s));
+        else LRR_HIP(hipMemcpyAsync(parts[i], slot + off, sizeof(double) * len[i], hipMemcpyDeviceToDevice, s));
+        off += len[i];
+    }
+}
+
+static void eig_copy(const Tape& tp, const Buffers& b, double* W, bool save, hipStream_t s) {
+    for (int bb = 0; bb < tp.p.t; ++bb) {
+        const size_t LL = (size_t)tp.p.L[bb] * tp.p.L[bb];
+        if (save) LRR_HIP(hipMemcpyAsync(W + tp.woff[bb], b.Wm[bb], sizeof(double) * LL, hipMemcpyDeviceToDevice, s));
+        else LRR_HIP(hipMemcpyAsync(b.Wm[bb], W + tp.woff[bb], sizeof(double) * LL, hipMemcpyDeviceToDevice, s));
+    }
+}
+
+// Hooks of the recorded forward: checkpoint the state every `every` iterations.
+static IterHooks tape_forward_hooks(Tape& tp, Buffers& b, hipStream_t s) {
+    IterHooks h;
+    h.begin = [&tp, &b, s](int k) {
+        if (k % tp.every) return;
+        const int i = k / tp.every;
+        state_copy(tp, b, tp.ck + tp.state_doubles() * i, true, s);
+        eig_copy(tp, b, tp.ckW + tp.sumLL * i, true, s);
+        LRR_HIP(hipMemcpyAsync(tp.ckWarm + (size_t)tp.p.t * i, b.warm, sizeof(int) * tp.p.t,
+                               hipMemcpyDeviceToDevice, s));
+    };
+    return h;
+}
+
+// Upload the backward descriptors (after the recorded forward has laid out b).
+static void tape_descriptors(Tape& tp, hipStream_t s) {
+    const Plan& p = tp.p;
+    const Buffers& b = tp.b;
+    const int m = p.m, n = p.n, c = p.ncols, t = p.t;
+    const double* M = tp.pr.A;
+    const int lda = (int)tp.pr.lda;
+    std::vector<GemmDesc> g(G_COUNT + GB_COUNT * t, GemmDesc{});
+    g[G_MQ64] = GemmDesc{M, b.Q, b.T, m, c, n, lda, n, m, -1.0, 1.0, nullptr, nullptr};
+    g[G_VBMZ] = GemmDesc{M, tp.Zt, tp.Vb, m, c, n, lda, n, m, 1.0, 1.0, nullptr, nullptr};
+    g[G_MBVZ] = GemmDesc{b.V, tp.Zt, tp.Mbar, m, n, c, m, n, m, 1.0, 1.0, nullptr, nullptr};
+    g[G_WB] = GemmDesc{b.K, tp.Vb, tp.Wb, m, c, m, m, m, m, 1.0, 0.0, nullptr, nullptr};
+    g[G_ZTMW] = GemmDesc{M, tp.Wb, tp.Zt, n, c, m, lda, m, n, -1.0, 1.0, nullptr, nullptr};
+    g[G_MBWQ] = GemmDesc{tp.Wb, b.Q, tp.Mbar, m, n, c, m, n, m, -1.0, 1.0, nullptr, nullptr};
+    g[G_G1] = GemmDesc{tp.Wb, b.V, tp.Gm, m, m, c, m, m, m, 1.0, 0.0, nullptr, nullptr};
+    g[G_G2] = GemmDesc{b.V, tp.Wb, tp.Gm, m, m, c, m, m, m, 1.0, 1.0, nullptr, nullptr};
+    g[G_MBGM] = GemmDesc{tp.Gm, M, tp.Mbar, m, n, m, m, lda, m, -1.0, 1.0, nullptr, nullptr};
+    // combine reverse (block 1 spans the projection)
+    const int L0 = p.L[0], l1 = p.boff[1];
+    double* Gz = tp.Zt;          // dL/dZ with the columns in block order
+    g[G_H] = GemmDesc{b.U, Gz, b.H, L0, n, n, n, n, L0, 1.0, 0.0, nullptr, nullptr};
+    g[G_CJ] = GemmDesc{b.U, b.H, tp.cJ, n, n, L0, n, L0, n, 1.0, 0.0, nullptr, nullptr};
+    g[G_R1] = GemmDesc{tp.Sb, b.Wm[0], tp.Cb, l1, l1, L0, L0, L0, L0, 1.0, 0.0, nullptr, nullptr};
+    g[G_B1] = GemmDesc{b.Y, tp.Cb, tp.B1, n, l1, l1, n, L0, n, 1.0, 0.0, nullptr, nullptr};
+    g[G_A1] = GemmDesc{b.J, tp.B1, tp.A1, n, l1, n, n, n, n, 1.0, 0.0, nullptr, nullptr};
+    g[G_A2] = GemmDesc{Gz, tp.B1, tp.A2, n, l1, n, n, n, n, 1.0, 0.0, nullptr, nullptr};
+    g[G_F1] = GemmDesc{Gz, tp.A1, tp.F, n, l1, n, n, n, n, 1.0, 0.0, nullptr, nullptr};
+    g[G_F2] = GemmDesc{b.J, tp.A2, tp.F, n, l1, n, n, n, n, 1.0, 1.0, nullptr, nullptr};
+    g[G_FP] = GemmDesc{b.U, tp.F, tp.B1, L0, l1, n, n, n, L0, 1.0, 0.0, nullptr, nullptr};
+    g[G_F3] = GemmDesc{b.U, tp.B1, tp.F, n, l1, L0, n, L0, n, -1.0, 1.0, nullptr, nullptr};
+    std::vector<lrr::BwDesc> bw(t);
+    for (int bb = 0; bb < t; ++bb) {
+        const int l = p.boff[bb + 1] - p.boff[bb], L = p.L[bb];
+        const size_t on = (size_t)p.boff[bb] * n;
+        const int* run = b.svt_run + bb;
+        double *S = tp.Sb + tp.woff[bb], *C = tp.Cb + tp.woff[bb], *N = tp.Nb + tp.woff[bb];
+        const double* W = b.Wm[bb];
+        GemmDesc* gb = g.data() + G_COUNT;
+        gb[GB_S * t + bb] = GemmDesc{b.Y + on, tp.Jt + on, S, l, l, n, n, n, L, 1.0, 0.0, run, nullptr};
+        gb[GB_C1 * t + bb] = GemmDesc{C, W, S, L, L, L, L, L, L, 1.0, 0.0, run, nullptr};
+        gb[GB_C2 * t + bb] = GemmDesc{W, S, C, L, L, L, L, L, L, 1.0, 0.0, run, nullptr};
+        gb[GB_T1 * t + bb] = GemmDesc{W, N, S, L, L, L, L, L, L, 1.0, 0.0, run, nullptr};
+        gb[GB_T2 * t + bb] = GemmDesc{S, W, C, L, L, L, L, L, L, 1.0, 0.0, run, nullptr};
+        gb[GB_Y1 * t + bb] = GemmDesc{tp.Jt + on, b.Pm[bb], tp.cZ + on, n, l, l, n, L, n, 1.0, 0.0, run, nullptr};
+        gb[GB_Y2 * t + bb] = GemmDesc{b.Y + on, C, tp.cZ + on, n, l, l, n, L, n, 1.0, 1.0, run, nullptr};
+        bw[bb] = lrr::BwDesc{W, b.lam[bb], b.Wg[bb], S, C, N, L, l, run};
+    }
+    LRR_HIP(hipMemcpyAsync(tp.gd, g.data(), sizeof(GemmDesc) * g.size(), hipMemcpyHostToDevice, s));
+    LRR_HIP(hipMemcpyAsync(tp.bwd, bw.data(), sizeof(lrr::BwDesc) * t, hipMemcpyHostToDevice, s));
+    LRR_HIP(hipStreamSynchronize(s));   // host vectors go out of scope
+}
+
+// The reverse sweep.  Writes dM (m x n, ld lddm) if requested and returns dlambda.
+static double tape_backward(lrr_ctx* ctx, Tape& tp, const double* dZ, long lddz, double* dM, long lddm, hipStream_t s) {
+    Plan& p = tp.p;
+    Buffers& b = tp.b;
+    const int m = p.m, n = p.n, c = p.ncols, t = p.t;
+    const size_t nc = (size_t)n * c, mc = (size_t)m * c;
+    GemmDesc* gd = tp.gd;
+    GemmDesc* gb = tp.gd + G_COUNT;
+    const int* act = b.active;
+    auto zero = [&](double* x, size_t len) { LRR_HIP(hipMemsetAsync(x, 0, sizeof(double) * len, s)); };
+    zero(tp.cZ, nc); zero(tp.cY2, nc); zero(tp.cJ, nc);
+    zero(tp.cE, mc); zero(tp.cY1, mc); zero(tp.Xbar, mc);
+    zero(tp.Mbar, (size_t)m * n); zero(tp.lamcol, c);
+
+    // ---- combine reverse: Z = U1 U1^T [J_1 ... J_t], columns put back by perm
+    if (tp.rank0 > 0) {
+        const int L0 = p.L[0], l1 = p.boff[1];
+        lrr::launch_init_iter(b.it, b.mu_sched, tp.K - 1, s);
+        lrr::launch_gather_cols(dZ, lddz, tp.Zt, n, n, c, b.perm, s);
+        lrr::launch_dgemm(gd + G_H, 1, L0, n, true, false, s);        // H = U1^T dZp
+        lrr::launch_dgemm(gd + G_CJ, 1, n, n, false, false, s);       // dJcat = U1 H
+        lrr::launch_bw_rdiag(b.Wm[0], b.lam[0], tp.Sb, L0, l1, b.it, s);
+        lrr::launch_dgemm(gd + G_R1, 1, l1, l1, false, true, s);      // R1 = W diag(r) W^T
+        lrr::launch_dgemm(gd + G_B1, 1, n, l1, false, false, s);      // (J1^+)^T = Y1 R1
+        lrr::launch_dgemm(gd + G_A1, 1, n, l1, true, false, s);       // Jcat^T (J1^+)^T
+        lrr::launch_dgemm(gd + G_A2, 1, n, l1, true, false, s);       // dZp^T (J1^+)^T
+        lrr::launch_dgemm(gd + G_F1, 1, n, l1, false, false, s);      // F = (Pbar + Pbar^T)(J1^+)^T
+        lrr::launch_dgemm(gd + G_F2, 1, n, l1, false, false, s);
+        lrr::launch_dgemm(gd + G_FP, 1, L0, l1, true, false, s);      // F -= U1 (U1^T F)
+        lrr::launch_dgemm(gd + G_F3, 1, n, l1, false, false, s);
+        lrr::launch_add_cols(tp.cJ, n, tp.F, n, n, l1, s);
+    }
+
+    // ---- segments, last first
+    const size_t st = tp.state_doubles();
+    bool first = true;
+    for (int sg = tp.nck - 1; sg >= 0; --sg) {
+        const int k0 = sg * tp.every, k1 = std::min(tp.K, k0 + tp.every);
+        // replay [k0, k1) from the checkpoint, recording states and decompositions
+        state_copy(tp, b, tp.ck + st * sg, false, s);
+        eig_copy(tp, b, tp.ckW + tp.sumLL * sg, false, s);
+        LRR_HIP(hipMemcpyAsync(b.warm, tp.ckWarm + (size_t)t * sg, sizeof(int) * t, hipMemcpyDeviceToDevice, s));
+        if (p.pm.dMQ) { zero(b.Q, nc); zero(b.MQacc, mc); }
+        // the reverse step needs every eigenpair of each Gram matrix, also the
+        // ones below tau^2 that the forward solve leaves unresolved
+        lrr::launch_init_iter(b.it, b.mu_sched, k0, s, 1);
+        IterHooks h;
+        h.begin = [&](int k) { state_copy(tp, b, tp.seg + st * (k - k0), true, s); };
+        h.end = [&](int k) {
+            const int j = k - k0;
+            eig_copy(tp, b, tp.segW + tp.sumLL * j, true, s);
+            for (int bb = 0; bb < t; ++bb)
+                LRR_HIP(hipMemcpyAsync(tp.segLam + tp.sumL * j + tp.loff[bb], b.lam[bb], sizeof(double) * p.L[bb],
+                                       hipMemcpyDeviceToDevice, s));
+            LRR_HIP(hipMemcpyAsync(tp.segRun + (size_t)t * j, b.svt_run, sizeof(int) * t, hipMemcpyDeviceToDevice, s));
+        };
+        iterate_alm(ctx, tp.pr, p, b, s, k0, k1, &h);
+
+        for (int k = k1 - 1; k >= k0; --k) {
+            const int j = k - k0;
+            const double* Z0 = tp.seg + st * j;
+            const double* E0 = Z0 + nc;
+            const double* Y10 = E0 + mc;
+            const double* Y20 = Y10 + mc;
+            lrr::launch_init_iter(b.it, b.mu_sched, k, s);
+            eig_copy(tp, b, tp.segW + tp.sumLL * j, false, s);
+            for (int bb = 0; bb < t; ++bb)
+                LRR_HIP(hipMemcpyAsync(b.lam[bb], tp.segLam + tp.sumL * j + tp.loff[bb], sizeof(double) * p.L[bb],
+                                       hipMemcpyDeviceToDevice, s));
+            LRR_HIP(hipMemcpyAsync(b.svt_run, tp.segRun + (size_t)t * j, sizeof(int) * t, hipMemcpyDeviceToDevice, s));
+            // recompute the iteration's intermediates (FP64)
+            lrr::launch_form_Y(Z0, Y20, b.Y, b.colsq, n, n, c, b.colblk, act, b.it, s);
+            lrr::launch_bw_wg(tp.bwd, t, p.maxL, b.it, s);
+            lrr::launch_dgemm(b.g_P, t, p.maxl, p.maxl, false, true, s);
+            lrr::launch_dgemm(b.g_J, t, n, p.maxl, false, false, s);
+            lrr::launch_zero_norun(b.J, n, n, c, b.colblk, b.svt_run, act, s);
+            lrr::launch_form_QT(b.J, Y20, b.Q, nullptr, n, n, b.X, E0, Y10, b.T, m, m, c, b.colblk, act, b.it, s);
+            lrr::launch_dgemm(gd + G_MQ64, 1, m, c, false, false, s);
+            lrr::launch_dgemm(b.g_KV, t, m, p.maxl, false, false, s);
+            // reverse step
+            lrr::launch_bw_estep(E0, b.V, tp.cE, tp.cY1, tp.Vb, tp.lamcol, m, m, c, b.colblk, act, b.it,
+                                 tp.pr.lam, s);
+            lrr::launch_bw_zt(tp.cZ, tp.cY2, first ? tp.cJ : nullptr, tp.Zt, tp.Jt, n, n, c, b.colblk, act, b.it, s);
+            first = false;
+            lrr::launch_dgemm(gd + G_VBMZ, 1, m, c, false, false, s);     // Vbar += M Zt
+            lrr::launch_dgemm(gd + G_MBVZ, 1, m, n, false, true, s);      // dM += V Zt^T
+            lrr::launch_dgemm(gd + G_WB, 1, m, c, false, false, s);       // Wb = K^{-1} Vbar
+            lrr::launch_dgemm(gd + G_ZTMW, 1, n, c, true, false, s);      // Qbar = Zt - M^T Wb
+            lrr::launch_dgemm(gd + G_MBWQ, 1, m, n, false, true, s);      // dM -= Wb Q^T
+            lrr::launch_dgemm(gd + G_G1, 1, m, m, false, true, s);        // G = Wb V^T + V Wb^T
+            lrr::launch_dgemm(gd + G_G2, 1, m, m, false, true, s);
+            lrr::launch_dgemm(gd + G_MBGM, 1, m, n, false, false, s);     // dM -= G M
+            lrr::launch_bw_mid(tp.Zt, tp.Jt, tp.cY2, tp.Wb, tp.Xbar, tp.cE, tp.cY1, n, n, m, m, c, b.colblk, act,
+                               b.it, s);
+            // thresholding reverse per block
+            lrr::launch_dgemm(gb + GB_S * t, t, p.maxl, p.maxl, true, false, s);
+            lrr::launch_bw_sym(tp.bwd, t, p.maxL, s);
+            lrr::launch_dgemm(gb + GB_C1 * t, t, p.maxL, p.maxL, false, false, s);
+            lrr::launch_dgemm(gb + GB_C2 * t, t, p.maxL, p.maxL, true, false, s);
+            lrr::launch_bw_phi(tp.bwd, t, p.maxL, b.it, s);
+            lrr::launch_dgemm(gb + GB_T1 * t, t, p.maxL, p.maxL, false, false, s);
+            lrr::launch_dgemm(gb + GB_T2 * t, t, p.maxL, p.maxL, false, true, s);
+            lrr::launch_dgemm(gb + GB_Y1 * t, t, n, p.maxl, false, false, s);
+            lrr::launch_dgemm(gb + GB_Y2 * t, t, n, p.maxl, false, false, s);
+            lrr::launch_zero_norun(tp.cZ, n, n, c, b.colblk, b.svt_run, act, s);
+            lrr::launch_bw_final(tp.cZ, tp.cY2, n, n, c, b.colblk, act, b.it, s);
+        }
+    }
+    // the blocks' columns of M, then the outputs
+    lrr::launch_scatter_add(tp.Xbar, m, tp.Mbar, m, m, c, b.perm, s);
+    if (dM) lrr::launch_copy_cols(tp.Mbar, m, dM, lddm, m, n, s);
+    std::vector<double> lc(c);
+    LRR_HIP(hipMemcpyAsync(lc.data(), tp.lamcol, sizeof(double) * c, hipMemcpyDeviceToHost, s));
+    LRR_HIP(hipStreamSynchronize(s));
+    double dl = 0.0;
+    for (int j = 0; j < c; ++j) dl += lc[j];
+    tp.valid = false;   // the replay overwrote the forward's final state
+    return dl;
+}
+
+namespace {
 }  // namespace
 
 namespace lrr {
@@ -838,7 +1199,9 @@ void lrr_ctx_destroy(lrr_ctx* ctx) {
         if (ctx->dflag) (void)hipFree(ctx->dflag);
         if (ctx->dwork) (void)hipFree(ctx->dwork);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        tape_free(ctx->tape);
     }
+    delete ctx->tape;
     delete ctx;
 }
 
@@ -878,6 +1241,7 @@ lrr_status lrr_solve(lrr_ctx* ctx, int m, int n, int l, const void* A, int lda, 
     if (opts) o = *opts; else lrr_opts_default(&o);
     std::string why;
     if (!opts_valid(o, why)) return fail(ctx, LRR_EINVAL, why);
+    if (ctx->tape) ctx->tape->valid = false;
     return guarded(ctx, [&]() -> lrr_status {
         LRR_HIP(hipSetDevice(ctx->device));
         hipStream_t s = static_cast<hipStream_t>(stream);
@@ -911,6 +1275,9 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
     lrr_opts o;
     if (opts) o = *opts; else lrr_opts_default(&o);
     if (!opts_valid(o, why)) return fail(ctx, LRR_EINVAL, why);
+    if (ctx->tape) ctx->tape->valid = false;
+    if (o.save_for_backward && o.fixed_iters <= 0)
+        return fail(ctx, LRR_EINVAL, "save_for_backward needs fixed_iters > 0 (the unrolled map)");
     return guarded(ctx, [&]() -> lrr_status {
         LRR_HIP(hipSetDevice(ctx->device));
         hipStream_t s = static_cast<hipStream_t>(stream);
@@ -919,7 +1286,12 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
         Problem pr{m, n, n, t, static_cast<const double*>(M), ldm, nullptr, 0, perm, offsets, lambda, o};
         Plan p = make_plan(pr);
         Buffers b{};
-        Result r = run_alm(ctx, pr, p, b, s, true);
+        IterHooks hooks;
+        if (o.save_for_backward) {
+            tape_begin(ctx, pr, p);
+            hooks = tape_forward_hooks(*ctx->tape, b, s);
+        }
+        Result r = run_alm(ctx, pr, p, b, s, true, o.save_for_backward ? &hooks : nullptr);
         // C step: U1 = Y_1 W_1 diag(h_1) spans the column space of J_1 (zero
         // columns where sigma <= tau); Z = U1 (U1^T [J_1 ... J_t]), columns put back.
         const int L0 = p.L[0], l0 = p.boff[1];
@@ -948,6 +1320,13 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
                      [&] { lrr::launch_xgemm(b.g_Z, 1, n, n, false, false, gm, s); });
         }
         if (S) lrr::launch_scatter_cols(b.E, m, static_cast<double*>(S), lds, m, n, b.perm, s);
+        if (o.save_for_backward) {
+            Tape& tp = *ctx->tape;
+            tp.b = b;
+            tp.rank0 = r1;
+            tape_descriptors(tp, s);
+            tp.valid = true;
+        }
         LRR_HIP(hipStreamSynchronize(s));
         if (ctx->prof.on) ctx->prof.flush();
         fill_info(info, r, r1);
@@ -979,9 +1358,18 @@ lrr_status lrr_prof_entry(const lrr_ctx* ctx, int idx, const char** name, double
 
 lrr_status dfc_lrr_backward(lrr_ctx* ctx, const void* dZ, int lddz, double* dlambda, void* dM, int lddm,
                             void* stream) {
-    (void)dZ; (void)lddz; (void)dlambda; (void)dM; (void)lddm; (void)stream;
     if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
-    return fail(ctx, LRR_ENOTAPE, "no recorded forward pass on this context");
+    if (!ctx->tape || !ctx->tape->valid)
+        return fail(ctx, LRR_ENOTAPE, "no recorded forward pass on this context");
+    Tape& tp = *ctx->tape;
+    if (!dZ || !dlambda) return fail(ctx, LRR_EINVAL, "dZ and dlambda must not be NULL");
+    if (lddz < tp.p.n || (dM && lddm < tp.p.m)) return fail(ctx, LRR_EINVAL, "leading dimension too small");
+    return guarded(ctx, [&]() -> lrr_status {
+        LRR_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        *dlambda = tape_backward(ctx, tp, static_cast<const double*>(dZ), lddz, static_cast<double*>(dM), lddm, s);
+        return LRR_OK;
+    });
 }
 
 }  // extern "C"

@@ -8,6 +8,7 @@ full-size GPU solve element by element where the oracle can compute it once.
 
     python tests/golden/make_golden.py 2 [3 ...]
     python tests/golden/make_golden.py 4b1      # block 1 of workload 4 only
+    python tests/golden/make_golden.py 5g       # workload 5: the oracle gradient
 
 Workload 4 is too large for the oracle's DFC run (40 blocks, n = 20000); its
 fingerprint covers the first block, solved as one LRR problem with the whole M
@@ -59,8 +60,43 @@ def block_fingerprint(cfg: int, block: int):
     print(f"workload {cfg} block {block}: {el:.1f}s iters={r.iters} rank={r.rank} -> {path}", flush=True)
 
 
+def gradient_fingerprint(cfg: int):
+    """Unrolled DFC-LRR (fixed iteration count) and the oracle's reverse sweep for
+    L = ||W o |Z| ||_F^2: dL/dlambda, ||dL/dM||_F, dL/dM at 512 seeded positions
+    and <dL/dM, D> for two seeded directions D."""
+    from oracle import adjoint as adj
+    p = make_config(cfg)
+    W = p.extra["W"]
+    opts = oracle.ALMOptions(fixed_iters=p.extra["fixed_iters"])
+    t0 = time.time()
+    tapes = adj.dfc_forward(p.M, p.lam, p.perm, p.offsets, opts)
+    Z = adj.dfc_combine(tapes, p.perm)[0]
+    L = float(np.sum((W * Z) ** 2))
+    Mbar, lambar = adj.dfc_backward(tapes, p.perm, p.offsets, 2.0 * W ** 2 * Z)
+    el = time.time() - t0
+    rng = np.random.default_rng(4244)
+    idx = np.stack([rng.integers(0, p.m, 512), rng.integers(0, p.n, 512)], axis=1)
+    D = rng.standard_normal((2, p.m, p.n))
+    Wp, _ = probes(p.n)
+    out = {
+        "workload": p.name, "config": cfg, "m": p.m, "n": p.n, "t": p.t, "lam": p.lam,
+        "fixed_iters": opts.fixed_iters, "oracle_seconds": el, "loss": L, "dlam": lambar,
+        "dM_fro": float(np.linalg.norm(Mbar)), "probe_idx": idx.tolist(),
+        "dM_at": [float(Mbar[i, j]) for i, j in idx],
+        "dM_dir": [float(np.sum(Mbar * D[i])) for i in range(2)],
+        "Zw": (Z @ Wp).T.tolist(), "Z_fro": float(np.linalg.norm(Z)),
+    }
+    path = os.path.join(HERE, f"workload{cfg}_gradient_oracle.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print(f"workload {cfg} gradient: {el:.1f}s L={L:.6e} dlam={lambar:.6e} -> {path}", flush=True)
+
+
 def main(cfgs):
     for cfg in cfgs:
+        if cfg == "5g":
+            gradient_fingerprint(5)
+            continue
         if isinstance(cfg, str):
             c, b = cfg.split("b")
             block_fingerprint(int(c), int(b))
@@ -92,4 +128,4 @@ def main(cfgs):
 
 
 if __name__ == "__main__":
-    main([a if "b" in a else int(a) for a in sys.argv[1:]] or [2])
+    main([a if ("b" in a or "g" in a) else int(a) for a in sys.argv[1:]] or [2])

@@ -1,0 +1,115 @@
+"""Pins of the oracle's reverse-mode gradient against central finite differences
+of the forward map it differentiates (h = 1e-6, FP64), step by step and for the
+whole unrolled DFC-LRR map with the loss L = ||W o |Z| ||_F^2."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import adjoint as adj
+from paper_1304_5583_amd.datagen import small_problem
+
+H = 1e-6
+
+
+def _fd(f, x, d):
+    return (f(x + H * d) - f(x - H * d)) / (2 * H)
+
+
+@pytest.mark.parametrize("n,l,rank", [(12, 7, 7), (15, 9, 4), (8, 8, 8)])
+def test_svt_backward_matches_finite_differences(n, l, rank):
+    rng = np.random.default_rng(n + l + rank)
+    Y = rng.standard_normal((n, rank)) @ rng.standard_normal((rank, l))
+    s = np.linalg.svd(Y, compute_uv=False)
+    tau = 0.5 * (s[1] + s[2])                     # a threshold between singular values
+    G = rng.standard_normal((n, l))
+    Yb = adj.svt_backward(G, Y, tau)
+    for t in range(4):
+        D = rng.standard_normal((n, l))
+        fd = _fd(lambda y: float(np.sum(G * adj.svt_full(y, tau)[0])), Y, D)
+        assert abs(fd - float(np.sum(Yb * D))) <= 1e-6 * (1 + abs(fd))
+
+
+def test_svt_backward_zero_when_all_below_threshold():
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((9, 5))
+    tau = 1.01 * np.linalg.norm(Y, 2)
+    assert np.all(adj.svt_backward(rng.standard_normal((9, 5)), Y, tau) == 0.0)
+
+
+def test_shrink_backward_matches_finite_differences():
+    rng = np.random.default_rng(5)
+    q = rng.standard_normal((6, 10)) * rng.uniform(0.1, 2.0, 10)
+    theta = float(np.median(np.linalg.norm(q, axis=0)))   # half the columns shrink to zero
+    eb = rng.standard_normal(q.shape)
+    qb, thb = adj.shrink_backward(q, eb, theta)
+    for t in range(3):
+        D = rng.standard_normal(q.shape)
+        fd = _fd(lambda x: float(np.sum(eb * oracle.l21_shrink(x, theta))), q, D)
+        assert abs(fd - float(np.sum(qb * D))) <= 1e-6 * (1 + abs(fd))
+    fd = (np.sum(eb * oracle.l21_shrink(q, theta + H)) - np.sum(eb * oracle.l21_shrink(q, theta - H))) / (2 * H)
+    assert abs(fd - thb) <= 1e-6 * (1 + abs(fd))
+
+
+def _opts(iters=25):
+    # a fast schedule so that a short unrolled run thresholds and shrinks
+    return oracle.ALMOptions(mu0=0.05, rho=1.25, mu_max=1e10, fixed_iters=iters)
+
+
+def test_unrolled_lrr_gradient_matches_finite_differences():
+    p = small_problem(21, m=14, k=2, r=2, ns=8, n_replace=2, t=1, lam=0.4)
+    X, A, lam = p.M[:, :10].copy(), p.M.copy(), p.lam
+    rng = np.random.default_rng(8)
+    Wz = rng.standard_normal((A.shape[1], X.shape[1]))
+    Wj = rng.standard_normal((A.shape[1], X.shape[1]))
+
+    def loss(X_, A_, lam_):
+        tp = adj.unrolled_forward(X_, A_, lam_, _opts())
+        return float(np.sum(Wz * tp.states[-1][0]) + np.sum(Wj * tp.J))
+
+    tp = adj.unrolled_forward(X, A, lam, _opts())
+    assert np.linalg.matrix_rank(tp.J, 1e-8) > 0
+    Xb, Ab, lb = adj.unrolled_backward(tp, Wz, Wj)
+    for t in range(3):
+        DX = rng.standard_normal(X.shape)
+        DA = rng.standard_normal(A.shape)
+        fdx = _fd(lambda x: loss(x, A, lam), X, DX)
+        fda = _fd(lambda a: loss(X, a, lam), A, DA)
+        assert abs(fdx - np.sum(Xb * DX)) <= 1e-5 * (1 + abs(fdx))
+        assert abs(fda - np.sum(Ab * DA)) <= 1e-5 * (1 + abs(fda))
+    fdl = (loss(X, A, lam + H) - loss(X, A, lam - H)) / (2 * H)
+    assert abs(fdl - lb) <= 1e-5 * (1 + abs(fdl))
+
+
+def test_unrolled_dfc_gradient_matches_finite_differences():
+    p = small_problem(22, m=16, k=3, r=2, ns=8, n_replace=3, t=3, lam=0.4)
+    rng = np.random.default_rng(9)
+    Wm = rng.uniform(0.0, 1.0, (p.n, p.n))
+
+    def loss_and_dZ(M_, lam_):
+        tapes = []
+        for i in range(p.t):
+            cols = p.perm[p.offsets[i]:p.offsets[i + 1]]
+            tapes.append(adj.unrolled_forward(M_[:, cols], M_, lam_, _opts()))
+        Z = adj.dfc_combine(tapes, p.perm)[0]
+        return float(np.sum((Wm * Z) ** 2)), 2.0 * Wm ** 2 * Z
+
+    L0, dZ = loss_and_dZ(p.M, p.lam)
+    Z, Mb, lb = adj.dfc_forward_backward(p.M, p.lam, p.perm, p.offsets, _opts(), dZ)
+    assert np.isfinite(L0) and np.abs(Mb).max() > 0
+    for t in range(3):
+        D = rng.standard_normal(p.M.shape)
+        fd = _fd(lambda M_: loss_and_dZ(M_, p.lam)[0], p.M, D)
+        assert abs(fd - np.sum(Mb * D)) <= 1e-5 * (1 + abs(fd))
+    fdl = (loss_and_dZ(p.M, p.lam + H)[0] - loss_and_dZ(p.M, p.lam - H)[0]) / (2 * H)
+    assert abs(fdl - lb) <= 1e-5 * (1 + abs(fdl))
+
+
+def test_unrolled_forward_is_the_fixed_count_alm():
+    """The recorded forward is lrr_alm with fixed_iters (same iterates)."""
+    p = small_problem(23, m=12, k=2, r=2, ns=6, n_replace=2, t=1, lam=0.4)
+    X = p.M[:, :8]
+    tp = adj.unrolled_forward(X, p.M, p.lam, _opts(15))
+    r = oracle.lrr_alm(X, p.M, p.lam, _opts(15))
+    assert np.allclose(tp.states[-1][0], r.Z, rtol=0, atol=1e-12)
+    assert np.allclose(tp.J, r.J, rtol=0, atol=1e-12)
+    assert np.allclose(tp.states[-1][1], r.E, rtol=0, atol=1e-12)
