@@ -90,7 +90,10 @@ typedef struct {
     int save_for_backward;   /* record what dfc_lrr_backward needs                  */
     int checkpoint_every;    /* adjoint checkpoint spacing k (default 20)           */
     int eig_block;           /* Jacobi block width: 0 auto, 16 or 32                */
-    int reserved[7];         /* must be zero                                        */
+    int use_graph;           /* 1 (default): replay each iteration's Z- and E-step  */
+                             /* launches from a captured HIP graph; 0: launch them  */
+                             /* one by one (always so while profiling is enabled)   */
+    int reserved[6];         /* must be zero                                        */
 } lrr_opts;
 
 /* Per-block results; every pointer may be NULL, each non-NULL array has t entries. */

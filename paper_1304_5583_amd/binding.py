@@ -34,7 +34,7 @@ class lrr_opts(C.Structure):
         ("mu0", C.c_double), ("rho", C.c_double), ("mu_max", C.c_double), ("tol", C.c_double),
         ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("check_every", C.c_int),
         ("max_sweeps", C.c_int), ("save_for_backward", C.c_int), ("checkpoint_every", C.c_int),
-        ("eig_block", C.c_int), ("reserved", C.c_int * 7),
+        ("eig_block", C.c_int), ("use_graph", C.c_int), ("reserved", C.c_int * 6),
     ]
 
 

@@ -112,6 +112,7 @@ struct lrr_ctx {
     int* dflag = nullptr;        // device flag for the input check
     unsigned long long* dwork = nullptr;   // operation counters of the Jacobi kernels
     Tape* tape = nullptr;
+    hipStream_t capture = nullptr;         // private stream for graph capture
 };
 
 namespace {
@@ -348,6 +349,7 @@ bool opts_valid(const lrr_opts& o, std::string& why) {
         why = "negative count"; return false;
     }
     if (o.eig_block != 0 && o.eig_block != 16 && o.eig_block != 32) { why = "eig_block must be 0, 16 or 32"; return false; }
+    if (o.use_graph != 0 && o.use_graph != 1) { why = "use_graph must be 0 or 1"; return false; }
     for (int r : o.reserved) if (r != 0) { why = "reserved fields must be zero"; return false; }
     return true;
 }
@@ -419,6 +421,11 @@ Plan make_plan(const Problem& pr) {
     p.n_iter = pr.o.fixed_iters > 0 ? pr.o.fixed_iters : pr.o.max_iter;
     p.pm = product_modes(pr.o.precision);
     return p;
+}
+
+hipStream_t ctx_capture_stream(lrr_ctx* ctx) {
+    if (!ctx->capture) LRR_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+    return ctx->capture;
 }
 
 // Lay out the workspace, upload the descriptors, gather the observations,
@@ -586,6 +593,58 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     std::vector<int> h_act(t, 1);
     long long sweeps_total = 0;
     const double D = sizeof(double);
+    // one iteration's Z-step and E-step launches on stream st
+    auto zstep = [&](hipStream_t st, bool anchor, auto&& tm, double cact) {
+        tm("k_form_QT", 0.0, ((pm.dMQ ? 5.0 : 3.0) * n + 4.0 * m) * cact * D, [&] {
+            lrr::launch_form_QT(b.J, b.Y2, b.Q, pm.dMQ ? b.Dn : nullptr, n, n, b.X, b.E, b.Y1, b.T, m, m, c,
+                                b.colblk, b.active, b.it, st);
+        });
+        // T = P - M Q; the difference form carries M Q as a sum of products M dQ
+        if (anchor) {
+            // every kAnchorEvery iterations the rounding carried in the sum of
+            // products is dropped: M Q is formed once in FP64
+            tm("k_dgemm<false, false>", 2.0 * m * n * cact, 0.0, [&] {
+                lrr::launch_dgemm(b.g_MQa, t, m, p.maxl, false, false, st);
+            });
+        } else {
+            tm(lrr::xgemm_name(pm.MQ, false, false), 2.0 * m * n * cact, 0.0, [&] {
+                lrr::launch_xgemm(b.g_MQ, t, m, p.maxl, false, false, pm.MQ, st);
+            });
+        }
+        if (pm.dMQ)
+            tm("k_sub_cols", 0.0, 3.0 * m * cact * D, [&] {
+                lrr::launch_sub_cols(b.T, b.MQacc, m, m, c, b.colblk, b.active, st);
+            });
+        tm("k_dgemm<false, false>", 2.0 * m * m * cact, 0.0, [&] {
+            lrr::launch_dgemm(b.g_KV, t, m, p.maxl, false, false, st);
+        });
+        tm(lrr::xgemm_name(pm.MtV, true, false), 2.0 * n * m * cact, 0.0, [&] {
+            lrr::launch_xgemm(b.g_MtV, t, n, p.maxl, true, false, pm.MtV, st);
+        });
+        tm("k_update_Z", 0.0, 6.0 * n * cact * D, [&] {
+            lrr::launch_update_Z(b.Q, b.MtV, b.J, b.Z, b.Y2, n, n, c, b.colblk, bst, b.it, st);
+        });
+        tm("k_estep", 0.0, 5.0 * m * cact * D, [&] {
+            lrr::launch_estep(b.E, b.V, b.Y1, m, m, c, pr.lam, b.colblk, bst, b.it, st);
+        });
+        tm("k_check", 0.0, 0.0, [&] {
+            lrr::launch_check(bst, t, b.it, b.mu_sched, o.tol, fixed, b.n_active, st);
+        });
+    };
+    auto untimed = [](const char*, double, double, auto&& f) { f(); };
+    // graphs of the chain (plain and re-anchoring iterations); per-kernel
+    // timing needs the launches one by one, so profiling runs them eagerly
+    const bool use_graph = o.use_graph != 0 && !prof.on;
+    hipGraphExec_t g_plain = nullptr, g_anchor = nullptr;
+    hipStream_t cs = use_graph ? ctx_capture_stream(ctx) : nullptr;
+    struct GraphGuard {
+        hipGraphExec_t* a;
+        hipGraphExec_t* b;
+        ~GraphGuard() {
+            if (*a) (void)hipGraphExecDestroy(*a);
+            if (*b) (void)hipGraphExecDestroy(*b);
+        }
+    } graph_guard{&g_plain, &g_anchor};
     int k = k0;
     for (k = k0; k < k1; ++k) {
         if (hooks && hooks->begin) hooks->begin(k);
@@ -703,42 +762,24 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             });
             timed("k_mark_warm", 0.0, 0.0, [&] { lrr::launch_mark_warm(b.svt_run, b.warm, t, s); });
         }
-        // Z-step (push-through) and E-step
-        timed("k_form_QT", 0.0, ((pm.dMQ ? 5.0 : 3.0) * n + 4.0 * m) * cact * D, [&] {
-            lrr::launch_form_QT(b.J, b.Y2, b.Q, pm.dMQ ? b.Dn : nullptr, n, n, b.X, b.E, b.Y1, b.T, m, m, c,
-                                b.colblk, b.active, b.it, s);
-        });
-        // T = P - M Q; the difference form carries M Q as a sum of products M dQ
-        if (pm.dMQ && k > 0 && k % kAnchorEvery == 0) {
-            // every kAnchorEvery iterations the rounding carried in the sum of
-            // products is dropped: M Q is formed once in FP64
-            timed("k_dgemm<false, false>", 2.0 * m * n * cact, 0.0, [&] {
-                lrr::launch_dgemm(b.g_MQa, t, m, p.maxl, false, false, s);
-            });
+        // Z-step (push-through) and E-step: the same launches in every iteration
+        // (the penalty is read from DevIter), replayed from a captured graph
+        const bool anchor = pm.dMQ && k > 0 && k % kAnchorEvery == 0;
+        if (use_graph) {
+            hipGraphExec_t& ex = anchor ? g_anchor : g_plain;
+            if (!ex) {
+                hipGraph_t graph = nullptr;
+                LRR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                zstep(cs, anchor, untimed, cact);
+                LRR_HIP(hipStreamEndCapture(cs, &graph));
+                const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                LRR_HIP(e);
+            }
+            LRR_HIP(hipGraphLaunch(ex, s));
         } else {
-            timed(lrr::xgemm_name(pm.MQ, false, false), 2.0 * m * n * cact, 0.0, [&] {
-                lrr::launch_xgemm(b.g_MQ, t, m, p.maxl, false, false, pm.MQ, s);
-            });
+            zstep(s, anchor, timed, cact);
         }
-        if (pm.dMQ)
-            timed("k_sub_cols", 0.0, 3.0 * m * cact * D, [&] {
-                lrr::launch_sub_cols(b.T, b.MQacc, m, m, c, b.colblk, b.active, s);
-            });
-        timed("k_dgemm<false, false>", 2.0 * m * m * cact, 0.0, [&] {
-            lrr::launch_dgemm(b.g_KV, t, m, p.maxl, false, false, s);
-        });
-        timed(lrr::xgemm_name(pm.MtV, true, false), 2.0 * n * m * cact, 0.0, [&] {
-            lrr::launch_xgemm(b.g_MtV, t, n, p.maxl, true, false, pm.MtV, s);
-        });
-        timed("k_update_Z", 0.0, 6.0 * n * cact * D, [&] {
-            lrr::launch_update_Z(b.Q, b.MtV, b.J, b.Z, b.Y2, n, n, c, b.colblk, bst, b.it, s);
-        });
-        timed("k_estep", 0.0, 5.0 * m * cact * D, [&] {
-            lrr::launch_estep(b.E, b.V, b.Y1, m, m, c, pr.lam, b.colblk, bst, b.it, s);
-        });
-        timed("k_check", 0.0, 0.0, [&] {
-            lrr::launch_check(bst, t, b.it, b.mu_sched, o.tol, fixed, b.n_active, s);
-        });
         if (hooks && hooks->end) hooks->end(k);
         if (!fixed && ((k + 1) % check_every == 0 || k + 1 == p.n_iter)) {
             LRR_HIP(hipMemcpyAsync(h_misc + 1, b.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1175,6 +1216,7 @@ void lrr_opts_default(lrr_opts* o) {
     o->max_sweeps = 30;
     o->save_for_backward = 0;
     o->checkpoint_every = 20;
+    o->use_graph = 1;
     o->eig_block = 0;
 }
 
@@ -1200,6 +1242,7 @@ void lrr_ctx_destroy(lrr_ctx* ctx) {
         if (ctx->dwork) (void)hipFree(ctx->dwork);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
         tape_free(ctx->tape);
+        if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     }
     delete ctx->tape;
     delete ctx;
