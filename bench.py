@@ -114,6 +114,86 @@ def cpu_baseline(p, total_block_iters, target_s):
             "block_iters_per_s": rate}
 
 
+def _timed_solves(B, torch, p, Mt, Zt, ctx, opts, steps):
+    B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False, Zt=Zt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, _, info = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False, Zt=Zt)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, info
+
+
+def precision_forms(B, torch, p, Mt, Z64t, ctx, args):
+    """The reduced-precision forms on the benchmark workload: solves/s and the
+    relative Frobenius error of Z against the FP64 form's Z."""
+    out = {}
+    Zt = torch.empty_like(Z64t)
+    for name, prec in (("fp32", B.LRR_FP32), ("mixed_bf16x3", B.LRR_MIXED_BF16)):
+        sec, info = _timed_solves(B, torch, p, Mt, Zt, ctx, B.lrr_opts_default(precision=prec), 3)
+        err = (torch.linalg.norm(Zt - Z64t) / torch.linalg.norm(Z64t)).item()
+        out[name] = {"solves_per_s": 1.0 / sec, "ms_per_solve": 1e3 * sec, "err_vs_fp64_plain": err,
+                     "iters_per_block": info.iters.tolist()}
+        print(f"bench: {name}: {1e3 * sec:.1f} ms/solve err_vs_fp64={err:.2e}", file=sys.stderr, flush=True)
+    return out
+
+
+def workload4_mixed(B, torch, ctx):
+    """Workload 4 (m=512, n=20000, t=40): BF16x3 form against the FP64 form on
+    this GPU, one timed solve each after a warm-up."""
+    from paper_1304_5583_amd.datagen import make_config
+    p = make_config(4)
+    dev = torch.device("cuda:0")
+    Mt = B.to_device_colmajor(p.M, dev)
+    Z64 = torch.empty((p.n, p.n), dtype=torch.float64, device=dev)
+    Zmx = torch.empty_like(Z64)
+    s64, i64 = _timed_solves(B, torch, p, Mt, Z64, ctx, B.lrr_opts_default(), 1)
+    smx, imx = _timed_solves(B, torch, p, Mt, Zmx, ctx, B.lrr_opts_default(precision=B.LRR_MIXED_BF16), 1)
+    err = (torch.linalg.norm(Zmx - Z64) / torch.linalg.norm(Z64)).item()
+    print(f"bench: workload 4: fp64 {s64:.2f}s mixed {smx:.2f}s err={err:.2e}", file=sys.stderr, flush=True)
+    out = {"workload": p.name, "m": p.m, "n": p.n, "t": p.t, "fp64_solves_per_s": 1.0 / s64,
+           "mixed_solves_per_s": 1.0 / smx, "speedup": s64 / smx, "err_vs_fp64_plain": err,
+           "iters_fp64": [int(i64.iters.min()), int(i64.iters.max())],
+           "iters_mixed": [int(imx.iters.min()), int(imx.iters.max())]}
+    del Z64, Zmx, Mt
+    torch.cuda.empty_cache()
+    return out
+
+
+def workload5_adjoint(B, torch, ctx):
+    """Workload 5: FP32 forward of 200 unrolled iterations with checkpoints every
+    20 and the reverse sweep for L = ||W o |Z| ||_F^2; times both and compares
+    dL/dlambda with the stored oracle gradient."""
+    from paper_1304_5583_amd.datagen import make_config
+    p = make_config(5)
+    dev = torch.device("cuda:0")
+    Mt = B.to_device_colmajor(p.M, dev)
+    Wt = torch.from_numpy(p.extra["W"].T.copy()).to(dev)
+    opts = B.lrr_opts_default(precision=B.LRR_FP32, fixed_iters=p.extra["fixed_iters"],
+                              checkpoint_every=p.extra["checkpoint_every"], save_for_backward=1)
+    res = {}
+    for rep in range(2):    # the first pass allocates the record
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Zt, _, _ = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dlam, dMt = B.dfc_lrr_backward(2.0 * Wt ** 2 * Zt, ctx=ctx, m=p.m)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res = {"forward_ms": 1e3 * (t1 - t0), "backward_ms": 1e3 * (t2 - t1), "dlambda": dlam}
+    gpath = os.path.join(ROOT, "tests", "golden", "workload5_gradient_oracle.json")
+    if os.path.exists(gpath):
+        g = json.load(open(gpath))
+        res["dlambda_oracle"] = g["dlam"]
+        res["dlambda_rel_err"] = abs(dlam - g["dlam"]) / abs(g["dlam"])
+    res.update({"workload": p.name, "precision": "fp32 forward, fp64 reverse", "iters": p.extra["fixed_iters"],
+                "checkpoint_every": p.extra["checkpoint_every"]})
+    print(f"bench: workload 5 adjoint: forward {res['forward_ms']:.1f} ms backward {res['backward_ms']:.1f} ms",
+          file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +203,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eig-block", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the reduced-precision forms, workload 4 and the workload-5 adjoint")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -217,6 +299,10 @@ def main():
     if err:
         g = err[1]
         line["oracle_iters_per_block"] = g["iters"]
+    if not args.no_extras:
+        line["forms"] = precision_forms(B, torch, p, Mt, Zt, ctx, args)
+        line["workload4_mixed_vs_fp64"] = workload4_mixed(B, torch, ctx)
+        line["workload5_adjoint"] = workload5_adjoint(B, torch, ctx)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, int(info.iters.sum()), args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -74,6 +74,22 @@ typedef enum {
     LRR_SOLVE_PUSHTHROUGH = 2/* Cholesky of I + A A^T (m x m), same iterates        */
 } lrr_solve_form;
 
+/* Coordinates of the n-row iterates Z, J, Y2.  Started at zero, they stay in
+ * range(A^T) (every update is a product with A^T or a column operation), so with
+ * an orthonormal basis Qm of that range (n x r, r = numerical rank of A <= m)
+ * Z = Qm Zr exactly and the iteration can run on r-row coefficients: the Gram
+ * matrix of the thresholding step and the dictionary products shrink from n to
+ * r rows, and the n x n states are never formed.  The results agree with the
+ * full coordinates to rounding; the coupling residual max|Z - J| is bounded by
+ * the coefficient columns' 2-norms (times 1 and 1/sqrt(n)) and formed in full
+ * only when the bounds do not decide the stop test.  Basis directions with
+ * sigma^2 <= 1e-14 sigma_max^2 are dropped. */
+typedef enum {
+    LRR_COORDS_AUTO = 0,     /* reduced when n > m (never for a recorded forward)   */
+    LRR_COORDS_FULL = 1,
+    LRR_COORDS_REDUCED = 2
+} lrr_coords;
+
 /* Inexact-ALM controls.  The paper does not print the solver's constants; these
  * are explicit so that any caller (and the CPU reference) can use the same ones. */
 typedef struct {
@@ -93,7 +109,8 @@ typedef struct {
     int use_graph;           /* 1 (default): replay each iteration's Z- and E-step  */
                              /* launches from a captured HIP graph; 0: launch them  */
                              /* one by one (always so while profiling is enabled)   */
-    int reserved[6];         /* must be zero                                        */
+    int coords;              /* lrr_coords: coordinates of the n-row iterates       */
+    int reserved[5];         /* must be zero                                        */
 } lrr_opts;
 
 /* Per-block results; every pointer may be NULL, each non-NULL array has t entries. */

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "liblrr.so")
 LRR_OK, LRR_NOT_CONVERGED = 0, 1
 LRR_EINVAL, LRR_ENOMEM, LRR_EDEVICE, LRR_ENUMERIC, LRR_ENOTAPE = -1, -2, -3, -4, -5
 LRR_FP64, LRR_FP32, LRR_MIXED_BF16 = 0, 1, 2
+LRR_COORDS_AUTO, LRR_COORDS_FULL, LRR_COORDS_REDUCED = 0, 1, 2
 STATUS_NAMES = {0: "LRR_OK", 1: "LRR_NOT_CONVERGED", -1: "LRR_EINVAL", -2: "LRR_ENOMEM",
                 -3: "LRR_EDEVICE", -4: "LRR_ENUMERIC", -5: "LRR_ENOTAPE"}
 
@@ -34,7 +35,7 @@ class lrr_opts(C.Structure):
         ("mu0", C.c_double), ("rho", C.c_double), ("mu_max", C.c_double), ("tol", C.c_double),
         ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("check_every", C.c_int),
         ("max_sweeps", C.c_int), ("save_for_backward", C.c_int), ("checkpoint_every", C.c_int),
-        ("eig_block", C.c_int), ("use_graph", C.c_int), ("reserved", C.c_int * 6),
+        ("eig_block", C.c_int), ("use_graph", C.c_int), ("coords", C.c_int), ("reserved", C.c_int * 5),
     ]
 
 

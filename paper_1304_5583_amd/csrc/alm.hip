@@ -180,9 +180,12 @@ __global__ __launch_bounds__(256) void k_sub_cols(double* __restrict__ T, const 
     for (int i = threadIdx.x; i < m; i += 256) T[o + i] -= A[o + i];
 }
 
+// In reduced coordinates (R2r set) the coefficient residual is stored and its
+// column 2-norm, which bounds the full-coordinate max-norm, goes to r2nrm.
 __global__ __launch_bounds__(256) void k_update_Z(const double* __restrict__ Q, const double* __restrict__ MtV,
                                                    const double* __restrict__ J, double* __restrict__ Z,
-                                                   double* __restrict__ Y2, int n, long ld,
+                                                   double* __restrict__ Y2, double* __restrict__ R2r,
+                                                   unsigned long long* __restrict__ r2nrm, int n, long ld,
                                                    const int* __restrict__ colblk, BlockState bs,
                                                    const DevIter* it) {
     __shared__ double red[4];
@@ -191,16 +194,76 @@ __global__ __launch_bounds__(256) void k_update_Z(const double* __restrict__ Q, 
     if (!bs.active[b]) return;
     const double mu = it->mu;
     const long o = j * ld;
-    double mx = 0.0;
+    double mx = 0.0, ss = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) {
         const double z = Q[o + i] + MtV[o + i];
         const double r2 = z - J[o + i];
         Z[o + i] = z;
         Y2[o + i] = Y2[o + i] + mu * r2;
         mx = fmax(mx, fabs(r2));
+        ss += r2 * r2;
+        if (R2r) R2r[o + i] = r2;
     }
+    if (R2r) {
+        ss = block_sum256(ss, red);
+        if (threadIdx.x == 0) atomic_max_nonneg(&r2nrm[b], sqrt(ss));
+    } else {
+        mx = block_max256(mx, red);
+        if (threadIdx.x == 0) atomic_max_nonneg(&bs.r2max[b], mx);
+    }
+}
+
+// Reduced coordinates, coupling residual R2 = Qm R2r: with Qm having orthonormal
+// columns, ||R2 e_j||_inf <= ||R2r e_j||_2 and ||R2 e_j||_inf >= ||R2r e_j||_2 / sqrt(n).
+// A block whose largest column 2-norm is below tol, or at least sqrt(n) tol, is
+// decided by the bound (which is recorded as its residual); the others get their
+// residual columns expanded (expand = 1) and the exact max-norm taken.
+__global__ void k_r2_decide(BlockState bs, unsigned long long* __restrict__ r2nrm, int* __restrict__ expand,
+                            int t, double tol, double sqrt_n) {
+    for (int b = threadIdx.x; b < t; b += blockDim.x) {
+        const double x = __longlong_as_double((long long)r2nrm[b]);
+        r2nrm[b] = 0ull;
+        int e = 0;
+        if (bs.active[b]) {
+            if (x < tol) bs.r2max[b] = (unsigned long long)__double_as_longlong(x);
+            else if (x >= sqrt_n * tol) bs.r2max[b] = (unsigned long long)__double_as_longlong(x / sqrt_n);
+            else e = 1;
+        }
+        expand[b] = e;
+    }
+}
+
+// max |A[:, j]| over the columns of blocks flagged in expand, into r2max
+__global__ __launch_bounds__(256) void k_colmax(const double* __restrict__ A, int n, long ld,
+                                                 const int* __restrict__ colblk, const int* __restrict__ expand,
+                                                 unsigned long long* __restrict__ out) {
+    __shared__ double red[4];
+    const int j = blockIdx.x;
+    const int b = colblk[j];
+    if (!expand[b]) return;
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) mx = fmax(mx, fabs(A[i + (long)j * ld]));
     mx = block_max256(mx, red);
-    if (threadIdx.x == 0) atomic_max_nonneg(&bs.r2max[b], mx);
+    if (threadIdx.x == 0) atomic_max_nonneg(&out[b], mx);
+}
+
+// Wk[:, j] = W[:, idx[j]] / sqrt(lam[idx[j]]) (m rows)
+__global__ __launch_bounds__(256) void k_gather_scaled(const double* __restrict__ W, long ldw,
+                                                        const double* __restrict__ lam,
+                                                        const int* __restrict__ idx, double* __restrict__ Wk,
+                                                        long ldk, int m) {
+    const int j = blockIdx.x;
+    const int src = idx[j];
+    const double sc = lam[src] > 0.0 ? 1.0 / sqrt(lam[src]) : 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) Wk[i + j * ldk] = W[i + (long)src * ldw] * sc;
+}
+
+// T = (3 I - G) / 2 (r x r), the Newton-Schulz orthogonalisation factor
+__global__ __launch_bounds__(256) void k_ns_factor(const double* __restrict__ G, double* __restrict__ T, int r) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long)r * r) return;
+    const int i = (int)(idx % r), j = (int)(idx / r);
+    T[idx] = (i == j ? 1.5 : 0.0) - 0.5 * G[idx];
 }
 
 __global__ __launch_bounds__(256) void k_estep(double* __restrict__ E, const double* __restrict__ V,
@@ -326,10 +389,27 @@ void launch_sub_cols(double* T, const double* A, int m, long ld, int ncols, cons
                      const int* active, hipStream_t s) {
     hipLaunchKernelGGL(k_sub_cols, dim3(ncols), dim3(256), 0, s, T, A, m, ld, colblk, active);
 }
-void launch_update_Z(const double* Q, const double* MtV, const double* J, double* Z, double* Y2, int n,
-                     long ld, int ncols, const int* colblk, BlockState bs, const DevIter* it,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_update_Z, dim3(ncols), dim3(256), 0, s, Q, MtV, J, Z, Y2, n, ld, colblk, bs, it);
+void launch_update_Z(const double* Q, const double* MtV, const double* J, double* Z, double* Y2, double* R2r,
+                     unsigned long long* r2nrm, int n, long ld, int ncols, const int* colblk, BlockState bs,
+                     const DevIter* it, hipStream_t s) {
+    hipLaunchKernelGGL(k_update_Z, dim3(ncols), dim3(256), 0, s, Q, MtV, J, Z, Y2, R2r, r2nrm, n, ld, colblk, bs,
+                       it);
+}
+void launch_r2_decide(BlockState bs, unsigned long long* r2nrm, int* expand, int t, double tol, double sqrt_n,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_r2_decide, dim3(1), dim3(256), 0, s, bs, r2nrm, expand, t, tol, sqrt_n);
+}
+void launch_colmax(const double* A, int n, long ld, int ncols, const int* colblk, const int* expand,
+                   unsigned long long* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_colmax, dim3(ncols), dim3(256), 0, s, A, n, ld, colblk, expand, out);
+}
+void launch_gather_scaled(const double* W, long ldw, const double* lam, const int* idx, double* Wk, long ldk,
+                          int m, int r, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_scaled, dim3(r), dim3(256), 0, s, W, ldw, lam, idx, Wk, ldk, m);
+}
+void launch_ns_factor(const double* G, double* T, int r, hipStream_t s) {
+    const long nn = (long)r * r;
+    hipLaunchKernelGGL(k_ns_factor, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, G, T, r);
 }
 void launch_estep(double* E, const double* V, double* Y1, int m, long ld, int ncols, double lam,
                   const int* colblk, BlockState bs, const DevIter* it, hipStream_t s) {

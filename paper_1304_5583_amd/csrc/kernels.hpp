@@ -61,9 +61,16 @@ void launch_form_QT(const double* J, const double* Y2, double* Q, double* dQ, in
                     const int* colblk, const int* active, const DevIter* it, hipStream_t s);
 void launch_sub_cols(double* T, const double* A, int m, long ld, int ncols, const int* colblk,
                      const int* active, hipStream_t s);
-void launch_update_Z(const double* Q, const double* MtV, const double* J, double* Z, double* Y2, int n,
-                     long ld, int ncols, const int* colblk, BlockState bs, const DevIter* it,
-                     hipStream_t s);
+void launch_update_Z(const double* Q, const double* MtV, const double* J, double* Z, double* Y2, double* R2r,
+                     unsigned long long* r2nrm, int n, long ld, int ncols, const int* colblk, BlockState bs,
+                     const DevIter* it, hipStream_t s);
+void launch_r2_decide(BlockState bs, unsigned long long* r2nrm, int* expand, int t, double tol, double sqrt_n,
+                      hipStream_t s);
+void launch_colmax(const double* A, int n, long ld, int ncols, const int* colblk, const int* expand,
+                   unsigned long long* out, hipStream_t s);
+void launch_gather_scaled(const double* W, long ldw, const double* lam, const int* idx, double* Wk, long ldk,
+                          int m, int r, hipStream_t s);
+void launch_ns_factor(const double* G, double* T, int r, hipStream_t s);
 void launch_estep(double* E, const double* V, double* Y1, int m, long ld, int ncols, double lam,
                   const int* colblk, BlockState bs, const DevIter* it, hipStream_t s);
 void launch_check(BlockState bs, int t, DevIter* it, const double* mu_sched, double tol, int fixed,

@@ -162,6 +162,12 @@ struct Plan {
     int maxL = 0, maxl = 0;
     int n_iter = 0;
     ProductModes pm;             // arithmetic of each large product
+    // coordinates of the n-row iterates (Z, J, Y2 and their temporaries): n rows,
+    // or nr <= min(m, n) coefficients on an orthonormal basis Qm of range(M^T)
+    bool reduced = false;
+    int nrb = 0;                 // rows the layout reserves (n, or min(m, n))
+    int nr = 0;                  // rows in use (n, or the numerical rank of M)
+    int Lm = 0, bq = 16;         // padded order / Jacobi block of the M M^T eigensolve
 };
 
 struct Buffers {
@@ -169,6 +175,12 @@ struct Buffers {
     double *K, *Lb, *Linv, *Tb, *Dinv;
     double *colsq, *mu_sched;
     double *Dn, *MQacc;          // difference form of M Q only
+    // reduced coordinates only
+    double *Qm, *Qtmp, *Mr, *R2r, *R2full, *Ur, *Gb, *Wq, *Rq, *lamq, *scaleq, *Gq, *Tq;
+    int *protq, *loq, *stq, *runq, *idxq, *expand;
+    unsigned long long* r2nrm;
+    EigDesc* eq;
+    GemmDesc *g_red, *g_exp;
     int *colblk, *boff, *perm;
     int *active, *svt_run, *iters, *rank, *eigst, *n_active, *eig_any, *flag;
     std::vector<int*> prot;
@@ -202,7 +214,9 @@ int round_up(int x, int a) { return ((x + a - 1) / a) * a; }
 // Lay out every buffer; with a null base only the size is computed.
 size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need_X) {
     Arena a{base, 0};
-    const size_t n = p.n, m = p.m, c = p.ncols, t = p.t;
+    const size_t m = p.m, c = p.ncols, t = p.t;
+    const size_t n = p.nrb;      // rows of the iterates
+    const size_t nfull = p.n;
     b.X = a.take<double>(m * c);
     b.Z = a.take<double>(n * c);
     b.J = a.take<double>(n * c);
@@ -290,10 +304,43 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.eig = a.take<EigDesc>(t);
     b.svt = a.take<SvtDesc>(t);
     if (with_combine) {
-        b.U = a.take<double>(n * p.L[0]);
+        b.U = a.take<double>(nfull * p.L[0]);
         b.H = a.take<double>((size_t)p.L[0] * c);
     } else {
         b.U = b.H = nullptr;
+    }
+    if (p.reduced) {
+        const size_t Lm = p.Lm;
+        b.Qm = a.take<double>(nfull * n);
+        b.Qtmp = a.take<double>(nfull * n);
+        b.Mr = a.take<double>(m * n);
+        b.R2r = a.take<double>(n * c);
+        b.R2full = a.take<double>(nfull * c);
+        b.Ur = with_combine ? a.take<double>(n * p.L[0]) : nullptr;
+        b.Gb = a.take<double>(Lm * Lm);
+        b.Wq = a.take<double>(Lm * Lm);
+        b.Rq = a.take<double>(Lm * 2 * p.bq);
+        b.lamq = a.take<double>(Lm);
+        b.scaleq = a.take<double>(1);
+        b.Gq = a.take<double>(n * n);
+        b.Tq = a.take<double>(n * n);
+        b.protq = a.take<int>(Lm / (2 * p.bq) + 1);
+        b.loq = a.take<int>(Lm);
+        b.stq = a.take<int>(2);
+        b.runq = a.take<int>(1);
+        b.idxq = a.take<int>(m);
+        b.expand = a.take<int>(t);
+        b.r2nrm = a.take<unsigned long long>(t);
+        b.eq = a.take<EigDesc>(1);
+        b.g_red = a.take<GemmDesc>(5);
+        b.g_exp = a.take<GemmDesc>(t);
+    } else {
+        b.Qm = b.Qtmp = b.Mr = b.R2r = b.R2full = b.Ur = b.Gb = b.Wq = b.Rq = b.lamq = b.scaleq = nullptr;
+        b.Gq = b.Tq = nullptr;
+        b.protq = b.loq = b.stq = b.runq = b.idxq = b.expand = nullptr;
+        b.r2nrm = nullptr;
+        b.eq = nullptr;
+        b.g_red = b.g_exp = nullptr;
     }
     (void)need_X;
     return a.off + 256;
@@ -350,6 +397,7 @@ bool opts_valid(const lrr_opts& o, std::string& why) {
     }
     if (o.eig_block != 0 && o.eig_block != 16 && o.eig_block != 32) { why = "eig_block must be 0, 16 or 32"; return false; }
     if (o.use_graph != 0 && o.use_graph != 1) { why = "use_graph must be 0 or 1"; return false; }
+    if (o.coords < 0 || o.coords > 2) { why = "unknown coords"; return false; }
     for (int r : o.reserved) if (r != 0) { why = "reserved fields must be zero"; return false; }
     return true;
 }
@@ -420,12 +468,93 @@ Plan make_plan(const Problem& pr) {
     }
     p.n_iter = pr.o.fixed_iters > 0 ? pr.o.fixed_iters : pr.o.max_iter;
     p.pm = product_modes(pr.o.precision);
+    // reduced coordinates: explicit request, or automatic when the dictionary is
+    // wider than tall (the iterates then live in a space of dimension <= m < n);
+    // the reverse-mode record keeps full coordinates
+    const int coords = pr.o.coords;
+    p.reduced = coords == LRR_COORDS_REDUCED ||
+                (coords == LRR_COORDS_AUTO && pr.n > pr.m && !pr.o.save_for_backward);
+    if (pr.o.save_for_backward) p.reduced = false;
+    p.nrb = p.reduced ? std::min(pr.m, pr.n) : pr.n;
+    p.nr = p.nrb;
+    p.bq = pr.m > 512 ? 32 : 16;
+    p.Lm = round_up(pr.m, 2 * p.bq);
     return p;
 }
 
 hipStream_t ctx_capture_stream(lrr_ctx* ctx) {
     if (!ctx->capture) LRR_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
     return ctx->capture;
+}
+
+
+// Reduced coordinates: every iterate of the n-row state (Z, J, Y2) starts at
+// zero and is updated only by products with M^T and by column operations, so
+// it stays in range(M^T) (pinned on the oracle).  With Qm an orthonormal basis
+// of that range (n x r, r = numerical rank of M), Z = Qm Zr exactly and the
+// whole iteration runs on r-row coefficients: the Gram matrix Y^T Y equals
+// Yr^T Yr, and the dictionary products use Mr = M Qm (m x r).
+// Qm = M^T W diag(1/sigma) from the eigen-decomposition M M^T = W diag(sigma^2)
+// W^T (kept: sigma^2 > 1e-14 sigma_max^2), then one Newton-Schulz step
+// Qm <- Qm (3 I - Qm^T Qm) / 2 restores orthonormality to rounding.
+constexpr double kRankCut = 1e-14;
+
+void build_basis(const Problem& pr, Plan& p, Buffers& b, hipStream_t s) {
+    const int m = p.m, n = p.n, Lm = p.Lm, bq = p.bq;
+    // G = M M^T (padded to Lm), eigen-decomposition by block Jacobi from the identity
+    LRR_HIP(hipMemsetAsync(b.Gb, 0, sizeof(double) * (size_t)Lm * Lm, s));
+    GemmDesc gG{pr.A, pr.A, b.Gb, m, m, n, (int)pr.lda, (int)pr.lda, Lm, 1.0, 0.0, nullptr, nullptr};
+    std::vector<int> lo(Lm);
+    for (int i = 0; i < Lm; ++i) lo[i] = i >= m ? 1 : 0;
+    const int one = 1;
+    LRR_HIP(hipMemcpyAsync(b.g_red, &gG, sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+    LRR_HIP(hipMemcpyAsync(b.loq, lo.data(), sizeof(int) * Lm, hipMemcpyHostToDevice, s));
+    LRR_HIP(hipMemcpyAsync(b.runq, &one, sizeof(int), hipMemcpyHostToDevice, s));
+    EigDesc ed{b.Gb, b.Wq, b.Rq, b.lamq, Lm, m, b.runq, b.stq, b.scaleq, b.protq, b.loq, nullptr};
+    LRR_HIP(hipMemcpyAsync(b.eq, &ed, sizeof(EigDesc), hipMemcpyHostToDevice, s));
+    lrr::launch_dgemm(b.g_red, 1, m, m, false, true, s);
+    lrr::launch_set_identity(b.Wq, Lm, s);
+    lrr::launch_jacobi_init(b.eq, 1, s);
+    int* any = b.idxq;     // scratch flag until the index list is written
+    int h_any = 1;
+    for (int sw = 0; sw < 80; ++sw) {
+        LRR_HIP(hipMemsetAsync(any, 0, sizeof(int), s));
+        lrr::launch_jacobi_check(b.eq, 1, Lm, any, s);
+        LRR_HIP(hipMemcpyAsync(&h_any, any, sizeof(int), hipMemcpyDeviceToHost, s));
+        LRR_HIP(hipStreamSynchronize(s));
+        if (h_any == 0) break;
+        for (int r = 0; r < Lm / bq - 1; ++r) lrr::launch_jacobi_round(b.eq, 1, Lm, bq, r, s);
+    }
+    lrr::launch_jacobi_eigvals(b.eq, 1, s);
+    std::vector<double> lam(Lm);
+    LRR_HIP(hipMemcpyAsync(lam.data(), b.lamq, sizeof(double) * Lm, hipMemcpyDeviceToHost, s));
+    LRR_HIP(hipStreamSynchronize(s));
+    double lmax = 0.0;
+    for (int i = 0; i < m; ++i) lmax = std::max(lmax, lam[i]);
+    std::vector<int> idx;
+    for (int i = 0; i < m; ++i)
+        if (lam[i] > kRankCut * lmax) idx.push_back(i);
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return lam[x] > lam[y]; });
+    if ((int)idx.size() > p.nrb) idx.resize(p.nrb);   // rank(M) <= min(m, n)
+    if (idx.empty()) idx.push_back(0);     // M = 0: a single zero column (scaled by 0 below)
+    const int r = (int)idx.size();
+    p.nr = r;
+    LRR_HIP(hipMemcpyAsync(b.idxq, idx.data(), sizeof(int) * r, hipMemcpyHostToDevice, s));
+    // Wk = W_kept diag(1/sigma) (m x r, in the Gram buffer), Qm = M^T Wk, NS step, Mr = M Qm
+    GemmDesc g[4] = {
+        GemmDesc{pr.A, b.Gb, b.Qm, n, r, m, (int)pr.lda, m, n, 1.0, 0.0, nullptr, nullptr},
+        GemmDesc{b.Qm, b.Qm, b.Gq, r, r, n, n, n, r, 1.0, 0.0, nullptr, nullptr},
+        GemmDesc{b.Qm, b.Tq, b.Qtmp, n, r, r, n, r, n, 1.0, 0.0, nullptr, nullptr},
+        GemmDesc{pr.A, b.Qtmp, b.Mr, m, r, n, (int)pr.lda, n, m, 1.0, 0.0, nullptr, nullptr}};
+    LRR_HIP(hipMemcpyAsync(b.g_red + 1, g, sizeof(g), hipMemcpyHostToDevice, s));
+    lrr::launch_gather_scaled(b.Wq, Lm, b.lamq, b.idxq, b.Gb, m, m, r, s);
+    lrr::launch_dgemm(b.g_red + 1, 1, n, r, true, false, s);
+    lrr::launch_dgemm(b.g_red + 2, 1, r, r, true, false, s);
+    lrr::launch_ns_factor(b.Gq, b.Tq, r, s);
+    lrr::launch_dgemm(b.g_red + 3, 1, n, r, false, false, s);
+    lrr::launch_dgemm(b.g_red + 4, 1, m, r, false, false, s);
+    std::swap(b.Qm, b.Qtmp);       // the orthonormalised basis
+    LRR_HIP(hipStreamSynchronize(s));   // host descriptors go out of scope
 }
 
 // Lay out the workspace, upload the descriptors, gather the observations,
@@ -439,6 +568,12 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     LRR_HIP(hipMemsetAsync(ctx->dwork, 0, 2 * sizeof(unsigned long long), s));
     layout(p, static_cast<char*>(ctx->ws), b, with_combine, true);
     ensure_pinned(ctx, sizeof(int) * (4 * (size_t)t + 16) + sizeof(double) * 2 * t);
+    if (p.reduced) build_basis(pr, p, b, s);
+    else p.nr = n;
+    const int nr = p.nr;
+    // dictionary of the Z-step products: M, or Mr = M Qm in reduced coordinates
+    const double* Md = p.reduced ? b.Mr : pr.A;
+    const int ldmd = p.reduced ? m : (int)pr.lda;
 
     // ---- host-side tables -------------------------------------------------
     std::vector<int> colblk(c);
@@ -449,20 +584,20 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     for (int k = 1; k < (int)sched.size(); ++k) sched[k] = std::min(o.rho * sched[k - 1], o.mu_max);
 
     std::vector<GemmDesc> gram(t), gRT(t), gRSG(t), gRXE(t), gOG(t), gBq(t), gP(t), gJ(t);
-    std::vector<GemmDesc> gMQ(t), gMQa(t), gKV(t), gMtV(t);
+    std::vector<GemmDesc> gMQ(t), gMQa(t), gKV(t), gMtV(t), gExp(t);
     std::vector<EigDesc> eig(t);
     std::vector<SvtDesc> svt(t);
     std::vector<RefDesc> ref(t);
     for (int bb = 0; bb < t; ++bb) {
         const int l = p.boff[bb + 1] - p.boff[bb], L = p.L[bb];
         const size_t LL = (size_t)L * L;
-        double* Yb = b.Y + (size_t)p.boff[bb] * n;
-        double* Jb = b.J + (size_t)p.boff[bb] * n;
+        double* Yb = b.Y + (size_t)p.boff[bb] * nr;
+        double* Jb = b.J + (size_t)p.boff[bb] * nr;
         const int* run = b.svt_run + bb;
         const int* rrun = b.ref_run + bb;
         double* X = b.Wm[bb];
         double* T = b.TX[bb];
-        gram[bb] = GemmDesc{Yb, Yb, b.Bm[bb], l, l, n, n, n, L, 1.0, 0.0, run, nullptr};
+        gram[bb] = GemmDesc{Yb, Yb, b.Bm[bb], l, l, nr, nr, nr, L, 1.0, 0.0, run, nullptr};
         // refinement: T = B X, [S | G] = X^T [T | X], XE = X E
         gRT[bb] = GemmDesc{b.Bm[bb], X, T, L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
         gRSG[bb] = GemmDesc{X, T, b.SG[bb], L, 2 * L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
@@ -471,20 +606,21 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         gOG[bb] = GemmDesc{X, X, b.SG[bb] + LL, L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
         gBq[bb] = GemmDesc{X, T, b.Bq[bb], L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
         gP[bb] = GemmDesc{b.Wg[bb], X, b.Pm[bb], l, l, L, L, L, L, 1.0, 0.0, run, nullptr};
-        gJ[bb] = GemmDesc{Yb, b.Pm[bb], Jb, n, l, l, n, L, n, 1.0, 0.0, run, nullptr};
+        gJ[bb] = GemmDesc{Yb, b.Pm[bb], Jb, nr, l, l, nr, L, nr, 1.0, 0.0, run, nullptr};
         const int* act = b.active + bb;
-        const size_t o_n = (size_t)p.boff[bb] * n, o_m = (size_t)p.boff[bb] * m;
+        const size_t o_n = (size_t)p.boff[bb] * nr, o_m = (size_t)p.boff[bb] * m;
         if (p.pm.dMQ) {
-            gMQ[bb] = GemmDesc{pr.A, b.Dn + o_n, b.MQacc + o_m, m, l, n, (int)pr.lda, n, m, 1.0, 1.0, act,
-                               nullptr};
+            gMQ[bb] = GemmDesc{Md, b.Dn + o_n, b.MQacc + o_m, m, l, nr, ldmd, nr, m, 1.0, 1.0, act, nullptr};
             // re-anchoring: the carried product replaced by an FP64 M Q
-            gMQa[bb] = GemmDesc{pr.A, b.Q + o_n, b.MQacc + o_m, m, l, n, (int)pr.lda, n, m, 1.0, 0.0, act,
-                                nullptr};
+            gMQa[bb] = GemmDesc{Md, b.Q + o_n, b.MQacc + o_m, m, l, nr, ldmd, nr, m, 1.0, 0.0, act, nullptr};
         }
         else
-            gMQ[bb] = GemmDesc{pr.A, b.Q + o_n, b.T + o_m, m, l, n, (int)pr.lda, n, m, -1.0, 1.0, act, nullptr};
+            gMQ[bb] = GemmDesc{Md, b.Q + o_n, b.T + o_m, m, l, nr, ldmd, nr, m, -1.0, 1.0, act, nullptr};
         gKV[bb] = GemmDesc{b.K, b.T + o_m, b.V + o_m, m, l, m, m, m, m, 1.0, 0.0, act, nullptr};
-        gMtV[bb] = GemmDesc{pr.A, b.V + o_m, b.MtV + o_n, n, l, m, (int)pr.lda, m, n, 1.0, 0.0, act, nullptr};
+        gMtV[bb] = GemmDesc{Md, b.V + o_m, b.MtV + o_n, nr, l, m, ldmd, m, nr, 1.0, 0.0, act, nullptr};
+        if (p.reduced)   // expansion of the coupling residual: R2 = Qm R2r
+            gExp[bb] = GemmDesc{b.Qm, b.R2r + o_n, b.R2full + (size_t)p.boff[bb] * n, n, l, nr, n, nr, n, 1.0,
+                                0.0, b.expand + bb, nullptr};
         eig[bb] = EigDesc{b.Bq[bb], X, b.Rm[bb], b.lam[bb], L, l, run, b.eigst + 2 * bb,
                           b.eigscale + bb, b.prot[bb], b.lo[bb], ctx->dwork};
         svt[bb] = SvtDesc{b.Bq[bb], X, b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
@@ -513,6 +649,7 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     up(b.g_MQa, gMQa.data(), sizeof(GemmDesc) * t);
     up(b.g_KV, gKV.data(), sizeof(GemmDesc) * t);
     up(b.g_MtV, gMtV.data(), sizeof(GemmDesc) * t);
+    if (p.reduced) up(b.g_exp, gExp.data(), sizeof(GemmDesc) * t);
 
     up(b.g_KK, &gKK, sizeof(GemmDesc));
     up(b.eig, eig.data(), sizeof(EigDesc) * t);
@@ -522,7 +659,7 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     // ---- setup: observations, state, factorisation (once per solve) -------
     if (pr.perm) lrr::launch_gather_cols(pr.A, pr.lda, b.X, m, m, c, b.perm, s);
     else lrr::launch_copy_cols(pr.X, pr.ldx, b.X, m, m, c, s);
-    const size_t nc = (size_t)n * c, mc = (size_t)m * c;
+    const size_t nc = (size_t)nr * c, mc = (size_t)m * c;
     LRR_HIP(hipMemsetAsync(b.Z, 0, sizeof(double) * nc, s));
     LRR_HIP(hipMemsetAsync(b.J, 0, sizeof(double) * nc, s));
     LRR_HIP(hipMemsetAsync(b.Y2, 0, sizeof(double) * nc, s));
@@ -551,6 +688,7 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     LRR_HIP(hipMemsetAsync(b.r2max, 0, sizeof(unsigned long long) * t, s));
     LRR_HIP(hipMemsetAsync(b.res1, 0, sizeof(double) * t, s));
     LRR_HIP(hipMemsetAsync(b.res2, 0, sizeof(double) * t, s));
+    if (p.reduced) LRR_HIP(hipMemsetAsync(b.r2nrm, 0, sizeof(unsigned long long) * t, s));
     lrr::launch_init_iter(b.it, b.mu_sched, 0, s);
 
     // K = I + A A^T, then K^{-1} (FP64 Cholesky, once per solve)
@@ -570,7 +708,8 @@ struct IterHooks {
 // workspace (DevIter must hold iteration k0); leaves the state there.
 Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t s, int k0, int k1,
                    const IterHooks* hooks = nullptr) {
-    const int m = p.m, n = p.n, c = p.ncols, t = p.t;
+    // n: rows of the iterates (the numerical rank of M in reduced coordinates)
+    const int m = p.m, n = p.nr, nfull = p.n, c = p.ncols, t = p.t;
     const lrr_opts& o = pr.o;
     int* hp = static_cast<int*>(ctx->pinned);
     BlockState bst{b.active, b.svt_run, b.iters, b.rank, b.res1, b.res2, b.r1max, b.r2max};
@@ -621,9 +760,21 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         tm(lrr::xgemm_name(pm.MtV, true, false), 2.0 * n * m * cact, 0.0, [&] {
             lrr::launch_xgemm(b.g_MtV, t, n, p.maxl, true, false, pm.MtV, st);
         });
-        tm("k_update_Z", 0.0, 6.0 * n * cact * D, [&] {
-            lrr::launch_update_Z(b.Q, b.MtV, b.J, b.Z, b.Y2, n, n, c, b.colblk, bst, b.it, st);
+        tm("k_update_Z", 0.0, (p.reduced ? 7.0 : 6.0) * n * cact * D, [&] {
+            lrr::launch_update_Z(b.Q, b.MtV, b.J, b.Z, b.Y2, b.R2r, b.r2nrm, n, n, c, b.colblk, bst, b.it, st);
         });
+        if (p.reduced) {
+            // max-norm of R2 = Qm R2r: decided by the column 2-norm bounds, else expanded
+            tm("k_r2_decide", 0.0, 0.0, [&] {
+                lrr::launch_r2_decide(bst, b.r2nrm, b.expand, t, o.tol, std::sqrt((double)nfull), st);
+            });
+            tm("k_dgemm<false, false>", 0.0, 0.0, [&] {
+                lrr::launch_dgemm(b.g_exp, t, nfull, p.maxl, false, false, st);
+            });
+            tm("k_colmax", 0.0, 0.0, [&] {
+                lrr::launch_colmax(b.R2full, nfull, nfull, c, b.colblk, b.expand, b.r2max, st);
+            });
+        }
         tm("k_estep", 0.0, 5.0 * m * cact * D, [&] {
             lrr::launch_estep(b.E, b.V, b.Y1, m, m, c, pr.lam, b.colblk, bst, b.it, st);
         });
@@ -1297,7 +1448,14 @@ lrr_status lrr_solve(lrr_ctx* ctx, int m, int n, int l, const void* A, int lda, 
         Plan p = make_plan(pr);
         Buffers b{};
         Result r = run_alm(ctx, pr, p, b, s, false);
-        lrr::launch_copy_cols(b.Z, n, static_cast<double*>(Z), ldz, n, l, s);
+        if (p.reduced) {
+            // Z = Qm Zr
+            GemmDesc gz{b.Qm, b.Z, static_cast<double*>(Z), n, l, p.nr, n, p.nr, ldz, 1.0, 0.0, nullptr, nullptr};
+            LRR_HIP(hipMemcpyAsync(b.g_U, &gz, sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+            lrr::launch_dgemm(b.g_U, 1, n, l, false, false, s);
+        } else {
+            lrr::launch_copy_cols(b.Z, n, static_cast<double*>(Z), ldz, n, l, s);
+        }
         if (E) lrr::launch_copy_cols(b.E, m, static_cast<double*>(E), lde, m, l, s);
         LRR_HIP(hipStreamSynchronize(s));
         fill_info(info, r, r.rank[0]);
@@ -1344,21 +1502,30 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
             for (int j = 0; j < n; ++j)
                 LRR_HIP(hipMemsetAsync(Zo + (size_t)j * ldz, 0, sizeof(double) * n, s));
         } else {
-            GemmDesc gU{b.Y, b.Wm[0], b.U, n, L0, l0, n, L0, n, 1.0, 0.0, nullptr, nullptr};
-            GemmDesc gH{b.U, b.J, b.H, L0, n, n, n, n, L0, 1.0, 0.0, nullptr, nullptr};
+            // in reduced coordinates U1 = Qm Ur with Ur = Yr W diag(h) and
+            // U1^T [J_1 ... J_t] = Ur^T [Jr_1 ... Jr_t]
+            const int nr = p.nr;
+            double* Uc = p.reduced ? b.Ur : b.U;
+            GemmDesc gU{b.Y, b.Wm[0], Uc, nr, L0, l0, nr, L0, nr, 1.0, 0.0, nullptr, nullptr};
+            GemmDesc gH{Uc, b.J, b.H, L0, n, nr, nr, nr, L0, 1.0, 0.0, nullptr, nullptr};
             GemmDesc gZ{b.U, b.H, Zo, n, n, L0, n, L0, ldz, 1.0, 0.0, nullptr, b.perm};
+            GemmDesc gQU{b.Qm, b.Ur, b.U, n, L0, nr, n, nr, n, 1.0, 0.0, nullptr, nullptr};
             GemmDesc hd[3] = {gU, gH, gZ};
             LRR_HIP(hipMemcpyAsync(b.g_U, &hd[0], sizeof(GemmDesc), hipMemcpyHostToDevice, s));
             LRR_HIP(hipMemcpyAsync(b.g_H, &hd[1], sizeof(GemmDesc), hipMemcpyHostToDevice, s));
             LRR_HIP(hipMemcpyAsync(b.g_Z, &hd[2], sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+            if (p.reduced) LRR_HIP(hipMemcpyAsync(b.g_red, &gQU, sizeof(GemmDesc), hipMemcpyHostToDevice, s));
             LrrProf& prof = ctx->prof;
             const int gm = p.pm.comb;
-            prof.run(s, "k_dgemm<false, false>", 2.0 * n * L0 * l0, 0.0,
-                     [&] { lrr::launch_dgemm(b.g_U, 1, n, L0, false, false, s); });
-            prof.run(s, "k_scale_cols", 0.0, 2.0 * n * L0 * sizeof(double),
-                     [&] { lrr::launch_scale_cols(b.U, n, n, L0, b.h[0], s); });
-            prof.run(s, lrr::xgemm_name(gm, true, false), 2.0 * L0 * n * n, 0.0,
+            prof.run(s, "k_dgemm<false, false>", 2.0 * nr * L0 * l0, 0.0,
+                     [&] { lrr::launch_dgemm(b.g_U, 1, nr, L0, false, false, s); });
+            prof.run(s, "k_scale_cols", 0.0, 2.0 * nr * L0 * sizeof(double),
+                     [&] { lrr::launch_scale_cols(Uc, nr, nr, L0, b.h[0], s); });
+            prof.run(s, lrr::xgemm_name(gm, true, false), 2.0 * L0 * n * nr, 0.0,
                      [&] { lrr::launch_xgemm(b.g_H, 1, L0, n, true, false, gm, s); });
+            if (p.reduced)
+                prof.run(s, "k_dgemm<false, false>", 2.0 * n * L0 * nr, 0.0,
+                         [&] { lrr::launch_dgemm(b.g_red, 1, n, L0, false, false, s); });
             prof.run(s, lrr::xgemm_name(gm, false, false), 2.0 * n * n * L0, 0.0,
                      [&] { lrr::launch_xgemm(b.g_Z, 1, n, n, false, false, gm, s); });
         }

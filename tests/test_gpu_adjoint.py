@@ -6,7 +6,10 @@ Loss L = ||W o |Z| ||_F^2 with a seeded W ~ U[0, 1]^{n x n}, so dL/dZ = 2 W^2 o 
 Tolerances: FP64 forward vs the oracle gradient, relative Frobenius error of dM
 and relative error of dlambda <= 1e-7 (both sides FP64; the eigen-decomposition
 of the Gram matrix and the SVD agree to rounding); finite differences with
-h = 1e-6 agree to 1e-5 relative (truncation h^2 and rounding 1e-16/h)."""
+h = 1e-6 agree to 1e-5 relative (truncation h^2 and rounding 1e-16/h).  The
+finite differences use full coordinates (the recorded forward does too): the
+reduced coordinates drop basis directions with sigma^2 <= 1e-14 sigma_max^2, and
+a perturbation h D of a rank-deficient M creates singular values of that size."""
 import numpy as np
 import pytest
 
@@ -76,7 +79,7 @@ def test_backward_matches_finite_differences_on_gpu():
     W = rng.uniform(0.0, 1.0, (p.n, p.n))
     fast = dict(mu0=0.05, rho=1.25)
     L, Z, dlam, dM, info = _gpu_grad(B, torch, p, W, _opts(B, 30, 10, **fast))
-    plain = B.lrr_opts_default(fixed_iters=30, **fast)
+    plain = B.lrr_opts_default(fixed_iters=30, coords=B.LRR_COORDS_FULL, **fast)
     h = 1e-6
     fd = (_loss_gpu(B, torch, p.M, p.lam + h, p, W, plain) - _loss_gpu(B, torch, p.M, p.lam - h, p, W, plain)) / (2 * h)
     say(f"[adjoint FD] dlam={dlam:.8e} fd={fd:.8e}")
@@ -135,3 +138,50 @@ def test_autograd_function_gradients():
     assert torch.equal(Zt.detach(), Zt2)
     assert torch.allclose(gM, dMt, rtol=0, atol=1e-12 * float(dMt.abs().max()))
     assert abs(float(gl) - dl) <= 1e-12 * abs(dl)
+
+
+def test_workload5_adjoint_vs_oracle_gradient_and_finite_differences():
+    """Workload 5 as stated: the workload-2 generator, 200 unrolled iterations,
+    checkpoints every 20, L = ||W o |Z| ||_F^2 with the seeded W.  The FP32
+    forward (the workload's form) and the FP64 forward are differentiated and
+    compared with the stored oracle gradient (written by tests/golden/make_golden.py
+    from the oracle only): dlambda, <dM, D> for two seeded directions, dM at 512
+    seeded positions (relative to max|dM|) and ||dM||_F, within 1e-4 for the FP32
+    forward and 1e-7 for the FP64 forward.  Central differences of the FP64 GPU
+    forward (h = 1e-6) check dlambda and one direction within 1e-5."""
+    import json
+    import os
+    from paper_1304_5583_amd import binding as B
+    from paper_1304_5583_amd.datagen import make_config
+    torch = need_gpu()
+    path = os.path.join(os.path.dirname(__file__), "golden", "workload5_gradient_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("gradient fingerprint not generated")
+    g = json.load(open(path))
+    p = make_config(5)
+    W = p.extra["W"]
+    K, every = p.extra["fixed_iters"], p.extra["checkpoint_every"]
+    rng = np.random.default_rng(4244)
+    idx = np.array(g["probe_idx"])
+    rng.integers(0, p.m, 512), rng.integers(0, p.n, 512)     # advance as the writer did
+    D = rng.standard_normal((2, p.m, p.n))
+    for prec, tol in ((1, 1e-4), (0, 1e-7)):
+        L, Z, dlam, dM, info = _gpu_grad(B, torch, p, W, _opts(B, K, every, prec))
+        e_l = abs(dlam - g["dlam"]) / abs(g["dlam"])
+        e_dir = max(abs(float(np.sum(dM * D[i])) - g["dM_dir"][i]) / abs(g["dM_dir"][i]) for i in range(2))
+        at = np.array([dM[i, j] for i, j in idx])
+        e_at = float(np.abs(at - np.array(g["dM_at"])).max() / np.abs(dM).max())
+        e_fro = abs(np.linalg.norm(dM) - g["dM_fro"]) / g["dM_fro"]
+        e_L = abs(L - g["loss"]) / g["loss"]
+        say(f"[workload 5 precision {prec}] loss rel={e_L:.2e} dlam={dlam:.8e} oracle={g['dlam']:.8e} rel={e_l:.2e} "
+            f"dir={e_dir:.2e} at={e_at:.2e} fro={e_fro:.2e}")
+        assert max(e_l, e_dir, e_at, e_fro, e_L) <= tol
+    plain = B.lrr_opts_default(fixed_iters=K, coords=B.LRR_COORDS_FULL)
+    h = 1e-6
+    fd = (_loss_gpu(B, torch, p.M, p.lam + h, p, W, plain) - _loss_gpu(B, torch, p.M, p.lam - h, p, W, plain)) / (2 * h)
+    fdm = (_loss_gpu(B, torch, p.M + h * D[0], p.lam, p, W, plain) -
+           _loss_gpu(B, torch, p.M - h * D[0], p.lam, p, W, plain)) / (2 * h)
+    ad = float(np.sum(dM * D[0]))     # FP64 forward, the last pass of the loop above
+    say(f"  FD dlam={fd:.8e} gpu={dlam:.8e}  FD <dM, D0>={fdm:.8e} gpu={ad:.8e}")
+    assert abs(fd - dlam) <= 1e-5 * abs(fd)
+    assert abs(fdm - ad) <= 1e-5 * abs(fdm)

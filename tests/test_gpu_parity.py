@@ -233,3 +233,44 @@ def test_graph_replay_matches_eager_launches(prec):
         for Zt, St, it in runs:
             assert it == ref[2]
             assert bool((Zt == ref[0]).all()) and bool((St == ref[1]).all())
+
+
+@pytest.mark.parametrize("coords", [1, 2])
+@pytest.mark.parametrize("seed,m,t,uneven", [(51, 40, 3, (30, 44)), (52, 150, 4, None)])
+def test_full_and_reduced_coordinates_vs_oracle(coords, seed, m, t, uneven):
+    """Both coordinate choices of the n-row iterates against the oracle, on a
+    wide dictionary (n > m) and on a tall one (m > n, where reduced coordinates
+    keep all n directions)."""
+    import oracle
+    from paper_1304_5583_amd.datagen import small_problem
+    need_gpu()
+    p = small_problem(seed, m=m, k=3, r=4, ns=35, n_replace=8, t=t, lam=0.3, uneven=uneven)
+    say(f"[coords {coords} s{seed}] m={p.m} n={p.n} t={p.t}")
+    Zg, Sg, info = _gpu_dfc(p, coords=coords)
+    with one_thread():
+        ref = oracle.dfc_lrr(p.M, p.lam, p.perm, p.offsets)
+    ez, es = rel(Zg, ref.Z), rel(Sg, ref.S)
+    say(f"  relZ={ez:.2e} relS={es:.2e} iters={info.iters.tolist()} oracle={[b.iters for b in ref.blocks]}")
+    assert info.status == 0 and ez <= TOL_Z and es <= TOL_Z
+    assert np.all(np.abs(info.iters - np.array([b.iters for b in ref.blocks])) <= 1)
+    assert info.rank.tolist() == [b.rank for b in ref.blocks]
+
+
+def test_reduced_coordinates_rank_deficient_dictionary():
+    """A dictionary of numerical rank 12 < m = 60 < n: the basis keeps 12
+    directions; LRR on it matches the oracle."""
+    import oracle
+    from paper_1304_5583_amd import binding as B
+    need_gpu()
+    rng = np.random.default_rng(53)
+    A = rng.standard_normal((60, 12)) @ rng.standard_normal((12, 90))
+    X = A[:, :30] + 0.01 * rng.standard_normal((60, 30))
+    for coords in (1, 2):
+        Zt, Et, info = B.lrr_solve(B.to_device_colmajor(A), B.to_device_colmajor(X), 0.2,
+                                   opts=B.lrr_opts_default(coords=coords))
+        with one_thread():
+            ref = oracle.lrr_alm(X, A, 0.2)
+        ez = rel(B.from_device_colmajor(Zt), ref.Z)
+        say(f"[rank-deficient coords {coords}] relZ={ez:.2e} iters={info.iters.tolist()} oracle={ref.iters}")
+        assert info.status == 0 and ez <= TOL_Z
+        assert abs(int(info.iters[0]) - ref.iters) <= 1
