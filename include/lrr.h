@@ -85,7 +85,8 @@ typedef enum {
  * only when the bounds do not decide the stop test.  Basis directions with
  * sigma^2 <= 1e-14 sigma_max^2 are dropped. */
 typedef enum {
-    LRR_COORDS_AUTO = 0,     /* reduced when n > m (never for a recorded forward)   */
+    LRR_COORDS_AUTO = 0,     /* reduced when n >= 2m (the basis costs an m x m      */
+                             /* eigensolve), never for a recorded forward           */
     LRR_COORDS_FULL = 1,
     LRR_COORDS_REDUCED = 2
 } lrr_coords;

@@ -89,6 +89,7 @@ struct RefDesc {
     double* eprev;      // previous step's largest correction
     int* run;           // refinement step applied to this matrix
     int* cont;          // refinement continues after this step
+    double* Xb;         // L x L copy of X before the refinement (restored if it fails)
     int L, l, block;
 };
 

@@ -30,13 +30,13 @@ void launch_jacobi_sweep_end(const EigDesc* d_descs, int count, int* d_any, hipS
 void launch_jacobi_eigvals(const EigDesc* d_descs, int count, hipStream_t s);
 
 // refsyev.hip
-void launch_ref_begin(const RefDesc* d, int count, const int* svt_run, const int* warm, hipStream_t s);
+void launch_ref_begin(const RefDesc* d, int count, int maxL, const int* svt_run, const int* warm, hipStream_t s);
 void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, hipStream_t s);
 void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s);
 void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s);
 void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, int* n_open, hipStream_t s);
 void launch_ref_next(const RefDesc* d, int count, hipStream_t s);
-void launch_orth_guard(const RefDesc* d, int count, int maxL, hipStream_t s);
+void launch_orth_guard(const RefDesc* d, int count, int maxL, const int* warm, hipStream_t s);
 void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hipStream_t s);
 void launch_orth_E(const RefDesc* d, int count, int maxL, hipStream_t s);
 void launch_ref_set_run(const RefDesc* d, int count, const int* svt_run, hipStream_t s);

@@ -230,15 +230,27 @@ __global__ __launch_bounds__(256) void k_orth_E(const RefDesc* __restrict__ desc
 }
 
 // a matrix whose estimate lost orthogonality restarts from the identity
-__global__ __launch_bounds__(256) void k_orth_guard(const RefDesc* __restrict__ descs) {
+// A refinement that lost orthogonality is discarded: X returns to the previous
+// iteration's eigenvectors (the identity on a block's first decomposition),
+// from which the Jacobi sweeps finish the decomposition.
+__global__ __launch_bounds__(256) void k_orth_guard(const RefDesc* __restrict__ descs, const int* __restrict__ warm) {
     const RefDesc d = descs[blockIdx.y];
     if (d.run[0] == 0) return;
     const double dev = __longlong_as_double((long long)d.emax[0]);
     if (!(dev <= kOrthTol)) {
         const long L = d.L;
         const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-        if (idx < L * L) d.X[idx] = ((idx % L) == (idx / L)) ? 1.0 : 0.0;
+        if (idx < L * L) d.X[idx] = warm[d.block] ? d.Xb[idx] : (((idx % L) == (idx / L)) ? 1.0 : 0.0);
     }
+}
+
+// X is kept before a refinement starts
+__global__ __launch_bounds__(256) void k_ref_backup(const RefDesc* __restrict__ descs) {
+    const RefDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0) return;
+    const long L = d.L;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx < L * L) d.Xb[idx] = d.X[idx];
 }
 
 __global__ void k_orth_reset(const RefDesc* __restrict__ descs, int count) {
@@ -267,9 +279,9 @@ void launch_orth_E(const RefDesc* d, int count, int maxL, hipStream_t s) {
     hipLaunchKernelGGL(k_orth_reset, dim3((count + 63) / 64), dim3(64), 0, s, d, count);
     hipLaunchKernelGGL(k_orth_E, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d);
 }
-void launch_orth_guard(const RefDesc* d, int count, int maxL, hipStream_t s) {
+void launch_orth_guard(const RefDesc* d, int count, int maxL, const int* warm, hipStream_t s) {
     const long n = (long)maxL * maxL;
-    hipLaunchKernelGGL(k_orth_guard, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_orth_guard, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d, warm);
 }
 void launch_ref_next(const RefDesc* d, int count, hipStream_t s) {
     hipLaunchKernelGGL(k_ref_next, dim3((count + 63) / 64), dim3(64), 0, s, d, count);
@@ -281,9 +293,11 @@ void launch_mark_warm(const int* svt_run, int* warm, int t, hipStream_t s) {
     hipLaunchKernelGGL(k_mark_warm, dim3((t + 63) / 64), dim3(64), 0, s, svt_run, warm, t);
 }
 
-void launch_ref_begin(const RefDesc* d, int count, const int* svt_run, const int* warm, hipStream_t s) {
+void launch_ref_begin(const RefDesc* d, int count, int maxL, const int* svt_run, const int* warm, hipStream_t s) {
+    const long n = (long)maxL * maxL;
     hipLaunchKernelGGL(k_ref_begin, dim3((count + 63) / 64), dim3(64), 0, s, d, count, svt_run, warm);
     hipLaunchKernelGGL(k_ref_scale, dim3(count), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_ref_backup, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d);
 }
 void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, hipStream_t s) {
     hipLaunchKernelGGL(k_ref_rows, dim3(maxL, count), dim3(256), 0, s, d, it);

@@ -473,7 +473,7 @@ Plan make_plan(const Problem& pr) {
     // the reverse-mode record keeps full coordinates
     const int coords = pr.o.coords;
     p.reduced = coords == LRR_COORDS_REDUCED ||
-                (coords == LRR_COORDS_AUTO && pr.n > pr.m && !pr.o.save_for_backward);
+                (coords == LRR_COORDS_AUTO && pr.n >= 2 * pr.m && !pr.o.save_for_backward);
     if (pr.o.save_for_backward) p.reduced = false;
     p.nrb = p.reduced ? std::min(pr.m, pr.n) : pr.n;
     p.nr = p.nrb;
@@ -626,7 +626,7 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         svt[bb] = SvtDesc{b.Bq[bb], X, b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
         ref[bb] = RefDesc{b.Bm[bb], X, b.SG[bb], b.Eb[bb], b.XE[bb], b.lam[bb], b.lo[bb], b.ref_scale + bb,
                           b.ref_emax + bb, b.ref_unres + bb, b.ref_eprev + bb, b.ref_run + bb,
-                          b.ref_cont + bb, L, l, bb};
+                          b.ref_cont + bb, b.Bq[bb], L, l, bb};
     }
     GemmDesc gKK{pr.A, pr.A, b.K, m, m, n, (int)pr.lda, (int)pr.lda, m, 1.0, 0.0, nullptr, nullptr};
 
@@ -826,7 +826,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 lrr::launch_dgemm(b.g_gram, t, p.maxl, p.maxl, true, false, s);
             });
             // Newton refinement of the previous iteration's eigenvectors
-            timed("k_ref_begin", 0.0, 0.0, [&] { lrr::launch_ref_begin(b.ref, t, b.svt_run, b.warm, s); });
+            timed("k_ref_begin", 0.0, 0.0, [&] { lrr::launch_ref_begin(b.ref, t, p.maxL, b.svt_run, b.warm, s); });
             std::vector<int> h_ref(t, 0);
             LRR_HIP(hipMemcpyAsync(h_ref.data(), b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
             sync();
@@ -873,7 +873,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 });
                 timed("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, s); });
             }
-            timed("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, s); });
+            timed("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, b.warm, s); });
             timed("k_dgemm<false, false>", f_L3, 0.0, [&] {
                 lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, s);
             });
