@@ -57,6 +57,11 @@ lrr_status lrr_diag_syevj(lrr_ctx *ctx, int count, const int *l, const double *B
  * bytes (column kernels: every matrix element read or written once) of each
  * launch.  lrr_prof_enable also clears the table. */
 lrr_status lrr_prof_enable(lrr_ctx *ctx, int on);
+/* Restrict the timing to kernels whose name starts with `prefix` (NULL or "":
+ * all kernels), so that the events bracket only the launches of interest.  The
+ * Z-step/E-step chain is replayed from its graph unless one of its kernels is
+ * being timed. */
+lrr_status lrr_prof_filter(lrr_ctx *ctx, const char *prefix);
 int lrr_prof_count(const lrr_ctx *ctx);
 /* Entry idx (0 <= idx < lrr_prof_count): name (owned by ctx), total ms, number
  * of launches, total algorithmic flops and bytes. */

@@ -47,6 +47,7 @@ struct LrrProf {
         double flops, bytes;
     };
     bool on = false;
+    std::string filter;          // time only kernels whose name starts with this (empty: all)
     std::vector<Entry> entries;
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
@@ -67,9 +68,12 @@ struct LrrProf {
         pool.pop_back();
         return e;
     }
+    bool wants(const char* name) const {
+        return on && (filter.empty() || std::strncmp(name, filter.c_str(), filter.size()) == 0);
+    }
     template <class F>
     void run(hipStream_t s, const char* name, double flops, double bytes, F&& f) {
-        if (!on) { f(); return; }
+        if (!wants(name)) { f(); return; }
         hipEvent_t a = get(), b = get();
         LRR_HIP(hipEventRecord(a, s));
         f();
@@ -785,7 +789,11 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     auto untimed = [](const char*, double, double, auto&& f) { f(); };
     // graphs of the chain (plain and re-anchoring iterations); per-kernel
     // timing needs the launches one by one, so profiling runs them eagerly
-    const bool use_graph = o.use_graph != 0 && !prof.on;
+    const bool chain_timed = prof.wants("k_form_QT") || prof.wants(lrr::xgemm_name(pm.MQ, false, false)) ||
+                             prof.wants("k_dgemm<false, false>") || prof.wants(lrr::xgemm_name(pm.MtV, true, false)) ||
+                             prof.wants("k_sub_cols") || prof.wants("k_update_Z") || prof.wants("k_r2_decide") ||
+                             prof.wants("k_colmax") || prof.wants("k_estep") || prof.wants("k_check");
+    const bool use_graph = o.use_graph != 0 && !chain_timed;
     hipGraphExec_t g_plain = nullptr, g_anchor = nullptr;
     hipStream_t cs = use_graph ? ctx_capture_stream(ctx) : nullptr;
     struct GraphGuard {
@@ -1549,6 +1557,12 @@ lrr_status lrr_prof_enable(lrr_ctx* ctx, int on) {
     ctx->prof.flush();
     ctx->prof.entries.clear();
     ctx->prof.on = on != 0;
+    return LRR_OK;
+}
+
+lrr_status lrr_prof_filter(lrr_ctx* ctx, const char* prefix) {
+    if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
+    ctx->prof.filter = prefix ? prefix : "";
     return LRR_OK;
 }
 
