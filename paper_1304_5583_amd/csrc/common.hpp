@@ -70,8 +70,10 @@ struct EigDesc {
     int* st;            // [0] converged, [1] pairs that rotated in the current sweep
     double* scale;      // max |diag| of B at the start, for the absolute floor
     int* prot;          // per pair of the current round: 1 if it rotated
-    int* lo;            // per index: Gershgorin disc below tau^2 (pairs of two such are skipped)
+    int* lo;            // per index: Gershgorin disc below the cut (pairs of two such are skipped)
     unsigned long long* work;  // [0] FP64 operations of the pair solves, [1] of the tile updates
+    const double* cut;  // cut factor nu of the block: lo when the disc lies below min(tau^2, nu * scale)
+    int* passes;        // sweep-loop passes of the current eigensolve (counted while open)
 };
 
 // Warm-started eigenvector refinement of one Gram matrix (see refsyev.hip).
@@ -90,6 +92,7 @@ struct RefDesc {
     int* run;           // refinement step applied to this matrix
     int* cont;          // refinement continues after this step
     double* Xb;         // L x L copy of X before the refinement (restored if it fails)
+    const double* cut;  // cut factor of the block (as EigDesc::cut)
     int L, l, block;
 };
 

@@ -40,6 +40,7 @@ void launch_orth_guard(const RefDesc* d, int count, int maxL, const int* warm, h
 void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hipStream_t s);
 void launch_orth_E(const RefDesc* d, int count, int maxL, hipStream_t s);
 void launch_ref_set_run(const RefDesc* d, int count, const int* svt_run, hipStream_t s);
+void launch_lo_mode(const int* svt_run, const int* warm, int* passes, double* cut, int t, hipStream_t s);
 void launch_mark_warm(const int* svt_run, int* warm, int t, hipStream_t s);
 
 // alm.hip

@@ -14,10 +14,18 @@
 //
 // A pair (i, j) is resolvable when |s_ij + lambda_j r_ij| <= 0.1 |lambda_j -
 // lambda_i| (inside the linear regime of the update) and the two Gershgorin
-// discs of S are not both below tau^2: every eigenvalue whose disc lies below
-// tau^2 is discarded by the threshold step, so rotations among such indices
-// cannot change the result.  Couplings that stay unresolvable are left to the
-// block-Jacobi sweeps that follow.
+// discs of S are not both below the cut min(tau^2, nu scale): every eigenvalue
+// whose disc lies below tau^2 is discarded by the threshold step, so rotations
+// among such indices cannot change the result.  Couplings that stay
+// unresolvable are left to the block-Jacobi sweeps that follow.
+//
+// The cut factor nu is per block and starts at 0 (every eigenpair resolved):
+// the eigenvectors below tau^2 are the ones that cross the threshold as tau
+// shrinks, and while the refinement carries them from one iteration to the
+// next they cost nothing.  A warm eigensolve that still needs more than
+// kSwitchSweeps Jacobi sweeps shows that they are not carried (a spread of
+// small, drifting eigenvalues); from then on that block leaves the eigenpairs
+// below min(tau^2, kLoCut scale) unresolved.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -30,6 +38,14 @@ constexpr double kFirstStepCap = 0.1;    // largest correction accepted in the f
 constexpr double kOrthTol = 1e-6;         // |I - X^T X| above this after one step: restart cold
 constexpr double kRelTol = 1e-15;
 constexpr double kAbsFloor = 1e-14;
+constexpr double kLoCut = 1e-2;           // cut factor after the switch
+constexpr int kSwitchSweeps = 8;          // warm sweeps that trigger it
+
+// lo flag of one index from its Gershgorin disc: skipped only below both tau^2
+// and the block's cut
+__device__ __forceinline__ int lo_flag(double disc, double tau, double nu, double scale) {
+    return disc < fmin(tau * tau * (1.0 - 1e-9), nu * scale) ? 1 : 0;
+}
 
 // row pass: lambda_i, Gershgorin flag lo_i of S (padding: lambda 0, lo 1)
 __global__ __launch_bounds__(256) void k_ref_rows(const RefDesc* __restrict__ descs, const DevIter* it) {
@@ -53,7 +69,7 @@ __global__ __launch_bounds__(256) void k_ref_rows(const RefDesc* __restrict__ de
         if (i < d.l) {
             const double sii = S[i + i * L];
             d.lam[i] = sii / G[i + i * L];
-            d.lo[i] = (!it->full && sii + r < tau * tau * (1.0 - 1e-9)) ? 1 : 0;
+            d.lo[i] = it->full ? 0 : lo_flag(sii + r, tau, d.cut[0], d.scale[0]);
         } else {
             d.lam[i] = 0.0;
             d.lo[i] = 1;
@@ -199,8 +215,20 @@ __global__ __launch_bounds__(256) void k_lo_rows(const EigDesc* __restrict__ des
     if (threadIdx.x == 0) {
         const double r = (red[0] + red[1]) + (red[2] + red[3]);
         const double tau = it->tau;
-        d.lo[i] = (i >= d.l) ? 1 : ((!it->full && d.B[i + i * L] + r < tau * tau * (1.0 - 1e-9)) ? 1 : 0);
+        d.lo[i] = (i >= d.l) ? 1 : (it->full ? 0 : lo_flag(d.B[i + i * L] + r, tau, d.cut[0], d.scale[0]));
+        if (i == 0) d.passes[0] += 1;
     }
+}
+
+// end of a block's eigensolve: a warm solve that needed many sweeps switches
+// the block to the cut kLoCut (for the rest of the solve); counters restart
+__global__ void k_lo_mode(const int* __restrict__ svt_run, const int* __restrict__ warm, int* __restrict__ passes,
+                          double* __restrict__ cut, int t) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= t) return;
+    // passes = sweeps + 1 (the last pass finds nothing to rotate)
+    if (svt_run[b] && warm[b] && cut[b] == 0.0 && passes[b] > kSwitchSweeps + 1) cut[b] = kLoCut;
+    passes[b] = 0;
 }
 
 // orthogonalisation step (Newton-Schulz for the polar factor): E = (I - G)/2,
@@ -288,6 +316,9 @@ void launch_ref_next(const RefDesc* d, int count, hipStream_t s) {
 }
 void launch_ref_set_run(const RefDesc* d, int count, const int* svt_run, hipStream_t s) {
     hipLaunchKernelGGL(k_ref_set_run, dim3((count + 63) / 64), dim3(64), 0, s, d, count, svt_run);
+}
+void launch_lo_mode(const int* svt_run, const int* warm, int* passes, double* cut, int t, hipStream_t s) {
+    hipLaunchKernelGGL(k_lo_mode, dim3((t + 63) / 64), dim3(64), 0, s, svt_run, warm, passes, cut, t);
 }
 void launch_mark_warm(const int* svt_run, int* warm, int t, hipStream_t s) {
     hipLaunchKernelGGL(k_mark_warm, dim3((t + 63) / 64), dim3(64), 0, s, svt_run, warm, t);

@@ -193,7 +193,8 @@ struct Buffers {
     DevIter* it;
     std::vector<double*> Bm, Wm, Wg, Pm, Rm, lam, h, TX, SG, Eb, XE, Bq;
     std::vector<int*> lo;
-    int *warm, *ref_run, *ref_unres, *ref_cont;
+    int *warm, *ref_run, *ref_unres, *ref_cont, *passes;
+    double* locut;
     double *ref_eprev, *ref_scale;
     unsigned long long* ref_emax;
     GemmDesc *g_gram, *g_refT, *g_refSG, *g_refXE, *g_orthG, *g_Bq, *g_P, *g_J, *g_MQ, *g_MQa, *g_KV, *g_MtV, *g_U, *g_H,
@@ -280,6 +281,8 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
         b.prot[i] = a.take<int>(L / (2 * p.bs) + 1);
     }
     b.warm = a.take<int>(t);
+    b.passes = a.take<int>(t);
+    b.locut = a.take<double>(t);
     b.ref_run = a.take<int>(t);
     b.ref_cont = a.take<int>(t);
     b.ref_unres = a.take<int>(t);
@@ -626,11 +629,11 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
             gExp[bb] = GemmDesc{b.Qm, b.R2r + o_n, b.R2full + (size_t)p.boff[bb] * n, n, l, nr, n, nr, n, 1.0,
                                 0.0, b.expand + bb, nullptr};
         eig[bb] = EigDesc{b.Bq[bb], X, b.Rm[bb], b.lam[bb], L, l, run, b.eigst + 2 * bb,
-                          b.eigscale + bb, b.prot[bb], b.lo[bb], ctx->dwork};
+                          b.eigscale + bb, b.prot[bb], b.lo[bb], ctx->dwork, b.locut + bb, b.passes + bb};
         svt[bb] = SvtDesc{b.Bq[bb], X, b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
         ref[bb] = RefDesc{b.Bm[bb], X, b.SG[bb], b.Eb[bb], b.XE[bb], b.lam[bb], b.lo[bb], b.ref_scale + bb,
                           b.ref_emax + bb, b.ref_unres + bb, b.ref_eprev + bb, b.ref_run + bb,
-                          b.ref_cont + bb, b.Bq[bb], L, l, bb};
+                          b.ref_cont + bb, b.Bq[bb], b.locut + bb, L, l, bb};
     }
     GemmDesc gKK{pr.A, pr.A, b.K, m, m, n, (int)pr.lda, (int)pr.lda, m, 1.0, 0.0, nullptr, nullptr};
 
@@ -687,6 +690,8 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     up(b.active, ones.data(), sizeof(int) * t);
     LRR_HIP(hipMemsetAsync(b.iters, 0, sizeof(int) * t, s));
     LRR_HIP(hipMemsetAsync(b.warm, 0, sizeof(int) * t, s));
+    LRR_HIP(hipMemsetAsync(b.passes, 0, sizeof(int) * t, s));
+    LRR_HIP(hipMemsetAsync(b.locut, 0, sizeof(double) * t, s));   // every eigenpair resolved at first
     LRR_HIP(hipMemsetAsync(b.rank, 0, sizeof(int) * t, s));
     LRR_HIP(hipMemsetAsync(b.r1max, 0, sizeof(unsigned long long) * t, s));
     LRR_HIP(hipMemsetAsync(b.r2max, 0, sizeof(unsigned long long) * t, s));
@@ -919,6 +924,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             timed("k_dgemm<false, false>", f_J, 0.0, [&] {
                 lrr::launch_dgemm(b.g_J, t, n, p.maxl, false, false, s);
             });
+            timed("k_lo_mode", 0.0, 0.0, [&] { lrr::launch_lo_mode(b.svt_run, b.warm, b.passes, b.locut, t, s); });
             timed("k_mark_warm", 0.0, 0.0, [&] { lrr::launch_mark_warm(b.svt_run, b.warm, t, s); });
         }
         // Z-step (push-through) and E-step: the same launches in every iteration
