@@ -1,4 +1,5 @@
-"""Thin ctypes binding of the gfx950 DFC-LRR library (include/lrr.h, include/lrr_diag.h).
+"""Thin ctypes binding of the gfx950 DFC-LRR library (include/lrr.h, include/lrr_diag.h,
+include/lrr_segment.h).
 
 Argument marshalling only: every step of the solve runs in the HIP library.
 Matrices are torch tensors on the GPU.  The library is column-major; a
@@ -36,6 +37,14 @@ class lrr_opts(C.Structure):
         ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("check_every", C.c_int),
         ("max_sweeps", C.c_int), ("save_for_backward", C.c_int), ("checkpoint_every", C.c_int),
         ("eig_block", C.c_int), ("use_graph", C.c_int), ("coords", C.c_int), ("reserved", C.c_int * 5),
+    ]
+
+
+class lrr_seg_info(C.Structure):
+    _fields_ = [
+        ("rank", C.c_int), ("range_rank", C.c_int), ("sketch", C.c_int), ("embed_iters", C.c_int),
+        ("embed_resid", C.c_double), ("theta_k", C.c_double), ("theta_k1", C.c_double),
+        ("kmeans_iters", C.c_int), ("n_keep", C.c_int),
     ]
 
 
@@ -95,6 +104,8 @@ def load_library(path: str = LIB_PATH):
     lib.lrr_diag_spd_inverse.restype = i
     lib.lrr_diag_syevj.argtypes = [vp, i, ip, vp, i, C.c_long, vp, i, vp, i, ip, vp]
     lib.lrr_diag_syevj.restype = i
+    lib.lrr_segment.argtypes = [vp, i, vp, i, i, vp, d, i, vp, C.POINTER(lrr_seg_info), vp]
+    lib.lrr_segment.restype = i
     _lib = lib
     return lib
 
@@ -319,6 +330,40 @@ def lrr_diag_syevj(Bs, ls, eig_block: int = 16, ctx: Context | None = None):
                                        _stream(torch, Bs.device))
     _check(st, ctx, allow_nc=False)
     return lam, W, sw.value
+
+
+def lrr_segment(Zt, k: int, exclude=None, rank_tol: float = 1e-6, rank_bound: int = 0,
+                ctx: Context | None = None):
+    """Cluster labels of the n points from Z (Section 4.1.2 pipeline, include/lrr_segment.h).
+
+    Zt: (n, n) float64 CUDA tensor holding the column-major Z (as returned by
+    ``lrr_solve`` / ``dfc_lrr_solve``).  exclude: None or a length-n bool/uint8
+    array or tensor (True: point left out, label -1).  Returns (labels, info)
+    with labels an int64 CUDA tensor of length n and info a dict of
+    ``lrr_seg_info``; info["converged"] is False when the call returned
+    LRR_NOT_CONVERGED."""
+    import torch
+    _require_cuda_f64(torch, Zt)
+    n = Zt.shape[0]
+    if Zt.shape != (n, n):
+        raise ValueError("Zt must be square")
+    ctx = ctx or get_context(Zt.device.index or 0)
+    ex = None
+    if exclude is not None:
+        ex = torch.as_tensor(np.asarray(exclude.cpu() if torch.is_tensor(exclude) else exclude).astype(np.uint8),
+                             device=Zt.device)
+        if ex.numel() != n:
+            raise ValueError("exclude must have n entries")
+    labels = torch.empty(n, dtype=torch.int64, device=Zt.device)
+    info = lrr_seg_info()
+    st = load_library().lrr_segment(ctx.handle, n, C.c_void_p(Zt.data_ptr()), int(Zt.stride(0)), int(k),
+                                    C.c_void_p(ex.data_ptr()) if ex is not None else None, float(rank_tol),
+                                    int(rank_bound), C.c_void_p(labels.data_ptr()), C.byref(info),
+                                    _stream(torch, Zt.device))
+    _check(st, ctx, allow_nc=True)
+    out = {f: getattr(info, f) for f, _ in lrr_seg_info._fields_}
+    out["converged"] = st == LRR_OK
+    return labels, out
 
 
 # ---------------------------------------------------------------- layout helpers

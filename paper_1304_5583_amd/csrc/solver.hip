@@ -117,6 +117,8 @@ struct lrr_ctx {
     unsigned long long* dwork = nullptr;   // operation counters of the Jacobi kernels
     Tape* tape = nullptr;
     hipStream_t capture = nullptr;         // private stream for graph capture
+    void* seg_ws = nullptr;                // workspace of lrr_segment (kept apart from the solver's)
+    size_t seg_bytes = 0;
 };
 
 namespace {
@@ -1357,6 +1359,21 @@ namespace {
 namespace lrr {
 lrr_status ctx_fail(lrr_ctx* ctx, lrr_status st, const std::string& msg) { return fail(ctx, st, msg); }
 int ctx_device(const lrr_ctx* ctx) { return ctx ? ctx->device : 0; }
+void* ctx_seg_workspace(lrr_ctx* ctx, size_t bytes) {
+    if (ctx->seg_bytes < bytes) {
+        if (ctx->seg_ws) { (void)hipFree(ctx->seg_ws); ctx->seg_ws = nullptr; ctx->seg_bytes = 0; }
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) throw std::bad_alloc();
+        ctx->seg_ws = p;
+        ctx->seg_bytes = bytes;
+    }
+    return ctx->seg_ws;
+}
+void ctx_timed(lrr_ctx* ctx, hipStream_t s, const char* name, double flops, double bytes,
+               const std::function<void()>& f) {
+    ctx->prof.run(s, name, flops, bytes, f);
+}
+void ctx_prof_flush(lrr_ctx* ctx) { ctx->prof.flush(); }
 }  // namespace lrr
 
 // ============================================================================
@@ -1403,6 +1420,7 @@ void lrr_ctx_destroy(lrr_ctx* ctx) {
     if (hipSetDevice(ctx->device) == hipSuccess) {
         ctx->prof.release();
         if (ctx->ws) (void)hipFree(ctx->ws);
+        if (ctx->seg_ws) (void)hipFree(ctx->seg_ws);
         if (ctx->dflag) (void)hipFree(ctx->dflag);
         if (ctx->dwork) (void)hipFree(ctx->dwork);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
