@@ -9,11 +9,10 @@
 //                  on sigma = sqrt(eigenvalue));
 //   affinity       A = U_keep U_keep^T (MFMA FP64 GEMM), then |A| scaled by
 //                  D^-1/2 on both sides in two passes over HBM;
-//   embedding      block subspace iteration on S = (L + I) / 2 (eigenvalues in
-//                  [0, 1], the same eigenvectors and order as L): X <- S X, then
-//                  the eigen-decomposition of (S X)^T (S X) re-orthonormalises
-//                  the block and aligns it with the Ritz vectors; converged when
-//                  the k leading columns satisfy |S x - theta x| <= tol;
+//   embedding      Chebyshev-filtered block subspace iteration with a
+//                  Rayleigh-Ritz step on L (FP64 GEMMs with the nk x nk
+//                  affinity), converged when the k leading Ritz vectors satisfy
+//                  |L x - theta x| <= tol;
 //   k-means        farthest-point seeding in one workgroup, Lloyd steps with
 //                  one thread per point (assignment) and one per (cluster,
 //                  coordinate) (centre update, a sequential sum in point order,
@@ -43,6 +42,7 @@ int ctx_device(const lrr_ctx* ctx);
 void* ctx_seg_workspace(lrr_ctx* ctx, size_t bytes);
 void ctx_timed(lrr_ctx* ctx, hipStream_t s, const char* name, double flops, double bytes,
                const std::function<void()>& f);
+void ctx_prof_flush(lrr_ctx* ctx);   // after the stream is synchronised
 }  // namespace lrr
 
 namespace {
@@ -52,8 +52,10 @@ using lrr::GemmDesc;
 
 constexpr int kSketchExtra = 16;       // sketch columns beyond the rank bound
 constexpr double kRangeCut = 1e-14;    // eigenvalue cut of Y^T Y for the range basis
-constexpr double kEmbedTol = 1e-10;    // residual |S x - theta x| of the embedding
-constexpr int kEmbedMaxIter = 3000;
+constexpr double kEmbedTol = 2e-10;    // residual |L x - theta x| of the embedding
+constexpr int kEmbedMaxOuter = 400;    // filter + Rayleigh-Ritz rounds
+constexpr double kSpread = 1e5;        // largest amplification ratio of one filter
+constexpr int kMaxDegree = 16;
 constexpr int kKmeansMaxIter = 300;
 constexpr int kMaxDirect = 8192;       // largest n without a sketch
 constexpr int kBs = 16;                // Jacobi block size (L is a multiple of 2 kBs)
@@ -167,12 +169,12 @@ __global__ __launch_bounds__(256) void k_norm_aff(double* __restrict__ A, long l
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) col[i] = fabs(col[i]) * s[i] * sj;
 }
 
-// largest |Y_j - theta_j X_j| over the k leading columns; theta_j = sqrt(lam[idx[j]])
+// largest |Y_j - theta_j X_j| over the k leading columns; theta_j = lam[idx[j]]
 __global__ __launch_bounds__(256) void k_resid(const double* __restrict__ Y, const double* __restrict__ X, long ld,
                                                int n, const double* __restrict__ lam, const int* __restrict__ idx,
                                                unsigned long long* __restrict__ out) {
     const int j = blockIdx.x;
-    const double th = sqrt(fmax(lam[idx[j]], 0.0));
+    const double th = lam[idx[j]];
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) {
         const double r = Y[i + (long)j * ld] - th * X[i + (long)j * ld];
@@ -198,6 +200,13 @@ __global__ __launch_bounds__(256) void k_rownorm(const double* __restrict__ X, l
     double nrm = sqrt(ss);
     if (nrm == 0.0) nrm = 1.0;
     for (int c = 0; c < k; ++c) Et[c + (long)i * k] = X[i + (long)c * ldx] / nrm;
+}
+
+// Z = beta X + gamma Y (element-wise over n values)
+__global__ __launch_bounds__(256) void k_axpby(const double* __restrict__ X, const double* __restrict__ Y,
+                                               double* __restrict__ Z, long n, double beta, double gamma) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) Z[i] = beta * X[i] + gamma * Y[i];
 }
 
 __device__ __forceinline__ double sqdist(const double* __restrict__ a, const double* __restrict__ b, int k) {
@@ -358,7 +367,7 @@ struct Eig {
 };
 
 struct Work {
-    double *Om, *Y, *Q0, *Q, *Gq, *Tq, *Wk, *Bt, *Qk, *Uk, *A, *s, *X, *Yb, *Et, *d2, *Ct;
+    double *Om, *Y, *Q0, *Q, *Gq, *Tq, *Wk, *Bt, *Qk, *Uk, *A, *s, *X, *LX, *LQ, *B0, *B1, *B2, *Et, *d2, *Ct;
     int *keep, *labA, *labB, *nchg;
     unsigned long long* res;
     GemmDesc* g;
@@ -379,7 +388,11 @@ size_t layout(Slab& a, Work& w, int n, int p, int nk, int k, int p2, int Lmax, b
     w.A = a.take<double>((size_t)nk * nk);
     w.s = a.take<double>(nk);
     w.X = a.take<double>((size_t)nk * p2);
-    w.Yb = a.take<double>((size_t)nk * p2);
+    w.LX = a.take<double>((size_t)nk * p2);
+    w.LQ = a.take<double>((size_t)nk * p2);
+    w.B0 = a.take<double>((size_t)nk * p2);
+    w.B1 = a.take<double>((size_t)nk * p2);
+    w.B2 = a.take<double>((size_t)nk * p2);
     w.Et = a.take<double>((size_t)nk * k);
     w.d2 = a.take<double>(nk);
     w.Ct = a.take<double>((size_t)k * k);
@@ -558,42 +571,102 @@ extern "C" lrr_status lrr_segment(lrr_ctx* ctx, int n, const void* Zv, int ldz, 
         });
 
         // ---- spectral embedding: k leading eigenvectors of L -------------------------
-        // start: uniform block in Yb, orthonormalised like every iterate
-        hipLaunchKernelGGL(k_fill_uniform, dim3(grid1((long)nk * p2)), dim3(256), 0, s, w.Yb, (long)nk, nk, p2,
-                           0xE3B0ull);
-        auto align = [&]() {
-            g.clear_eig(L3);
-            g.gemm(9, true, false, p2, p2, nk, 1.0, w.Yb, nk, w.Yb, nk, 0.0, e.A, L3);
-            g.eig(p2, L3, 0.0, 0);
-            hipLaunchKernelGGL(k_pick_cols, dim3(p2), dim3(256), 0, s, e.W, (long)L3, e.lam, e.idx, p2, 1, w.Wk,
-                               (long)p2);
-            g.gemm(10, false, false, nk, p2, p2, 1.0, w.Yb, nk, w.Wk, p2, 0.0, w.X, nk);
-        };
-        align();
-        int it = 0;
-        double resid = 0.0;
-        bool conv = false;
-        for (it = 0; it < kEmbedMaxIter; ++it) {
-            // Yb = S X = (L X + X) / 2
-            lrr::launch_copy_cols(w.X, nk, w.Yb, nk, nk, p2, s);
-            g.gemm(11, false, false, nk, p2, nk, 0.5, w.A, nk, w.X, nk, 0.5, w.Yb, nk);
-            if (it > 0) {
-                LRR_HIP(hipMemsetAsync(w.res, 0, sizeof(unsigned long long), s));
-                hipLaunchKernelGGL(k_resid, dim3(k), dim3(256), 0, s, w.Yb, w.X, (long)nk, nk, e.lam, e.idx, w.res);
-                unsigned long long rb = 0;
-                LRR_HIP(hipMemcpyAsync(&rb, w.res, sizeof(rb), hipMemcpyDeviceToHost, s));
-                g.sync();
-                std::memcpy(&resid, &rb, sizeof(double));
-                if (resid <= kEmbedTol) { conv = true; break; }
-            }
-            align();
-        }
-        // Ritz values of S for the report (theta_k, theta_k+1)
-        std::vector<double> lamh(p2);
+        // Chebyshev-filtered subspace iteration (Zhou and Saad, J. Comput. Phys.
+        // 2007) with a Rayleigh-Ritz step on L after each filter.  L has its
+        // spectrum in [-1, 1] (W >= 0 entry-wise, Perron root 1), so the filter
+        // T_m((t - c) / e), c and e mapping [-1, b] onto [-1, 1] and normalised
+        // to 1 at t = 1, damps everything below the smallest Ritz value b of the
+        // block and amplifies the eigenvalues above it.  Its degree is capped so
+        // that the filtered block stays within a condition number of about
+        // kSpread, which the two Gram passes of the orthonormalisation resolve.
+        double* B3[3] = {w.B0, w.B1, w.B2};
+        std::vector<double> lamh(p2), th(p2);
         std::vector<int> idxh(p2);
-        LRR_HIP(hipMemcpyAsync(lamh.data(), e.lam, sizeof(double) * p2, hipMemcpyDeviceToHost, s));
-        LRR_HIP(hipMemcpyAsync(idxh.data(), e.idx, sizeof(int) * p2, hipMemcpyDeviceToHost, s));
-        g.sync();
+        int products = 0;
+        // Y <- orthonormal basis of span(Y) (two passes of Y W diag(lam)^-1/2); tmp is scratch
+        auto orth = [&](double* Y, double* tmp) {
+            double* src = Y;
+            double* dst = tmp;
+            for (int pass = 0; pass < 2; ++pass) {
+                g.clear_eig(L3);
+                g.gemm(9, true, false, p2, p2, nk, 1.0, src, nk, src, nk, 0.0, e.A, L3);
+                g.eig(p2, L3, 0.0, 0);
+                hipLaunchKernelGGL(k_pick_cols, dim3(p2), dim3(256), 0, s, e.W, (long)L3, e.lam, e.idx, p2, 1,
+                                   w.Wk, (long)p2);
+                g.gemm(10, false, false, nk, p2, p2, 1.0, src, nk, w.Wk, p2, 0.0, dst, nk);
+                std::swap(src, dst);
+            }
+        };
+        // Rayleigh-Ritz on the orthonormal block Q: X = Ritz vectors (decreasing
+        // Ritz values th), LX = L X; returns the largest residual of the k leading ones
+        auto rayleigh_ritz = [&](const double* Q) {
+            g.gemm(11, false, false, nk, p2, nk, 1.0, w.A, nk, Q, nk, 0.0, w.LQ, nk);
+            ++products;
+            g.clear_eig(L3);
+            g.gemm(12, true, false, p2, p2, nk, 1.0, Q, nk, w.LQ, nk, 0.0, e.A, L3);
+            g.eig(p2, L3, 0.0, 0);
+            hipLaunchKernelGGL(k_pick_cols, dim3(p2), dim3(256), 0, s, e.W, (long)L3, e.lam, e.idx, p2, 0, w.Wk,
+                               (long)p2);
+            g.gemm(13, false, false, nk, p2, p2, 1.0, Q, nk, w.Wk, p2, 0.0, w.X, nk);
+            g.gemm(14, false, false, nk, p2, p2, 1.0, w.LQ, nk, w.Wk, p2, 0.0, w.LX, nk);
+            LRR_HIP(hipMemsetAsync(w.res, 0, sizeof(unsigned long long), s));
+            hipLaunchKernelGGL(k_resid, dim3(k), dim3(256), 0, s, w.LX, w.X, (long)nk, nk, e.lam, e.idx, w.res);
+            unsigned long long rb = 0;
+            LRR_HIP(hipMemcpyAsync(lamh.data(), e.lam, sizeof(double) * p2, hipMemcpyDeviceToHost, s));
+            LRR_HIP(hipMemcpyAsync(idxh.data(), e.idx, sizeof(int) * p2, hipMemcpyDeviceToHost, s));
+            LRR_HIP(hipMemcpyAsync(&rb, w.res, sizeof(rb), hipMemcpyDeviceToHost, s));
+            g.sync();
+            for (int j = 0; j < p2; ++j) th[j] = lamh[idxh[j]];
+            double r;
+            std::memcpy(&r, &rb, sizeof(double));
+            return r;
+        };
+        // Y = p_m(L) X / p_m(1), three-term recurrence on ratios of T_j(x0)
+        auto filter = [&](int m, double b) {
+            const double a = -1.0;
+            const double ee = 0.5 * (b - a), cc = 0.5 * (b + a);
+            const double x0 = (1.0 - cc) / ee;
+            double rp = 1.0 / x0;   // T_0(x0) / T_1(x0)
+            double* prev = w.X;
+            double* cur = B3[0];
+            double* nxt = B3[1];
+            lrr::launch_copy_cols(w.X, nk, cur, nk, nk, p2, s);
+            g.gemm(15, false, false, nk, p2, nk, rp / ee, w.A, nk, w.X, nk, -cc * rp / ee, cur, nk);
+            ++products;
+            for (int j = 1; j < m; ++j) {
+                const double rj = 1.0 / (2.0 * x0 - rp);   // T_j / T_{j+1}
+                const double al = 2.0 * rj / ee;
+                hipLaunchKernelGGL(k_axpby, dim3(grid1((long)nk * p2)), dim3(256), 0, s, cur, prev, nxt,
+                                   (long)nk * p2, -cc * al, -rp * rj);
+                g.gemm(15, false, false, nk, p2, nk, al, w.A, nk, cur, nk, 1.0, nxt, nk);
+                ++products;
+                rp = rj;
+                if (j == 1) { prev = B3[0]; cur = B3[1]; nxt = B3[2]; }
+                else { double* t0 = prev; prev = cur; cur = nxt; nxt = t0; }
+            }
+            return std::make_pair(cur, cur == B3[0] ? B3[1] : B3[0]);
+        };
+        hipLaunchKernelGGL(k_fill_uniform, dim3(grid1((long)nk * p2)), dim3(256), 0, s, B3[0], (long)nk, nk, p2,
+                           0xE3B0ull);
+        orth(B3[0], B3[1]);
+        double resid = rayleigh_ritz(B3[0]);
+        bool conv = resid <= kEmbedTol;
+        int outer = 0;
+        for (outer = 0; !conv && outer < kEmbedMaxOuter; ++outer) {
+            double b = th[p2 - 1];
+            const double gapk = th[k - 1] - b;
+            if (!(gapk > 1e-12)) b = th[k - 1] - 1e-12;   // flat block: keep the interval below theta_k
+            b = std::max(b, -0.999);                       // the interval [-1, b] must not be empty
+            const double ee = 0.5 * (b + 1.0), cc = 0.5 * (b - 1.0);
+            const double x0 = std::max((1.0 - cc) / ee, 1.0 + 1e-15);
+            int m = (int)std::floor(std::log(kSpread) / std::acosh(x0));
+            m = std::max(1, std::min(m, kMaxDegree));
+            auto yc = filter(m, b);
+            orth(yc.first, yc.second);
+            resid = rayleigh_ritz(yc.first);
+            conv = resid <= kEmbedTol;
+        }
+        const int it = products;
 
         // ---- k-means on the unit rows -------------------------------------------------
         g.timed("k_rownorm", 0.0, 0.0, [&] {
@@ -624,14 +697,15 @@ extern "C" lrr_status lrr_segment(lrr_ctx* ctx, int n, const void* Zv, int ldz, 
         hipLaunchKernelGGL(k_km_relabel, dim3(1), dim3(1024), 0, s, cur, w.keep, nk, k, labels);
         LRR_HIP(hipGetLastError());
         g.sync();
+        lrr::ctx_prof_flush(ctx);
         if (info) {
             info->rank = r;
             info->range_rank = q;
             info->sketch = p;
             info->embed_iters = it;
-            info->embed_resid = 2.0 * resid;
-            info->theta_k = 2.0 * std::sqrt(std::max(lamh[idxh[k - 1]], 0.0)) - 1.0;
-            info->theta_k1 = (p2 > k) ? 2.0 * std::sqrt(std::max(lamh[idxh[k]], 0.0)) - 1.0 : 0.0;
+            info->embed_resid = resid;
+            info->theta_k = th[k - 1];
+            info->theta_k1 = (p2 > k) ? th[k] : 0.0;
             info->kmeans_iters = std::min(kit + 1, kKmeansMaxIter);
             info->n_keep = nk;
         }
