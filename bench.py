@@ -156,12 +156,52 @@ def workload4_mixed(B, torch, ctx):
     smx, imx = _timed_solves(B, torch, p, Mt, Zmx, ctx, B.lrr_opts_default(precision=B.LRR_MIXED_BF16), 1)
     err = (torch.linalg.norm(Zmx - Z64) / torch.linalg.norm(Z64)).item()
     print(f"bench: workload 4: fp64 {s64:.2f}s mixed {smx:.2f}s err={err:.2e}", file=sys.stderr, flush=True)
+    del Zmx
     out = {"workload": p.name, "m": p.m, "n": p.n, "t": p.t, "fp64_solves_per_s": 1.0 / s64,
            "mixed_solves_per_s": 1.0 / smx, "speedup": s64 / smx, "err_vs_fp64_plain": err,
            "iters_fp64": [int(i64.iters.min()), int(i64.iters.max())],
-           "iters_mixed": [int(imx.iters.min()), int(imx.iters.max())]}
-    del Z64, Zmx, Mt
+           "iters_mixed": [int(imx.iters.min()), int(imx.iters.max())],
+           "segmentation": segmentation(B, torch, p, Z64, ctx, reps=1)}
+    del Z64, Mt
     torch.cuda.empty_cache()
+    return out
+
+
+def _accuracy(pred, truth):
+    """Section 4.1.2 segmentation accuracy: each cluster takes the majority true
+    label of its points; mean over classes of the fraction labelled correctly
+    (points labelled -1 on either side are skipped)."""
+    import numpy as np
+    keep = (pred >= 0) & (truth >= 0)
+    pred, truth = pred[keep], truth[keep]
+    vote = {c: np.bincount(truth[pred == c]).argmax() for c in np.unique(pred)}
+    mapped = np.array([vote[c] for c in pred])
+    return float(np.mean([np.mean(mapped[truth == g] == g) for g in np.unique(truth)]))
+
+
+def segmentation(B, torch, p, Zt, ctx, golden=None, reps=3):
+    """Section 4.1.2 labels from the solve's Z on the GPU (lrr_segment, range
+    sketch with the largest block width as rank bound): time per call, the
+    embedding's products with the affinity, and the labels against the stored
+    oracle labels (workloads with an oracle record) or the ground truth."""
+    import numpy as np
+    k = p.extra["k"]
+    bound = int(np.diff(p.offsets).max())
+    lab, info = B.lrr_segment(Zt, k, p.outliers, rank_bound=bound, ctx=ctx)   # sizes the workspace
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lab, info = B.lrr_segment(Zt, k, p.outliers, rank_bound=bound, ctx=ctx)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    got = lab.cpu().numpy()
+    out = {"ms": ms, "k": k, "n_keep": info["n_keep"], "rank": info["rank"], "sketch": info["sketch"],
+           "embed_products": info["embed_iters"], "embed_resid": info["embed_resid"],
+           "theta_k": info["theta_k"], "theta_k1": info["theta_k1"], "kmeans_iters": info["kmeans_iters"],
+           "accuracy_vs_truth": _accuracy(got, np.where(p.outliers, -1, p.labels))}
+    if golden is not None and "labels" in golden:
+        out["labels_equal_oracle"] = got.tolist() == golden["labels"]
+    print(f"bench: segmentation {p.name}: {ms:.1f} ms products {info['embed_iters']}", file=sys.stderr, flush=True)
     return out
 
 
@@ -316,6 +356,7 @@ def main():
         g = err[1]
         line["oracle_iters_per_block"] = g["iters"]
     if not args.no_extras:
+        line["segmentation"] = segmentation(B, torch, p, Zt, ctx, err[1] if err else None)
         line["forms"] = precision_forms(B, torch, p, Mt, Zt, ctx, args)
         line["workload4_mixed_vs_fp64"] = workload4_mixed(B, torch, ctx)
         line["workload5_adjoint"] = workload5_adjoint(B, torch, ctx)

@@ -13,7 +13,8 @@
 //                  Rayleigh-Ritz step on L (FP64 GEMMs with the nk x nk
 //                  affinity), converged when the k leading Ritz vectors satisfy
 //                  |L x - theta x| <= tol;
-//   k-means        farthest-point seeding in one workgroup, Lloyd steps with
+//   k-means        farthest-point seeding (one distance pass and one arg-max
+//                  per centre, chained on the device), Lloyd steps with
 //                  one thread per point (assignment) and one per (cluster,
 //                  coordinate) (centre update, a sequential sum in point order,
 //                  so the result does not depend on scheduling);
@@ -60,6 +61,7 @@ constexpr int kKmeansMaxIter = 300;
 constexpr int kMaxDirect = 8192;       // largest n without a sketch
 constexpr int kBs = 16;                // Jacobi block size (L is a multiple of 2 kBs)
 constexpr int kMaxK = 1024;
+constexpr int kSeedParts = 1024;       // workgroups of one seeding step
 
 int round_up(int x, int a) { return ((x + a - 1) / a) * a; }
 
@@ -239,46 +241,63 @@ __device__ int block_argmax(double v, int i, double* sv, int* si) {
     return r;
 }
 
-// farthest-point seeding (one workgroup): centre 0 is the point farthest from
-// the mean, centre s the point farthest from centres 0..s-1; Ct row s = point
-__global__ __launch_bounds__(1024) void k_km_seed(const double* __restrict__ Et, int n, int k,
-                                                  double* __restrict__ d2, double* __restrict__ Ct) {
-    __shared__ double sv[1024];
-    __shared__ int si[1024];
-    __shared__ double mean[kMaxK];
-    for (int c = 0; c < k; ++c) {
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < n; i += 1024) acc += Et[c + (long)i * k];
-        sv[threadIdx.x] = acc;
-        __syncthreads();
-        for (int w = 512; w > 0; w >>= 1) {
-            if (threadIdx.x < w) sv[threadIdx.x] += sv[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) mean[c] = sv[0] / n;
-        __syncthreads();
-    }
+// mean of the embedded points, one workgroup per coordinate (fixed-order sum)
+__global__ __launch_bounds__(256) void k_seed_mean(const double* __restrict__ Et, int n, int k,
+                                                   double* __restrict__ mean) {
+    const int c = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += Et[c + (long)i * k];
+    acc = lrr::wave_sum(acc);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) mean[c] = ((red[0] + red[1]) + (red[2] + red[3])) / n;
+}
+
+// one farthest-point step over the points: distance to `ref` (mode 0: the
+// mean, d2 untouched; 1: the first centre, d2 = distance; 2: a further centre,
+// d2 = min(d2, distance)), then the arg-max of the step's criterion per workgroup
+__global__ __launch_bounds__(256) void k_seed_dist(const double* __restrict__ Et, int n, int k,
+                                                   const double* __restrict__ ref, double* __restrict__ d2,
+                                                   int mode, double* __restrict__ pv, int* __restrict__ pi) {
+    __shared__ double sv[256];
+    __shared__ int si[256];
     double best = -1.0;
     int bi = INT_MAX;
-    for (int i = threadIdx.x; i < n; i += 1024) {
-        const double d = sqdist(Et + (long)i * k, mean, k);
-        if (d > best) { best = d; bi = i; }
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const double d = sqdist(Et + (long)i * k, ref, k);
+        double v = d;
+        if (mode == 1) d2[i] = d;
+        else if (mode == 2) { v = fmin(d2[i], d); d2[i] = v; }
+        if (v > best) { best = v; bi = i; }
     }
-    int j = block_argmax(best, bi, sv, si);
-    for (int s = 0; s < k; ++s) {
-        const double* cj = Et + (long)j * k;
-        for (int c = threadIdx.x; c < k; c += 1024) Ct[c + (long)s * k] = cj[c];
-        if (s + 1 == k) break;
-        best = -1.0;
-        bi = INT_MAX;
-        for (int i = threadIdx.x; i < n; i += 1024) {
-            const double d = sqdist(Et + (long)i * k, cj, k);
-            const double m = (s == 0) ? d : fmin(d2[i], d);
-            d2[i] = m;
-            if (m > best) { best = m; bi = i; }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const double a = sv[threadIdx.x], b = sv[threadIdx.x + w];
+            const int ia = si[threadIdx.x], ib = si[threadIdx.x + w];
+            if (b > a || (b == a && ib < ia)) { sv[threadIdx.x] = b; si[threadIdx.x] = ib; }
         }
-        j = block_argmax(best, bi, sv, si);
+        __syncthreads();
     }
+    if (threadIdx.x == 0) { pv[blockIdx.x] = sv[0]; pi[blockIdx.x] = si[0]; }
+}
+
+// arg-max over the workgroup partials (ties: lowest point index); the chosen
+// point becomes centre s
+__global__ __launch_bounds__(1024) void k_seed_pick(const double* __restrict__ pv, const int* __restrict__ pi,
+                                                    int parts, const double* __restrict__ Et, int k,
+                                                    double* __restrict__ Ct, int s) {
+    __shared__ double sv[1024];
+    __shared__ int si[1024];
+    double best = -1.0;
+    int bi = INT_MAX;
+    for (int j = threadIdx.x; j < parts; j += 1024)
+        if (pv[j] > best || (pv[j] == best && pi[j] < bi)) { best = pv[j]; bi = pi[j]; }
+    const int jbest = block_argmax(best, bi, sv, si);
+    for (int c = threadIdx.x; c < k; c += 1024) Ct[c + (long)s * k] = Et[c + (long)jbest * k];
 }
 
 // nearest centre of each point (ties: lowest centre); counts changed labels
@@ -367,8 +386,8 @@ struct Eig {
 };
 
 struct Work {
-    double *Om, *Y, *Q0, *Q, *Gq, *Tq, *Wk, *Bt, *Qk, *Uk, *A, *s, *X, *LX, *LQ, *B0, *B1, *B2, *Et, *d2, *Ct;
-    int *keep, *labA, *labB, *nchg;
+    double *Om, *Y, *Q0, *Q, *Gq, *Tq, *Wk, *Bt, *Qk, *Uk, *A, *s, *X, *LX, *LQ, *B0, *B1, *B2, *Et, *d2, *Ct, *mean, *pv;
+    int *pi, *keep, *labA, *labB, *nchg;
     unsigned long long* res;
     GemmDesc* g;
     Eig e;
@@ -395,6 +414,9 @@ size_t layout(Slab& a, Work& w, int n, int p, int nk, int k, int p2, int Lmax, b
     w.B2 = a.take<double>((size_t)nk * p2);
     w.Et = a.take<double>((size_t)nk * k);
     w.d2 = a.take<double>(nk);
+    w.mean = a.take<double>(k);
+    w.pv = a.take<double>(kSeedParts);
+    w.pi = a.take<int>(kSeedParts);
     w.Ct = a.take<double>((size_t)k * k);
     w.keep = a.take<int>(nk);
     w.labA = a.take<int>(nk);
@@ -672,9 +694,25 @@ extern "C" lrr_status lrr_segment(lrr_ctx* ctx, int n, const void* Zv, int ldz, 
         g.timed("k_rownorm", 0.0, 0.0, [&] {
             hipLaunchKernelGGL(k_rownorm, dim3(grid1(nk)), dim3(256), 0, s, w.X, (long)nk, nk, k, w.Et);
         });
-        g.timed("k_km_seed", 0.0, 0.0, [&] {
-            hipLaunchKernelGGL(k_km_seed, dim3(1), dim3(1024), 0, s, w.Et, nk, k, w.d2, w.Ct);
-        });
+        {
+            // farthest-point seeding: centre 0 is the point farthest from the mean,
+            // centre s + 1 the point farthest from centres 0..s
+            const int parts = (int)std::min<long>(grid1(nk), kSeedParts);
+            g.timed("k_seed_mean", 0.0, 0.0, [&] {
+                hipLaunchKernelGGL(k_seed_mean, dim3(k), dim3(256), 0, s, w.Et, nk, k, w.mean);
+            });
+            for (int c = 0; c < k; ++c) {
+                const double* ref = (c == 0) ? w.mean : w.Ct + (long)(c - 1) * k;
+                const int mode = (c == 0) ? 0 : (c == 1 ? 1 : 2);
+                g.timed("k_seed_dist", 0.0, 0.0, [&] {
+                    hipLaunchKernelGGL(k_seed_dist, dim3(parts), dim3(256), 0, s, w.Et, nk, k, ref, w.d2, mode,
+                                       w.pv, w.pi);
+                });
+                g.timed("k_seed_pick", 0.0, 0.0, [&] {
+                    hipLaunchKernelGGL(k_seed_pick, dim3(1), dim3(1024), 0, s, w.pv, w.pi, parts, w.Et, k, w.Ct, c);
+                });
+            }
+        }
         int* cur = w.labA;
         int* nxt = w.labB;
         int kit = 0;
