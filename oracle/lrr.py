@@ -28,6 +28,14 @@ What it computes
 * Algorithm 1 (DFC-LRR): the columns of M are split into t blocks C_i (the split
   is an input), each block is solved with M as the dictionary (Eq. 2), and the
   C step projects [Z_1 ... Z_t] onto the column space of Z_1 (Section 2.2).
+* The alternative of the Section 2.2 footnote (``dfc_lrr_local``): each block
+  is solved with C_i in both places of Eq. (1), so Z_i is l x l, and the C step
+  is a low-rank approximation of diag(Z_1, ..., Z_t).  The paper does not name
+  the approximation or its rank; the reading taken here is the best rank-k
+  approximation in the Frobenius norm (truncated SVD), which for a
+  block-diagonal matrix keeps the k largest singular triplets pooled over the
+  blocks, with k = max_i rank(Z_i) by default (the k' of the run-time remark of
+  Section 2.2); k = -1 keeps every triplet.
 
 Readings where the paper is silent (each is listed in the design notes):
 update order J -> Z -> E -> (Y1, Y2) -> mu; stop when both residuals are below
@@ -49,7 +57,7 @@ import scipy.linalg as sla
 
 __all__ = [
     "ALMOptions", "LRRResult", "DFCResult", "svt", "l21_shrink", "lrr_alm",
-    "column_projection", "dfc_lrr", "trivial_lambda", "objective", "dual_gap",
+    "column_projection", "dfc_lrr", "dfc_lrr_local", "trivial_lambda", "objective", "dual_gap",
 ]
 
 
@@ -95,6 +103,7 @@ class DFCResult:
     S: np.ndarray                  # m x n, original column order
     blocks: list = field(default_factory=list)   # LRRResult per block
     U1: np.ndarray | None = None   # basis of the column space of Z_1
+    combine_rank: int = 0          # rank of the combined estimate
 
 
 def svt(Y: np.ndarray, tau: float):
@@ -256,3 +265,51 @@ def dfc_lrr(M: np.ndarray, lam: float, perm: np.ndarray, offsets: np.ndarray,
     S = np.empty((m, n))
     S[:, perm] = np.concatenate([r.E for r in results], axis=1)
     return DFCResult(Z=Z, S=S, blocks=results, U1=U1)
+
+
+def dfc_lrr_local(M: np.ndarray, lam: float, perm: np.ndarray, offsets: np.ndarray, rank: int = 0,
+                  opts: ALMOptions | None = None) -> DFCResult:
+    """The footnote alternative of Section 2.2 with a given D-step partition.
+
+    Block i (original columns perm[offsets[i]:offsets[i+1]]) solves Eq. (1) with
+    C_i as both dictionary and observations, so its estimate J_i = U_i s_i V_i^T is
+    l_i x l_i and indexes the block's own points in rows and columns.  C step:
+    the rank-k truncated SVD of diag(J_1, ..., J_t): the k largest singular values
+    over all blocks are kept (ties: earlier block, then larger value first within
+    a block's descending list), each block keeps its own triplets among them.
+    k = 0 means max_i rank(J_i); k = -1 keeps all.  Z (n x n) holds block i's
+    result at rows and columns perm[offsets[i]:offsets[i+1]] and zeros elsewhere."""
+    M = np.asarray(M, dtype=np.float64)
+    m, n = M.shape
+    perm = np.asarray(perm, dtype=np.int64)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    if sorted(perm.tolist()) != list(range(n)):
+        raise ValueError("perm is not a permutation")
+    if offsets[0] != 0 or offsets[-1] != n or np.any(np.diff(offsets) <= 0):
+        raise ValueError("bad offsets")
+    results = []
+    for i in range(len(offsets) - 1):
+        C = M[:, perm[offsets[i]:offsets[i + 1]]]
+        results.append(lrr_alm(C, C, lam, opts))
+    pool = [(float(r.s[j]), i, j) for i, r in enumerate(results) for j in range(r.s.size)]
+    total = len(pool)
+    if rank == 0:
+        k = max(r.rank for r in results)
+    elif rank < 0:
+        k = total
+    else:
+        k = min(rank, total)
+    # descending by value; equal values keep the pooled (block, position) order
+    order = sorted(range(total), key=lambda q: -pool[q][0])
+    kept = [[] for _ in results]
+    for q in order[:k]:
+        kept[pool[q][1]].append(pool[q][2])
+    Z = np.zeros((n, n))
+    for i, r in enumerate(results):
+        cols = perm[offsets[i]:offsets[i + 1]]
+        j = np.array(sorted(kept[i]), dtype=np.int64)
+        Zi = (r.U[:, j] * r.s[j]) @ r.V[:, j].T if j.size else np.zeros((cols.size, cols.size))
+        Z[np.ix_(cols, cols)] = Zi
+    S = np.empty((m, n))
+    S[:, perm] = np.concatenate([r.E for r in results], axis=1)
+    return DFCResult(Z=Z, S=S, blocks=results, U1=None, combine_rank=k)
