@@ -177,6 +177,26 @@ lrr_status dfc_lrr_solve(lrr_ctx *ctx, int m, int n, const void *M, int ldm,
                          lrr_info *info, void *stream);
 
 /*
+ * The alternative formulation of the Section 2.2 footnote: block i solves Eq. (1)
+ * with C_i = M[:, block] as both dictionary and observations, so its estimate
+ * J_i (at termination, exactly low rank) is l_i x l_i and relates the block's
+ * own points; all blocks run batched as in dfc_lrr_solve, each with its own
+ * (I + C_i C_i^T)^{-1}.  C step: the best rank-k approximation in the Frobenius
+ * norm of diag(J_1, ..., J_t) -- the k largest singular triplets pooled over the
+ * blocks -- with k = combine_rank if > 0, max_i rank(J_i) if 0, every triplet if
+ * < 0.  Z (n x n, ldz >= n) receives block i at rows and columns
+ * perm[offsets[i] .. offsets[i+1]-1] and zeros elsewhere; S (optional) the
+ * outlier estimates in the original column order (m x n, lds >= m);
+ * info->combine_rank the k used.  opts.coords and opts.solve_form are ignored
+ * (full coordinates, push-through solve); save_for_backward is rejected
+ * (LRR_EINVAL).
+ */
+lrr_status dfc_lrr_solve_local(lrr_ctx *ctx, int m, int n, const void *M, int ldm,
+                               double lambda, int t, const int *perm, const int *offsets,
+                               int combine_rank, const lrr_opts *opts, void *Z, int ldz,
+                               void *S, int lds, lrr_info *info, void *stream);
+
+/*
  * Reverse-mode derivative of the last dfc_lrr_solve on ctx, which must have run
  * with save_for_backward = 1 and fixed_iters > 0 (the unrolled map).  Given
  * dZ = dL/dZ (n x n, device, original column order) it writes dL/dlambda to

@@ -104,6 +104,9 @@ def load_library(path: str = LIB_PATH):
     lib.lrr_diag_spd_inverse.restype = i
     lib.lrr_diag_syevj.argtypes = [vp, i, ip, vp, i, C.c_long, vp, i, vp, i, ip, vp]
     lib.lrr_diag_syevj.restype = i
+    lib.dfc_lrr_solve_local.argtypes = [vp, i, i, vp, i, d, i, ip, ip, i, C.POINTER(lrr_opts), vp, i, vp, i,
+                                        C.POINTER(lrr_info), vp]
+    lib.dfc_lrr_solve_local.restype = i
     lib.lrr_segment.argtypes = [vp, i, vp, i, i, vp, d, i, vp, C.POINTER(lrr_seg_info), vp]
     lib.lrr_segment.restype = i
     _lib = lib
@@ -256,6 +259,31 @@ def dfc_lrr_solve(Mt, lam: float, perm, offsets, opts: lrr_opts | None = None,
                                       C.c_void_p(Zt.data_ptr()), n,
                                       C.c_void_p(St.data_ptr()) if St is not None else None, m,
                                       C.byref(info), _stream(torch, Mt.device))
+    _check(st, ctx)
+    return Zt, St, SolveInfo(st, *arrs, info.batch_iters, info.combine_rank)
+
+
+def dfc_lrr_solve_local(Mt, lam: float, perm, offsets, combine_rank: int = 0, opts: lrr_opts | None = None,
+                        ctx: Context | None = None, want_S: bool = True, Zt=None):
+    """Footnote variant of Section 2.2 (every block its own dictionary, truncated-SVD
+    combine of diag(J_1..J_t)).  Same tensors and return value as dfc_lrr_solve."""
+    import torch
+    _require_cuda_f64(torch, Mt)
+    n, m = Mt.shape
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int32)
+    t = len(offsets) - 1
+    ctx = ctx or get_context(Mt.device.index or 0)
+    opts = opts or lrr_opts_default()
+    if Zt is None:
+        Zt = torch.empty((n, n), dtype=torch.float64, device=Mt.device)
+    St = torch.empty((n, m), dtype=torch.float64, device=Mt.device) if want_S else None
+    info, arrs = _make_info(t)
+    st = load_library().dfc_lrr_solve_local(ctx.handle, m, n, C.c_void_p(Mt.data_ptr()), m, float(lam), t,
+                                            _ip(perm), _ip(offsets), int(combine_rank), C.byref(opts),
+                                            C.c_void_p(Zt.data_ptr()), n,
+                                            C.c_void_p(St.data_ptr()) if St is not None else None, m,
+                                            C.byref(info), _stream(torch, Mt.device))
     _check(st, ctx)
     return Zt, St, SolveInfo(st, *arrs, info.batch_iters, info.combine_rank)
 

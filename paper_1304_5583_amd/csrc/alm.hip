@@ -343,6 +343,20 @@ __global__ __launch_bounds__(256) void k_scale_cols(double* __restrict__ U, long
     for (int i = threadIdx.x; i < rows; i += 256) U[i + j * ld] *= s;
 }
 
+// block-diagonal scatter of per-block estimates (local mode): column j of the
+// concatenated blocks, block bb, rows a < l_bb go to out[perm[boff_bb + a], perm[j]]
+__global__ __launch_bounds__(256) void k_scatter_block_diag(const double* __restrict__ J, long ldj,
+                                                             const int* __restrict__ colblk,
+                                                             const int* __restrict__ boff,
+                                                             const int* __restrict__ perm, double* __restrict__ out,
+                                                             long ldo) {
+    const int j = blockIdx.x;
+    const int bb = colblk[j];
+    const int o = boff[bb], l = boff[bb + 1] - o;
+    double* col = out + (long)perm[j] * ldo;
+    for (int a = threadIdx.x; a < l; a += 256) col[perm[o + a]] = J[a + j * ldj];
+}
+
 __global__ void k_set_identity(double* __restrict__ W, int L) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < (long)L * L) W[idx] = ((idx % L) == (idx / L)) ? 1.0 : 0.0;
@@ -424,6 +438,10 @@ void launch_init_iter(DevIter* it, const double* mu_sched, int k, hipStream_t s,
 }
 void launch_scale_cols(double* U, long ld, int rows, int ncols, const double* h, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_cols, dim3(ncols), dim3(256), 0, s, U, ld, rows, h);
+}
+void launch_scatter_block_diag(const double* J, long ldj, int ncols, const int* colblk, const int* boff,
+                               const int* perm, double* out, long ldo, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_block_diag, dim3(ncols), dim3(256), 0, s, J, ldj, colblk, boff, perm, out, ldo);
 }
 void launch_set_identity(double* W, int L, hipStream_t s) {
     const long n = (long)L * L;

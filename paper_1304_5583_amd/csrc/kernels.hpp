@@ -79,6 +79,8 @@ void launch_check(BlockState bs, int t, DevIter* it, const double* mu_sched, dou
 void launch_init_iter(DevIter* it, const double* mu_sched, int k, hipStream_t s, int full = 0);
 void launch_scale_cols(double* U, long ld, int rows, int ncols, const double* h, hipStream_t s);
 void launch_set_identity(double* W, int L, hipStream_t s);
+void launch_scatter_block_diag(const double* J, long ldj, int ncols, const int* colblk, const int* boff,
+                               const int* perm, double* out, long ldo, hipStream_t s);
 
 // adjoint.hip
 void launch_bw_estep(const double* E0, const double* V, double* cE, const double* cY1, double* Vb,

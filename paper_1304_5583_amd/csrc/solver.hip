@@ -174,6 +174,9 @@ struct Plan {
     int nrb = 0;                 // rows the layout reserves (n, or min(m, n))
     int nr = 0;                  // rows in use (n, or the numerical rank of M)
     int Lm = 0, bq = 16;         // padded order / Jacobi block of the M M^T eigensolve
+    // every block its own dictionary (the observations C_b, Section 2.2 footnote):
+    // the iterates of block b use rows [0, l_b) of maxl rows, K is per block
+    bool local = false;
 };
 
 struct Buffers {
@@ -235,7 +238,7 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.Y1 = a.take<double>(m * c);
     b.T = a.take<double>(m * c);
     b.V = a.take<double>(m * c);
-    b.K = a.take<double>(m * m);
+    b.K = a.take<double>((p.local ? t : 1) * m * m);   // K^{-1}, one per block in local mode
     b.Lb = a.take<double>(m * m);
     b.Linv = a.take<double>(m * m);
     b.Tb = a.take<double>(m * m);
@@ -308,7 +311,7 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.g_U = a.take<GemmDesc>(1);
     b.g_H = a.take<GemmDesc>(1);
     b.g_Z = a.take<GemmDesc>(1);
-    b.g_KK = a.take<GemmDesc>(1);
+    b.g_KK = a.take<GemmDesc>(p.local ? t : 1);
     b.g_spd = a.take<GemmDesc>(lrr::spd_inverse_desc_count(p.m));
     b.eig = a.take<EigDesc>(t);
     b.svt = a.take<SvtDesc>(t);
@@ -434,6 +437,7 @@ struct Problem {
     const int* offsets;           // host, t + 1
     double lam;
     lrr_opts o;
+    int local = 0;                // 1: block b uses its own observations as dictionary
 };
 
 struct Result {
@@ -485,6 +489,13 @@ Plan make_plan(const Problem& pr) {
                 (coords == LRR_COORDS_AUTO && pr.n >= 2 * pr.m && !pr.o.save_for_backward);
     if (pr.o.save_for_backward) p.reduced = false;
     p.nrb = p.reduced ? std::min(pr.m, pr.n) : pr.n;
+    p.local = pr.local != 0;
+    if (p.local) {
+        // rows of a block's iterates index its own points: l_b <= maxl rows; rows
+        // beyond l_b meet zero dictionary columns and stay exactly zero
+        p.reduced = false;
+        p.nrb = p.maxl;
+    }
     p.nr = p.nrb;
     p.bq = pr.m > 512 ? 32 : 16;
     p.Lm = round_up(pr.m, 2 * p.bq);
@@ -578,7 +589,7 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     layout(p, static_cast<char*>(ctx->ws), b, with_combine, true);
     ensure_pinned(ctx, sizeof(int) * (4 * (size_t)t + 16) + sizeof(double) * 2 * t);
     if (p.reduced) build_basis(pr, p, b, s);
-    else p.nr = n;
+    else if (!p.local) p.nr = n;
     const int nr = p.nr;
     // dictionary of the Z-step products: M, or Mr = M Qm in reduced coordinates
     const double* Md = p.reduced ? b.Mr : pr.A;
@@ -618,15 +629,21 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         gJ[bb] = GemmDesc{Yb, b.Pm[bb], Jb, nr, l, l, nr, L, nr, 1.0, 0.0, run, nullptr};
         const int* act = b.active + bb;
         const size_t o_n = (size_t)p.boff[bb] * nr, o_m = (size_t)p.boff[bb] * m;
+        // dictionary of this block: M (or Mr), or in local mode its own columns
+        // C_b (m x l, inside the gathered observations) with l inner rows
+        const double* Mb = p.local ? b.X + o_m : Md;
+        const int ldb_ = p.local ? m : ldmd;
+        const int kin = p.local ? l : nr;
+        const double* Kb = b.K + (p.local ? (size_t)bb * m * m : 0);
         if (p.pm.dMQ) {
-            gMQ[bb] = GemmDesc{Md, b.Dn + o_n, b.MQacc + o_m, m, l, nr, ldmd, nr, m, 1.0, 1.0, act, nullptr};
+            gMQ[bb] = GemmDesc{Mb, b.Dn + o_n, b.MQacc + o_m, m, l, kin, ldb_, nr, m, 1.0, 1.0, act, nullptr};
             // re-anchoring: the carried product replaced by an FP64 M Q
-            gMQa[bb] = GemmDesc{Md, b.Q + o_n, b.MQacc + o_m, m, l, nr, ldmd, nr, m, 1.0, 0.0, act, nullptr};
+            gMQa[bb] = GemmDesc{Mb, b.Q + o_n, b.MQacc + o_m, m, l, kin, ldb_, nr, m, 1.0, 0.0, act, nullptr};
         }
         else
-            gMQ[bb] = GemmDesc{Md, b.Q + o_n, b.T + o_m, m, l, nr, ldmd, nr, m, -1.0, 1.0, act, nullptr};
-        gKV[bb] = GemmDesc{b.K, b.T + o_m, b.V + o_m, m, l, m, m, m, m, 1.0, 0.0, act, nullptr};
-        gMtV[bb] = GemmDesc{Md, b.V + o_m, b.MtV + o_n, nr, l, m, ldmd, m, nr, 1.0, 0.0, act, nullptr};
+            gMQ[bb] = GemmDesc{Mb, b.Q + o_n, b.T + o_m, m, l, kin, ldb_, nr, m, -1.0, 1.0, act, nullptr};
+        gKV[bb] = GemmDesc{Kb, b.T + o_m, b.V + o_m, m, l, m, m, m, m, 1.0, 0.0, act, nullptr};
+        gMtV[bb] = GemmDesc{Mb, b.V + o_m, b.MtV + o_n, kin, l, m, ldb_, m, nr, 1.0, 0.0, act, nullptr};
         if (p.reduced)   // expansion of the coupling residual: R2 = Qm R2r
             gExp[bb] = GemmDesc{b.Qm, b.R2r + o_n, b.R2full + (size_t)p.boff[bb] * n, n, l, nr, n, nr, n, 1.0,
                                 0.0, b.expand + bb, nullptr};
@@ -637,7 +654,13 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
                           b.ref_emax + bb, b.ref_unres + bb, b.ref_eprev + bb, b.ref_run + bb,
                           b.ref_cont + bb, b.Bq[bb], b.locut + bb, L, l, bb};
     }
-    GemmDesc gKK{pr.A, pr.A, b.K, m, m, n, (int)pr.lda, (int)pr.lda, m, 1.0, 0.0, nullptr, nullptr};
+    std::vector<GemmDesc> gKK(p.local ? t : 1);
+    if (p.local)
+        for (int bb = 0; bb < t; ++bb)
+            gKK[bb] = GemmDesc{b.X + (size_t)p.boff[bb] * m, b.X + (size_t)p.boff[bb] * m, b.K + (size_t)bb * m * m,
+                               m, m, p.boff[bb + 1] - p.boff[bb], m, m, m, 1.0, 0.0, nullptr, nullptr};
+    else
+        gKK[0] = GemmDesc{pr.A, pr.A, b.K, m, m, n, (int)pr.lda, (int)pr.lda, m, 1.0, 0.0, nullptr, nullptr};
 
     auto up = [&](void* dst, const void* src, size_t bytes) {
         LRR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
@@ -660,7 +683,7 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     up(b.g_MtV, gMtV.data(), sizeof(GemmDesc) * t);
     if (p.reduced) up(b.g_exp, gExp.data(), sizeof(GemmDesc) * t);
 
-    up(b.g_KK, &gKK, sizeof(GemmDesc));
+    up(b.g_KK, gKK.data(), sizeof(GemmDesc) * gKK.size());
     up(b.eig, eig.data(), sizeof(EigDesc) * t);
     up(b.svt, svt.data(), sizeof(SvtDesc) * t);
     if (pr.perm) up(b.perm, pr.perm, sizeof(int) * c);
@@ -674,6 +697,8 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     LRR_HIP(hipMemsetAsync(b.Y2, 0, sizeof(double) * nc, s));
     LRR_HIP(hipMemsetAsync(b.E, 0, sizeof(double) * mc, s));
     LRR_HIP(hipMemsetAsync(b.Y1, 0, sizeof(double) * mc, s));
+    // local mode: the rows of M^T V beyond a block's width are never written
+    if (p.local) LRR_HIP(hipMemsetAsync(b.MtV, 0, sizeof(double) * nc, s));
     // the carried product M Q starts from Q = 0
     if (p.pm.dMQ) {
         LRR_HIP(hipMemsetAsync(b.Q, 0, sizeof(double) * nc, s));
@@ -702,10 +727,14 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     if (p.reduced) LRR_HIP(hipMemsetAsync(b.r2nrm, 0, sizeof(unsigned long long) * t, s));
     lrr::launch_init_iter(b.it, b.mu_sched, 0, s);
 
-    // K = I + A A^T, then K^{-1} (FP64 Cholesky, once per solve)
-    lrr::launch_dgemm(b.g_KK, 1, m, m, false, true, s);
-    lrr::launch_add_identity(b.K, m, m, 1.0, s);
-    lrr::spd_inverse(b.K, m, b.Lb, b.Linv, b.Dinv, b.Tb, b.g_spd, b.flag, s);
+    // K = I + A A^T, then K^{-1} (FP64 Cholesky, once per solve; per block in
+    // local mode, A = C_b)
+    for (size_t bb = 0; bb < gKK.size(); ++bb) {
+        double* Kb = b.K + bb * (size_t)m * m;
+        lrr::launch_dgemm(b.g_KK + bb, 1, m, m, false, true, s);
+        lrr::launch_add_identity(Kb, m, m, 1.0, s);
+        lrr::spd_inverse(Kb, m, b.Lb, b.Linv, b.Dinv, b.Tb, b.g_spd, b.flag, s);
+    }
 }
 
 // Hooks of iterate_alm: called before iteration k starts and after it ends
@@ -986,6 +1015,66 @@ Result run_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
                const IterHooks* hooks = nullptr) {
     setup_alm(ctx, pr, p, b, s, with_combine);
     return iterate_alm(ctx, pr, p, b, s, 0, p.n_iter, hooks);
+}
+
+// C step of the footnote variant (Section 2.2): the best rank-k approximation
+// of diag(J_1, ..., J_t).  Block b's last thresholding step left
+// J_b = Y_b W_b diag(g_b) W_b^T with g = 1 - tau_b / sigma on the kept Gram
+// eigenvalues sigma^2, so the singular values of J_b are sigma - tau_b and its
+// right singular vectors the columns of W_b.  The k largest over all blocks are
+// kept (k = 0: max_b rank(J_b); k < 0: all); each block is rebuilt as
+// Y_b W_b diag(g_b m_b) W_b^T with the 0/1 mask m_b of its kept triplets, and
+// the blocks are scattered to rows and columns perm of Z.  Returns k.
+int combine_local(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, const Result& r, int rank_req,
+                  double* Zo, int ldz, hipStream_t s) {
+    const int t = p.t, nr = p.nr, n = p.n, c = p.ncols;
+    std::vector<double> sched(p.n_iter + 2);
+    sched[0] = pr.o.mu0;
+    for (size_t k = 1; k < sched.size(); ++k) sched[k] = std::min(pr.o.rho * sched[k - 1], pr.o.mu_max);
+    struct Cand { double sv; int b, i; };
+    std::vector<Cand> pool;
+    std::vector<std::vector<double>> lam(t), h(t);
+    for (int bb = 0; bb < t; ++bb) {
+        lam[bb].resize(p.L[bb]);
+        h[bb].resize(p.L[bb]);
+        LRR_HIP(hipMemcpyAsync(lam[bb].data(), b.lam[bb], sizeof(double) * p.L[bb], hipMemcpyDeviceToHost, s));
+        LRR_HIP(hipMemcpyAsync(h[bb].data(), b.h[bb], sizeof(double) * p.L[bb], hipMemcpyDeviceToHost, s));
+    }
+    LRR_HIP(hipStreamSynchronize(s));
+    int rmax = 0;
+    for (int bb = 0; bb < t; ++bb) {
+        if (r.rank[bb] == 0 || r.iters[bb] == 0) continue;   // J_b = 0 (exact zero test)
+        rmax = std::max(rmax, r.rank[bb]);
+        const double tau = 1.0 / sched[r.iters[bb] - 1];
+        const int l = p.boff[bb + 1] - p.boff[bb];
+        for (int i = 0; i < l; ++i)
+            if (h[bb][i] > 0.0) pool.push_back(Cand{std::sqrt(std::max(lam[bb][i], 0.0)) - tau, bb, i});
+    }
+    const int total = (int)pool.size();
+    const int k = rank_req == 0 ? rmax : (rank_req < 0 ? total : std::min(rank_req, total));
+    std::stable_sort(pool.begin(), pool.end(), [](const Cand& x, const Cand& y) { return x.sv > y.sv; });
+    std::vector<std::vector<double>> mask(t);
+    for (int bb = 0; bb < t; ++bb) mask[bb].assign(p.L[bb], 0.0);
+    for (int q = 0; q < k; ++q) mask[pool[q].b][pool[q].i] = 1.0;
+    std::vector<GemmDesc> gP(t), gJ(t);
+    for (int bb = 0; bb < t; ++bb) {
+        const int l = p.boff[bb + 1] - p.boff[bb], L = p.L[bb];
+        // the mask goes into h (no longer needed), then Wg <- Wg diag(mask)
+        LRR_HIP(hipMemcpyAsync(b.h[bb], mask[bb].data(), sizeof(double) * L, hipMemcpyHostToDevice, s));
+        lrr::launch_scale_cols(b.Wg[bb], L, L, L, b.h[bb], s);
+        gP[bb] = GemmDesc{b.Wg[bb], b.Wm[bb], b.Pm[bb], l, l, L, L, L, L, 1.0, 0.0, nullptr, nullptr};
+        gJ[bb] = GemmDesc{b.Y + (size_t)p.boff[bb] * nr, b.Pm[bb], b.J + (size_t)p.boff[bb] * nr, nr, l, l, nr, L,
+                          nr, 1.0, 0.0, nullptr, nullptr};
+    }
+    LRR_HIP(hipMemcpyAsync(b.g_P, gP.data(), sizeof(GemmDesc) * t, hipMemcpyHostToDevice, s));
+    LRR_HIP(hipMemcpyAsync(b.g_J, gJ.data(), sizeof(GemmDesc) * t, hipMemcpyHostToDevice, s));
+    LrrProf& prof = ctx->prof;
+    prof.run(s, "k_dgemm<false, true>", 0.0, 0.0, [&] { lrr::launch_dgemm(b.g_P, t, p.maxl, p.maxl, false, true, s); });
+    prof.run(s, "k_dgemm<false, false>", 0.0, 0.0, [&] { lrr::launch_dgemm(b.g_J, t, nr, p.maxl, false, false, s); });
+    for (int j = 0; j < n; ++j) LRR_HIP(hipMemsetAsync(Zo + (size_t)j * ldz, 0, sizeof(double) * n, s));
+    lrr::launch_scatter_block_diag(b.J, nr, c, b.colblk, b.boff, b.perm, Zo, ldz, s);
+    LRR_HIP(hipStreamSynchronize(s));   // host masks and descriptors go out of scope
+    return k;
 }
 
 void fill_info(lrr_info* info, const Result& r, int combine_rank) {
@@ -1572,6 +1661,39 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
         LRR_HIP(hipStreamSynchronize(s));
         if (ctx->prof.on) ctx->prof.flush();
         fill_info(info, r, r1);
+        return r.converged ? LRR_OK : LRR_NOT_CONVERGED;
+    });
+}
+
+lrr_status dfc_lrr_solve_local(lrr_ctx* ctx, int m, int n, const void* M, int ldm, double lambda, int t,
+                               const int* perm, const int* offsets, int combine_rank, const lrr_opts* opts,
+                               void* Z, int ldz, void* S, int lds, lrr_info* info, void* stream) {
+    if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
+    if (m <= 0 || n <= 0) return fail(ctx, LRR_EINVAL, "dimensions must be positive");
+    if (!M || !Z) return fail(ctx, LRR_EINVAL, "M and Z must not be NULL");
+    if (ldm < m || ldz < n || (S && lds < m)) return fail(ctx, LRR_EINVAL, "leading dimension too small");
+    if (!(lambda > 0) || !std::isfinite(lambda)) return fail(ctx, LRR_EINVAL, "lambda must be positive and finite");
+    std::string why;
+    if (check_partition_impl(n, t, perm, offsets, why) != LRR_OK) return fail(ctx, LRR_EINVAL, why);
+    lrr_opts o;
+    if (opts) o = *opts; else lrr_opts_default(&o);
+    if (!opts_valid(o, why)) return fail(ctx, LRR_EINVAL, why);
+    if (o.save_for_backward) return fail(ctx, LRR_EINVAL, "the local-dictionary variant has no reverse mode");
+    if (ctx->tape) ctx->tape->valid = false;
+    return guarded(ctx, [&]() -> lrr_status {
+        LRR_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (input_nonfinite(ctx, static_cast<const double*>(M), ldm, m, n, s))
+            return fail(ctx, LRR_ENUMERIC, "non-finite value in M");
+        Problem pr{m, n, n, t, static_cast<const double*>(M), ldm, nullptr, 0, perm, offsets, lambda, o, 1};
+        Plan p = make_plan(pr);
+        Buffers b{};
+        Result r = run_alm(ctx, pr, p, b, s, false, nullptr);
+        const int k = combine_local(ctx, pr, p, b, r, combine_rank, static_cast<double*>(Z), ldz, s);
+        if (S) lrr::launch_scatter_cols(b.E, m, static_cast<double*>(S), lds, m, n, b.perm, s);
+        LRR_HIP(hipStreamSynchronize(s));
+        if (ctx->prof.on) ctx->prof.flush();
+        fill_info(info, r, k);
         return r.converged ? LRR_OK : LRR_NOT_CONVERGED;
     });
 }

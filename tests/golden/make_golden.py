@@ -9,6 +9,7 @@ full-size GPU solve element by element where the oracle can compute it once.
     python tests/golden/make_golden.py 2 [3 ...]
     python tests/golden/make_golden.py 4b1      # block 1 of workload 4 only
     python tests/golden/make_golden.py 5g       # workload 5: the oracle gradient
+    python tests/golden/make_golden.py 2l       # workload 2, footnote variant (local dictionaries)
 
 Workload 4 is too large for the oracle's DFC run (40 blocks, n = 20000); its
 fingerprint covers the first block, solved as one LRR problem with the whole M
@@ -92,10 +93,37 @@ def gradient_fingerprint(cfg: int):
     print(f"workload {cfg} gradient: {el:.1f}s L={L:.6e} dlam={lambar:.6e} -> {path}", flush=True)
 
 
+def local_fingerprint(cfg: int):
+    """The footnote variant of Section 2.2 on a workload: every block its own
+    dictionary, combine = best rank-k approximation of diag(J_1..J_t) with the
+    default k = max_i rank(J_i)."""
+    p = make_config(cfg)
+    t0 = time.time()
+    d = oracle.dfc_lrr_local(p.M, p.lam, p.perm, p.offsets)
+    el = time.time() - t0
+    W, idx = probes(p.n)
+    out = {
+        "workload": p.name, "variant": "local", "config": cfg, "m": p.m, "n": p.n, "t": p.t, "lam": p.lam,
+        "oracle_seconds": el, "combine_rank": d.combine_rank,
+        "iters": [b.iters for b in d.blocks], "rank": [b.rank for b in d.blocks],
+        "Zw": (d.Z @ W).T.tolist(), "probe_idx": idx.tolist(),
+        "Z_at": [float(d.Z[i, j]) for i, j in idx],
+        "Z_fro": float(np.linalg.norm(d.Z)), "S_fro": float(np.linalg.norm(d.S)),
+    }
+    path = os.path.join(HERE, f"workload{cfg}_local_oracle.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print(f"workload {cfg} local: {el:.1f}s iters={out['iters']} rank={out['rank']} k={d.combine_rank} -> {path}",
+          flush=True)
+
+
 def main(cfgs):
     for cfg in cfgs:
         if cfg == "5g":
             gradient_fingerprint(5)
+            continue
+        if isinstance(cfg, str) and cfg.endswith("l"):
+            local_fingerprint(int(cfg[:-1]))
             continue
         if isinstance(cfg, str):
             c, b = cfg.split("b")
@@ -128,4 +156,4 @@ def main(cfgs):
 
 
 if __name__ == "__main__":
-    main([a if ("b" in a or "g" in a) else int(a) for a in sys.argv[1:]] or [2])
+    main([a if ("b" in a or "g" in a or "l" in a) else int(a) for a in sys.argv[1:]] or [2])
