@@ -7,9 +7,10 @@ from .lrr import (ALMOptions, DFCResult, LRRResult, column_projection, dfc_lrr, 
                   l21_shrink, lrr_alm, objective, svt, trivial_lambda)
 from .segment import segment, segmentation_accuracy, oracle_constraints
 from . import adjoint
+from . import slr
 
 __all__ = [
     "ALMOptions", "DFCResult", "LRRResult", "column_projection", "dfc_lrr", "dfc_lrr_local", "dual_gap",
     "l21_shrink", "lrr_alm", "objective", "svt", "trivial_lambda", "segment",
-    "segmentation_accuracy", "oracle_constraints", "adjoint",
+    "segmentation_accuracy", "oracle_constraints", "adjoint", "slr",
 ]
