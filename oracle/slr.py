@@ -16,8 +16,9 @@ samples i and j is |Z_ij| + |Z_ji| (Z is not symmetric; both directions of the
 representation count), a sample is never its own neighbour, ties in the
 affinity go to the lower index, and the neighbours are listed by decreasing
 affinity.  The Lasso is written in its Gram form min w^T G w - 2 b^T w +
-alpha 1^T w (G = D^T D, b = D^T x) and solved by cyclic exact coordinate
-minimisation run until the optimality conditions hold to rounding; G is
+alpha 1^T w (G = D^T D, b = D^T x) and solved by the active-set method of
+Lawson and Hanson with a pivot for entering columns that depend on the free
+ones (see nn_lasso), a finite method that ends at the optimality conditions; G is
 singular whenever the neighbours of a sample span fewer dimensions than there
 are of them (the normal case here: they come from the sample's own subspace),
 so only the optimal value is unique in general, and the weights are unique
@@ -51,15 +52,23 @@ def nn_lasso_objective(G: np.ndarray, b: np.ndarray, xx: float, alpha: float, w:
     return float(w @ G @ w - 2.0 * b @ w + xx + alpha * np.sum(w))
 
 
-def nn_lasso(G: np.ndarray, b: np.ndarray, alpha: float, tol: float = 1e-13,
-             max_sweeps: int = 200000) -> np.ndarray:
-    """Minimiser of w^T G w - 2 b^T w + alpha 1^T w over w >= 0.
+def nn_lasso(G: np.ndarray, b: np.ndarray, alpha: float, tol: float = 1e-12, dep_tol: float = 1e-10) -> np.ndarray:
+    """Minimiser of w^T G w - 2 b^T w + alpha 1^T w over w >= 0 (alpha > 0).
 
-    Cyclic coordinate minimisation: coordinate j in turn moves to the exact
-    minimiser of the objective along it, max(0, w_j - g_j / (2 G_jj)) with the
-    gradient g = 2 G w - 2 b + alpha; the gradient is re-formed from w every
-    sweep.  Stops when the optimality conditions hold to tol (relative to the
-    problem's scale): |g_j| where w_j > 0, max(0, -g_j) where w_j = 0."""
+    The active-set method of Lawson and Hanson (Solving Least Squares Problems,
+    1974, ch. 23) in Gram form, with gradient g = 2 G w - 2 b + alpha and the
+    free set P kept linearly independent:
+      * stop when the optimality conditions hold to tol of the problem's scale
+        (|g_j| on P, max(0, -g_j) off P);
+      * otherwise the coordinate j off P with the most negative gradient enters;
+      * if column j depends on the free columns (its Cholesky pivot falls below
+        dep_tol of the largest diagonal entry), D_j = D_P beta and the objective
+        falls linearly along w_P -= t beta, w_j += t (its slope is
+        alpha (1 - sum(beta)) = g_j < 0): move until the first free weight with
+        beta_i > 0 reaches zero and swap it out;
+      * then the stationary point s of the face P, G_PP s = b_P - alpha/2, is
+        taken if positive; otherwise w moves towards s until the first weight
+        reaches zero, that index leaves P, and the face is solved again."""
     G = np.asarray(G, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     k = b.size
@@ -67,18 +76,54 @@ def nn_lasso(G: np.ndarray, b: np.ndarray, alpha: float, tol: float = 1e-13,
     if k == 0:
         return w
     scale = max(1.0, float(np.max(np.abs(2.0 * b - alpha))), float(np.max(np.abs(2.0 * G))))
-    for _ in range(max_sweeps):
+    dmax = float(np.max(np.diag(G)))
+    P: list[int] = []
+    for _ in range(10 * k + 20):
         g = 2.0 * G @ w - 2.0 * b + alpha
-        viol = np.where(w > 0, np.abs(g), np.maximum(0.0, -g))
+        free = np.zeros(k, dtype=bool)
+        free[P] = True
+        viol = np.where(free, np.abs(g), np.maximum(0.0, -g))
         if float(np.max(viol)) <= tol * scale:
-            break
-        for j in range(k):
-            if G[j, j] <= 0.0:
-                continue                      # a zero column: its weight stays 0 (gradient alpha > 0)
-            gj = 2.0 * (G[j] @ w) - 2.0 * b[j] + alpha
-            wj = max(0.0, w[j] - gj / (2.0 * G[j, j]))
-            w[j] = wj
-    return w
+            return w
+        cand = np.where(free, np.inf, g)
+        j = int(np.argmin(cand))
+        if not cand[j] < 0:
+            # only free coordinates violate: re-solve the face below
+            j = -1
+        if j >= 0:
+            if P:
+                L = np.linalg.cholesky(G[np.ix_(P, P)])
+                y = np.linalg.solve(L, G[P, j])
+                piv = G[j, j] - float(y @ y)
+            else:
+                piv = G[j, j]
+            if piv <= dep_tol * dmax:
+                beta = np.linalg.solve(G[np.ix_(P, P)], G[P, j])
+                pos = [q for q in range(len(P)) if beta[q] > 0]
+                t = min(w[P[q]] / beta[q] for q in pos)
+                out = min((q for q in pos if w[P[q]] / beta[q] == t), key=lambda q: P[q])
+                for q in range(len(P)):
+                    w[P[q]] -= t * beta[q]
+                w[j] = t
+                w[P[out]] = 0.0
+                P = [P[q] for q in range(len(P)) if q != out] + [j]
+            else:
+                P = P + [j]
+        while P:
+            s = np.linalg.solve(G[np.ix_(P, P)], b[P] - alpha / 2.0)
+            if np.all(s > 0):
+                w[:] = 0.0
+                w[P] = s
+                break
+            ratios = [(w[P[q]] / (w[P[q]] - s[q]), P[q]) for q in range(len(P)) if s[q] <= 0]
+            t = min(r for r, _ in ratios)
+            for q in range(len(P)):
+                w[P[q]] += t * (s[q] - w[P[q]])
+            gone = {i for r, i in ratios if r == t}
+            for i in gone:
+                w[i] = 0.0
+            P = [i for i in P if i not in gone]
+    raise RuntimeError("non-negative Lasso: step limit reached")
 
 
 def slr_graph(M: np.ndarray, Z: np.ndarray, nk: int, alpha: float):
