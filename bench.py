@@ -232,6 +232,22 @@ def local_variant(B, torch, p, Mt, ctx, reps=3):
     return out
 
 
+def slr_graph(B, torch, p, Mt, Zt, ctx, nk=500, alpha=0.05, reps=3):
+    """Section 4.2.2 SLR-graph on the solve's Z with the paper's settings
+    (n_k = 500 neighbours, alpha = 0.05): time per call and Lasso statistics."""
+    B.lrr_slr_graph(Mt, Zt, nk, alpha, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        nbr, w, obj, info = B.lrr_slr_graph(Mt, Zt, nk, alpha, ctx=ctx)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    out = {"ms": ms, "nk": nk, "alpha": alpha, "max_steps": info["max_steps"], "max_kkt": info["max_kkt"],
+           "not_converged": info["not_converged"], "edges_per_sample": float((w > 0).sum().item()) / p.n}
+    print(f"bench: SLR-graph {p.name}: {ms:.1f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def workload5_adjoint(B, torch, ctx):
     """Workload 5: FP32 forward of 200 unrolled iterations with checkpoints every
     20 and the reverse sweep for L = ||W o |Z| ||_F^2; times both and compares
@@ -387,6 +403,7 @@ def main():
         line["forms"] = precision_forms(B, torch, p, Mt, Zt, ctx, args)
         if args.workload == 2:
             line["local_variant"] = local_variant(B, torch, p, Mt, ctx)
+            line["slr_graph"] = slr_graph(B, torch, p, Mt, Zt, ctx)
         line["workload4_mixed_vs_fp64"] = workload4_mixed(B, torch, ctx)
         line["workload5_adjoint"] = workload5_adjoint(B, torch, ctx)
     if not args.no_cpu_baseline:

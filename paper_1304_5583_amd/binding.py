@@ -1,5 +1,5 @@
 """Thin ctypes binding of the gfx950 DFC-LRR library (include/lrr.h, include/lrr_diag.h,
-include/lrr_segment.h).
+include/lrr_segment.h, include/lrr_slr.h).
 
 Argument marshalling only: every step of the solve runs in the HIP library.
 Matrices are torch tensors on the GPU.  The library is column-major; a
@@ -46,6 +46,10 @@ class lrr_seg_info(C.Structure):
         ("embed_resid", C.c_double), ("theta_k", C.c_double), ("theta_k1", C.c_double),
         ("kmeans_iters", C.c_int), ("n_keep", C.c_int),
     ]
+
+
+class lrr_slr_info(C.Structure):
+    _fields_ = [("max_steps", C.c_int), ("not_converged", C.c_int), ("max_kkt", C.c_double)]
 
 
 class lrr_info(C.Structure):
@@ -107,6 +111,8 @@ def load_library(path: str = LIB_PATH):
     lib.dfc_lrr_solve_local.argtypes = [vp, i, i, vp, i, d, i, ip, ip, i, C.POINTER(lrr_opts), vp, i, vp, i,
                                         C.POINTER(lrr_info), vp]
     lib.dfc_lrr_solve_local.restype = i
+    lib.lrr_slr_graph.argtypes = [vp, i, i, vp, i, vp, i, i, d, vp, vp, vp, C.POINTER(lrr_slr_info), vp]
+    lib.lrr_slr_graph.restype = i
     lib.lrr_segment.argtypes = [vp, i, vp, i, i, vp, d, i, vp, C.POINTER(lrr_seg_info), vp]
     lib.lrr_segment.restype = i
     _lib = lib
@@ -392,6 +398,31 @@ def lrr_segment(Zt, k: int, exclude=None, rank_tol: float = 1e-6, rank_bound: in
     out = {f: getattr(info, f) for f, _ in lrr_seg_info._fields_}
     out["converged"] = st == LRR_OK
     return labels, out
+
+
+def lrr_slr_graph(Mt, Zt, nk: int, alpha: float = 0.05, want_obj: bool = True, ctx: Context | None = None):
+    """SLR-graph of Section 4.2.2 (include/lrr_slr.h).  Mt: (n, m) tensor holding M,
+    Zt: (n, n) tensor holding the column-major Z.  Returns (nbr (n, nk) int32,
+    w (n, nk) float64, obj (n,) float64 or None, info dict); row i of nbr / w
+    lists sample i's neighbours and edge weights."""
+    import torch
+    _require_cuda_f64(torch, Mt, Zt)
+    n, m = Mt.shape
+    if Zt.shape != (n, n):
+        raise ValueError("Zt must be n x n")
+    ctx = ctx or get_context(Mt.device.index or 0)
+    nbr = torch.empty((n, nk), dtype=torch.int32, device=Mt.device)
+    w = torch.empty((n, nk), dtype=torch.float64, device=Mt.device)
+    obj = torch.empty(n, dtype=torch.float64, device=Mt.device) if want_obj else None
+    info = lrr_slr_info()
+    st = load_library().lrr_slr_graph(ctx.handle, m, n, C.c_void_p(Mt.data_ptr()), m, C.c_void_p(Zt.data_ptr()),
+                                      int(Zt.stride(0)), int(nk), float(alpha), C.c_void_p(nbr.data_ptr()),
+                                      C.c_void_p(w.data_ptr()), C.c_void_p(obj.data_ptr()) if obj is not None else None,
+                                      C.byref(info), _stream(torch, Mt.device))
+    _check(st, ctx, allow_nc=True)
+    out = {f: getattr(info, f) for f, _ in lrr_slr_info._fields_}
+    out["converged"] = st == LRR_OK
+    return nbr, w, obj, out
 
 
 # ---------------------------------------------------------------- layout helpers

@@ -1,0 +1,436 @@
+// SLR-graph construction (Section 4.2.2) on the GPU.
+//
+//   neighbours   one workgroup per sample: the affinities |Z_ij| + |Z_ji| of
+//                all j go to LDS with their indices and are ordered by a
+//                bitonic network (decreasing affinity, ties by index); the
+//                first n_k indices are the sample's basis;
+//   Gram         G = M^T M once (FP64 MFMA GEMM); D_i^T D_i and D_i^T x_i are
+//                gathers from G;
+//   Lasso        one workgroup per sample: the Lawson-Hanson active set on
+//                w^T G_i w - 2 b^T w + alpha 1^T w, w >= 0, with the free set
+//                P kept independent (a dependent entering column is pivoted
+//                in along its dependence); the gradient over all n_k
+//                coordinates is one gathered row of G per free index, the
+//                factorisations of G_PP (|P| <= 64) run in LDS with all
+//                threads, the triangular solves in one wave with the unknowns
+//                in registers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "../../include/lrr_slr.h"
+
+struct lrr_ctx;   // defined in solver.hip
+
+namespace lrr {
+lrr_status ctx_fail(lrr_ctx* ctx, lrr_status st, const std::string& msg);
+int ctx_device(const lrr_ctx* ctx);
+void* ctx_seg_workspace(lrr_ctx* ctx, size_t bytes);
+void ctx_timed(lrr_ctx* ctx, hipStream_t s, const char* name, double flops, double bytes,
+               const std::function<void()>& f);
+void ctx_prof_flush(lrr_ctx* ctx);
+}  // namespace lrr
+
+namespace {
+
+constexpr int kMaxN = 4096;          // affinity row held in LDS for the ordering
+constexpr int kMaxNk = 1024;
+constexpr double kTol = 1e-12;       // optimality tolerance relative to the sample's scale
+constexpr double kDepTol = 1e-10;    // Cholesky pivot / max diagonal below which a column is dependent
+constexpr int kMaxP = 64;            // largest free set (Lasso support) held in LDS
+
+// neighbours of sample i = blockIdx.x: P = power of two >= n entries in LDS
+__global__ __launch_bounds__(256) void k_slr_select(const double* __restrict__ Z, long ldz, int n, int P, int nk,
+                                                    int* __restrict__ nbr) {
+    extern __shared__ char smem[];
+    double* key = reinterpret_cast<double*>(smem);
+    int* idx = reinterpret_cast<int*>(key + P);
+    const int i = blockIdx.x;
+    for (int j = threadIdx.x; j < P; j += 256) {
+        double v = -1.0;                       // below every affinity: padding and the sample itself
+        if (j < n && j != i) v = fabs(Z[j + (long)i * ldz]) + fabs(Z[i + (long)j * ldz]);
+        key[j] = v;
+        idx[j] = j;
+    }
+    __syncthreads();
+    // bitonic network; "before" = larger key, or equal key and smaller index
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int s = k >> 1; s > 0; s >>= 1) {
+            for (int a = threadIdx.x; a < P; a += 256) {
+                const int b = a ^ s;
+                if (b > a) {
+                    const bool up = (a & k) == 0;          // this run is ordered "before" first
+                    const double ka = key[a], kb = key[b];
+                    const int ia = idx[a], ib = idx[b];
+                    const bool b_first = kb > ka || (kb == ka && ib < ia);
+                    if (b_first == up) {
+                        key[a] = kb; key[b] = ka;
+                        idx[a] = ib; idx[b] = ia;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int a = threadIdx.x; a < nk; a += 256) nbr[(long)i * nk + a] = idx[a];
+}
+
+// deterministic max over the 256 threads
+__device__ double block_max256(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_sum256(double v, double* red) {
+    v = lrr::wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double r = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return r;
+}
+
+// (value, index) arg-min over the 256 threads: smaller value wins, ties to the lower index
+__device__ void block_argmin256(double v, int i, double* sv, int* si, double& vout, int& iout) {
+    sv[threadIdx.x] = v;
+    si[threadIdx.x] = i;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const double a = sv[threadIdx.x], b = sv[threadIdx.x + w];
+            const int ia = si[threadIdx.x], ib = si[threadIdx.x + w];
+            if (b < a || (b == a && ib < ia)) { sv[threadIdx.x] = b; si[threadIdx.x] = ib; }
+        }
+        __syncthreads();
+    }
+    vout = sv[0];
+    iout = si[0];
+    __syncthreads();
+}
+
+// Cholesky factor (lower, in place, column-major p x p) of the matrix in A; all
+// threads take part; returns the last pivot (before the square root), or
+// -infinity if an earlier pivot fails the threshold (the factor is then incomplete)
+__device__ double chol_lds(double* A, int p, double thr, double* flag) {
+    double last = 0.0;
+    for (int c = 0; c < p; ++c) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double piv = A[c + c * p];
+            flag[0] = piv;
+            if (c + 1 < p && !(piv > thr)) flag[0] = -1.0;
+            else A[c + c * p] = piv > 0.0 ? sqrt(piv) : 0.0;
+        }
+        __syncthreads();
+        last = flag[0];
+        if (c + 1 < p && !(last > thr)) return -INFINITY;
+        if (c + 1 == p) break;
+        const double lcc = A[c + c * p];
+        for (int r = c + 1 + threadIdx.x; r < p; r += 256) A[r + c * p] /= lcc;
+        __syncthreads();
+        const int q = p - c - 1;
+        for (int e = threadIdx.x; e < q * q; e += 256) {
+            const int rr = c + 1 + e % q, cc = c + 1 + e / q;
+            if (rr >= cc) A[rr + cc * p] -= A[rr + c * p] * A[cc + c * p];
+        }
+    }
+    __syncthreads();
+    return last;
+}
+
+// wave 0 only (all 64 lanes active): x = L^-1 r over the leading p <= 64 rows of
+// the factor in A (ld = ldA).  Lane q keeps x_q in a register; each row's dot
+// product is a wave reduction, so no LDS traffic or barrier is needed inside.
+__device__ void forward_w0(const double* A, int ldA, int p, const double* r, double* x) {
+    const int lane = threadIdx.x;
+    double xl = 0.0;
+    for (int q = 0; q < p; ++q) {
+        const double part = lrr::wave_sum(lane < q ? A[q + lane * ldA] * xl : 0.0);
+        const double xq = (r[q] - part) / A[q + q * ldA];
+        if (lane == q) xl = xq;
+    }
+    if (lane < p) x[lane] = xl;
+}
+
+// wave 0 only: x = L^-T y
+__device__ void backward_w0(const double* A, int ldA, int p, const double* y, double* x) {
+    const int lane = threadIdx.x;
+    double xl = 0.0;
+    for (int q = p - 1; q >= 0; --q) {
+        const double part = lrr::wave_sum((lane > q && lane < p) ? A[lane + q * ldA] * xl : 0.0);
+        const double xq = (y[q] - part) / A[q + q * ldA];
+        if (lane == q) xl = xq;
+    }
+    if (lane < p) x[lane] = xl;
+}
+
+// non-negative Lasso of sample i = blockIdx.x: the active set of Lawson and
+// Hanson in Gram form with the free set kept independent (the same steps as
+// the reference solver: entering index = most negative gradient off P; a
+// dependent entering column moves along its dependence and swaps out the first
+// free weight that reaches zero; the face is then solved, stepping back to the
+// first weight that would turn non-positive)
+__global__ __launch_bounds__(256) void k_slr_lasso(const double* __restrict__ G, long ldg, int nk, double alpha,
+                                                   const int* __restrict__ nbr, double* __restrict__ wout,
+                                                   double* __restrict__ obj, int* __restrict__ steps_out,
+                                                   double* __restrict__ kkt_out) {
+    extern __shared__ char smem[];
+    double* g = reinterpret_cast<double*>(smem);
+    double* b = g + nk;
+    int* nb = reinterpret_cast<int*>(b + nk);
+    int* pos = nb + nk;                      // position in the free set, or -1
+    __shared__ double A[kMaxP * kMaxP];
+    __shared__ double wP[kMaxP], sv[kMaxP], rhs[kMaxP], ytmp[kMaxP];
+    __shared__ int P[kMaxP + 1];
+    __shared__ double rv[256];
+    __shared__ int ri[256];
+    __shared__ double red[4], flag[2];
+    __shared__ int np_s, state;
+    const int i = blockIdx.x;
+    const int* my = nbr + (long)i * nk;
+    double sc = 1.0, dm = 0.0;
+    for (int a = threadIdx.x; a < nk; a += 256) {
+        const int q = my[a];
+        nb[a] = q;
+        b[a] = G[q + (long)i * ldg];
+        pos[a] = -1;
+        const double d = G[q + (long)q * ldg];
+        sc = fmax(sc, fmax(fabs(2.0 * b[a] - alpha), 2.0 * d));
+        dm = fmax(dm, d);
+    }
+    if (threadIdx.x == 0) np_s = 0;
+    const double scale = block_max256(sc, red);
+    const double dmax = block_max256(dm, red);
+    const double tol = kTol * scale, thr = kDepTol * dmax;
+    int steps = 0;
+    double viol = 0.0;
+    int status = 0;                          // 0 running, 1 optimal, 2 gave up
+    while (status == 0) {
+        if (threadIdx.x == 0) state = 0;
+        __syncthreads();
+        const int p = np_s;
+        // gradient g = 2 G w - 2 b + alpha over all coordinates, and the violation
+        double v = 0.0, gmin = 0.0;
+        int jmin = INT_MAX;
+        for (int a = threadIdx.x; a < nk; a += 256) {
+            double ga = alpha - 2.0 * b[a];
+            const double* row = G + nb[a];
+            for (int r = 0; r < p; ++r) ga += 2.0 * wP[r] * row[(long)nb[P[r]] * ldg];
+            g[a] = ga;
+            if (pos[a] >= 0) v = fmax(v, fabs(ga));
+            else {
+                v = fmax(v, fmax(0.0, -ga));
+                if (ga < gmin || (ga == gmin && ga < 0.0 && a < jmin)) { gmin = ga; jmin = a; }
+            }
+        }
+        viol = block_max256(v, red);
+        if (viol <= tol) { status = 1; break; }
+        if (++steps > 10 * nk + 20) { status = 2; break; }
+        double gj;
+        int j;
+        block_argmin256(gmin, jmin, rv, ri, gj, j);
+        if (!(gj < 0.0)) j = -1;             // only free coordinates violate: solve the face again
+        if (j >= 0) {
+            if (p + 1 > kMaxP) { status = 2; break; }
+            // factor G over P + {j}; the last pivot decides dependence
+            for (int e = threadIdx.x; e < (p + 1) * (p + 1); e += 256) {
+                const int r = e % (p + 1), c = e / (p + 1);
+                const int ar = (r < p) ? P[r] : j, ac = (c < p) ? P[c] : j;
+                A[e] = G[nb[ar] + (long)nb[ac] * ldg];
+            }
+            const double last = chol_lds(A, p + 1, thr, flag);
+            if (last == -INFINITY) { status = 2; break; }   // the free columns themselves degenerated
+            if (!(last > thr)) {
+                if (p == 0) { status = 2; break; }    // a zero column cannot have g_j < 0
+                // D_j = D_P beta: beta = L^-T (L^-1 G_Pj), where L^-1 G_Pj is row p of the factor
+                if (threadIdx.x < 64) {
+                    for (int q = threadIdx.x; q < p; q += 64) rhs[q] = A[p + q * (p + 1)];
+                }
+                __syncthreads();
+                if (threadIdx.x < 64) backward_w0(A, p + 1, p, rhs, ytmp);
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double t = INFINITY;
+                    int out = -1;
+                    for (int q = 0; q < p; ++q) {
+                        if (ytmp[q] > 0.0) {
+                            const double r = wP[q] / ytmp[q];
+                            if (r < t || (r == t && P[q] < P[out])) { t = r; out = q; }
+                        }
+                    }
+                    if (out < 0) state = 2;
+                    else {
+                        for (int q = 0; q < p; ++q) wP[q] -= t * ytmp[q];
+                        pos[P[out]] = -1;
+                        for (int q = out; q + 1 < p; ++q) { P[q] = P[q + 1]; wP[q] = wP[q + 1]; pos[P[q]] = q; }
+                        P[p - 1] = j;
+                        wP[p - 1] = t;
+                        pos[j] = p - 1;
+                        state = 0;
+                    }
+                }
+                __syncthreads();
+                if (state == 2) { status = 2; break; }
+            } else {
+                if (threadIdx.x == 0) {
+                    P[p] = j;
+                    wP[p] = 0.0;
+                    pos[j] = p;
+                    np_s = p + 1;
+                }
+                __syncthreads();
+            }
+        }
+        // face solve on P, stepping back while a weight would turn non-positive
+        for (int inner = 0; inner < kMaxP + 1 && np_s > 0; ++inner) {
+            const int pp = np_s;
+            for (int e = threadIdx.x; e < pp * pp; e += 256) {
+                const int r = e % pp, c = e / pp;
+                A[e] = G[nb[P[r]] + (long)nb[P[c]] * ldg];
+            }
+            for (int q = threadIdx.x; q < pp; q += 256) rhs[q] = b[P[q]] - 0.5 * alpha;
+            const double lp = chol_lds(A, pp, 0.0, flag);
+            if (!(lp > 0.0)) { if (threadIdx.x == 0) state = 2; __syncthreads(); break; }
+            __syncthreads();
+            if (threadIdx.x < 64) forward_w0(A, pp, pp, rhs, ytmp);
+            __syncthreads();
+            if (threadIdx.x < 64) backward_w0(A, pp, pp, ytmp, sv);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                bool allpos = true;
+                for (int q = 0; q < pp; ++q) allpos &= sv[q] > 0.0;
+                if (allpos) {
+                    for (int q = 0; q < pp; ++q) wP[q] = sv[q];
+                    state = 1;
+                } else {
+                    // step towards the face point up to the first weight that reaches
+                    // zero; every weight whose ratio attains the step leaves P
+                    double t = INFINITY;
+                    for (int q = 0; q < pp; ++q)
+                        if (sv[q] <= 0.0) {
+                            const double den = wP[q] - sv[q];
+                            t = fmin(t, den > 0.0 ? wP[q] / den : 0.0);
+                        }
+                    int c = 0;
+                    for (int q = 0; q < pp; ++q) {
+                        bool gone = false;
+                        if (sv[q] <= 0.0) {
+                            const double den = wP[q] - sv[q];
+                            gone = (den > 0.0 ? wP[q] / den : 0.0) == t;
+                        }
+                        const double wn = wP[q] + t * (sv[q] - wP[q]);
+                        if (gone || !(wn > 0.0)) pos[P[q]] = -1;
+                        else { P[c] = P[q]; wP[c] = wn; pos[P[c]] = c; ++c; }
+                    }
+                    np_s = c;
+                    state = 0;
+                }
+            }
+            __syncthreads();
+            if (state != 0) break;
+        }
+        if (state == 2) { status = 2; break; }
+    }
+    // weights, optimal objective, statistics
+    for (int a = threadIdx.x; a < nk; a += 256) {
+        const int q = pos[a];
+        wout[(long)i * nk + a] = q >= 0 ? wP[q] : 0.0;
+    }
+    if (obj) {
+        // w^T G w = w^T (g + 2 b - alpha) / 2 with the last gradient of the free set
+        double t = 0.0;
+        for (int a = threadIdx.x; a < nk; a += 256) {
+            const int q = pos[a];
+            if (q >= 0) t += wP[q] * (0.5 * (g[a] + 2.0 * b[a] - alpha) - 2.0 * b[a] + alpha);
+        }
+        const double s = block_sum256(t, red);
+        if (threadIdx.x == 0) obj[i] = s + G[i + (long)i * ldg];
+    }
+    if (threadIdx.x == 0) {
+        steps_out[i] = steps;
+        kkt_out[i] = status == 1 ? viol / scale : INFINITY;
+    }
+}
+
+unsigned grid1(long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+extern "C" lrr_status lrr_slr_graph(lrr_ctx* ctx, int m, int n, const void* Mv, int ldm, const void* Zv, int ldz,
+                                    int nk, double alpha, int* nbr, double* w, double* obj, lrr_slr_info* info,
+                                    void* stream) {
+    if (!ctx) return lrr::ctx_fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
+    if (m < 1 || n < 2 || !Mv || !Zv || ldm < m || ldz < n || !nbr || !w)
+        return lrr::ctx_fail(ctx, LRR_EINVAL, "bad M / Z / output arguments");
+    if (n > kMaxN) return lrr::ctx_fail(ctx, LRR_EINVAL, "n > 4096 is not supported by the neighbour ordering");
+    if (nk < 1 || nk > n - 1 || nk > kMaxNk) return lrr::ctx_fail(ctx, LRR_EINVAL, "nk must lie in [1, min(n-1, 1024)]");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return lrr::ctx_fail(ctx, LRR_EINVAL, "alpha must be positive");
+    const double* M = static_cast<const double*>(Mv);
+    const double* Z = static_cast<const double*>(Zv);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    try {
+        if (hipSetDevice(lrr::ctx_device(ctx)) != hipSuccess)
+            return lrr::ctx_fail(ctx, LRR_EDEVICE, "hipSetDevice failed");
+        int P = 1;
+        while (P < n) P <<= 1;
+        // workspace: G (n x n), per-sample step counts and violations, one descriptor
+        const size_t offG = 0, offS = offG + sizeof(double) * (size_t)n * n;
+        const size_t offK = (offS + sizeof(int) * (size_t)n + 255) & ~size_t(255);
+        const size_t offD = (offK + sizeof(double) * (size_t)n + 255) & ~size_t(255);
+        const size_t bytes = offD + sizeof(lrr::GemmDesc);
+        char* base = static_cast<char*>(lrr::ctx_seg_workspace(ctx, bytes));
+        double* G = reinterpret_cast<double*>(base + offG);
+        int* steps = reinterpret_cast<int*>(base + offS);
+        double* kkt = reinterpret_cast<double*>(base + offK);
+        lrr::GemmDesc* gd = reinterpret_cast<lrr::GemmDesc*>(base + offD);
+
+        lrr::ctx_timed(ctx, s, "k_slr_select", 0.0, 16.0 * n * (double)n, [&] {
+            hipLaunchKernelGGL(k_slr_select, dim3(n), dim3(256), (size_t)P * (sizeof(double) + sizeof(int)), s, Z,
+                               (long)ldz, n, P, nk, nbr);
+        });
+        lrr::GemmDesc h{M, M, G, n, n, m, ldm, ldm, n, 1.0, 0.0, nullptr, nullptr};
+        LRR_HIP(hipMemcpyAsync(gd, &h, sizeof(h), hipMemcpyHostToDevice, s));
+        lrr::ctx_timed(ctx, s, "k_dgemm<true, false>", 2.0 * n * (double)n * m, 0.0,
+                       [&] { lrr::launch_dgemm(gd, 1, n, n, true, false, s); });
+        const size_t lds = (size_t)nk * (2 * sizeof(double) + 2 * sizeof(int));
+        lrr::ctx_timed(ctx, s, "k_slr_lasso", 0.0, 0.0, [&] {
+            hipLaunchKernelGGL(k_slr_lasso, dim3(n), dim3(256), lds, s, G, (long)n, nk, alpha, nbr, w, obj, steps,
+                               kkt);
+        });
+        LRR_HIP(hipGetLastError());
+        std::vector<int> hs(n);
+        std::vector<double> hk(n);
+        LRR_HIP(hipMemcpyAsync(hs.data(), steps, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+        LRR_HIP(hipMemcpyAsync(hk.data(), kkt, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        LRR_HIP(hipStreamSynchronize(s));
+        lrr::ctx_prof_flush(ctx);
+        int smax = 0, nc = 0;
+        double kmax = 0.0;
+        for (int i = 0; i < n; ++i) {
+            smax = std::max(smax, hs[i]);
+            if (hk[i] <= kTol) kmax = std::max(kmax, hk[i]);
+            if (!(hk[i] <= kTol)) ++nc;
+        }
+        if (info) {
+            info->max_steps = smax;
+            info->not_converged = nc;
+            info->max_kkt = kmax;
+        }
+        return nc ? LRR_NOT_CONVERGED : LRR_OK;
+    } catch (const lrr::HipError& e) {
+        return lrr::ctx_fail(ctx, LRR_EDEVICE, e.msg);
+    } catch (const std::bad_alloc&) {
+        return lrr::ctx_fail(ctx, LRR_ENOMEM, "SLR-graph workspace allocation failed");
+    }
+}
