@@ -13,7 +13,8 @@
 //            accumulated rotation R_pq (2BS x 2BS);
 //   phase B  every tile pair (P, Q), P <= Q, of the round is replaced by
 //            R_P^T B[P, Q] R_Q (and its transpose), and the eigenvector
-//            accumulator gets W[:, P] <- W[:, P] R_P.
+//            accumulator gets W[:, P] <- W[:, P] R_P; the 2BS-square products
+//            run on the FP64 matrix cores out of LDS.
 // Pairs of indices whose Gershgorin discs both lie below tau^2 are never
 // rotated: the thresholding step discards every eigenvalue of that cluster, so
 // only the subspace it spans matters, not a basis of it.
@@ -162,6 +163,31 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
     if (tid == 0) d.prot[P] = rotated;
 }
 
+// C (PB x PB, into LDS) = op(A) B for PB x PB operands in LDS (row stride PB + 1),
+// on the FP64 matrix cores: the (PB/16)^2 output tiles of 16 x 16 are spread over
+// the four waves, each a chain of PB/4 v_mfma_f64_16x16x4f64 (register v of a
+// lane holds row lane/16 + 4v, column lane%16 of its tile).  TA: op(A) = A^T.
+template <int PB, bool TA>
+__device__ __forceinline__ void mm_lds(const double (*A)[PB + 1], const double (*B)[PB + 1], double (*C)[PB + 1],
+                                       int tid) {
+    constexpr int NTILE = PB / 16;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int t = wave; t < NTILE * NTILE; t += 4) {
+        const int ti = (t % NTILE) * 16, tj = (t / NTILE) * 16;
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < PB; kk += 4) {
+            const int k = kk + lk;
+            const double a = TA ? A[k][ti + lr] : A[ti + lr][k];
+            const double b = B[k][tj + lr];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) C[ti + lk + 4 * v][tj + lr] = acc[v];
+    }
+}
+
 // phase B: tiles of B and row chunks of W
 template <int BS>
 __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict__ descs, int round) {
@@ -205,23 +231,17 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
             RQ[i][j] = d.prot[Q] ? RgQ[i + (long)j * PB] : (i == j ? 1.0 : 0.0);
         }
         __syncthreads();
-        for (int idx = tid; idx < PB * PB; idx += 256) {
-            const int i = idx % PB, j = idx / PB;
-            double acc = 0.0;
-#pragma unroll 8
-            for (int k = 0; k < PB; ++k) acc += X[i][k] * RQ[k][j];
-            T[i][j] = acc;
-        }
+        mm_lds<PB, false>(X, RQ, T, tid);       // T = X R_Q
+        __syncthreads();
+        mm_lds<PB, true>(RP, T, X, tid);        // X = R_P^T T (X is free after the first product)
         __syncthreads();
         for (int idx = tid; idx < PB * PB; idx += 256) {
             const int i = idx % PB, j = idx / PB;
-            double acc = 0.0;
-#pragma unroll 8
-            for (int k = 0; k < PB; ++k) acc += RP[k][i] * T[k][j];
             const long gi = (i < BS) ? (long)p1 * BS + i : (long)q1 * BS + (i - BS);
             const long gj = (j < BS) ? (long)p2 * BS + j : (long)q2 * BS + (j - BS);
-            d.B[gi + gj * L] = acc;
-            if (P != Q) d.B[gj + gi * L] = acc;
+            const double v = X[i][j];
+            d.B[gi + gj * L] = v;
+            if (P != Q) d.B[gj + gi * L] = v;
         }
     } else {
         const int w = item - ntri;
@@ -242,14 +262,13 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
                 if (rr == 0) RP[i][j] = RgP[i + (long)j * PB];
             }
             __syncthreads();
+            mm_lds<PB, false>(X, RP, T, tid);   // T = W panel R_P
+            __syncthreads();
             for (int idx = tid; idx < PB * PB; idx += 256) {
                 const int i = idx % PB, j = idx / PB;
-                double acc = 0.0;
-#pragma unroll 8
-                for (int k = 0; k < PB; ++k) acc += X[i][k] * RP[k][j];
                 const long gi = r0 + rr + i;
                 const long gj = (j < BS) ? (long)p1 * BS + j : (long)q1 * BS + (j - BS);
-                if (gi < L) d.W[gi + gj * L] = acc;
+                if (gi < L) d.W[gi + gj * L] = T[i][j];
             }
             __syncthreads();
         }
