@@ -34,6 +34,8 @@ namespace {
 
 constexpr double kRelTol = 1e-15;
 constexpr double kAbsFloor = 1e-14;
+constexpr int kPairThreads = 512;  // the pair kernel's rounds are bound by the 2x2 and R updates:
+                                   // 512 threads measured 6% faster than 256, 1024 no faster
 constexpr int kInnerSweeps = 1;   // one cyclic sweep per pair and round (block-Jacobi
                                   // converges with 1-2 more outer sweeps, each far cheaper)
 
@@ -354,9 +356,9 @@ void launch_jacobi_init(const EigDesc* d_descs, int count, hipStream_t s) {
 void launch_jacobi_pairs(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s) {
     const int npair = maxL / bs / 2;
     if (bs == 16)
-        hipLaunchKernelGGL((k_jacobi_pairs<16, 256>), dim3(npair, count), dim3(256), 0, s, d_descs, round);
+        hipLaunchKernelGGL((k_jacobi_pairs<16, kPairThreads>), dim3(npair, count), dim3(kPairThreads), 0, s, d_descs, round);
     else
-        hipLaunchKernelGGL((k_jacobi_pairs<32, 256>), dim3(npair, count), dim3(256), 0, s, d_descs, round);
+        hipLaunchKernelGGL((k_jacobi_pairs<32, kPairThreads>), dim3(npair, count), dim3(kPairThreads), 0, s, d_descs, round);
 }
 
 void launch_jacobi_apply(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s) {

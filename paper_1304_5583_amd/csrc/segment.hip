@@ -483,7 +483,7 @@ struct Seg {
             sync();
             if (h_any == 0) break;
             for (int r = 0; r < L / kBs - 1; ++r) {
-                timed("k_jacobi_pairs<16, 256>", 0.0, 0.0, [&] { lrr::launch_jacobi_pairs(e.d, 1, L, kBs, r, s); });
+                timed("k_jacobi_pairs<16, 512>", 0.0, 0.0, [&] { lrr::launch_jacobi_pairs(e.d, 1, L, kBs, r, s); });
                 timed("k_jacobi_apply<16>", 0.0, 0.0, [&] { lrr::launch_jacobi_apply(e.d, 1, L, kBs, r, s); });
             }
         }

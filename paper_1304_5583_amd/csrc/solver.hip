@@ -940,7 +940,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 if (h_misc[0] == 0 || sw == max_sweeps) break;
                 ++sweeps_total;
                 for (int r = 0; r < nb - 1; ++r) {
-                    timed(p.bs == 16 ? "k_jacobi_pairs<16, 256>" : "k_jacobi_pairs<32, 256>", 0.0, 0.0, [&] {
+                    timed(p.bs == 16 ? "k_jacobi_pairs<16, 512>" : "k_jacobi_pairs<32, 512>", 0.0, 0.0, [&] {
                         lrr::launch_jacobi_pairs(b.eig, t, p.maxL, p.bs, r, s);
                     });
                     timed(p.bs == 16 ? "k_jacobi_apply<16>" : "k_jacobi_apply<32>", 0.0, 0.0, [&] {
