@@ -6,11 +6,12 @@
 //
 // Tiling: a 256-thread workgroup owns a 64 x 64 tile of C; each of its four
 // 64-wide wavefronts owns a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16.
-// K advances in steps of 32 (eight MFMA k-chunks of 4).  Operand tiles are
+// K advances in steps of 16 (four MFMA k-chunks of 4).  Operand tiles are
 // double-buffered in LDS and the next tile is fetched into registers while the
-// current one is multiplied, so a workgroup hides its own load latency (the
-// solver's products launch only about one workgroup per CU).  Loads zero-fill
-// at the matrix edges, so any M, N, K is legal.
+// current one is multiplied, so a workgroup hides its own load latency.  With
+// 16-deep tiles a workgroup holds 34 KB of LDS, so four fit on a CU (32-deep
+// tiles allowed two and ran the batched 512-order products at 38-40 instead of
+// 44-47 TFLOP/s).  Loads zero-fill at the matrix edges, so any M, N, K is legal.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -18,7 +19,7 @@ namespace lrr {
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 32, PAD = 2;
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
 constexpr int NLD = (BM * BK) / 256;   // elements of each operand tile per thread
 
 // One K-tile of op(A) (BM x BK) and op(B) (BK x BN) in registers.
