@@ -26,6 +26,8 @@
 // kSwitchSweeps Jacobi sweeps shows that they are not carried (a spread of
 // small, drifting eigenvalues); from then on that block leaves the eigenpairs
 // below min(tau^2, kLoCut scale) unresolved.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -34,6 +36,7 @@ namespace lrr {
 namespace {
 
 constexpr double kLinCap = 0.1;
+constexpr long kStatGroups = 64;         // workgroups per matrix of the kernels that also reduce statistics
 constexpr double kFirstStepCap = 0.1;    // largest correction accepted in the first step
 constexpr double kOrthTol = 1e-6;         // |I - X^T X| above this after one step: restart cold
 constexpr double kRelTol = 1e-15;
@@ -57,9 +60,10 @@ __global__ __launch_bounds__(256) void k_ref_rows(const RefDesc* __restrict__ de
     const double* S = d.SG;
     const double* G = d.SG + L * L;
     __shared__ double red[4];
+    // Gershgorin radius from column i (S is symmetric; the column is contiguous)
     double rs = 0.0;
     for (int j = threadIdx.x; j < d.l; j += 256)
-        if (j != i) rs += fabs(S[i + j * L]);
+        if (j != i) rs += fabs(S[j + i * L]);
     rs = wave_sum(rs);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rs;
     __syncthreads();
@@ -82,11 +86,12 @@ __global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs
     const RefDesc d = descs[blockIdx.y];
     if (d.run[0] == 0) return;
     const long L = d.L;
-    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
     if ((long)blockIdx.x * 256 >= L * L) return;   // whole workgroup past the matrix
     double emax = 0.0;
     int unres = 0;
-    if (idx < L * L) {
+    // a few workgroups stride over the matrix: one atomic per workgroup for the
+    // statistics (one per 256 entries serialised on the two addresses)
+    for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < L * L; idx += (long)gridDim.x * 256) {
         const int i = (int)(idx % L), j = (int)(idx / L);
         const double* S = d.SG;
         const double* G = d.SG + L * L;
@@ -104,12 +109,12 @@ __global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs
             const bool ok = !both_lo && dl != 0.0 && fabs(num) <= kLinCap * fabs(dl);
             if (ok) {
                 e = num / dl;
-                emax = fabs(e);
+                emax = fmax(emax, fabs(e));
             } else {
                 e = 0.5 * rij;
                 if (!both_lo && i < j && i < d.l && j < d.l) {
                     const double sii = S[i + i * L], sjj = S[j + j * L];
-                    if (fabs(sij) > fmax(kRelTol * sqrt(fabs(sii * sjj)), kAbsFloor * d.scale[0])) unres = 1;
+                    if (fabs(sij) > fmax(kRelTol * sqrt(fabs(sii * sjj)), kAbsFloor * d.scale[0])) unres += 1;
                 }
             }
         }
@@ -206,9 +211,9 @@ __global__ __launch_bounds__(256) void k_lo_rows(const EigDesc* __restrict__ des
     if (i >= d.L) return;
     const long L = d.L;
     __shared__ double red[4];
-    double rs = 0.0;
+    double rs = 0.0;   // column i of the symmetric matrix, contiguous
     for (int j = threadIdx.x; j < d.l; j += 256)
-        if (j != i) rs += fabs(d.B[i + j * L]);
+        if (j != i) rs += fabs(d.B[j + i * L]);
     rs = wave_sum(rs);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rs;
     __syncthreads();
@@ -237,15 +242,14 @@ __global__ __launch_bounds__(256) void k_orth_E(const RefDesc* __restrict__ desc
     const RefDesc d = descs[blockIdx.y];
     if (d.run[0] == 0) return;
     const long L = d.L;
-    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
     if ((long)blockIdx.x * 256 >= L * L) return;   // whole workgroup past the matrix
     double dev = 0.0;
-    if (idx < L * L) {
+    for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < L * L; idx += (long)gridDim.x * 256) {
         const int i = (int)(idx % L), j = (int)(idx / L);
         const double g = d.SG[L * L + idx];
         const double e = (i == j) ? 0.5 * (1.0 - g) : -0.5 * g;
         d.E[idx] = e;
-        dev = 2.0 * fabs(e);
+        dev = fmax(dev, 2.0 * fabs(e));
     }
     dev = wave_max(dev);
     __shared__ double wmax[4];
@@ -305,7 +309,8 @@ __global__ void k_mark_warm(const int* __restrict__ svt_run, int* __restrict__ w
 void launch_orth_E(const RefDesc* d, int count, int maxL, hipStream_t s) {
     const long n = (long)maxL * maxL;
     hipLaunchKernelGGL(k_orth_reset, dim3((count + 63) / 64), dim3(64), 0, s, d, count);
-    hipLaunchKernelGGL(k_orth_E, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_orth_E, dim3((unsigned)std::min<long>((n + 255) / 256, kStatGroups), count), dim3(256), 0,
+                       s, d);
 }
 void launch_orth_guard(const RefDesc* d, int count, int maxL, const int* warm, hipStream_t s) {
     const long n = (long)maxL * maxL;
@@ -335,7 +340,8 @@ void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, h
 }
 void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s) {
     const long n = (long)maxL * maxL;
-    hipLaunchKernelGGL(k_ref_E, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_ref_E, dim3((unsigned)std::min<long>((n + 255) / 256, kStatGroups), count), dim3(256), 0,
+                       s, d);
 }
 void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s) {
     const long n = (long)maxL * maxL;
