@@ -1,7 +1,8 @@
 """Kernel-level GPU checks through the diagnostic C-ABI entry points.
 
 Each building block is compared with a plain float64 reference on the same
-inputs: the MFMA GEMM (all transpose cases, ragged edges), the blocked
+inputs: the MFMA GEMM (all transpose cases, ragged edges, grids of more than
+a thousand tiles), the blocked
 Cholesky-based inverse of I + A A^T, and the batched block-Jacobi eigensolver
 (uneven orders, clusters, rank deficiency)."""
 import numpy as np
@@ -13,7 +14,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
-@pytest.mark.parametrize("M,N,K", [(64, 64, 16), (77, 131, 45), (1, 5, 3), (200, 9, 300)])
+@pytest.mark.parametrize("M,N,K", [(64, 64, 16), (77, 131, 45), (1, 5, 3), (200, 9, 300),
+                                   (2111, 2061, 37), (1030, 4100, 21)])
 def test_dgemm_matches_float64(ta, tb, M, N, K):
     torch = need_gpu()
     from paper_1304_5583_amd import binding as B
