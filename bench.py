@@ -282,6 +282,16 @@ def workload5_adjoint(B, torch, ctx):
     return res
 
 
+def tuned_schedule(path, p):
+    """The schedule-table entry a tuned FP64 solve of workload p uses (None: no entry)."""
+    maxl = int(max(p.offsets[i + 1] - p.offsets[i] for i in range(p.t)))
+    for line in open(path):
+        f = line.split("#")[0].split()
+        if len(f) == 9 and [int(x) for x in f[:5]] == [p.m, p.n, p.t, maxl, 0]:
+            return dict(zip(("eig_block", "use_graph", "check_every", "coords"), (int(x) for x in f[5:])))
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,7 +300,9 @@ def main():
     ap.add_argument("--workload", type=int, default=2, help="workload number (default 2)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--eig-block", type=int, default=0)
+    ap.add_argument("--eig-block", type=int, default=0,
+                    help="Jacobi block width (16 or 32); default: the autotuned schedule table")
+    ap.add_argument("--no-tune", action="store_true", help="ignore the autotuned schedule table")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the reduced-precision forms, workload 4 and the workload-5 adjoint")
     ap.add_argument("--calib-copy", action="store_true",
@@ -316,7 +328,14 @@ def main():
     Mt = B.to_device_colmajor(p.M, dev)
     Zt = torch.empty((p.n, p.n), dtype=torch.float64, device=dev)
     ctx = B.get_context(0)
-    opts = B.lrr_opts_default(eig_block=args.eig_block)
+    schedule = "default"
+    if args.eig_block or args.no_tune or not os.path.exists(B.TUNE_TABLE):
+        opts = B.lrr_opts_default(eig_block=args.eig_block)
+    else:
+        B.lrr_tune_load(B.TUNE_TABLE, ctx=ctx)
+        opts = B.lrr_opts_default(tune=1)
+        schedule = tuned_schedule(B.TUNE_TABLE, p) or "default"
+    print(f"bench: schedule {schedule}", file=sys.stderr, flush=True)
 
     def step():
         return B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False, Zt=Zt)
@@ -383,7 +402,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": p.name, "m": p.m, "n": p.n, "t": p.t, "lambda": p.lam, "tol": p.tol,
-                   "precision": "fp64", "mu0": opts.mu0, "rho": opts.rho, "mu_max": opts.mu_max},
+                   "precision": "fp64", "mu0": opts.mu0, "rho": opts.rho, "mu_max": opts.mu_max,
+                   "schedule": schedule},
         "alm_iters_per_s": batch_iters / elapsed,
         "alm_block_iters_per_s": block_iters / elapsed,
         "iters_per_block": info.iters.tolist(),

@@ -111,7 +111,10 @@ typedef struct {
                              /* launches from a captured HIP graph; 0: launch them  */
                              /* one by one (always so while profiling is enabled)   */
     int coords;              /* lrr_coords: coordinates of the n-row iterates       */
-    int reserved[5];         /* must be zero                                        */
+    int tune;                /* 1: take eig_block, use_graph, check_every, coords   */
+                             /* from the ctx's schedule table entry for this shape  */
+                             /* (lrr_tune_load), if there is one; 0 (default): not  */
+    int reserved[4];         /* must be zero                                        */
 } lrr_opts;
 
 /* Per-block results; every pointer may be NULL, each non-NULL array has t entries. */
@@ -138,6 +141,18 @@ void lrr_ctx_destroy(lrr_ctx *ctx);
 
 /* Message of the last failure on ctx (or of the last failure without a ctx). */
 const char *lrr_last_error(const lrr_ctx *ctx);
+
+/* Schedule table written by the autotuner (paper_1304_5583_amd/autotune.py): one
+ * entry per line, "m n t maxl precision eig_block use_graph check_every coords"
+ * (integers; '#' starts a comment; maxl = the largest block width).  A solve with
+ * opts.tune = 1 whose (m, n, t, maxl, precision) equal an entry's runs with that
+ * entry's Jacobi block width, graph use, convergence-check spacing and
+ * coordinates -- schedule choices the tuner accepted only where they reproduce
+ * the default schedule's iterates (same iteration counts, Z within 1e-8).  path
+ * NULL clears the table; a malformed file leaves the previous table and returns
+ * LRR_EINVAL naming the line.  At context creation the file named by the
+ * environment variable LRR_TUNE_TABLE, if set and well formed, is loaded. */
+lrr_status lrr_tune_load(lrr_ctx *ctx, const char *path);
 
 /* Host-only check of a D-step partition (Algorithm 1, SampleCols): perm must be a
  * permutation of 0..n-1 and offsets[0] = 0 < offsets[1] < ... < offsets[t] = n.

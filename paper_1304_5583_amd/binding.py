@@ -36,7 +36,8 @@ class lrr_opts(C.Structure):
         ("mu0", C.c_double), ("rho", C.c_double), ("mu_max", C.c_double), ("tol", C.c_double),
         ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("check_every", C.c_int),
         ("max_sweeps", C.c_int), ("save_for_backward", C.c_int), ("checkpoint_every", C.c_int),
-        ("eig_block", C.c_int), ("use_graph", C.c_int), ("coords", C.c_int), ("reserved", C.c_int * 5),
+        ("eig_block", C.c_int), ("use_graph", C.c_int), ("coords", C.c_int), ("tune", C.c_int),
+        ("reserved", C.c_int * 4),
     ]
 
 
@@ -88,6 +89,8 @@ def load_library(path: str = LIB_PATH):
     lib.lrr_ctx_destroy.restype = None
     lib.lrr_last_error.argtypes = [vp]
     lib.lrr_last_error.restype = C.c_char_p
+    lib.lrr_tune_load.argtypes = [vp, C.c_char_p]
+    lib.lrr_tune_load.restype = i
     lib.lrr_check_partition.argtypes = [i, i, ip, ip]
     lib.lrr_check_partition.restype = i
     lib.lrr_workspace_bytes.argtypes = [i, i, i, ip, C.POINTER(lrr_opts), C.POINTER(C.c_size_t)]
@@ -135,6 +138,17 @@ def lrr_opts_default(**overrides) -> lrr_opts:
 
 def _ip(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+TUNE_TABLE = os.path.join(HERE, "tune_table.txt")
+
+
+def lrr_tune_load(path: str | None = TUNE_TABLE, ctx: Context | None = None):
+    """Load the autotuner's schedule table into the context (None clears it);
+    solves with opts.tune = 1 then use the entry for their shape."""
+    ctx = ctx or get_context(0)
+    st = load_library().lrr_tune_load(ctx.handle, path.encode() if path is not None else None)
+    _check(st, ctx, allow_nc=False)
 
 
 def lrr_check_partition(n: int, perm, offsets) -> int:

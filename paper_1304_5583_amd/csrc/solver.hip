@@ -21,6 +21,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cctype>
+#include <cstdio>
+#include <cstdlib>
 #include <functional>
 #include <cmath>
 #include <cstring>
@@ -105,6 +108,12 @@ struct LrrProf {
 
 struct Tape;   // record of the last dfc_lrr_solve for dfc_lrr_backward
 
+// One line of the autotuner's schedule table.
+struct TuneEntry {
+    int m, n, t, maxl, precision;     // the problem shape the entry is for
+    int eig_block, use_graph, check_every, coords;
+};
+
 struct lrr_ctx {
     LrrProf prof;
     int device = 0;
@@ -119,6 +128,7 @@ struct lrr_ctx {
     hipStream_t capture = nullptr;         // private stream for graph capture
     void* seg_ws = nullptr;                // workspace of lrr_segment (kept apart from the solver's)
     size_t seg_bytes = 0;
+    std::vector<TuneEntry> tune;           // schedule table (lrr_tune_load)
 };
 
 namespace {
@@ -410,8 +420,53 @@ bool opts_valid(const lrr_opts& o, std::string& why) {
     if (o.eig_block != 0 && o.eig_block != 16 && o.eig_block != 32) { why = "eig_block must be 0, 16 or 32"; return false; }
     if (o.use_graph != 0 && o.use_graph != 1) { why = "use_graph must be 0 or 1"; return false; }
     if (o.coords < 0 || o.coords > 2) { why = "unknown coords"; return false; }
+    if (o.tune != 0 && o.tune != 1) { why = "tune must be 0 or 1"; return false; }
     for (int r : o.reserved) if (r != 0) { why = "reserved fields must be zero"; return false; }
     return true;
+}
+
+// the schedule of a tuned solve: the table entry for this shape, if any
+void apply_tune(const lrr_ctx* ctx, lrr_opts& o, int m, int n, int t, int maxl) {
+    if (!o.tune) return;
+    for (const TuneEntry& e : ctx->tune) {
+        if (e.m == m && e.n == n && e.t == t && e.maxl == maxl && e.precision == o.precision) {
+            o.eig_block = e.eig_block;
+            o.use_graph = e.use_graph;
+            o.check_every = e.check_every;
+            o.coords = e.coords;
+            return;
+        }
+    }
+}
+
+// parse a schedule table; returns false with a message naming the line
+bool parse_tune(const char* path, std::vector<TuneEntry>& out, std::string& why) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) { why = std::string("cannot open ") + path; return false; }
+    char line[512];
+    int no = 0;
+    bool ok = true;
+    while (std::fgets(line, sizeof(line), f)) {
+        ++no;
+        if (char* c = std::strchr(line, '#')) *c = '\0';
+        bool blank = true;
+        for (const char* c = line; *c; ++c) if (!std::isspace((unsigned char)*c)) { blank = false; break; }
+        if (blank) continue;
+        TuneEntry e;
+        char extra;
+        const int k = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %c", &e.m, &e.n, &e.t, &e.maxl, &e.precision,
+                                  &e.eig_block, &e.use_graph, &e.check_every, &e.coords, &extra);
+        if (k != 9 || e.m < 1 || e.n < 1 || e.t < 1 || e.maxl < 1 || e.precision < 0 || e.precision > 2 ||
+            (e.eig_block != 16 && e.eig_block != 32) || (e.use_graph != 0 && e.use_graph != 1) ||
+            e.check_every < 1 || e.coords < 0 || e.coords > 2) {
+            why = std::string(path) + ": malformed entry on line " + std::to_string(no);
+            ok = false;
+            break;
+        }
+        out.push_back(e);
+    }
+    std::fclose(f);
+    return ok;
 }
 
 lrr_status check_partition_impl(int n, int t, const int* perm, const int* offsets, std::string& why) {
@@ -1500,7 +1555,22 @@ lrr_status lrr_ctx_create(int device, lrr_ctx** out) {
     if (device < 0 || device >= count) return fail(nullptr, LRR_EINVAL, "device index out of range");
     lrr_ctx* c = new lrr_ctx();
     c->device = device;
+    if (const char* path = std::getenv("LRR_TUNE_TABLE")) {
+        std::vector<TuneEntry> t;
+        std::string why;
+        if (parse_tune(path, t, why)) c->tune = std::move(t);
+    }
     *out = c;
+    return LRR_OK;
+}
+
+lrr_status lrr_tune_load(lrr_ctx* ctx, const char* path) {
+    if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
+    if (!path) { ctx->tune.clear(); return LRR_OK; }
+    std::vector<TuneEntry> t;
+    std::string why;
+    if (!parse_tune(path, t, why)) return fail(ctx, LRR_EINVAL, why);
+    ctx->tune = std::move(t);
     return LRR_OK;
 }
 
@@ -1564,6 +1634,7 @@ lrr_status lrr_solve(lrr_ctx* ctx, int m, int n, int l, const void* A, int lda, 
             input_nonfinite(ctx, static_cast<const double*>(X), ldx, m, l, s))
             return fail(ctx, LRR_ENUMERIC, "non-finite value in A or X");
         int offs[2] = {0, l};
+        apply_tune(ctx, o, m, n, 1, l);
         Problem pr{m, n, l, 1, static_cast<const double*>(A), lda, static_cast<const double*>(X), ldx,
                    nullptr, offs, lambda, o};
         Plan p = make_plan(pr);
@@ -1605,6 +1676,9 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
         hipStream_t s = static_cast<hipStream_t>(stream);
         if (input_nonfinite(ctx, static_cast<const double*>(M), ldm, m, n, s))
             return fail(ctx, LRR_ENUMERIC, "non-finite value in M");
+        int maxl = 0;
+        for (int b = 0; b < t; ++b) maxl = std::max(maxl, offsets[b + 1] - offsets[b]);
+        apply_tune(ctx, o, m, n, t, maxl);
         Problem pr{m, n, n, t, static_cast<const double*>(M), ldm, nullptr, 0, perm, offsets, lambda, o};
         Plan p = make_plan(pr);
         Buffers b{};
@@ -1685,6 +1759,9 @@ lrr_status dfc_lrr_solve_local(lrr_ctx* ctx, int m, int n, const void* M, int ld
         hipStream_t s = static_cast<hipStream_t>(stream);
         if (input_nonfinite(ctx, static_cast<const double*>(M), ldm, m, n, s))
             return fail(ctx, LRR_ENUMERIC, "non-finite value in M");
+        int maxl = 0;
+        for (int b = 0; b < t; ++b) maxl = std::max(maxl, offsets[b + 1] - offsets[b]);
+        apply_tune(ctx, o, m, n, t, maxl);
         Problem pr{m, n, n, t, static_cast<const double*>(M), ldm, nullptr, 0, perm, offsets, lambda, o, 1};
         Plan p = make_plan(pr);
         Buffers b{};
