@@ -74,6 +74,10 @@ struct EigDesc {
     unsigned long long* work;  // [0] FP64 operations of the pair solves, [1] of the tile updates
     const double* cut;  // cut factor nu of the block: lo when the disc lies below min(tau^2, nu * scale)
     int* passes;        // sweep-loop passes of the current eigensolve (counted while open)
+    int* need;          // (L/bs)^2 flags (may be null): the check marks index-block pairs (p <= q,
+                        // at p * (L/bs) + q) holding an entry that still needs a rotation
+    const int* sched;   // (may be null) explicit rounds: entry r * (L/bs/2) + P is the pair
+                        // p | q << 16 of slot P in round r; every round pairs all L/bs blocks
 };
 
 // Warm-started eigenvector refinement of one Gram matrix (see refsyev.hip).

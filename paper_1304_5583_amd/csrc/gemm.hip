@@ -4,14 +4,21 @@
 // A A^T and Y^T Y, the dictionary products M Q and M^T V, the solve with the
 // inverse factor, the reconstruction of the thresholded block and the combine.
 //
-// Tiling: a 256-thread workgroup owns a 64 x 64 tile of C; each of its four
-// 64-wide wavefronts owns a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16.
-// K advances in steps of 16 (four MFMA k-chunks of 4).  Operand tiles are
-// double-buffered in LDS and the next tile is fetched into registers while the
-// current one is multiplied, so a workgroup hides its own load latency.  With
-// 16-deep tiles a workgroup holds 34 KB of LDS, so four fit on a CU (32-deep
+// Tiling: a 256-thread workgroup owns a BM x 64 tile of C; each of its four
+// 64-wide wavefronts owns a (BM/2) x 32 part as MFMA tiles of 16 x 16.  BM is 64
+// unless the batch has fewer than 512 such tiles; then BM = 32 doubles the
+// number of workgroups, so that every CU holds two and one hides the other's
+// load latency (the four Gram matrices of order 500 of a 4-block problem ran at
+// 21-30 TFLOP/s with one 64-row workgroup per CU, the 40-block problem's at
+// 47-55).  Both heights sum every element over K in the same order, so the
+// choice does not change the result.  K advances in steps of 16 (four MFMA
+// k-chunks of 4).  Operand tiles are double-buffered in LDS and the next tile is
+// fetched into registers while the current one is multiplied.  With 16-deep
+// tiles a 64-row workgroup holds 34 KB of LDS, so four fit on a CU (32-deep
 // tiles allowed two and ran the batched 512-order products at 38-40 instead of
-// 44-47 TFLOP/s).  Loads zero-fill at the matrix edges, so any M, N, K is legal.
+// 44-47 TFLOP/s).  Whole K-tiles of interior workgroups are read with 16-byte
+// vector loads (7-10 % faster than element loads); loads at the matrix edges
+// are bounds-tested and zero-fill, so any M, N, K is legal.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -19,100 +26,105 @@ namespace lrr {
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
-constexpr int NLD = (BM * BK) / 256;   // elements of each operand tile per thread
+constexpr int BN = 64, BK = 16, PAD = 2;
+constexpr int NLB = (BN * BK) / 256;   // elements of the op(B) tile per thread
 
 // One K-tile of op(A) (BM x BK) and op(B) (BK x BN) in registers.
+template <int BM>
 struct Frag {
-    double a[NLD];
-    double b[NLD];
+    static constexpr int NLA = (BM * BK) / 256;   // elements of the op(A) tile per thread
+    double a[NLA];
+    double b[NLB];
 };
 
-template <bool TA, bool TB>
-__device__ __forceinline__ void load_tile(Frag& f, const double* __restrict__ A, long lda,
+// Thread -> element map of the operand tiles.  Every thread holds a run of NLA
+// (op(A)) or NLB (op(B)) elements that are contiguous in memory:
+//   op(A) = A   : run along the BM rows of one k      (row (tid % 16) * NLA, k = tid / 16)
+//   op(A) = A^T : run along k of one row              (row tid / TPR, k = (tid % TPR) * NLA)
+//   op(B) = B   : run along k of one column           (column tid / 4, k = (tid % 4) * 4)
+//   op(B) = B^T : run along the BN columns of one k   (column (tid % 16) * 4, k = tid / 16)
+template <int BM, bool TA>
+__device__ __forceinline__ void a_slot(int tid, int& i, int& kk) {
+    constexpr int NLA = Frag<BM>::NLA, TPR = BK / NLA;
+    if (!TA) { i = (tid & 15) * NLA; kk = tid >> 4; }
+    else     { i = tid / TPR; kk = (tid % TPR) * NLA; }
+}
+template <bool TB>
+__device__ __forceinline__ void b_slot(int tid, int& j, int& kk) {
+    if (!TB) { j = tid >> 2; kk = (tid & 3) * 4; }
+    else     { j = (tid & 15) * 4; kk = tid >> 4; }
+}
+
+// bounds-tested loads (zero outside the matrices)
+template <int BM, bool TA, bool TB>
+__device__ __forceinline__ void load_tile(Frag<BM>& f, const double* __restrict__ A, long lda,
                                           const double* __restrict__ B, long ldb, int M, int N, int K,
                                           int m0, int n0, int k0, int tid) {
-    if (!TA) {   // op(A)(i,k) = A[i + k*lda]: 16 threads cover 64 rows of one k
-        const int i = (tid & 15) * 4, kk = tid >> 4;
+    constexpr int NLA = Frag<BM>::NLA;
+    int i, ka, j, kb;
+    a_slot<BM, TA>(tid, i, ka);
+    b_slot<TB>(tid, j, kb);
 #pragma unroll
-        for (int h = 0; h < NLD / 4; ++h) {
-            const int gk = k0 + kk + 16 * h;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int gi = m0 + i + v;
-                f.a[4 * h + v] = (gi < M && gk < K) ? A[gi + gk * lda] : 0.0;
-            }
-        }
-    } else {     // op(A)(i,k) = A[k + i*lda]: 8 threads cover 32 k of one row
-        const int i = tid >> 2, kk = (tid & 3) * 4;
-#pragma unroll
-        for (int h = 0; h < NLD / 4; ++h) {
-            const int gi = m0 + i;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int gk = k0 + kk + 16 * h + v;
-                f.a[4 * h + v] = (gi < M && gk < K) ? A[gk + gi * lda] : 0.0;
-            }
-        }
+    for (int v = 0; v < NLA; ++v) {
+        const int gi = m0 + i + (TA ? 0 : v), gk = k0 + ka + (TA ? v : 0);
+        f.a[v] = (gi < M && gk < K) ? (TA ? A[gk + gi * lda] : A[gi + gk * lda]) : 0.0;
     }
-    if (!TB) {   // op(B)(k,j) = B[k + j*ldb]: contiguous in k
-        const int j = tid >> 2, kk = (tid & 3) * 4;
 #pragma unroll
-        for (int h = 0; h < NLD / 4; ++h) {
-            const int gj = n0 + j;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int gk = k0 + kk + 16 * h + v;
-                f.b[4 * h + v] = (gj < N && gk < K) ? B[gk + gj * ldb] : 0.0;
-            }
-        }
-    } else {     // op(B)(k,j) = B[j + k*ldb]: contiguous in j
-        const int j = (tid & 15) * 4, kk = tid >> 4;
-#pragma unroll
-        for (int h = 0; h < NLD / 4; ++h) {
-            const int gk = k0 + kk + 16 * h;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int gj = n0 + j + v;
-                f.b[4 * h + v] = (gj < N && gk < K) ? B[gj + gk * ldb] : 0.0;
-            }
-        }
+    for (int v = 0; v < NLB; ++v) {
+        const int gj = n0 + j + (TB ? v : 0), gk = k0 + kb + (TB ? 0 : v);
+        f.b[v] = (gj < N && gk < K) ? (TB ? B[gj + gk * ldb] : B[gk + gj * ldb]) : 0.0;
     }
 }
 
-template <bool TA, bool TB>
-__device__ __forceinline__ void store_tile(const Frag& f, double (*As)[BM + PAD], double (*Bs)[BN + PAD],
+// interior tile with 16-byte aligned runs: unchecked 16-byte vector loads
+template <int BM, bool TA, bool TB>
+__device__ __forceinline__ void load_tile_vec(Frag<BM>& f, const double* __restrict__ A, long lda,
+                                              const double* __restrict__ B, long ldb, int m0, int n0, int k0,
+                                              int tid) {
+    constexpr int NLA = Frag<BM>::NLA;
+    int i, ka, j, kb;
+    a_slot<BM, TA>(tid, i, ka);
+    b_slot<TB>(tid, j, kb);
+    const double* pa = TA ? A + (k0 + ka) + (long)(m0 + i) * lda : A + (m0 + i) + (long)(k0 + ka) * lda;
+    const double* pb = TB ? B + (n0 + j) + (long)(k0 + kb) * ldb : B + (k0 + kb) + (long)(n0 + j) * ldb;
+#pragma unroll
+    for (int v = 0; v < NLA; v += 2) {
+        const double2 x = *reinterpret_cast<const double2*>(pa + v);
+        f.a[v] = x.x;
+        f.a[v + 1] = x.y;
+    }
+#pragma unroll
+    for (int v = 0; v < NLB; v += 2) {
+        const double2 x = *reinterpret_cast<const double2*>(pb + v);
+        f.b[v] = x.x;
+        f.b[v + 1] = x.y;
+    }
+}
+
+template <int BM, bool TA, bool TB>
+__device__ __forceinline__ void store_tile(const Frag<BM>& f, double (*As)[BM + PAD], double (*Bs)[BN + PAD],
                                            int tid) {
-    if (!TA) {
-        const int i = (tid & 15) * 4, kk = tid >> 4;
+    constexpr int NLA = Frag<BM>::NLA;
+    int i, ka, j, kb;
+    a_slot<BM, TA>(tid, i, ka);
+    b_slot<TB>(tid, j, kb);
 #pragma unroll
-        for (int h = 0; h < NLD / 4; ++h)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) As[kk + 16 * h][i + v] = f.a[4 * h + v];
-    } else {
-        const int i = tid >> 2, kk = (tid & 3) * 4;
-#pragma unroll
-        for (int h = 0; h < NLD / 4; ++h)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) As[kk + 16 * h + v][i] = f.a[4 * h + v];
+    for (int v = 0; v < NLA; ++v) {
+        if (!TA) As[ka][i + v] = f.a[v];
+        else As[ka + v][i] = f.a[v];
     }
-    if (!TB) {
-        const int j = tid >> 2, kk = (tid & 3) * 4;
 #pragma unroll
-        for (int h = 0; h < NLD / 4; ++h)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Bs[kk + 16 * h + v][j] = f.b[4 * h + v];
-    } else {
-        const int j = (tid & 15) * 4, kk = tid >> 4;
-#pragma unroll
-        for (int h = 0; h < NLD / 4; ++h)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Bs[kk + 16 * h][j + v] = f.b[4 * h + v];
+    for (int v = 0; v < NLB; ++v) {
+        if (!TB) Bs[kb + v][j] = f.b[v];
+        else Bs[kb][j + v] = f.b[v];
     }
 }
 
-template <bool TA, bool TB>
+// BM = 64: each wave owns a 32 x 32 quarter (2 x 2 MFMA tiles); BM = 32 (grids too
+// small to give every CU two workgroups): each wave owns 16 x 32 (1 x 2 tiles).
+template <int BM, bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_dgemm(const GemmDesc* __restrict__ descs) {
+    constexpr int WM = BM / 2, TX = WM / 16;
     const GemmDesc d = descs[blockIdx.z];
     if (d.active && d.active[0] == 0) return;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -125,11 +137,12 @@ __global__ __launch_bounds__(256) void k_dgemm(const GemmDesc* __restrict__ desc
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
 
-    dbl4 acc[2][2];
-    for (int x = 0; x < 2; ++x)
+    dbl4 acc[TX][2];
+#pragma unroll
+    for (int x = 0; x < TX; ++x)
         for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
 
     const double* __restrict__ A = d.A;
@@ -137,26 +150,41 @@ __global__ __launch_bounds__(256) void k_dgemm(const GemmDesc* __restrict__ desc
     const int M = d.M, N = d.N, K = d.K;
     const long lda = d.lda, ldb = d.ldb;
 
-    Frag f;
-    load_tile<TA, TB>(f, A, lda, B, ldb, M, N, K, m0, n0, 0, tid);
-    store_tile<TA, TB>(f, As[0], Bs[0], tid);
+    // whole K-tiles of an interior workgroup with 16-byte aligned operands are
+    // read with unchecked vector loads; the rest (edges, a partial last K-tile,
+    // odd strides or offsets) with bounds-tested element loads
+    const bool vec = m0 + BM <= M && n0 + BN <= N && (lda & 1) == 0 && (ldb & 1) == 0 &&
+                     (reinterpret_cast<unsigned long>(A) & 15) == 0 &&
+                     (reinterpret_cast<unsigned long>(B) & 15) == 0;
+    const int kvec = vec ? (K / BK) * BK : 0;
+
+    Frag<BM> f;
+    if (BK <= kvec) load_tile_vec<BM, TA, TB>(f, A, lda, B, ldb, m0, n0, 0, tid);
+    else load_tile<BM, TA, TB>(f, A, lda, B, ldb, M, N, K, m0, n0, 0, tid);
+    store_tile<BM, TA, TB>(f, As[0], Bs[0], tid);
     __syncthreads();
     int cur = 0;
     for (int k0 = 0; k0 < K; k0 += BK) {
-        const bool more = k0 + BK < K;
+        const int kn = k0 + BK;
         // the next tile's global loads are in flight while this one is multiplied
-        if (more) load_tile<TA, TB>(f, A, lda, B, ldb, M, N, K, m0, n0, k0 + BK, tid);
+        if (kn < K) {
+            if (kn + BK <= kvec) load_tile_vec<BM, TA, TB>(f, A, lda, B, ldb, m0, n0, kn, tid);
+            else load_tile<BM, TA, TB>(f, A, lda, B, ldb, M, N, K, m0, n0, kn, tid);
+        }
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kr = kk + lk;
-            const double a0 = As[cur][kr][wm + lr], a1 = As[cur][kr][wm + 16 + lr];
+            double a[TX];
+#pragma unroll
+            for (int x = 0; x < TX; ++x) a[x] = As[cur][kr][wm + 16 * x + lr];
             const double b0 = Bs[cur][kr][wn + lr], b1 = Bs[cur][kr][wn + 16 + lr];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+#pragma unroll
+            for (int x = 0; x < TX; ++x) {
+                acc[x][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b0, acc[x][0], 0, 0, 0);
+                acc[x][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b1, acc[x][1], 0, 0, 0);
+            }
         }
-        if (more) store_tile<TA, TB>(f, As[cur ^ 1], Bs[cur ^ 1], tid);
+        if (kn < K) store_tile<BM, TA, TB>(f, As[cur ^ 1], Bs[cur ^ 1], tid);
         __syncthreads();
         cur ^= 1;
     }
@@ -166,7 +194,7 @@ __global__ __launch_bounds__(256) void k_dgemm(const GemmDesc* __restrict__ desc
     const double alpha = d.alpha, beta = d.beta;
     const long ldc = d.ldc;
 #pragma unroll
-    for (int x = 0; x < 2; ++x) {
+    for (int x = 0; x < TX; ++x) {
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
             const int gj = n0 + wn + y * 16 + lr;
@@ -186,17 +214,27 @@ __global__ __launch_bounds__(256) void k_dgemm(const GemmDesc* __restrict__ desc
     }
 }
 
+template <int BM>
+void launch_bm(const GemmDesc* d_descs, int count, int maxM, int maxN, bool ta, bool tb, hipStream_t stream) {
+    dim3 grid((maxM + BM - 1) / BM, (maxN + BN - 1) / BN, count);
+    dim3 block(256);
+    if (!ta && !tb) hipLaunchKernelGGL((k_dgemm<BM, false, false>), grid, block, 0, stream, d_descs);
+    else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<BM, true, false>), grid, block, 0, stream, d_descs);
+    else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<BM, false, true>), grid, block, 0, stream, d_descs);
+    else hipLaunchKernelGGL((k_dgemm<BM, true, true>), grid, block, 0, stream, d_descs);
+}
+
 }  // namespace
 
 void launch_dgemm(const GemmDesc* d_descs, int count, int maxM, int maxN, bool ta, bool tb,
                   hipStream_t stream) {
     if (count <= 0 || maxM <= 0 || maxN <= 0) return;
-    dim3 grid((maxM + BM - 1) / BM, (maxN + BN - 1) / BN, count);
-    dim3 block(256);
-    if (!ta && !tb) hipLaunchKernelGGL((k_dgemm<false, false>), grid, block, 0, stream, d_descs);
-    else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<true, false>), grid, block, 0, stream, d_descs);
-    else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<false, true>), grid, block, 0, stream, d_descs);
-    else hipLaunchKernelGGL((k_dgemm<true, true>), grid, block, 0, stream, d_descs);
+    // 64-row tiles unless that leaves fewer than two workgroups per CU (256 CUs);
+    // both tile heights sum every element in the same order, so the choice does
+    // not change a bit of the result
+    const long tiles64 = (long)((maxM + 63) / 64) * ((maxN + BN - 1) / BN) * count;
+    if (tiles64 < 512) launch_bm<32>(d_descs, count, maxM, maxN, ta, tb, stream);
+    else launch_bm<64>(d_descs, count, maxM, maxN, ta, tb, stream);
 }
 
 }  // namespace lrr

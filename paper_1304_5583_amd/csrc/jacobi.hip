@@ -15,6 +15,9 @@
 //            R_P^T B[P, Q] R_Q (and its transpose), and the eigenvector
 //            accumulator gets W[:, P] <- W[:, P] R_P; the 2BS-square products
 //            run on the FP64 matrix cores out of LDS.
+// Rounds come from the circle method (a full sweep) or, when the check found
+// couplings in only a few index-block pairs, from a host-built schedule of
+// perfect matchings that covers just those pairs (EigDesc::sched).
 // Pairs of indices whose Gershgorin discs both lie below tau^2 are never
 // rotated: the thresholding step discards every eigenvalue of that cluster, so
 // only the subspace it spans matters, not a basis of it.
@@ -47,8 +50,19 @@ __device__ __forceinline__ void sym_schur2(double app, double aqq, double apq, d
     s = t * c;
 }
 
+// blocks (p, q) of slot P in a round: the circle method, or the explicit schedule
+__device__ __forceinline__ void round_pair(const EigDesc& d, int nb, int round, int P, int sched, int& p, int& q) {
+    if (sched) {
+        const int v = d.sched[round * (nb / 2) + P];
+        p = v & 0xffff;
+        q = v >> 16;
+    } else {
+        rr_pair(nb, round, P, p, q);
+    }
+}
+
 template <int BS, int NT>
-__global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__ descs, int round) {
+__global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__ descs, int round, int sched) {
     constexpr int PB = 2 * BS;
     constexpr int NP = PB / 2;   // rotations per inner round
     const EigDesc d = descs[blockIdx.y];
@@ -57,7 +71,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
     const int P = blockIdx.x;
     if (P >= nb / 2 || round >= nb - 1) return;
     int p, q;
-    rr_pair(nb, round, P, p, q);
+    round_pair(d, nb, round, P, sched, p, q);
 
     __shared__ double S[PB][PB + 1];
     __shared__ double R[PB][PB + 1];
@@ -192,7 +206,7 @@ __device__ __forceinline__ void mm_lds(const double (*A)[PB + 1], const double (
 
 // phase B: tiles of B and row chunks of W
 template <int BS>
-__global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict__ descs, int round) {
+__global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict__ descs, int round, int sched) {
     constexpr int PB = 2 * BS;
     constexpr int RC = 64;   // rows of W per workgroup
     const EigDesc d = descs[blockIdx.y];
@@ -219,8 +233,8 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
         if (!d.prot[P] && !d.prot[Q]) return;
         if (tid == 0 && d.work) atomicAdd(&d.work[1], 4ull * PB * PB * PB);   // two PB^3 products
         int p1, q1, p2, q2;
-        rr_pair(nb, round, P, p1, q1);
-        rr_pair(nb, round, Q, p2, q2);
+        round_pair(d, nb, round, P, sched, p1, q1);
+        round_pair(d, nb, round, Q, sched, p2, q2);
         const double* RgP = d.R + (long)P * PB * PB;
         const double* RgQ = d.R + (long)Q * PB * PB;
         for (int idx = tid; idx < PB * PB; idx += 256) {
@@ -251,7 +265,7 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
         if (!d.prot[P]) return;
         if (tid == 0 && d.work) atomicAdd(&d.work[1], 2ull * RC * PB * PB);   // RC x PB times PB x PB
         int p1, q1;
-        rr_pair(nb, round, P, p1, q1);
+        round_pair(d, nb, round, P, sched, p1, q1);
         const double* RgP = d.R + (long)P * PB * PB;
         const int r0 = chunk * RC;
         // reuse X as a RC x PB panel when RC <= PB, else loop in pieces of PB rows
@@ -294,19 +308,25 @@ __global__ __launch_bounds__(256) void k_jacobi_init(const EigDesc* __restrict__
     }
 }
 
-// one launch per sweep: does any off-diagonal entry still need a rotation?
-__global__ __launch_bounds__(256) void k_jacobi_offcheck(const EigDesc* __restrict__ descs, int* n_open) {
+// one launch per sweep: does any off-diagonal entry still need a rotation?  With
+// bs > 0 and need set, the index-block pairs holding such entries are marked.
+__global__ __launch_bounds__(256) void k_jacobi_offcheck(const EigDesc* __restrict__ descs, int* n_open, int bs) {
     const EigDesc d = descs[blockIdx.y];
     if (d.run[0] == 0 || d.st[0] != 0) return;
     const long L = d.L;
     const long total = (long)d.l * d.l;
     const double floor_abs = kAbsFloor * d.scale[0];
+    int* const mark = (bs > 0) ? d.need : nullptr;
+    const int nb = (bs > 0) ? d.L / bs : 0;
     int need = 0;
     for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long)gridDim.x * 256) {
         const int i = (int)(idx % d.l), j = (int)(idx / d.l);
         if (i < j && !(d.lo[i] && d.lo[j])) {
             const double a = d.B[i + j * L];
-            if (fabs(a) > fmax(kRelTol * sqrt(fabs(d.B[i + i * L] * d.B[j + j * L])), floor_abs)) need = 1;
+            if (fabs(a) > fmax(kRelTol * sqrt(fabs(d.B[i + i * L] * d.B[j + j * L])), floor_abs)) {
+                need = 1;
+                if (mark) mark[(i / bs) * nb + j / bs] = 1;   // every writer stores 1
+            }
         }
     }
     __shared__ int any;
@@ -353,24 +373,28 @@ void launch_jacobi_init(const EigDesc* d_descs, int count, hipStream_t s) {
     hipLaunchKernelGGL(k_jacobi_init, dim3(count), dim3(256), 0, s, d_descs);
 }
 
-void launch_jacobi_pairs(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s) {
+void launch_jacobi_pairs(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s,
+                         bool sched) {
     const int npair = maxL / bs / 2;
     if (bs == 16)
-        hipLaunchKernelGGL((k_jacobi_pairs<16, kPairThreads>), dim3(npair, count), dim3(kPairThreads), 0, s, d_descs, round);
+        hipLaunchKernelGGL((k_jacobi_pairs<16, kPairThreads>), dim3(npair, count), dim3(kPairThreads), 0, s, d_descs,
+                           round, (int)sched);
     else
-        hipLaunchKernelGGL((k_jacobi_pairs<32, kPairThreads>), dim3(npair, count), dim3(kPairThreads), 0, s, d_descs, round);
+        hipLaunchKernelGGL((k_jacobi_pairs<32, kPairThreads>), dim3(npair, count), dim3(kPairThreads), 0, s, d_descs,
+                           round, (int)sched);
 }
 
-void launch_jacobi_apply(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s) {
+void launch_jacobi_apply(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s,
+                         bool sched) {
     const int npair = maxL / bs / 2;
     const int ntri = npair * (npair + 1) / 2;
     const int nchunks = (maxL + 63) / 64;
     if (bs == 16)
         hipLaunchKernelGGL((k_jacobi_apply<16>), dim3(ntri + nchunks * npair, count), dim3(256), 0, s,
-                           d_descs, round);
+                           d_descs, round, (int)sched);
     else
         hipLaunchKernelGGL((k_jacobi_apply<32>), dim3(ntri + nchunks * npair, count), dim3(256), 0, s,
-                           d_descs, round);
+                           d_descs, round, (int)sched);
 }
 
 void launch_jacobi_round(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s) {
@@ -378,9 +402,9 @@ void launch_jacobi_round(const EigDesc* d_descs, int count, int maxL, int bs, in
     launch_jacobi_apply(d_descs, count, maxL, bs, round, s);
 }
 
-void launch_jacobi_check(const EigDesc* d_descs, int count, int maxL, int* d_open, hipStream_t s) {
+void launch_jacobi_check(const EigDesc* d_descs, int count, int maxL, int* d_open, hipStream_t s, int bs) {
     const int blocks = (maxL * maxL + 255) / 256 < 64 ? (maxL * maxL + 255) / 256 : 64;
-    hipLaunchKernelGGL(k_jacobi_offcheck, dim3(blocks, count), dim3(256), 0, s, d_descs, d_open);
+    hipLaunchKernelGGL(k_jacobi_offcheck, dim3(blocks, count), dim3(256), 0, s, d_descs, d_open, bs);
     hipLaunchKernelGGL(k_jacobi_close, dim3((count + 63) / 64), dim3(64), 0, s, d_descs, count, d_open);
 }
 

@@ -23,9 +23,13 @@ void launch_add_identity(double* A, int lda, int m, double s, hipStream_t st);
 // jacobi.hip
 void launch_jacobi_init(const EigDesc* d_descs, int count, hipStream_t s);
 void launch_jacobi_round(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s);
-void launch_jacobi_pairs(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s);
-void launch_jacobi_apply(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s);
-void launch_jacobi_check(const EigDesc* d_descs, int count, int maxL, int* d_open, hipStream_t s);
+// sched: take the round's pairs from EigDesc::sched instead of the circle method
+void launch_jacobi_pairs(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s,
+                         bool sched = false);
+void launch_jacobi_apply(const EigDesc* d_descs, int count, int maxL, int bs, int round, hipStream_t s,
+                         bool sched = false);
+// bs > 0: also mark the index-block pairs that need rotations (EigDesc::need)
+void launch_jacobi_check(const EigDesc* d_descs, int count, int maxL, int* d_open, hipStream_t s, int bs = 0);
 void launch_jacobi_sweep_end(const EigDesc* d_descs, int count, int* d_any, hipStream_t s);
 void launch_jacobi_eigvals(const EigDesc* d_descs, int count, hipStream_t s);
 
@@ -37,7 +41,9 @@ void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s);
 void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, int* n_open, hipStream_t s);
 void launch_ref_next(const RefDesc* d, int count, hipStream_t s);
 void launch_orth_guard(const RefDesc* d, int count, int maxL, const int* warm, hipStream_t s);
-void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hipStream_t s);
+// count_pass: count this pass of the sweep loop toward the block's switch rule
+void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hipStream_t s,
+                    bool count_pass = true);
 void launch_orth_E(const RefDesc* d, int count, int maxL, hipStream_t s);
 void launch_ref_set_run(const RefDesc* d, int count, const int* svt_run, hipStream_t s);
 void launch_lo_mode(const int* svt_run, const int* warm, int* passes, double* cut, int t, hipStream_t s);

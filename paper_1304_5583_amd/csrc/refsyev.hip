@@ -203,8 +203,10 @@ __global__ __launch_bounds__(256) void k_ref_scale(const RefDesc* __restrict__ d
     if (threadIdx.x == 0) d.scale[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
-// Gershgorin flags of the Jacobi matrix (for the cleanup sweeps)
-__global__ __launch_bounds__(256) void k_lo_rows(const EigDesc* __restrict__ descs, const DevIter* it) {
+// Gershgorin flags of the Jacobi matrix (for the cleanup sweeps); count_pass:
+// the pass follows a full sweep (or starts the eigensolve) and is counted
+__global__ __launch_bounds__(256) void k_lo_rows(const EigDesc* __restrict__ descs, const DevIter* it,
+                                                 int count_pass) {
     const EigDesc d = descs[blockIdx.y];
     if (d.run[0] == 0 || d.st[0] != 0) return;
     const int i = blockIdx.x;
@@ -221,7 +223,7 @@ __global__ __launch_bounds__(256) void k_lo_rows(const EigDesc* __restrict__ des
         const double r = (red[0] + red[1]) + (red[2] + red[3]);
         const double tau = it->tau;
         d.lo[i] = (i >= d.l) ? 1 : (it->full ? 0 : lo_flag(d.B[i + i * L] + r, tau, d.cut[0], d.scale[0]));
-        if (i == 0) d.passes[0] += 1;
+        if (i == 0 && count_pass) d.passes[0] += 1;
     }
 }
 
@@ -350,8 +352,8 @@ void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s) {
 void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, int* n_open, hipStream_t s) {
     hipLaunchKernelGGL(k_ref_update, dim3((count + 63) / 64), dim3(64), 0, s, d, count, step, max_steps, n_open);
 }
-void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hipStream_t s) {
-    hipLaunchKernelGGL(k_lo_rows, dim3(maxL, count), dim3(256), 0, s, d, it);
+void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hipStream_t s, bool count_pass) {
+    hipLaunchKernelGGL(k_lo_rows, dim3(maxL, count), dim3(256), 0, s, d, it, (int)count_pass);
 }
 
 }  // namespace lrr

@@ -209,6 +209,7 @@ struct Buffers {
     std::vector<double*> Bm, Wm, Wg, Pm, Rm, lam, h, TX, SG, Eb, XE, Bq;
     std::vector<int*> lo;
     int *warm, *ref_run, *ref_unres, *ref_cont, *passes;
+    int *need_all, *sched_all;   // targeted Jacobi rounds: check marks and round schedules, all blocks
     double* locut;
     double *ref_eprev, *ref_scale;
     unsigned long long* ref_emax;
@@ -222,6 +223,7 @@ struct Buffers {
 };
 
 constexpr int kRefSteps = 10;  // cap on refinement steps per thresholding step
+constexpr int kMaxTargeted = 60;   // cap on targeted Jacobi passes per eigensolve
 constexpr int kAnchorEvery = 16;   // FP64 re-anchoring period of the carried product M Q
 
 int jacobi_bs(int maxl, int requested) {
@@ -230,6 +232,59 @@ int jacobi_bs(int maxl, int requested) {
 }
 
 int round_up(int x, int a) { return ((x + a - 1) / a) * a; }
+
+// Targeted Jacobi rounds.  need (nb x nb, p <= q at p * nb + q) marks the
+// index-block pairs that still hold an entry needing a rotation (p == q: inside
+// block p).  Greedy maximal matchings of the marked pairs, each completed to a
+// perfect matching of the nb blocks (a block inside which something is marked
+// goes with any free partner; the rest pair up in order), are written to out as
+// p | q << 16 per slot, nb / 2 slots per round.  Returns the number of rounds,
+// or -1 if more than cap would be needed.
+int plan_rounds(const int* need, int nb, int cap, int* out) {
+    std::vector<std::pair<int, int>> pend, keep;
+    std::vector<char> inner(nb, 0), used(nb);
+    for (int p = 0; p < nb; ++p)
+        for (int q = p; q < nb; ++q)
+            if (need[p * nb + q]) {
+                if (p == q) inner[p] = 1;
+                else pend.emplace_back(p, q);
+            }
+    int rounds = 0;
+    for (;;) {
+        bool left = !pend.empty();
+        for (int p = 0; p < nb && !left; ++p) left = inner[p] != 0;
+        if (!left) return rounds;
+        if (rounds == cap) return -1;
+        int* slot = out + (size_t)rounds * (nb / 2);
+        int ns = 0;
+        std::fill(used.begin(), used.end(), 0);
+        auto put = [&](int p, int q) {
+            slot[ns++] = std::min(p, q) | (std::max(p, q) << 16);
+            used[p] = used[q] = 1;
+            inner[p] = inner[q] = 0;   // a pair solve also sweeps inside both blocks
+        };
+        keep.clear();
+        for (const auto& e : pend) {
+            if (!used[e.first] && !used[e.second]) put(e.first, e.second);
+            else keep.push_back(e);
+        }
+        pend.swap(keep);
+        for (int p = 0; p < nb; ++p) {
+            if (!inner[p] || used[p]) continue;
+            int q = -1;
+            for (int x = 0; x < nb; ++x)
+                if (x != p && !used[x] && (q < 0 || (inner[x] && !inner[q]))) q = x;
+            put(p, q);   // nb is even, so a free partner exists
+        }
+        int u = -1;
+        for (int x = 0; x < nb; ++x) {
+            if (used[x]) continue;
+            if (u < 0) u = x;
+            else { put(u, x); u = -1; }
+        }
+        ++rounds;
+    }
+}
 
 // Lay out every buffer; with a null base only the size is computed.
 size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need_X) {
@@ -294,6 +349,16 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
         b.h[i] = a.take<double>(L);
         b.lo[i] = a.take<int>(L);
         b.prot[i] = a.take<int>(L / (2 * p.bs) + 1);
+    }
+    {
+        size_t nneed = 0, nsched = 0;
+        for (size_t i = 0; i < t; ++i) {
+            const size_t nb = p.L[i] / p.bs;
+            nneed += nb * nb;
+            nsched += (nb - 1) * (nb / 2);
+        }
+        b.need_all = a.take<int>(nneed);
+        b.sched_all = a.take<int>(nsched);
     }
     b.warm = a.take<int>(t);
     b.passes = a.take<int>(t);
@@ -661,6 +726,12 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     std::vector<GemmDesc> gram(t), gRT(t), gRSG(t), gRXE(t), gOG(t), gBq(t), gP(t), gJ(t);
     std::vector<GemmDesc> gMQ(t), gMQa(t), gKV(t), gMtV(t), gExp(t);
     std::vector<EigDesc> eig(t);
+    std::vector<size_t> need_off(t + 1, 0), sched_off(t + 1, 0);
+    for (int bb = 0; bb < t; ++bb) {
+        const size_t nb = p.L[bb] / p.bs;
+        need_off[bb + 1] = need_off[bb] + nb * nb;
+        sched_off[bb + 1] = sched_off[bb] + (nb - 1) * (nb / 2);
+    }
     std::vector<SvtDesc> svt(t);
     std::vector<RefDesc> ref(t);
     for (int bb = 0; bb < t; ++bb) {
@@ -703,7 +774,8 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
             gExp[bb] = GemmDesc{b.Qm, b.R2r + o_n, b.R2full + (size_t)p.boff[bb] * n, n, l, nr, n, nr, n, 1.0,
                                 0.0, b.expand + bb, nullptr};
         eig[bb] = EigDesc{b.Bq[bb], X, b.Rm[bb], b.lam[bb], L, l, run, b.eigst + 2 * bb,
-                          b.eigscale + bb, b.prot[bb], b.lo[bb], ctx->dwork, b.locut + bb, b.passes + bb};
+                          b.eigscale + bb, b.prot[bb], b.lo[bb], ctx->dwork, b.locut + bb, b.passes + bb,
+                          b.need_all + need_off[bb], b.sched_all + sched_off[bb]};
         svt[bb] = SvtDesc{b.Bq[bb], X, b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
         ref[bb] = RefDesc{b.Bm[bb], X, b.SG[bb], b.Eb[bb], b.XE[bb], b.lam[bb], b.lo[bb], b.ref_scale + bb,
                           b.ref_emax + bb, b.ref_unres + bb, b.ref_eprev + bb, b.ref_run + bb,
@@ -826,6 +898,14 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     };
     std::vector<int> h_act(t, 1);
     long long sweeps_total = 0;
+    // targeted Jacobi rounds: per-block offsets of the check marks and schedules
+    std::vector<size_t> need_off(t + 1, 0), sched_off(t + 1, 0);
+    for (int bb = 0; bb < t; ++bb) {
+        const size_t nbb = p.L[bb] / p.bs;
+        need_off[bb + 1] = need_off[bb] + nbb * nbb;
+        sched_off[bb + 1] = sched_off[bb] + (nbb - 1) * (nbb / 2);
+    }
+    std::vector<int> h_need(need_off[t]), h_sched(sched_off[t]), block_rounds(t, 0);
     const double D = sizeof(double);
     // one iteration's Z-step and E-step launches on stream st
     auto zstep = [&](hipStream_t st, bool anchor, auto&& tm, double cact) {
@@ -983,23 +1063,62 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             // whole decomposition on a block's first thresholding step)
             timed("k_jacobi_init", 0.0, 0.0, [&] { lrr::launch_jacobi_init(b.eig, t, s); });
             const int nb = p.maxL / p.bs;
-            for (int sw = 0; sw <= max_sweeps; ++sw) {
+            // A pass checks every matrix, then runs a full sweep (nb - 1 circle
+            // rounds) or, when the marked index-block pairs fit into at most
+            // (nb - 1) / 2 perfect matchings for every block, only those rounds.
+            // At most max_sweeps full sweeps and kMaxTargeted targeted passes.
+            int full = 0, targeted = 0;
+            bool counted = true;   // the pass follows a full sweep (or starts the solve)
+            for (;;) {
                 // converged matrices are closed here; the loop ends when none is open
-                timed("k_lo_rows", 0.0, 0.0, [&] { lrr::launch_lo_rows(b.eig, t, p.maxL, b.it, s); });
+                timed("k_lo_rows", 0.0, 0.0, [&] { lrr::launch_lo_rows(b.eig, t, p.maxL, b.it, s, counted); });
                 LRR_HIP(hipMemsetAsync(b.eig_any, 0, sizeof(int), s));
+                LRR_HIP(hipMemsetAsync(b.need_all, 0, sizeof(int) * h_need.size(), s));
                 timed("k_jacobi_offcheck", 0.0, 0.0, [&] {
-                    lrr::launch_jacobi_check(b.eig, t, p.maxL, b.eig_any, s);
+                    lrr::launch_jacobi_check(b.eig, t, p.maxL, b.eig_any, s, p.bs);
                 });
                 LRR_HIP(hipMemcpyAsync(h_misc, b.eig_any, sizeof(int), hipMemcpyDeviceToHost, s));
+                LRR_HIP(hipMemcpyAsync(h_need.data(), b.need_all, sizeof(int) * h_need.size(),
+                                       hipMemcpyDeviceToHost, s));
                 sync();
-                if (h_misc[0] == 0 || sw == max_sweeps) break;
+                if (h_misc[0] == 0 || full == max_sweeps) break;
                 ++sweeps_total;
-                for (int r = 0; r < nb - 1; ++r) {
+                int rounds = targeted < kMaxTargeted ? 0 : -1;
+                for (int bb = 0; bb < t && rounds >= 0; ++bb) {
+                    const int nbb = p.L[bb] / p.bs;
+                    // the block's schedule holds nbb - 1 rounds
+                    const int rb = plan_rounds(h_need.data() + need_off[bb], nbb, std::min((nb - 1) / 2, nbb - 1),
+                                               h_sched.data() + sched_off[bb]);
+                    rounds = rb < 0 ? -1 : std::max(rounds, rb);
+                    block_rounds[bb] = rb;
+                }
+                if (rounds > 0) {
+                    // blocks that need fewer rounds get circle rounds (any perfect matching is valid)
+                    for (int bb = 0; bb < t; ++bb) {
+                        const int nbb = p.L[bb] / p.bs;
+                        for (int r = block_rounds[bb]; r < std::min(rounds, nbb - 1); ++r)
+                            for (int P = 0; P < nbb / 2; ++P) {
+                                int a0, b0;
+                                lrr::rr_pair(nbb, r, P, a0, b0);
+                                h_sched[sched_off[bb] + (size_t)r * (nbb / 2) + P] = a0 | (b0 << 16);
+                            }
+                    }
+                    LRR_HIP(hipMemcpyAsync(b.sched_all, h_sched.data(), sizeof(int) * h_sched.size(),
+                                           hipMemcpyHostToDevice, s));
+                    ++targeted;
+                    counted = false;
+                } else {
+                    rounds = nb - 1;
+                    ++full;
+                    counted = true;
+                }
+                const bool sched = !counted;
+                for (int r = 0; r < rounds; ++r) {
                     timed(p.bs == 16 ? "k_jacobi_pairs<16, 512>" : "k_jacobi_pairs<32, 512>", 0.0, 0.0, [&] {
-                        lrr::launch_jacobi_pairs(b.eig, t, p.maxL, p.bs, r, s);
+                        lrr::launch_jacobi_pairs(b.eig, t, p.maxL, p.bs, r, s, sched);
                     });
                     timed(p.bs == 16 ? "k_jacobi_apply<16>" : "k_jacobi_apply<32>", 0.0, 0.0, [&] {
-                        lrr::launch_jacobi_apply(b.eig, t, p.maxL, p.bs, r, s);
+                        lrr::launch_jacobi_apply(b.eig, t, p.maxL, p.bs, r, s, sched);
                     });
                 }
             }
