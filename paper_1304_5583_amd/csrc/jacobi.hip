@@ -43,10 +43,11 @@ constexpr int kInnerSweeps = 1;   // one cyclic sweep per pair and round (block-
                                   // converges with 1-2 more outer sweeps, each far cheaper)
 
 // symmetric 2x2 Schur rotation: [c s; -s c]^T [app apq; apq aqq] [c s; -s c] is diagonal
-__device__ __forceinline__ void sym_schur2(double app, double aqq, double apq, double& c, double& s) {
+// (t = s / c is returned too; c comes from one reciprocal square root)
+__device__ __forceinline__ void sym_schur2(double app, double aqq, double apq, double& c, double& s, double& t) {
     const double theta = (aqq - app) / (2.0 * apq);
-    const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-    c = 1.0 / sqrt(1.0 + t * t);
+    t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+    c = rsqrt(1.0 + t * t);
     s = t * c;
 }
 
@@ -113,8 +114,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
                 const double app = S[a][a], aqq = S[b][b], apq = S[a][b];
                 double c = 1.0, s = 0.0, t = 0.0;
                 if (!(LO[a] && LO[b]) && fabs(apq) > fmax(kRelTol * sqrt(fabs(app * aqq)), floor_abs)) {
-                    sym_schur2(app, aqq, apq, c, s);
-                    t = s / c;
+                    sym_schur2(app, aqq, apq, c, s, t);
                 }
                 csc[tid] = c;
                 css[tid] = s;
@@ -123,7 +123,8 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
                 cse[tid] = aqq + t * apq;
             }
             __syncthreads();
-            for (int idx = tid; idx < NP * NP; idx += NT) {
+            // the sub-matrix: (P2, Q2) blocks of the round's 2 x 2 index pairs
+            auto s_item = [&](int idx) {
                 const int P2 = idx / NP, Q2 = idx % NP;
                 int aP, bP, aQ, bQ;
                 rr_pair(PB, r, P2, aP, bP);
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
                         S[aP][bP] = 0.0;
                         S[bP][aP] = 0.0;
                     }
-                    continue;
+                    return;
                 }
                 rr_pair(PB, r, Q2, aQ, bQ);
                 const double cP = csc[P2], sP = css[P2], cQ = csc[Q2], sQ = css[Q2];
@@ -149,8 +150,9 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
                 S[aP][bQ] = cP * t_ab - sP * t_bb;
                 S[bP][aQ] = sP * t_aa + cP * t_ba;
                 S[bP][bQ] = sP * t_ab + cP * t_bb;
-            }
-            for (int idx = tid; idx < PB * NP; idx += NT) {
+            };
+            // the accumulated rotation: row i, columns of pair Q2
+            auto r_item = [&](int idx) {
                 const int i = idx / NP, Q2 = idx % NP;
                 int aQ, bQ;
                 rr_pair(PB, r, Q2, aQ, bQ);
@@ -158,6 +160,17 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
                 const double ra = R[i][aQ], rb = R[i][bQ];
                 R[i][aQ] = cQ * ra - sQ * rb;
                 R[i][bQ] = sQ * ra + cQ * rb;
+            };
+            if constexpr (NT >= 2 * NP * NP) {
+                // the two updates touch disjoint arrays: the first NP^2 threads (whole
+                // waves) update S while the others rotate R, instead of every wave
+                // doing both in turn
+                if (tid < NP * NP) s_item(tid);
+                else
+                    for (int idx = tid - NP * NP; idx < PB * NP; idx += NT - NP * NP) r_item(idx);
+            } else {
+                for (int idx = tid; idx < NP * NP; idx += NT) s_item(idx);
+                for (int idx = tid; idx < PB * NP; idx += NT) r_item(idx);
             }
             __syncthreads();
         }
