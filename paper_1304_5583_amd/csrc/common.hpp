@@ -59,6 +59,16 @@ struct BlockState {
 };
 
 // Eigensolver descriptor of one symmetric matrix (padded size L, ld = L).
+// Operation counters of the Jacobi kernels: one atomic per workgroup, spread
+// over kWorkSlots counters 128 bytes apart per kind (0: pair solves, 1: tile
+// updates), so that workgroups on different XCDs do not queue on one address.
+constexpr int kWorkSlots = 64;
+constexpr int kWorkStride = 16;   // unsigned long longs between counters
+constexpr size_t kWorkBytes = 2 * kWorkSlots * kWorkStride * sizeof(unsigned long long);
+__host__ __device__ __forceinline__ size_t work_slot(int kind, int wg) {
+    return (size_t)(kind * kWorkSlots + wg % kWorkSlots) * kWorkStride;
+}
+
 struct EigDesc {
     double* B;          // L x L symmetric, diagonalised in place
     double* W;          // L x L, accumulates the rotations (eigenvectors)
@@ -71,7 +81,8 @@ struct EigDesc {
     double* scale;      // max |diag| of B at the start, for the absolute floor
     int* prot;          // per pair of the current round: 1 if it rotated
     int* lo;            // per index: Gershgorin disc below the cut (pairs of two such are skipped)
-    unsigned long long* work;  // [0] FP64 operations of the pair solves, [1] of the tile updates
+    unsigned long long* work;  // FP64 operation counters (may be null): pair solves, then tile
+                               // updates, each spread over kWorkSlots counters (work_slot)
     const double* cut;  // cut factor nu of the block: lo when the disc lies below min(tau^2, nu * scale)
     int* passes;        // sweep-loop passes of the current eigensolve (counted while open)
     int* need;          // (L/bs)^2 flags (may be null): the check marks index-block pairs (p <= q,

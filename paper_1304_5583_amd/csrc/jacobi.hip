@@ -182,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
     if (tid == 0 && d.work) {
         // per round: NP angles (~30 operations), (NP^2 - NP) 2x2 updates (24), PB*NP rotations of R (6)
         const unsigned long long per_round = 30ull * NP + 24ull * (NP * NP - NP) + 6ull * PB * NP;
-        atomicAdd(&d.work[0], per_round * (PB - 1));
+        atomicAdd(&d.work[work_slot(0, blockIdx.x + blockIdx.y * gridDim.x)], per_round * (PB - 1));
     }
     double* Rg = d.R + (long)P * PB * PB;
     for (int idx = tid; idx < PB * PB; idx += NT) {
@@ -244,7 +244,8 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
         while (rem >= npair - P) { rem -= npair - P; ++P; }
         const int Q = P + rem;
         if (!d.prot[P] && !d.prot[Q]) return;
-        if (tid == 0 && d.work) atomicAdd(&d.work[1], 4ull * PB * PB * PB);   // two PB^3 products
+        if (tid == 0 && d.work)   // two PB^3 products
+            atomicAdd(&d.work[work_slot(1, blockIdx.x + blockIdx.y * gridDim.x)], 4ull * PB * PB * PB);
         int p1, q1, p2, q2;
         round_pair(d, nb, round, P, sched, p1, q1);
         round_pair(d, nb, round, Q, sched, p2, q2);
@@ -268,15 +269,23 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
             const int i = idx % PB, j = idx / PB;
             const long gi = (i < BS) ? (long)p1 * BS + i : (long)q1 * BS + (i - BS);
             const long gj = (j < BS) ? (long)p2 * BS + j : (long)q2 * BS + (j - BS);
-            const double v = X[i][j];
-            d.B[gi + gj * L] = v;
-            if (P != Q) d.B[gj + gi * L] = v;
+            d.B[gi + gj * L] = X[i][j];
+        }
+        if (P != Q) {
+            // the mirrored tile, with consecutive threads on consecutive rows of it
+            for (int idx = tid; idx < PB * PB; idx += 256) {
+                const int j = idx % PB, i = idx / PB;
+                const long gi = (i < BS) ? (long)p1 * BS + i : (long)q1 * BS + (i - BS);
+                const long gj = (j < BS) ? (long)p2 * BS + j : (long)q2 * BS + (j - BS);
+                d.B[gj + gi * L] = X[i][j];
+            }
         }
     } else {
         const int w = item - ntri;
         const int P = w % npair, chunk = w / npair;
         if (!d.prot[P]) return;
-        if (tid == 0 && d.work) atomicAdd(&d.work[1], 2ull * RC * PB * PB);   // RC x PB times PB x PB
+        if (tid == 0 && d.work)   // RC x PB times PB x PB
+            atomicAdd(&d.work[work_slot(1, blockIdx.x + blockIdx.y * gridDim.x)], 2ull * RC * PB * PB);
         int p1, q1;
         round_pair(d, nb, round, P, sched, p1, q1);
         const double* RgP = d.R + (long)P * PB * PB;

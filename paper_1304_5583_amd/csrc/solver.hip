@@ -704,8 +704,8 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     const lrr_opts& o = pr.o;
     const size_t need = layout(p, nullptr, b, with_combine, true);
     ensure_ws(ctx, need);
-    if (!ctx->dwork) LRR_HIP(hipMalloc((void**)&ctx->dwork, 256));
-    LRR_HIP(hipMemsetAsync(ctx->dwork, 0, 2 * sizeof(unsigned long long), s));
+    if (!ctx->dwork) LRR_HIP(hipMalloc((void**)&ctx->dwork, lrr::kWorkBytes));
+    LRR_HIP(hipMemsetAsync(ctx->dwork, 0, lrr::kWorkBytes, s));
     layout(p, static_cast<char*>(ctx->ws), b, with_combine, true);
     ensure_pinned(ctx, sizeof(int) * (4 * (size_t)t + 16) + sizeof(double) * 2 * t);
     if (p.reduced) build_basis(pr, p, b, s);
@@ -1160,9 +1160,12 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     }
     if (prof.on) {
         // operations counted on the device by the Jacobi kernels over this solve
-        unsigned long long hw[2] = {0, 0};
-        LRR_HIP(hipMemcpyAsync(hw, ctx->dwork, sizeof(hw), hipMemcpyDeviceToHost, s));
+        std::vector<unsigned long long> slots(lrr::kWorkBytes / sizeof(unsigned long long));
+        LRR_HIP(hipMemcpyAsync(slots.data(), ctx->dwork, lrr::kWorkBytes, hipMemcpyDeviceToHost, s));
         sync();
+        unsigned long long hw[2] = {0, 0};
+        for (int kind = 0; kind < 2; ++kind)
+            for (int w = 0; w < lrr::kWorkSlots; ++w) hw[kind] += slots[lrr::work_slot(kind, w)];
         const std::string sfx = p.bs == 16 ? "<16" : "<32";
         for (auto& e : prof.entries) {
             if (e.name.rfind("k_jacobi_pairs" + sfx, 0) == 0) e.flops += (double)hw[0];
