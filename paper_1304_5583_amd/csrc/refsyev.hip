@@ -159,9 +159,10 @@ __global__ void k_ref_update(const RefDesc* __restrict__ descs, int count, int s
     const double e = __longlong_as_double((long long)d.emax[0]);
     const double limit = (step == 0) ? kFirstStepCap : d.eprev[0];
     const bool apply = (e <= limit);
-    // after a correction below 1e-12 the next one (quadratic in it) is at the
-    // rounding level, and so are the couplings it leaves: stop there
-    const bool cont = apply && e >= 1e-12 && step + 1 < max_steps;
+    // after a correction below 1e-10 the next one (quadratic in it) would be at
+    // the rounding level; what such a step would remove is left to the Jacobi
+    // check, whose tolerance decides convergence
+    const bool cont = apply && e >= 1e-10 && step + 1 < max_steps;
     d.eprev[0] = e;
     d.emax[0] = 0ull;
     d.unres[0] = 0;
