@@ -26,33 +26,41 @@ namespace lrr {
 
 namespace {
 
-constexpr int BN = 64, BK = 16, PAD = 2;
-constexpr int NLB = (BN * BK) / 256;   // elements of the op(B) tile per thread
+constexpr int BN = 64, PAD = 2;
+
+// K depth of a tile: 16 for both heights (LDS for four 64-row workgroups per
+// CU; 32-deep tiles with 32-row tiles, whose grids hold two workgroups per CU,
+// measured no faster: 507 vs 502 ms per workload-2 solve)
+template <int BM>
+constexpr int kDepth = 16;
 
 // One K-tile of op(A) (BM x BK) and op(B) (BK x BN) in registers.
 template <int BM>
 struct Frag {
+    static constexpr int BK = kDepth<BM>;
     static constexpr int NLA = (BM * BK) / 256;   // elements of the op(A) tile per thread
+    static constexpr int NLB = (BN * BK) / 256;   // elements of the op(B) tile per thread
     double a[NLA];
     double b[NLB];
 };
 
 // Thread -> element map of the operand tiles.  Every thread holds a run of NLA
 // (op(A)) or NLB (op(B)) elements that are contiguous in memory:
-//   op(A) = A   : run along the BM rows of one k      (row (tid % 16) * NLA, k = tid / 16)
-//   op(A) = A^T : run along k of one row              (row tid / TPR, k = (tid % TPR) * NLA)
-//   op(B) = B   : run along k of one column           (column tid / 4, k = (tid % 4) * 4)
-//   op(B) = B^T : run along the BN columns of one k   (column (tid % 16) * 4, k = tid / 16)
+//   op(A) = A   : run along the BM rows of one k   (row (tid % (BM/NLA)) * NLA, k = tid / (BM/NLA))
+//   op(A) = A^T : run along k of one row           (row tid / (BK/NLA), k = (tid % (BK/NLA)) * NLA)
+//   op(B) = B   : run along k of one column        (column tid / (BK/NLB), k = (tid % (BK/NLB)) * NLB)
+//   op(B) = B^T : run along the BN columns of one k (column (tid % (BN/NLB)) * NLB, k = tid / (BN/NLB))
 template <int BM, bool TA>
 __device__ __forceinline__ void a_slot(int tid, int& i, int& kk) {
-    constexpr int NLA = Frag<BM>::NLA, TPR = BK / NLA;
-    if (!TA) { i = (tid & 15) * NLA; kk = tid >> 4; }
-    else     { i = tid / TPR; kk = (tid % TPR) * NLA; }
+    constexpr int NLA = Frag<BM>::NLA, BK = Frag<BM>::BK;
+    if (!TA) { i = (tid % (BM / NLA)) * NLA; kk = tid / (BM / NLA); }
+    else     { i = tid / (BK / NLA); kk = (tid % (BK / NLA)) * NLA; }
 }
-template <bool TB>
+template <int BM, bool TB>
 __device__ __forceinline__ void b_slot(int tid, int& j, int& kk) {
-    if (!TB) { j = tid >> 2; kk = (tid & 3) * 4; }
-    else     { j = (tid & 15) * 4; kk = tid >> 4; }
+    constexpr int NLB = Frag<BM>::NLB, BK = Frag<BM>::BK;
+    if (!TB) { j = tid / (BK / NLB); kk = (tid % (BK / NLB)) * NLB; }
+    else     { j = (tid % (BN / NLB)) * NLB; kk = tid / (BN / NLB); }
 }
 
 // bounds-tested loads (zero outside the matrices)
@@ -60,10 +68,10 @@ template <int BM, bool TA, bool TB>
 __device__ __forceinline__ void load_tile(Frag<BM>& f, const double* __restrict__ A, long lda,
                                           const double* __restrict__ B, long ldb, int M, int N, int K,
                                           int m0, int n0, int k0, int tid) {
-    constexpr int NLA = Frag<BM>::NLA;
+    constexpr int NLA = Frag<BM>::NLA, NLB = Frag<BM>::NLB;
     int i, ka, j, kb;
     a_slot<BM, TA>(tid, i, ka);
-    b_slot<TB>(tid, j, kb);
+    b_slot<BM, TB>(tid, j, kb);
 #pragma unroll
     for (int v = 0; v < NLA; ++v) {
         const int gi = m0 + i + (TA ? 0 : v), gk = k0 + ka + (TA ? v : 0);
@@ -81,10 +89,10 @@ template <int BM, bool TA, bool TB>
 __device__ __forceinline__ void load_tile_vec(Frag<BM>& f, const double* __restrict__ A, long lda,
                                               const double* __restrict__ B, long ldb, int m0, int n0, int k0,
                                               int tid) {
-    constexpr int NLA = Frag<BM>::NLA;
+    constexpr int NLA = Frag<BM>::NLA, NLB = Frag<BM>::NLB;
     int i, ka, j, kb;
     a_slot<BM, TA>(tid, i, ka);
-    b_slot<TB>(tid, j, kb);
+    b_slot<BM, TB>(tid, j, kb);
     const double* pa = TA ? A + (k0 + ka) + (long)(m0 + i) * lda : A + (m0 + i) + (long)(k0 + ka) * lda;
     const double* pb = TB ? B + (n0 + j) + (long)(k0 + kb) * ldb : B + (k0 + kb) + (long)(n0 + j) * ldb;
 #pragma unroll
@@ -104,10 +112,10 @@ __device__ __forceinline__ void load_tile_vec(Frag<BM>& f, const double* __restr
 template <int BM, bool TA, bool TB>
 __device__ __forceinline__ void store_tile(const Frag<BM>& f, double (*As)[BM + PAD], double (*Bs)[BN + PAD],
                                            int tid) {
-    constexpr int NLA = Frag<BM>::NLA;
+    constexpr int NLA = Frag<BM>::NLA, NLB = Frag<BM>::NLB;
     int i, ka, j, kb;
     a_slot<BM, TA>(tid, i, ka);
-    b_slot<TB>(tid, j, kb);
+    b_slot<BM, TB>(tid, j, kb);
 #pragma unroll
     for (int v = 0; v < NLA; ++v) {
         if (!TA) As[ka][i + v] = f.a[v];
@@ -124,7 +132,7 @@ __device__ __forceinline__ void store_tile(const Frag<BM>& f, double (*As)[BM + 
 // small to give every CU two workgroups): each wave owns 16 x 32 (1 x 2 tiles).
 template <int BM, bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_dgemm(const GemmDesc* __restrict__ descs) {
-    constexpr int WM = BM / 2, TX = WM / 16;
+    constexpr int WM = BM / 2, TX = WM / 16, BK = Frag<BM>::BK;
     const GemmDesc d = descs[blockIdx.z];
     if (d.active && d.active[0] == 0) return;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;

@@ -17,16 +17,29 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("M,N,K", [(64, 64, 16), (77, 131, 45), (1, 5, 3), (200, 9, 300),
                                    (2111, 2061, 37), (1030, 4100, 21)])
 def test_dgemm_matches_float64(ta, tb, M, N, K):
+    _check_dgemm(ta, tb, M, N, K, (3, 1, 2))
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("M,N,K", [(128, 96, 100), (96, 128, 64), (512, 512, 500)])
+def test_dgemm_vector_loads(ta, tb, M, N, K):
+    """Even leading dimensions: interior tiles take the 16-byte loads (32-row
+    tiles on these small grids), the edges and a ragged last K tile the
+    bounds-tested loads."""
+    _check_dgemm(ta, tb, M, N, K, (4, 2, 2))
+
+
+def _check_dgemm(ta, tb, M, N, K, pads):
     torch = need_gpu()
     from paper_1304_5583_amd import binding as B
-    say(f"dgemm ta={ta} tb={tb} M={M} N={N} K={K}")
+    say(f"dgemm ta={ta} tb={tb} M={M} N={N} K={K} pads={pads}")
     rng = np.random.default_rng(M * 1000 + N + K)
     opA = rng.standard_normal((M, K))
     opB = rng.standard_normal((K, N))
     C0 = rng.standard_normal((M, N))
     A = opA.T if ta else opA          # stored matrix (column-major)
     Bm = opB.T if tb else opB
-    lda, ldb, ldc = A.shape[0] + 3, Bm.shape[0] + 1, M + 2
+    lda, ldb, ldc = A.shape[0] + pads[0], Bm.shape[0] + pads[1], M + pads[2]
     def dev(X, ld):
         P = np.zeros((ld, X.shape[1]))
         P[:X.shape[0]] = X
