@@ -50,6 +50,20 @@ lrr_status lrr_diag_syevj(lrr_ctx *ctx, int count, const int *l, const double *B
                           long strideB, double *lam, int ldlam, double *W, int eig_block,
                           int *sweeps, void *stream);
 
+/* Round schedule of a targeted Jacobi pass (host only, no device work).  After
+ * each check of the off-diagonal entries, the solver marks the pairs of
+ * index blocks (bs indices each) that still hold an entry above the tolerance
+ * and, when few are marked, runs only rounds that cover them instead of a full
+ * sweep of nb - 1 circle rounds.  need (HOST, nb x nb ints; entry p * nb + q is
+ * read for p <= q, p == q meaning inside block p) holds the marks; nb is even,
+ * 2 <= nb <= 65534.  Greedy matchings of the marked pairs, each completed to a
+ * perfect matching of the nb blocks, are written to out (HOST, cap * nb / 2
+ * ints, round r at out + r * nb / 2, pair p | q << 16 with p < q).  *rounds
+ * receives their number, or -1 if more than cap rounds would be needed (out
+ * then holds cap partial rounds).  LRR_EINVAL on a NULL pointer, an odd or
+ * out-of-range nb, or cap < 0. */
+lrr_status lrr_diag_plan_rounds(const int *need, int nb, int cap, int *out, int *rounds);
+
 /* Per-kernel timing of the solver's own launches.  When enabled, every kernel
  * launch of lrr_solve / dfc_lrr_solve is bracketed by HIP events recorded on the
  * solve's stream; durations are accumulated per kernel name together with the

@@ -111,6 +111,8 @@ def load_library(path: str = LIB_PATH):
     lib.lrr_diag_spd_inverse.restype = i
     lib.lrr_diag_syevj.argtypes = [vp, i, ip, vp, i, C.c_long, vp, i, vp, i, ip, vp]
     lib.lrr_diag_syevj.restype = i
+    lib.lrr_diag_plan_rounds.argtypes = [ip, i, i, ip, ip]
+    lib.lrr_diag_plan_rounds.restype = i
     lib.dfc_lrr_solve_local.argtypes = [vp, i, i, vp, i, d, i, ip, ip, i, C.POINTER(lrr_opts), vp, i, vp, i,
                                         C.POINTER(lrr_info), vp]
     lib.dfc_lrr_solve_local.restype = i
@@ -358,6 +360,21 @@ def lrr_diag_spd_inverse(At, ctx: Context | None = None):
                                              C.c_void_p(K.data_ptr()), m, _stream(torch, At.device))
     _check(st, ctx, allow_nc=False)
     return K
+
+
+def lrr_diag_plan_rounds(need, cap: int):
+    """Round schedule of a targeted Jacobi pass for the nb x nb marks `need`
+    (host only).  Returns (rounds, pairs) with pairs an int array (cap, nb/2, 2)
+    of which the first `rounds` rows are used; rounds = -1 if cap is too small."""
+    need = np.ascontiguousarray(need, dtype=np.int32)
+    nb = need.shape[0]
+    out = np.zeros(max(cap, 1) * max(nb // 2, 1), dtype=np.int32)
+    r = np.zeros(1, dtype=np.int32)
+    st = load_library().lrr_diag_plan_rounds(_ip(need), nb, cap, _ip(out), _ip(r))
+    if st != LRR_OK:
+        raise LRRError(st, "lrr_diag_plan_rounds: invalid arguments")
+    v = out[:cap * (nb // 2)].reshape(cap, nb // 2)
+    return int(r[0]), np.stack([v & 0xffff, v >> 16], axis=-1)
 
 
 def lrr_diag_syevj(Bs, ls, eig_block: int = 16, ctx: Context | None = None):

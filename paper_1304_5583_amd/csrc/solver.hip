@@ -1941,4 +1941,10 @@ lrr_status dfc_lrr_backward(lrr_ctx* ctx, const void* dZ, int lddz, double* dlam
     });
 }
 
+lrr_status lrr_diag_plan_rounds(const int* need, int nb, int cap, int* out, int* rounds) {
+    if (!need || !out || !rounds || nb < 2 || nb > 65534 || (nb & 1) || cap < 0) return LRR_EINVAL;
+    *rounds = plan_rounds(need, nb, cap, out);
+    return LRR_OK;
+}
+
 }  // extern "C"
