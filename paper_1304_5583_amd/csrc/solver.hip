@@ -878,7 +878,17 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     // n: rows of the iterates (the numerical rank of M in reduced coordinates)
     const int m = p.m, n = p.nr, nfull = p.n, c = p.ncols, t = p.t;
     const lrr_opts& o = pr.o;
-    int* hp = static_cast<int*>(ctx->pinned);
+    // targeted Jacobi rounds: per-block offsets of the check marks and schedules
+    std::vector<size_t> need_off(t + 1, 0), sched_off(t + 1, 0);
+    for (int bb = 0; bb < t; ++bb) {
+        const size_t nbb = p.L[bb] / p.bs;
+        need_off[bb + 1] = need_off[bb] + nbb * nbb;
+        sched_off[bb + 1] = sched_off[bb] + (nbb - 1) * (nbb / 2);
+    }
+    // pinned host area: the flags, then the check marks (read back every pass)
+    const size_t flag_bytes = (sizeof(int) * (4 * (size_t)t + 16) + sizeof(double) * 2 * t + 255) & ~size_t(255);
+    int* hp = static_cast<int*>(ensure_pinned(ctx, flag_bytes + sizeof(int) * need_off[t]));
+    int* h_need = reinterpret_cast<int*>(reinterpret_cast<char*>(hp) + flag_bytes);
     BlockState bst{b.active, b.svt_run, b.iters, b.rank, b.res1, b.res2, b.r1max, b.r2max};
     const ProductModes& pm = p.pm;
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
@@ -898,14 +908,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     };
     std::vector<int> h_act(t, 1);
     long long sweeps_total = 0;
-    // targeted Jacobi rounds: per-block offsets of the check marks and schedules
-    std::vector<size_t> need_off(t + 1, 0), sched_off(t + 1, 0);
-    for (int bb = 0; bb < t; ++bb) {
-        const size_t nbb = p.L[bb] / p.bs;
-        need_off[bb + 1] = need_off[bb] + nbb * nbb;
-        sched_off[bb + 1] = sched_off[bb] + (nbb - 1) * (nbb / 2);
-    }
-    std::vector<int> h_need(need_off[t]), h_sched(sched_off[t]), block_rounds(t, 0);
+    std::vector<int> h_sched(sched_off[t]), block_rounds(t, 0);
     const double D = sizeof(double);
     // one iteration's Z-step and E-step launches on stream st
     auto zstep = [&](hipStream_t st, bool anchor, auto&& tm, double cact) {
@@ -1073,12 +1076,12 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 // converged matrices are closed here; the loop ends when none is open
                 timed("k_lo_rows", 0.0, 0.0, [&] { lrr::launch_lo_rows(b.eig, t, p.maxL, b.it, s, counted); });
                 LRR_HIP(hipMemsetAsync(b.eig_any, 0, sizeof(int), s));
-                LRR_HIP(hipMemsetAsync(b.need_all, 0, sizeof(int) * h_need.size(), s));
+                LRR_HIP(hipMemsetAsync(b.need_all, 0, sizeof(int) * need_off[t], s));
                 timed("k_jacobi_offcheck", 0.0, 0.0, [&] {
                     lrr::launch_jacobi_check(b.eig, t, p.maxL, b.eig_any, s, p.bs);
                 });
                 LRR_HIP(hipMemcpyAsync(h_misc, b.eig_any, sizeof(int), hipMemcpyDeviceToHost, s));
-                LRR_HIP(hipMemcpyAsync(h_need.data(), b.need_all, sizeof(int) * h_need.size(),
+                LRR_HIP(hipMemcpyAsync(h_need, b.need_all, sizeof(int) * need_off[t],
                                        hipMemcpyDeviceToHost, s));
                 sync();
                 if (h_misc[0] == 0 || full == max_sweeps) break;
@@ -1087,7 +1090,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 for (int bb = 0; bb < t && rounds >= 0; ++bb) {
                     const int nbb = p.L[bb] / p.bs;
                     // the block's schedule holds nbb - 1 rounds
-                    const int rb = plan_rounds(h_need.data() + need_off[bb], nbb, std::min((nb - 1) / 2, nbb - 1),
+                    const int rb = plan_rounds(h_need + need_off[bb], nbb, std::min((nb - 1) / 2, nbb - 1),
                                                h_sched.data() + sched_off[bb]);
                     rounds = rb < 0 ? -1 : std::max(rounds, rb);
                     block_rounds[bb] = rb;
