@@ -885,10 +885,14 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         need_off[bb + 1] = need_off[bb] + nbb * nbb;
         sched_off[bb + 1] = sched_off[bb] + (nbb - 1) * (nbb / 2);
     }
-    // pinned host area: the flags, then the check marks (read back every pass)
+    // pinned host area: the flags, the check marks (read back every pass) and the
+    // round schedules (uploaded by targeted passes; rewritten only after the next
+    // pass's synchronisation, when the previous upload has completed)
     const size_t flag_bytes = (sizeof(int) * (4 * (size_t)t + 16) + sizeof(double) * 2 * t + 255) & ~size_t(255);
-    int* hp = static_cast<int*>(ensure_pinned(ctx, flag_bytes + sizeof(int) * need_off[t]));
+    const size_t need_bytes = (sizeof(int) * need_off[t] + 255) & ~size_t(255);
+    int* hp = static_cast<int*>(ensure_pinned(ctx, flag_bytes + need_bytes + sizeof(int) * sched_off[t]));
     int* h_need = reinterpret_cast<int*>(reinterpret_cast<char*>(hp) + flag_bytes);
+    int* h_sched = reinterpret_cast<int*>(reinterpret_cast<char*>(hp) + flag_bytes + need_bytes);
     BlockState bst{b.active, b.svt_run, b.iters, b.rank, b.res1, b.res2, b.r1max, b.r2max};
     const ProductModes& pm = p.pm;
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
@@ -896,6 +900,8 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
     int* h_run = hp;            // t ints
     int* h_misc = hp + t;       // scalars
+    int* h_ref = hp + t + 16;   // t ints: refinement still running, per block
+    int* h_act = hp + 2 * t + 16;   // t ints: block still iterating
 
     Result res;
     LrrProf& prof = ctx->prof;
@@ -906,9 +912,9 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         LRR_HIP(hipStreamSynchronize(s));
         if (prof.on) prof.flush();
     };
-    std::vector<int> h_act(t, 1);
+    std::fill(h_act, h_act + t, 1);
     long long sweeps_total = 0;
-    std::vector<int> h_sched(sched_off[t]), block_rounds(t, 0);
+    std::vector<int> block_rounds(t, 0);
     const double D = sizeof(double);
     // one iteration's Z-step and E-step launches on stream st
     auto zstep = [&](hipStream_t st, bool anchor, auto&& tm, double cact) {
@@ -1009,8 +1015,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             });
             // Newton refinement of the previous iteration's eigenvectors
             timed("k_ref_begin", 0.0, 0.0, [&] { lrr::launch_ref_begin(b.ref, t, p.maxL, b.svt_run, b.warm, s); });
-            std::vector<int> h_ref(t, 0);
-            LRR_HIP(hipMemcpyAsync(h_ref.data(), b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+            LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
             sync();
             for (int step = 0; step < kRefSteps; ++step) {
                 double fl = 0.0;
@@ -1036,7 +1041,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 });
                 timed("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, s); });
                 timed("k_ref_next", 0.0, 0.0, [&] { lrr::launch_ref_next(b.ref, t, s); });
-                LRR_HIP(hipMemcpyAsync(h_ref.data(), b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+                LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
                 sync();
             }
             // two Newton-Schulz steps X <- X (I + (I - X^T X)/2); an estimate that is
@@ -1091,7 +1096,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                     const int nbb = p.L[bb] / p.bs;
                     // the block's schedule holds nbb - 1 rounds
                     const int rb = plan_rounds(h_need + need_off[bb], nbb, std::min((nb - 1) / 2, nbb - 1),
-                                               h_sched.data() + sched_off[bb]);
+                                               h_sched + sched_off[bb]);
                     rounds = rb < 0 ? -1 : std::max(rounds, rb);
                     block_rounds[bb] = rb;
                 }
@@ -1106,7 +1111,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                                 h_sched[sched_off[bb] + (size_t)r * (nbb / 2) + P] = a0 | (b0 << 16);
                             }
                     }
-                    LRR_HIP(hipMemcpyAsync(b.sched_all, h_sched.data(), sizeof(int) * h_sched.size(),
+                    LRR_HIP(hipMemcpyAsync(b.sched_all, h_sched, sizeof(int) * sched_off[t],
                                            hipMemcpyHostToDevice, s));
                     ++targeted;
                     counted = false;
@@ -1156,7 +1161,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         if (hooks && hooks->end) hooks->end(k);
         if (!fixed && ((k + 1) % check_every == 0 || k + 1 == p.n_iter)) {
             LRR_HIP(hipMemcpyAsync(h_misc + 1, b.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-            LRR_HIP(hipMemcpyAsync(h_act.data(), b.active, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+            LRR_HIP(hipMemcpyAsync(h_act, b.active, sizeof(int) * t, hipMemcpyDeviceToHost, s));
             sync();
             if (h_misc[1] == 0) { ++k; break; }
         }
