@@ -5,12 +5,12 @@ this package.  It shares no code with the HIP library.
 """
 from .lrr import (ALMOptions, DFCResult, LRRResult, column_projection, dfc_lrr, dfc_lrr_local, dual_gap,
                   l21_shrink, lrr_alm, objective, svt, trivial_lambda)
-from .segment import segment, segmentation_accuracy, oracle_constraints
+from .segment import segment, segmentation_accuracy, oracle_constraints, outlier_flags
 from . import adjoint
 from . import slr
 
 __all__ = [
     "ALMOptions", "DFCResult", "LRRResult", "column_projection", "dfc_lrr", "dfc_lrr_local", "dual_gap",
     "l21_shrink", "lrr_alm", "objective", "svt", "trivial_lambda", "segment",
-    "segmentation_accuracy", "oracle_constraints", "adjoint", "slr",
+    "segmentation_accuracy", "oracle_constraints", "outlier_flags", "adjoint", "slr",
 ]

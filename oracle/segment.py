@@ -18,6 +18,11 @@ TEST INFRASTRUCTURE ONLY (see the oracle package docstring).
   its members; the score is the mean over classes of the fraction of that class
   labelled correctly (Section 4.1.2).  Columns labelled -1 (either side) are
   skipped.
+* ``outlier_flags``: the columns the method itself marks as outliers, from the
+  column-sparse outlier estimate S of Eq. (1)/(2): column j is flagged when
+  ||S[:, j]||_2 > delta ||M[:, j]||_2 (reading: the paper identifies outlier
+  columns through the column support of S, Section 4.1.1, with a threshold it
+  does not state; delta = 0.1 is used by default).
 * ``oracle_constraints``: the success test of Section 4.1.1 -- the oracle
   constraints of the appendix (column space of Z inside the row space of the
   clean data, outlier estimate supported on the outlier columns) within a
@@ -28,7 +33,9 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-__all__ = ["segment", "segmentation_accuracy", "oracle_constraints", "kmeans"]
+__all__ = ["segment", "segmentation_accuracy", "oracle_constraints", "kmeans", "outlier_flags"]
+
+OUTLIER_DELTA = 0.1
 
 
 def kmeans(Y: np.ndarray, k: int, max_iter: int = 300):
@@ -106,6 +113,14 @@ def segmentation_accuracy(pred: np.ndarray, truth: np.ndarray) -> float:
     mapped = np.array([assign[int(c)] for c in pred])
     recalls = [float(np.mean(mapped[truth == g] == g)) for g in np.unique(truth)]
     return float(np.mean(recalls))
+
+
+def outlier_flags(S: np.ndarray, M: np.ndarray, delta: float = OUTLIER_DELTA) -> np.ndarray:
+    """Boolean mask of the columns whose outlier estimate carries more than
+    delta of the column's norm: ||S[:, j]||_2 > delta ||M[:, j]||_2."""
+    s = np.sqrt(np.sum(np.asarray(S, dtype=np.float64) ** 2, axis=0))
+    m = np.sqrt(np.sum(np.asarray(M, dtype=np.float64) ** 2, axis=0))
+    return s > delta * m
 
 
 def oracle_constraints(Z: np.ndarray, E: np.ndarray, L0: np.ndarray, outlier_cols: np.ndarray,

@@ -64,7 +64,8 @@ def block_fingerprint(cfg: int, block: int):
 def gradient_fingerprint(cfg: int):
     """Unrolled DFC-LRR (fixed iteration count) and the oracle's reverse sweep for
     L = ||W o |Z| ||_F^2: dL/dlambda, ||dL/dM||_F, dL/dM at 512 seeded positions
-    and <dL/dM, D> for two seeded directions D."""
+    and <dL/dM, D> for six seeded directions D with i.i.d. standard normal
+    entries (the first two as drawn before, four more after them)."""
     from oracle import adjoint as adj
     p = make_config(cfg)
     W = p.extra["W"]
@@ -78,13 +79,15 @@ def gradient_fingerprint(cfg: int):
     rng = np.random.default_rng(4244)
     idx = np.stack([rng.integers(0, p.m, 512), rng.integers(0, p.n, 512)], axis=1)
     D = rng.standard_normal((2, p.m, p.n))
+    D_more = rng.standard_normal((4, p.m, p.n))
     Wp, _ = probes(p.n)
     out = {
         "workload": p.name, "config": cfg, "m": p.m, "n": p.n, "t": p.t, "lam": p.lam,
         "fixed_iters": opts.fixed_iters, "oracle_seconds": el, "loss": L, "dlam": lambar,
         "dM_fro": float(np.linalg.norm(Mbar)), "probe_idx": idx.tolist(),
         "dM_at": [float(Mbar[i, j]) for i, j in idx],
-        "dM_dir": [float(np.sum(Mbar * D[i])) for i in range(2)],
+        "dM_dir": [float(np.sum(Mbar * D[i])) for i in range(2)] +
+                  [float(np.sum(Mbar * D_more[i])) for i in range(4)],
         "Zw": (Z @ Wp).T.tolist(), "Z_fro": float(np.linalg.norm(Z)),
     }
     path = os.path.join(HERE, f"workload{cfg}_gradient_oracle.json")
@@ -135,7 +138,7 @@ def main(cfgs):
         el = time.time() - t0
         W, idx = probes(p.n)
         k = p.extra["k"]
-        labels = oracle.segment(d.Z, k, p.outliers)
+        labels = oracle.segment(d.Z, k)
         out = {
             "workload": p.name, "config": cfg, "m": p.m, "n": p.n, "t": p.t, "lam": p.lam,
             "oracle_seconds": el,
@@ -144,10 +147,13 @@ def main(cfgs):
             "Zw": (d.Z @ W).T.tolist(), "probe_idx": idx.tolist(),
             "Z_at": [float(d.Z[i, j]) for i, j in idx],
             "Z_fro": float(np.linalg.norm(d.Z)), "S_fro": float(np.linalg.norm(d.S)),
+            # Section 4.1.2 clusters every point (no outlier removal)
             "labels": labels.tolist(),
             # segmentation with the rank cut above the reduced forms' error level
-            "labels_rank_tol_1e-3": oracle.segment(d.Z, k, p.outliers, rank_tol=1e-3).tolist(),
-            "accuracy": oracle.segmentation_accuracy(labels, p.labels),
+            "labels_rank_tol_1e-3": oracle.segment(d.Z, k, rank_tol=1e-3).tolist(),
+            "accuracy": oracle.segmentation_accuracy(labels, np.where(p.outliers, -1, p.labels)),
+            # ||S[:, j]|| / ||M[:, j]||, the quantity the outlier flags threshold
+            "S_ratio": (np.linalg.norm(d.S, axis=0) / np.linalg.norm(p.M, axis=0)).tolist(),
         }
         path = os.path.join(HERE, f"workload{cfg}_oracle.json")
         with open(path, "w") as f:

@@ -113,3 +113,46 @@ def test_unrolled_forward_is_the_fixed_count_alm():
     assert np.allclose(tp.states[-1][0], r.Z, rtol=0, atol=1e-12)
     assert np.allclose(tp.J, r.J, rtol=0, atol=1e-12)
     assert np.allclose(tp.states[-1][1], r.E, rtol=0, atol=1e-12)
+
+
+def test_directional_check_catches_a_planted_gradient_error():
+    """The directional check used on the GPU gradient (central differences with
+    h = 1e-6 along seeded directions with standard normal entries, relative
+    error <= 1e-5 of the directional derivative, only on directions whose
+    derivative is at least a quarter of ||dM||_F, i.e. not dominated by
+    cancellation) accepts the oracle's gradient and rejects it after a planted
+    error of 1e-3 along dM itself and after one of 1e-3 ||dM||_F in a random
+    direction restricted to a single column."""
+    p = small_problem(24, m=16, k=3, r=2, ns=8, n_replace=3, t=3, lam=0.4)
+    rng = np.random.default_rng(10)
+    Wm = rng.uniform(0.0, 1.0, (p.n, p.n))
+
+    def loss_and_dZ(M_, lam_):
+        tapes = []
+        for i in range(p.t):
+            cols = p.perm[p.offsets[i]:p.offsets[i + 1]]
+            tapes.append(adj.unrolled_forward(M_[:, cols], M_, lam_, _opts()))
+        Z = adj.dfc_combine(tapes, p.perm)[0]
+        return float(np.sum((Wm * Z) ** 2)), 2.0 * Wm ** 2 * Z
+
+    _, dZ = loss_and_dZ(p.M, p.lam)
+    _, Mb, _ = adj.dfc_forward_backward(p.M, p.lam, p.perm, p.offsets, _opts(), dZ)
+    nrm = np.linalg.norm(Mb)
+    col = int(np.argmax(np.linalg.norm(Mb, axis=0)))
+    bad_dir = np.zeros_like(Mb)
+    bad_dir[:, col] = rng.standard_normal(p.m)
+    planted = [Mb * (1.0 + 1e-3), Mb + 1e-3 * nrm * bad_dir / np.linalg.norm(bad_dir)]
+    used = 0
+    caught = [False, False]
+    for t in range(8):
+        D = rng.standard_normal(p.M.shape)
+        D[:, col] += 3.0 * bad_dir[:, col] / np.linalg.norm(bad_dir[:, col])   # probe the planted column too
+        ad = float(np.sum(Mb * D))
+        if abs(ad) < 0.25 * nrm:
+            continue
+        used += 1
+        fd = _fd(lambda M_: loss_and_dZ(M_, p.lam)[0], p.M, D)
+        assert abs(fd - ad) <= 1e-5 * abs(fd)
+        for i, g in enumerate(planted):
+            caught[i] |= abs(fd - float(np.sum(g * D))) > 1e-5 * abs(fd)
+    assert used >= 3 and all(caught)

@@ -353,6 +353,32 @@ def test_segmentation_of_shape_interaction_matrix():
     assert sorted(np.unique(lab).tolist()) == [0, 1, 2, 3] and first == [0, 1, 2, 3]
 
 
+def test_segmentation_accuracy_hand_computed():
+    """Section 4.1.2 scoring on imperfect labellings, values worked out by hand.
+
+    Classes of sizes 4, 2, 6; clusters A = {0,1,2} (truth 0,0,0), B = {3,4,5,6}
+    (truth 0,1,1,2; majority 1) and C = {7..11} (truth 2 x 5).  Mapped labels
+    0,0,0,1,1,1,1,2,2,2,2,2: recall 3/4 for class 0, 2/2 for class 1, 5/6 for
+    class 2, so the mean over classes is (3/4 + 1 + 5/6) / 3 = 31/36.  The
+    per-sample fraction would be 10/12; mapping cluster B by its first member
+    (truth 0) would give (1 + 0 + 5/6) / 3."""
+    truth = np.array([0, 0, 0, 0, 1, 1, 2, 2, 2, 2, 2, 2])
+    pred = np.array([5, 5, 5, 7, 7, 7, 7, 9, 9, 9, 9, 9])
+    acc = oracle.segmentation_accuracy(pred, truth)
+    assert abs(acc - 31.0 / 36.0) <= 1e-15
+    assert abs(acc - 10.0 / 12.0) > 1e-2 and abs(acc - 11.0 / 18.0) > 1e-2
+    # majority vote is many-to-one: two clusters may both map to class 0
+    # (a one-to-one assignment would score class 0 at 1/2, i.e. 3/4 overall)
+    assert oracle.segmentation_accuracy(np.array([0, 0, 1, 1, 2, 2]), np.array([0, 0, 0, 0, 1, 1])) == 1.0
+    # a tied vote goes to the smaller class label: both clusters hold one point of
+    # each class and map to class 0, so class 0 scores 1 and class 1 scores 0
+    assert abs(oracle.segmentation_accuracy(np.array([4, 4, 6, 6]), np.array([1, 0, 0, 1])) - 0.5) <= 1e-15
+    # points labelled -1 on either side are skipped (outliers, excluded points)
+    acc2 = oracle.segmentation_accuracy(np.array([-1, 5, 5, 5, 7, 7, 7, 7, 9, 9, 9, 9, 9, 3]),
+                                        np.array([1, 0, 0, 0, 0, 1, 1, 2, 2, 2, 2, 2, 2, -1]))
+    assert abs(acc2 - 31.0 / 36.0) <= 1e-15
+
+
 @pytest.mark.slow
 def test_guarantee_regime_oracle_constraints():
     """P10 (Theorem 2 regime with the Section 4.1.1 generator, reported).
@@ -386,3 +412,26 @@ def test_guarantee_regime_oracle_constraints():
         dfc_ok += int(ez_d <= 1e-4)
     assert lrr_ok == len(seeds)
     assert dfc_ok >= 1
+
+
+def test_outlier_flags_worked_example_and_invariances():
+    """Outlier flags from the column-sparse estimate (column support of S,
+    Section 4.1.1; the threshold delta is a reading).  Worked by hand: column 0
+    has ||S|| = 5 = ||M|| (ratio 1), column 1 has S = 0, column 2 has
+    ||S|| = 0.05 against ||M|| = 1, column 3 has ||S|| = 0.5 = ||M|| / 2 exactly
+    (a tie is not flagged).  The flags do not change when a column of both S and
+    M is scaled, and only grow when S grows."""
+    S = np.array([[3.0, 0.0, 0.05, 0.3], [4.0, 0.0, 0.0, 0.4]])
+    M = np.array([[3.0, 1.0, 1.0, 0.6], [4.0, 1.0, 0.0, 0.8]])
+    assert oracle.outlier_flags(S, M, 0.1).tolist() == [True, False, False, True]
+    assert oracle.outlier_flags(S, M, 0.5).tolist() == [True, False, False, False]
+    assert oracle.outlier_flags(S, M, 0.01).tolist() == [True, False, True, True]
+    assert oracle.outlier_flags(S, M, 0.0).tolist() == [True, False, True, True]
+    rng = np.random.default_rng(3)
+    S2 = rng.standard_normal((7, 40)) * (rng.uniform(size=40) < 0.3)
+    M2 = rng.standard_normal((7, 40))
+    f = oracle.outlier_flags(S2, M2, 0.4)
+    c = rng.uniform(0.1, 10.0, 40)
+    assert np.array_equal(oracle.outlier_flags(S2 * c, M2 * c, 0.4), f)
+    assert np.all(oracle.outlier_flags(S2 * 1.5, M2, 0.4) >= f)
+    assert not oracle.outlier_flags(np.zeros_like(M2), M2, 0.0).any()
