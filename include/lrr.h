@@ -68,8 +68,17 @@ typedef enum {
                              /* MFMA products (hi hi + hi lo + lo hi), FP32 accum. */
 } lrr_precision;
 
+/* The Z-step solves (I + A^T A) Z = A^T (X - E + Y1/mu) + J - Y2/mu (Eq. 2's
+ * augmented Lagrangian).  Literal: the n x n matrix is factored (FP64 Cholesky)
+ * and inverted once per solve, and each iteration applies it with three FP64
+ * products (n x m, n x n and m x n per block).  Push-through: the same iterate
+ * through (I + A^T A)^{-1} = I - A^T (I + A A^T)^{-1} A, factoring the m x m
+ * matrix.  The literal form needs FP64 precision, full coordinates and no
+ * recorded forward (LRR_EINVAL otherwise); the footnote variant ignores the
+ * field.  AUTO takes the literal form when n <= m, the precision is FP64, the
+ * coordinates are full and no forward is recorded, and push-through otherwise. */
 typedef enum {
-    LRR_SOLVE_AUTO = 0,      /* push-through when m < n, literal otherwise          */
+    LRR_SOLVE_AUTO = 0,
     LRR_SOLVE_LITERAL = 1,   /* Cholesky of I + A^T A (n x n)                        */
     LRR_SOLVE_PUSHTHROUGH = 2/* Cholesky of I + A A^T (m x m), same iterates        */
 } lrr_solve_form;
@@ -86,7 +95,8 @@ typedef enum {
  * sigma^2 <= 1e-14 sigma_max^2 are dropped. */
 typedef enum {
     LRR_COORDS_AUTO = 0,     /* reduced when n >= 2m (the basis costs an m x m      */
-                             /* eigensolve), never for a recorded forward           */
+                             /* eigensolve), never for a recorded forward or an     */
+                             /* explicitly literal solve form                       */
     LRR_COORDS_FULL = 1,
     LRR_COORDS_REDUCED = 2
 } lrr_coords;

@@ -26,6 +26,7 @@ LRR_OK, LRR_NOT_CONVERGED = 0, 1
 LRR_EINVAL, LRR_ENOMEM, LRR_EDEVICE, LRR_ENUMERIC, LRR_ENOTAPE = -1, -2, -3, -4, -5
 LRR_FP64, LRR_FP32, LRR_MIXED_BF16 = 0, 1, 2
 LRR_COORDS_AUTO, LRR_COORDS_FULL, LRR_COORDS_REDUCED = 0, 1, 2
+LRR_SOLVE_AUTO, LRR_SOLVE_LITERAL, LRR_SOLVE_PUSHTHROUGH = 0, 1, 2
 STATUS_NAMES = {0: "LRR_OK", 1: "LRR_NOT_CONVERGED", -1: "LRR_EINVAL", -2: "LRR_ENOMEM",
                 -3: "LRR_EDEVICE", -4: "LRR_ENUMERIC", -5: "LRR_ENOTAPE"}
 
@@ -120,6 +121,8 @@ def load_library(path: str = LIB_PATH):
     lib.lrr_slr_graph.restype = i
     lib.lrr_segment.argtypes = [vp, i, vp, i, i, vp, d, i, vp, C.POINTER(lrr_seg_info), vp]
     lib.lrr_segment.restype = i
+    lib.lrr_outlier_flags.argtypes = [vp, i, i, vp, i, vp, i, d, vp, ip, vp]
+    lib.lrr_outlier_flags.restype = i
     _lib = lib
     return lib
 
@@ -429,6 +432,25 @@ def lrr_segment(Zt, k: int, exclude=None, rank_tol: float = 1e-6, rank_bound: in
     out = {f: getattr(info, f) for f, _ in lrr_seg_info._fields_}
     out["converged"] = st == LRR_OK
     return labels, out
+
+
+def lrr_outlier_flags(Mt, St, delta: float, ctx: Context | None = None):
+    """Columns the outlier estimate marks (include/lrr_segment.h): Mt and St are
+    (n, m) tensors holding M and S (m x n).  Returns (flags, count) with flags a
+    bool CUDA tensor of length n: ||S[:, j]|| > delta ||M[:, j]||."""
+    import torch
+    _require_cuda_f64(torch, Mt, St)
+    n, m = Mt.shape
+    if St.shape != (n, m):
+        raise ValueError("M and S must have the same shape")
+    ctx = ctx or get_context(Mt.device.index or 0)
+    flags = torch.empty(n, dtype=torch.uint8, device=Mt.device)
+    cnt = C.c_int(0)
+    st = load_library().lrr_outlier_flags(ctx.handle, m, n, C.c_void_p(Mt.data_ptr()), m,
+                                          C.c_void_p(St.data_ptr()), m, float(delta),
+                                          C.c_void_p(flags.data_ptr()), C.byref(cnt), _stream(torch, Mt.device))
+    _check(st, ctx, allow_nc=False)
+    return flags.bool(), cnt.value
 
 
 def lrr_slr_graph(Mt, Zt, nk: int, alpha: float = 0.05, want_obj: bool = True, ctx: Context | None = None):

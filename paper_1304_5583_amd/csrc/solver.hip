@@ -187,11 +187,16 @@ struct Plan {
     // every block its own dictionary (the observations C_b, Section 2.2 footnote):
     // the iterates of block b use rows [0, l_b) of maxl rows, K is per block
     bool local = false;
+    // Z-step in the literal form: the n x n inverse of I + A^T A (full
+    // coordinates, FP64 products) instead of the m x m one of I + A A^T
+    bool literal = false;
+    int ks = 0;                  // order of the factored matrix (m, or n when literal)
 };
 
 struct Buffers {
     double *X, *Z, *J, *Y2, *Y, *Q, *MtV, *E, *Y1, *T, *V;
     double *K, *Lb, *Linv, *Tb, *Dinv;
+    double* F1;                  // literal form: (I + A^T A)^{-1} A^T (n x m); K then holds K^{-1} - I
     double *colsq, *mu_sched;
     double *Dn, *MQacc;          // difference form of M Q only
     // reduced coordinates only
@@ -214,7 +219,7 @@ struct Buffers {
     double *ref_eprev, *ref_scale;
     unsigned long long* ref_emax;
     GemmDesc *g_gram, *g_refT, *g_refSG, *g_refXE, *g_orthG, *g_Bq, *g_P, *g_J, *g_MQ, *g_MQa, *g_KV, *g_MtV, *g_U, *g_H,
-        *g_Z, *g_spd, *g_KK;
+        *g_Z, *g_spd, *g_KK, *g_F1T, *g_F2Q, *g_AZ, *g_F1;
     RefDesc* ref;
     EigDesc* eig;
     SvtDesc* svt;
@@ -303,11 +308,13 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.Y1 = a.take<double>(m * c);
     b.T = a.take<double>(m * c);
     b.V = a.take<double>(m * c);
-    b.K = a.take<double>((p.local ? t : 1) * m * m);   // K^{-1}, one per block in local mode
-    b.Lb = a.take<double>(m * m);
-    b.Linv = a.take<double>(m * m);
-    b.Tb = a.take<double>(m * m);
-    b.Dinv = a.take<double>(m * 32);
+    const size_t ks = p.ks;      // order of the factored matrix
+    b.K = a.take<double>((p.local ? t : 1) * ks * ks);   // K^{-1}, one per block in local mode
+    b.Lb = a.take<double>(ks * ks);
+    b.Linv = a.take<double>(ks * ks);
+    b.Tb = a.take<double>(ks * ks);
+    b.Dinv = a.take<double>(ks * 32);
+    b.F1 = p.literal ? a.take<double>(nfull * m) : nullptr;
     b.Dn = p.pm.dMQ ? a.take<double>(n * c) : nullptr;
     b.MQacc = p.pm.dMQ ? a.take<double>(m * c) : nullptr;
     b.colsq = a.take<double>(c);
@@ -387,7 +394,11 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.g_H = a.take<GemmDesc>(1);
     b.g_Z = a.take<GemmDesc>(1);
     b.g_KK = a.take<GemmDesc>(p.local ? t : 1);
-    b.g_spd = a.take<GemmDesc>(lrr::spd_inverse_desc_count(p.m));
+    b.g_spd = a.take<GemmDesc>(lrr::spd_inverse_desc_count(p.ks));
+    b.g_F1T = a.take<GemmDesc>(t);
+    b.g_F2Q = a.take<GemmDesc>(t);
+    b.g_AZ = a.take<GemmDesc>(t);
+    b.g_F1 = a.take<GemmDesc>(1);
     b.eig = a.take<EigDesc>(t);
     b.svt = a.take<SvtDesc>(t);
     if (with_combine) {
@@ -486,6 +497,11 @@ bool opts_valid(const lrr_opts& o, std::string& why) {
     if (o.use_graph != 0 && o.use_graph != 1) { why = "use_graph must be 0 or 1"; return false; }
     if (o.coords < 0 || o.coords > 2) { why = "unknown coords"; return false; }
     if (o.tune != 0 && o.tune != 1) { why = "tune must be 0 or 1"; return false; }
+    if (o.solve_form == LRR_SOLVE_LITERAL) {
+        if (o.precision != LRR_FP64) { why = "the literal solve form runs in FP64 only"; return false; }
+        if (o.coords == LRR_COORDS_REDUCED) { why = "the literal solve form needs full coordinates"; return false; }
+        if (o.save_for_backward) { why = "the reverse mode records the push-through solve form"; return false; }
+    }
     for (int r : o.reserved) if (r != 0) { why = "reserved fields must be zero"; return false; }
     return true;
 }
@@ -606,7 +622,8 @@ Plan make_plan(const Problem& pr) {
     // the reverse-mode record keeps full coordinates
     const int coords = pr.o.coords;
     p.reduced = coords == LRR_COORDS_REDUCED ||
-                (coords == LRR_COORDS_AUTO && pr.n >= 2 * pr.m && !pr.o.save_for_backward);
+                (coords == LRR_COORDS_AUTO && pr.n >= 2 * pr.m && !pr.o.save_for_backward &&
+                 pr.o.solve_form != LRR_SOLVE_LITERAL);
     if (pr.o.save_for_backward) p.reduced = false;
     p.nrb = p.reduced ? std::min(pr.m, pr.n) : pr.n;
     p.local = pr.local != 0;
@@ -616,6 +633,15 @@ Plan make_plan(const Problem& pr) {
         p.reduced = false;
         p.nrb = p.maxl;
     }
+    // literal Z-step: on request, or automatically when the dictionary is at
+    // least as tall as wide (then n x n is the smaller factorisation); the
+    // reduced-precision forms, the reduced coordinates, a recorded forward and
+    // the local variant use the push-through form
+    if (!p.local && !p.reduced && !pr.o.save_for_backward) {
+        if (pr.o.solve_form == LRR_SOLVE_LITERAL) p.literal = true;
+        else if (pr.o.solve_form == LRR_SOLVE_AUTO && pr.n <= pr.m && pr.o.precision == LRR_FP64) p.literal = true;
+    }
+    p.ks = p.literal ? pr.n : pr.m;
     p.nr = p.nrb;
     p.bq = pr.m > 512 ? 32 : 16;
     p.Lm = round_up(pr.m, 2 * p.bq);
@@ -724,7 +750,7 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     for (int k = 1; k < (int)sched.size(); ++k) sched[k] = std::min(o.rho * sched[k - 1], o.mu_max);
 
     std::vector<GemmDesc> gram(t), gRT(t), gRSG(t), gRXE(t), gOG(t), gBq(t), gP(t), gJ(t);
-    std::vector<GemmDesc> gMQ(t), gMQa(t), gKV(t), gMtV(t), gExp(t);
+    std::vector<GemmDesc> gMQ(t), gMQa(t), gKV(t), gMtV(t), gExp(t), gF1T(t), gF2Q(t), gAZ(t);
     std::vector<EigDesc> eig(t);
     std::vector<size_t> need_off(t + 1, 0), sched_off(t + 1, 0);
     for (int bb = 0; bb < t; ++bb) {
@@ -744,9 +770,9 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         double* X = b.Wm[bb];
         double* T = b.TX[bb];
         gram[bb] = GemmDesc{Yb, Yb, b.Bm[bb], l, l, nr, nr, nr, L, 1.0, 0.0, run, nullptr};
-        // refinement: T = B X, [S | G] = X^T [T | X], XE = X E
+        // refinement: T = B X, S = X^T T, G = X^T X (symmetric kernel), XE = X E
         gRT[bb] = GemmDesc{b.Bm[bb], X, T, L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
-        gRSG[bb] = GemmDesc{X, T, b.SG[bb], L, 2 * L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
+        gRSG[bb] = GemmDesc{X, T, b.SG[bb], L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
         gRXE[bb] = GemmDesc{X, b.Eb[bb], b.XE[bb], L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
         // orthogonalisation: G = X^T X;  Jacobi matrix Bq = X^T (B X)
         gOG[bb] = GemmDesc{X, X, b.SG[bb] + LL, L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
@@ -769,6 +795,12 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         else
             gMQ[bb] = GemmDesc{Mb, b.Q + o_n, b.T + o_m, m, l, kin, ldb_, nr, m, -1.0, 1.0, act, nullptr};
         gKV[bb] = GemmDesc{Kb, b.T + o_m, b.V + o_m, m, l, m, m, m, m, 1.0, 0.0, act, nullptr};
+        if (p.literal) {
+            // Z = K^{-1} (A^T T + Q) = Q + [F1 T + (K^{-1} - I) Q], then T -= A Z
+            gF1T[bb] = GemmDesc{b.F1, b.T + o_m, b.MtV + o_n, nr, l, m, nr, m, nr, 1.0, 0.0, act, nullptr};
+            gF2Q[bb] = GemmDesc{b.K, b.Q + o_n, b.MtV + o_n, nr, l, nr, nr, nr, nr, 1.0, 1.0, act, nullptr};
+            gAZ[bb] = GemmDesc{Md, b.Z + o_n, b.T + o_m, m, l, nr, ldmd, nr, m, -1.0, 1.0, act, nullptr};
+        }
         gMtV[bb] = GemmDesc{Mb, b.V + o_m, b.MtV + o_n, kin, l, m, ldb_, m, nr, 1.0, 0.0, act, nullptr};
         if (p.reduced)   // expansion of the coupling residual: R2 = Qm R2r
             gExp[bb] = GemmDesc{b.Qm, b.R2r + o_n, b.R2full + (size_t)p.boff[bb] * n, n, l, nr, n, nr, n, 1.0,
@@ -782,7 +814,9 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
                           b.ref_cont + bb, b.Bq[bb], b.locut + bb, L, l, bb};
     }
     std::vector<GemmDesc> gKK(p.local ? t : 1);
-    if (p.local)
+    if (p.literal)
+        gKK[0] = GemmDesc{pr.A, pr.A, b.K, n, n, m, (int)pr.lda, (int)pr.lda, n, 1.0, 0.0, nullptr, nullptr};
+    else if (p.local)
         for (int bb = 0; bb < t; ++bb)
             gKK[bb] = GemmDesc{b.X + (size_t)p.boff[bb] * m, b.X + (size_t)p.boff[bb] * m, b.K + (size_t)bb * m * m,
                                m, m, p.boff[bb + 1] - p.boff[bb], m, m, m, 1.0, 0.0, nullptr, nullptr};
@@ -808,6 +842,13 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     up(b.g_MQa, gMQa.data(), sizeof(GemmDesc) * t);
     up(b.g_KV, gKV.data(), sizeof(GemmDesc) * t);
     up(b.g_MtV, gMtV.data(), sizeof(GemmDesc) * t);
+    if (p.literal) {
+        up(b.g_F1T, gF1T.data(), sizeof(GemmDesc) * t);
+        up(b.g_F2Q, gF2Q.data(), sizeof(GemmDesc) * t);
+        up(b.g_AZ, gAZ.data(), sizeof(GemmDesc) * t);
+        const GemmDesc gF1{b.K, pr.A, b.F1, n, m, n, n, (int)pr.lda, n, 1.0, 0.0, nullptr, nullptr};
+        up(b.g_F1, &gF1, sizeof(GemmDesc));
+    }
     if (p.reduced) up(b.g_exp, gExp.data(), sizeof(GemmDesc) * t);
 
     up(b.g_KK, gKK.data(), sizeof(GemmDesc) * gKK.size());
@@ -854,6 +895,16 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     if (p.reduced) LRR_HIP(hipMemsetAsync(b.r2nrm, 0, sizeof(unsigned long long) * t, s));
     lrr::launch_init_iter(b.it, b.mu_sched, 0, s);
 
+    // literal form: K = I + A^T A (n x n), K^{-1} (FP64 Cholesky, once per
+    // solve), F1 = K^{-1} A^T, then K^{-1} - I in place
+    if (p.literal) {
+        lrr::launch_dgemm(b.g_KK, 1, n, n, true, false, s);
+        lrr::launch_add_identity(b.K, n, n, 1.0, s);
+        lrr::spd_inverse(b.K, n, b.Lb, b.Linv, b.Dinv, b.Tb, b.g_spd, b.flag, s);
+        lrr::launch_dgemm(b.g_F1, 1, n, m, false, true, s);
+        lrr::launch_add_identity(b.K, n, n, -1.0, s);
+        return;
+    }
     // K = I + A A^T, then K^{-1} (FP64 Cholesky, once per solve; per block in
     // local mode, A = C_b)
     for (size_t bb = 0; bb < gKK.size(); ++bb) {
@@ -922,6 +973,32 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             lrr::launch_form_QT(b.J, b.Y2, b.Q, pm.dMQ ? b.Dn : nullptr, n, n, b.X, b.E, b.Y1, b.T, m, m, c,
                                 b.colblk, b.active, b.it, st);
         });
+        if (p.literal) {
+            // Z = K^{-1} (A^T T + Q) with K = I + A^T A, written as Z = Q + W with
+            // W = F1 T + (K^{-1} - I) Q; then T - A Z = X - E + Y1/mu - A Z, so
+            // E + (T - A Z) is the shrinkage input: the role V plays in the
+            // push-through form
+            tm("k_dgemm<false, false>", 2.0 * n * m * cact, 0.0, [&] {
+                lrr::launch_dgemm(b.g_F1T, t, n, p.maxl, false, false, st);
+            });
+            tm("k_dgemm<false, false>", 2.0 * n * n * cact, 0.0, [&] {
+                lrr::launch_dgemm(b.g_F2Q, t, n, p.maxl, false, false, st);
+            });
+            tm("k_update_Z", 0.0, 6.0 * n * cact * D, [&] {
+                lrr::launch_update_Z(b.Q, b.MtV, b.J, b.Z, b.Y2, nullptr, nullptr, n, n, c, b.colblk, bst, b.it,
+                                     st);
+            });
+            tm("k_dgemm<false, false>", 2.0 * m * n * cact, 0.0, [&] {
+                lrr::launch_dgemm(b.g_AZ, t, m, p.maxl, false, false, st);
+            });
+            tm("k_estep", 0.0, 5.0 * m * cact * D, [&] {
+                lrr::launch_estep(b.E, b.T, b.Y1, m, m, c, pr.lam, b.colblk, bst, b.it, st);
+            });
+            tm("k_check", 0.0, 0.0, [&] {
+                lrr::launch_check(bst, t, b.it, b.mu_sched, o.tol, fixed, b.n_active, st);
+            });
+            return;
+        }
         // T = P - M Q; the difference form carries M Q as a sum of products M dQ
         if (anchor) {
             // every kAnchorEvery iterations the rounding carried in the sum of
@@ -1010,9 +1087,9 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         if (any_run) {
             // Gram matrix of each block that needs a decomposition (FP64 in every
             // precision form)
-            timed("k_dgemm<true, false>", f_gram, 0.0, [&] {
-                lrr::launch_dgemm(b.g_gram, t, p.maxl, p.maxl, true, false, s);
-            });
+            // the symmetric kernel computes the tiles on and above the diagonal
+            const double hg = lrr::dgemm_sym_tiles(t, p.maxl) ? 0.5 : 1.0, hL = lrr::dgemm_sym_tiles(t, p.maxL) ? 0.5 : 1.0;
+            timed("k_dgemm_sym", hg * f_gram, 0.0, [&] { lrr::launch_dgemm_sym(b.g_gram, t, p.maxl, s); });
             // Newton refinement of the previous iteration's eigenvectors
             timed("k_ref_begin", 0.0, 0.0, [&] { lrr::launch_ref_begin(b.ref, t, p.maxL, b.svt_run, b.warm, s); });
             LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
@@ -1026,9 +1103,10 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 timed("k_dgemm<false, false>", fl, 0.0, [&] {
                     lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, s);
                 });
-                timed("k_dgemm<true, false>", 2.0 * fl, 0.0, [&] {
-                    lrr::launch_dgemm(b.g_refSG, t, p.maxL, 2 * p.maxL, true, false, s);
+                timed("k_dgemm<true, false>", fl, 0.0, [&] {
+                    lrr::launch_dgemm(b.g_refSG, t, p.maxL, p.maxL, true, false, s);
                 });
+                timed("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, s); });
                 timed("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, s); });
                 timed("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, s); });
                 // decide before applying: only quadratically shrinking corrections
@@ -1051,9 +1129,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 if (h_run[bb]) f_L3 += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
             timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run(b.ref, t, b.svt_run, s); });
             for (int ns = 0; ns < 2; ++ns) {
-                timed("k_dgemm<true, false>", f_L3, 0.0, [&] {
-                    lrr::launch_dgemm(b.g_orthG, t, p.maxL, p.maxL, true, false, s);
-                });
+                timed("k_dgemm_sym", hL * f_L3, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, s); });
                 timed("k_orth_E", 0.0, 0.0, [&] { lrr::launch_orth_E(b.ref, t, p.maxL, s); });
                 timed("k_dgemm<false, false>", f_L3, 0.0, [&] {
                     lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, s);

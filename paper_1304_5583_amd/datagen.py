@@ -241,6 +241,7 @@ def make_config(cfg: int, trial: int = 0) -> Problem:
     precision = {1: "fp64", 2: "fp64", 3: "fp64", 4: "mixed", 5: "fp32"}[cfg]
     k = int(labels.max()) + 1
     extra["k"] = k
+    extra["config"] = cfg
     return Problem(name=CONFIG_NAMES[cfg], M=M, labels=labels, outliers=outl,
                    perm=perm, offsets=offsets, lam=float(lam), tol=1e-8,
                    precision=precision, extra=extra)
