@@ -78,6 +78,33 @@ typedef struct lrr_seg_info {
 lrr_status lrr_segment(lrr_ctx* ctx, int n, const void* Z, int ldz, int k, const unsigned char* exclude,
                        double rank_tol, int rank_bound, long long* labels, lrr_seg_info* info, void* stream);
 
+/*
+ * Outlier columns as the method itself identifies them (Section 4.1.1: the
+ * outliers are the column support of the column-sparse estimate S of Eq. (1) /
+ * Eq. (2)).  Column j of the data is flagged when its outlier estimate carries
+ * more than the fraction delta of its norm,
+ *
+ *     ||S[:, j]||_2 > delta * ||M[:, j]||_2 .
+ *
+ * The paper names no threshold; delta is the caller's choice (delta = 0 flags
+ * every column with a nonzero estimate).  The result can serve as the exclude
+ * mask of lrr_segment.
+ *
+ * Arguments
+ *   m, n        rows and columns of M and S (m, n >= 1)
+ *   M, ldm      DEVICE pointer, double, column-major data (ldm >= m)
+ *   S, lds      DEVICE pointer, double, the outlier estimate in the same column
+ *               order, e.g. the S output of dfc_lrr_solve (lds >= m)
+ *   delta       threshold fraction, >= 0 and finite
+ *   flags       DEVICE pointer to n bytes (output: 1 flagged, 0 not)
+ *   n_flagged   HOST pointer (may be NULL): number of flagged columns
+ *   stream      hipStream_t (NULL: the null stream)
+ * Norms are FP64 sums in a fixed order.  Returns when the flags are complete;
+ * LRR_EINVAL for bad arguments (nothing written).
+ */
+lrr_status lrr_outlier_flags(lrr_ctx* ctx, int m, int n, const void* M, int ldm, const void* S, int lds,
+                             double delta, unsigned char* flags, int* n_flagged, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

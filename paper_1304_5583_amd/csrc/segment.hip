@@ -501,7 +501,58 @@ struct Seg {
     }
 };
 
+// Outlier flags from the column-sparse outlier estimate S (one wavefront per
+// column, lanes stride the rows, a fixed-order wave sum): flag j when
+// ||S[:, j]||_2 > delta ||M[:, j]||_2; the flagged columns are counted.
+__global__ __launch_bounds__(256) void k_outlier_flags(const double* __restrict__ M, long ldm,
+                                                        const double* __restrict__ S, long lds, int m, int n,
+                                                        double delta, unsigned char* __restrict__ flags,
+                                                        int* __restrict__ count) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;
+    const int lane = threadIdx.x & 63;
+    double ss = 0.0, sm = 0.0;
+    for (int i = lane; i < m; i += 64) {
+        const double a = S[i + (long)j * lds], b = M[i + (long)j * ldm];
+        ss += a * a;
+        sm += b * b;
+    }
+    ss = lrr::wave_sum(ss);
+    sm = lrr::wave_sum(sm);
+    if (lane == 0) {
+        const unsigned char f = sqrt(ss) > delta * sqrt(sm) ? 1 : 0;
+        flags[j] = f;
+        if (f) atomicAdd(count, 1);
+    }
+}
+
 }  // namespace
+
+extern "C" lrr_status lrr_outlier_flags(lrr_ctx* ctx, int m, int n, const void* M, int ldm, const void* S, int lds,
+                                        double delta, unsigned char* flags, int* n_flagged, void* stream) {
+    if (!ctx) return lrr::ctx_fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
+    if (m < 1 || n < 1 || !M || !S || !flags || ldm < m || lds < m)
+        return lrr::ctx_fail(ctx, LRR_EINVAL, "bad M / S / flags arguments");
+    if (!(delta >= 0.0) || !std::isfinite(delta)) return lrr::ctx_fail(ctx, LRR_EINVAL, "delta must be >= 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    try {
+        if (hipSetDevice(lrr::ctx_device(ctx)) != hipSuccess)
+            return lrr::ctx_fail(ctx, LRR_EDEVICE, "hipSetDevice failed");
+        int* dcount = static_cast<int*>(lrr::ctx_seg_workspace(ctx, 256));
+        LRR_HIP(hipMemsetAsync(dcount, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_outlier_flags, dim3((n + 3) / 4), dim3(256), 0, s, static_cast<const double*>(M),
+                           (long)ldm, static_cast<const double*>(S), (long)lds, m, n, delta, flags, dcount);
+        int cnt = 0;
+        LRR_HIP(hipMemcpyAsync(&cnt, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
+        LRR_HIP(hipStreamSynchronize(s));
+        if (n_flagged) *n_flagged = cnt;
+        return LRR_OK;
+    } catch (const lrr::HipError& e) {
+        return lrr::ctx_fail(ctx, LRR_EDEVICE, e.msg);
+    } catch (const std::bad_alloc&) {
+        return lrr::ctx_fail(ctx, LRR_ENOMEM, "segmentation workspace allocation failed");
+    }
+}
 
 extern "C" lrr_status lrr_segment(lrr_ctx* ctx, int n, const void* Zv, int ldz, int k, const unsigned char* exclude,
                                   double rank_tol, int rank_bound, long long* labels, lrr_seg_info* info,

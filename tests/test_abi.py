@@ -87,3 +87,5 @@ def test_null_ctx_and_bad_arguments_rejected_on_host():
     dl = C.c_double(0)
     assert lib.dfc_lrr_backward(None, None, 10, C.byref(dl), None, 5, None) == B.LRR_EINVAL
     assert lib.lrr_ctx_create(0, None) == B.LRR_EINVAL
+    flags = np.zeros(10, dtype=np.uint8)
+    assert lib.lrr_outlier_flags(None, 5, 10, None, 5, None, 5, 0.5, None, None, None) == B.LRR_EINVAL

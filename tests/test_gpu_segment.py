@@ -102,9 +102,10 @@ def test_full_workload_labels_equal_stored_oracle_labels(wl):
     Zt, _, info = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets)
     del Mt
     bound = int(np.diff(p.offsets).max())
+    exclude = None if "S_ratio" in g else p.outliers   # every point (Section 4.1.2)
     for rank_tol, key in ((1e-6, "labels"), (1e-3, "labels_rank_tol_1e-3")):
         for rb in (0, bound):
-            got, sinfo = _seg(Zt, k, p.outliers, rank_tol=rank_tol, rank_bound=rb)
+            got, sinfo = _seg(Zt, k, exclude, rank_tol=rank_tol, rank_bound=rb)
             say(f"[seg wl{wl}] tol={rank_tol} bound={rb} rank={sinfo['rank']} q={sinfo['range_rank']} "
                 f"it={sinfo['embed_iters']} res={sinfo['embed_resid']:.1e} theta_k={sinfo['theta_k']:.4f} "
                 f"theta_k1={sinfo['theta_k1']:.4f} km={sinfo['kmeans_iters']}")
@@ -113,10 +114,13 @@ def test_full_workload_labels_equal_stored_oracle_labels(wl):
 
 
 def test_workload4_properties():
-    """Workload 4 (n = 20000) through the sketch: k clusters, outliers -1, every
-    kept point labelled, the labels unchanged when the sketch grows, and the
-    segmentation accuracy at least that of the oracle's labels on the smaller
-    workloads of the same generator (1.0 there)."""
+    """Workload 4 (n = 20000) through the sketch, every point clustered (Section
+    4.1.2): k clusters, every point labelled, the labels unchanged when the
+    sketch grows, and the segmentation accuracy over the generator's clean
+    points at least that of the oracle's labels on the smaller workloads of the
+    same generator (1.0 there).  The outlier flags of the solve's own S are
+    reported (on this workload S = 0: the replaced columns are represented in
+    Z, not in S)."""
     need_gpu()
     import oracle
     from paper_1304_5583_amd import binding as B
@@ -124,24 +128,26 @@ def test_workload4_properties():
     p = make_config(4)
     k = p.extra["k"]
     Mt = B.to_device_colmajor(p.M)
-    Zt, _, info = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets)
-    del Mt
+    Zt, St, info = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets)
+    flags, nf = B.lrr_outlier_flags(Mt, St, 0.5)
+    say(f"[seg wl4] outlier flags from S (delta 0.5): {nf}, of them generator outliers: "
+        f"{int((flags.cpu().numpy() & p.outliers).sum())}")
+    del Mt, St
     bound = int(np.diff(p.offsets).max())
-    got, sinfo = _seg(Zt, k, p.outliers, rank_bound=bound)
+    got, sinfo = _seg(Zt, k, None, rank_bound=bound)
     say(f"[seg wl4] rank={sinfo['rank']} q={sinfo['range_rank']} it={sinfo['embed_iters']} "
         f"res={sinfo['embed_resid']:.1e} theta_k={sinfo['theta_k']:.4f} theta_k1={sinfo['theta_k1']:.4f} "
         f"km={sinfo['kmeans_iters']}")
     assert sinfo["converged"]
-    assert np.all(got[p.outliers] == -1)
-    kept = got[~p.outliers]
-    assert kept.min() == 0 and kept.max() == k - 1
+    assert got.min() == 0 and got.max() == k - 1
+    kept = got
     # renumbered by first appearance
     _, first = np.unique(kept, return_index=True)
     assert np.all(np.diff(first) > 0)
     acc = oracle.segmentation_accuracy(got, np.where(p.outliers, -1, p.labels))
     say(f"[seg wl4] accuracy={acc:.4f}")
     assert acc >= 0.99
-    got2, _ = _seg(Zt, k, p.outliers, rank_bound=bound + 64)
+    got2, _ = _seg(Zt, k, None, rank_bound=bound + 64)
     assert np.array_equal(got, got2)
 
 
@@ -203,3 +209,34 @@ def test_block_diagonal_affinity_recovers_subspaces():
         want = oracle.segment(Z, k)
     assert np.array_equal(got, want)
     assert oracle.segmentation_accuracy(got, truth) == 1.0
+
+
+def test_outlier_flags_vs_oracle():
+    """lrr_outlier_flags on the S of a GPU solve against oracle.outlier_flags on
+    the same S (both FP64; flags compared away from ratios within 1e-12 of the
+    threshold), for several thresholds, plus its argument checks."""
+    torch = need_gpu()
+    import oracle
+    from paper_1304_5583_amd import binding as B
+    from paper_1304_5583_amd.datagen import make_config, small_problem
+    for name, p in (("small", small_problem(51, m=40, k=3, r=3, ns=30, n_replace=6, t=3, lam=0.15)),
+                    ("workload 3", make_config(3))):
+        Mt = B.to_device_colmajor(p.M)
+        _, St, _ = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets)
+        S = B.from_device_colmajor(St)
+        ratio = np.linalg.norm(S, axis=0) / np.linalg.norm(p.M, axis=0)
+        for delta in (0.0, 0.05, 0.1, 0.5):
+            flags, cnt = B.lrr_outlier_flags(Mt, St, delta)
+            got = flags.cpu().numpy()
+            want = oracle.outlier_flags(S, p.M, delta)
+            far = np.abs(ratio - delta) > 1e-12
+            say(f"[outlier flags {name}] delta={delta} gpu={cnt} oracle={int(want.sum())} "
+                f"generator={int(p.outliers.sum())} hits={int((got & p.outliers).sum())}")
+            assert cnt == int(got.sum())
+            assert np.array_equal(got[far], want[far])
+        del Mt, St
+    Mt = B.to_device_colmajor(p.M)
+    with pytest.raises(B.LRRError):
+        B.lrr_outlier_flags(Mt, Mt, -1.0)
+    with pytest.raises(B.LRRError):
+        B.lrr_outlier_flags(Mt, Mt, float("nan"))
