@@ -19,7 +19,9 @@ extern "C" {
 /* C = alpha * op(A) op(B) + beta * C with op(X) = X or X^T (ta, tb != 0 means
  * transposed).  op(A) is M x K, op(B) is K x N, C is M x N.  The MFMA GEMM used
  * for every dense product of the solver (Gram matrices, dictionary products,
- * reconstruction, combine). */
+ * reconstruction, combine).  A^T A (ta, !tb, B == A, ldb == lda, M == N) runs
+ * the symmetric kernel of the solver's Gram matrices: the tiles on and above
+ * the diagonal are computed and mirrored, bitwise the full product. */
 lrr_status lrr_diag_dgemm(lrr_ctx *ctx, int ta, int tb, int M, int N, int K, double alpha,
                           const double *A, int lda, const double *B, int ldb, double beta,
                           double *C, int ldc, void *stream);

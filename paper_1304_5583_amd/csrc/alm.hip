@@ -180,39 +180,6 @@ __global__ __launch_bounds__(256) void k_sub_cols(double* __restrict__ T, const 
     for (int i = threadIdx.x; i < m; i += 256) T[o + i] -= A[o + i];
 }
 
-// In reduced coordinates (R2r set) the coefficient residual is stored and its
-// column 2-norm, which bounds the full-coordinate max-norm, goes to r2nrm.
-__global__ __launch_bounds__(256) void k_update_Z(const double* __restrict__ Q, const double* __restrict__ MtV,
-                                                   const double* __restrict__ J, double* __restrict__ Z,
-                                                   double* __restrict__ Y2, double* __restrict__ R2r,
-                                                   unsigned long long* __restrict__ r2nrm, int n, long ld,
-                                                   const int* __restrict__ colblk, BlockState bs,
-                                                   const DevIter* it) {
-    __shared__ double red[4];
-    const int j = blockIdx.x;
-    const int b = colblk[j];
-    if (!bs.active[b]) return;
-    const double mu = it->mu;
-    const long o = j * ld;
-    double mx = 0.0, ss = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        const double z = Q[o + i] + MtV[o + i];
-        const double r2 = z - J[o + i];
-        Z[o + i] = z;
-        Y2[o + i] = Y2[o + i] + mu * r2;
-        mx = fmax(mx, fabs(r2));
-        ss += r2 * r2;
-        if (R2r) R2r[o + i] = r2;
-    }
-    if (R2r) {
-        ss = block_sum256(ss, red);
-        if (threadIdx.x == 0) atomic_max_nonneg(&r2nrm[b], sqrt(ss));
-    } else {
-        mx = block_max256(mx, red);
-        if (threadIdx.x == 0) atomic_max_nonneg(&bs.r2max[b], mx);
-    }
-}
-
 // Reduced coordinates, coupling residual R2 = Qm R2r: with Qm having orthonormal
 // columns, ||R2 e_j||_inf <= ||R2r e_j||_2 and ||R2 e_j||_inf >= ||R2r e_j||_2 / sqrt(n).
 // A block whose largest column 2-norm is below tol, or at least sqrt(n) tol, is
@@ -298,6 +265,138 @@ __global__ __launch_bounds__(256) void k_estep(double* __restrict__ E, const dou
     }
     mx = block_max256(mx, red);
     if (threadIdx.x == 0) atomic_max_nonneg(&bs.r1max[b], mx);
+}
+
+// The same E-step with one wavefront per column and the column held in
+// registers (a single pass over HBM: E, V and Y1 read once, E and Y1 written
+// once, every load issued before the norm is reduced).  Lane l holds rows 2l
+// and 2l + 1 of every 128-row chunk (16-byte accesses when VEC, i.e. even
+// leading dimension); NCH chunks cover m <= 128 NCH.  The column norm is a
+// fixed-order sum (per lane, then the wave butterfly).
+template <bool VEC>
+__device__ __forceinline__ void ld2(const double* __restrict__ p, int i, int m, double& a, double& b) {
+    if (VEC && i + 1 < m) {
+        const double2 x = *reinterpret_cast<const double2*>(p + i);
+        a = x.x;
+        b = x.y;
+    } else {
+        a = i < m ? p[i] : 0.0;
+        b = i + 1 < m ? p[i + 1] : 0.0;
+    }
+}
+template <bool VEC>
+__device__ __forceinline__ void st2(double* __restrict__ p, int i, int m, double a, double b) {
+    if (VEC && i + 1 < m) {
+        *reinterpret_cast<double2*>(p + i) = double2{a, b};
+    } else {
+        if (i < m) p[i] = a;
+        if (i + 1 < m) p[i + 1] = b;
+    }
+}
+
+template <int NCH, bool VEC>
+__global__ __launch_bounds__(256) void k_estep_w(double* __restrict__ E, const double* __restrict__ V,
+                                                  double* __restrict__ Y1, int m, long ld, int ncols, double lam,
+                                                  const int* __restrict__ colblk, BlockState bs,
+                                                  const DevIter* it) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= ncols) return;
+    const int b = colblk[j];
+    if (!bs.active[b]) return;
+    const int lane = threadIdx.x & 63;
+    const double mu = it->mu;
+    const long o = (long)j * ld;
+    double q[NCH][2], y[NCH][2];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int i = c * 128 + 2 * lane;
+        double e0, e1, v0, v1;
+        ld2<VEC>(E + o, i, m, e0, e1);
+        ld2<VEC>(V + o, i, m, v0, v1);
+        ld2<VEC>(Y1 + o, i, m, y[c][0], y[c][1]);
+        q[c][0] = e0 + v0;   // = X - M Z + Y1/mu
+        q[c][1] = e1 + v1;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) s += q[c][0] * q[c][0] + q[c][1] * q[c][1];
+    s = wave_sum(s);
+    const double nrm = sqrt(s);
+    const double thr = lam / mu;
+    const double scale = (nrm > thr) ? 1.0 - thr / nrm : 0.0;
+    double mx = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int i = c * 128 + 2 * lane;
+        double e[2], yn[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            e[h] = q[c][h] * scale;
+            const double r1 = q[c][h] - y[c][h] / mu - e[h];
+            yn[h] = y[c][h] + mu * r1;
+            if (i + h < m) mx = fmax(mx, fabs(r1));
+        }
+        st2<VEC>(E + o, i, m, e[0], e[1]);
+        st2<VEC>(Y1 + o, i, m, yn[0], yn[1]);
+    }
+    mx = wave_max(mx);
+    if (lane == 0) atomic_max_nonneg(&bs.r1max[b], mx);
+}
+
+// k_update_Z with one wavefront per column (no workgroup barriers, 16-byte
+// accesses when VEC, the loads of four 128-row chunks issued before their
+// stores): Z = Q + M^T V, R2 = Z - J, Y2 += mu R2, and max|R2| or, in reduced
+// coordinates, the coefficient residual and its column 2-norm.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_update_Z_w(const double* __restrict__ Q, const double* __restrict__ MtV,
+                                                     const double* __restrict__ J, double* __restrict__ Z,
+                                                     double* __restrict__ Y2, double* __restrict__ R2r,
+                                                     unsigned long long* __restrict__ r2nrm, int n, long ld,
+                                                     int ncols, const int* __restrict__ colblk, BlockState bs,
+                                                     const DevIter* it) {
+    constexpr int G = 4;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= ncols) return;
+    const int b = colblk[j];
+    if (!bs.active[b]) return;
+    const int lane = threadIdx.x & 63;
+    const double mu = it->mu;
+    const long o = (long)j * ld;
+    double mx = 0.0, ss = 0.0;
+    for (int base = 0; base < n; base += 128 * G) {
+        double q[G][2], w[G][2], jj[G][2], y[G][2];
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            const int i = base + c * 128 + 2 * lane;
+            ld2<VEC>(Q + o, i, n, q[c][0], q[c][1]);
+            ld2<VEC>(MtV + o, i, n, w[c][0], w[c][1]);
+            ld2<VEC>(J + o, i, n, jj[c][0], jj[c][1]);
+            ld2<VEC>(Y2 + o, i, n, y[c][0], y[c][1]);
+        }
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            const int i = base + c * 128 + 2 * lane;
+            double z[2], r2[2], yn[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                z[h] = q[c][h] + w[c][h];
+                r2[h] = z[h] - jj[c][h];
+                yn[h] = y[c][h] + mu * r2[h];
+                mx = fmax(mx, fabs(r2[h]));   // rows past n hold zeros
+                ss += r2[h] * r2[h];
+            }
+            st2<VEC>(Z + o, i, n, z[0], z[1]);
+            st2<VEC>(Y2 + o, i, n, yn[0], yn[1]);
+            if (R2r) st2<VEC>(R2r + o, i, n, r2[0], r2[1]);
+        }
+    }
+    if (R2r) {
+        ss = wave_sum(ss);
+        if (lane == 0) atomic_max_nonneg(&r2nrm[b], sqrt(ss));
+    } else {
+        mx = wave_max(mx);
+        if (lane == 0) atomic_max_nonneg(&bs.r2max[b], mx);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_check(BlockState bs, int t, DevIter* it,
@@ -406,8 +505,13 @@ void launch_sub_cols(double* T, const double* A, int m, long ld, int ncols, cons
 void launch_update_Z(const double* Q, const double* MtV, const double* J, double* Z, double* Y2, double* R2r,
                      unsigned long long* r2nrm, int n, long ld, int ncols, const int* colblk, BlockState bs,
                      const DevIter* it, hipStream_t s) {
-    hipLaunchKernelGGL(k_update_Z, dim3(ncols), dim3(256), 0, s, Q, MtV, J, Z, Y2, R2r, r2nrm, n, ld, colblk, bs,
-                       it);
+    const dim3 grid((ncols + 3) / 4);
+    if ((ld & 1) == 0)
+        hipLaunchKernelGGL((k_update_Z_w<true>), grid, dim3(256), 0, s, Q, MtV, J, Z, Y2, R2r, r2nrm, n, ld, ncols,
+                           colblk, bs, it);
+    else
+        hipLaunchKernelGGL((k_update_Z_w<false>), grid, dim3(256), 0, s, Q, MtV, J, Z, Y2, R2r, r2nrm, n, ld, ncols,
+                           colblk, bs, it);
 }
 void launch_r2_decide(BlockState bs, unsigned long long* r2nrm, int* expand, int t, double tol, double sqrt_n,
                       hipStream_t s) {
@@ -425,9 +529,27 @@ void launch_ns_factor(const double* G, double* T, int r, hipStream_t s) {
     const long nn = (long)r * r;
     hipLaunchKernelGGL(k_ns_factor, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, G, T, r);
 }
+template <int NCH>
+void launch_estep_w(double* E, const double* V, double* Y1, int m, long ld, int ncols, double lam,
+                    const int* colblk, BlockState bs, const DevIter* it, hipStream_t s) {
+    const dim3 grid((ncols + 3) / 4);
+    if ((ld & 1) == 0)
+        hipLaunchKernelGGL((k_estep_w<NCH, true>), grid, dim3(256), 0, s, E, V, Y1, m, ld, ncols, lam, colblk, bs,
+                           it);
+    else
+        hipLaunchKernelGGL((k_estep_w<NCH, false>), grid, dim3(256), 0, s, E, V, Y1, m, ld, ncols, lam, colblk, bs,
+                           it);
+}
+
 void launch_estep(double* E, const double* V, double* Y1, int m, long ld, int ncols, double lam,
                   const int* colblk, BlockState bs, const DevIter* it, hipStream_t s) {
-    hipLaunchKernelGGL(k_estep, dim3(ncols), dim3(256), 0, s, E, V, Y1, m, ld, lam, colblk, bs, it);
+    // the column in registers up to m = 2048; beyond, the two-pass workgroup kernel
+    if (m <= 128) launch_estep_w<1>(E, V, Y1, m, ld, ncols, lam, colblk, bs, it, s);
+    else if (m <= 256) launch_estep_w<2>(E, V, Y1, m, ld, ncols, lam, colblk, bs, it, s);
+    else if (m <= 512) launch_estep_w<4>(E, V, Y1, m, ld, ncols, lam, colblk, bs, it, s);
+    else if (m <= 1024) launch_estep_w<8>(E, V, Y1, m, ld, ncols, lam, colblk, bs, it, s);
+    else if (m <= 2048) launch_estep_w<16>(E, V, Y1, m, ld, ncols, lam, colblk, bs, it, s);
+    else hipLaunchKernelGGL(k_estep, dim3(ncols), dim3(256), 0, s, E, V, Y1, m, ld, lam, colblk, bs, it);
 }
 void launch_check(BlockState bs, int t, DevIter* it, const double* mu_sched, double tol, int fixed,
                   int* n_active, hipStream_t s) {

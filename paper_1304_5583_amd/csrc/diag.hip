@@ -77,7 +77,12 @@ lrr_status lrr_diag_gemm(lrr_ctx* ctx, int precision, int ta, int tb, int M, int
         LRR_HIP(hipMemcpy(d, &h, sizeof(h), hipMemcpyHostToDevice));
         const int mode = precision == LRR_FP32 ? lrr::kGemmFP32
                          : precision == LRR_MIXED_BF16 ? lrr::kGemmBF16X3 : lrr::kGemmFP64;
-        lrr::launch_xgemm(d, 1, M, N, ta != 0, tb != 0, mode, s);
+        // A^T A (the same pointer and stride on both sides): the symmetric
+        // kernel computes the tiles on and above the diagonal and mirrors them
+        if (mode == lrr::kGemmFP64 && ta && !tb && A == B && lda == ldb && M == N)
+            lrr::launch_dgemm_sym(d, 1, N, s, true);
+        else
+            lrr::launch_xgemm(d, 1, M, N, ta != 0, tb != 0, mode, s);
         LRR_HIP(hipStreamSynchronize(s));
         LRR_HIP(hipFree(d));
         return LRR_OK;

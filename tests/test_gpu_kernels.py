@@ -53,6 +53,32 @@ def _check_dgemm(ta, tb, M, N, K, pads):
     assert np.array_equal(dC.cpu().numpy().T[M:], np.zeros((ldc - M, N)))
 
 
+@pytest.mark.parametrize("N,K,ld", [(512, 500, 512), (600, 333, 602), (130, 64, 131), (1000, 17, 1001),
+                                    (1500, 40, 1500)])
+def test_symmetric_product_is_bitwise_the_full_product(N, K, ld):
+    """C = A^T A through the symmetric kernel (tiles on and above the diagonal,
+    mirrored) equals, bit for bit, the full-tile kernel's product of A^T with a
+    separate copy of A (which takes the general path), and that full product is
+    itself exactly symmetric; beta = 0 never reads C (NaN-filled)."""
+    torch = need_gpu()
+    from paper_1304_5583_amd import binding as B
+    rng = np.random.default_rng(N + K)
+    A = np.zeros((ld, N))
+    A[:K] = rng.standard_normal((K, N))
+    dA = torch.from_numpy(np.ascontiguousarray(A.T)).cuda()
+    dA2 = dA.clone()
+    C1 = torch.full((N, N), float("nan"), dtype=torch.float64, device="cuda")
+    C2 = torch.full((N, N), float("nan"), dtype=torch.float64, device="cuda")
+    B.lrr_diag_dgemm(True, False, dA, dA, C1, N, N, K, ld, ld, N, alpha=1.0, beta=0.0)
+    B.lrr_diag_dgemm(True, False, dA, dA2, C2, N, N, K, ld, ld, N, alpha=1.0, beta=0.0)
+    c1, c2 = C1.cpu().numpy().T, C2.cpu().numpy().T
+    say(f"sym N={N} K={K}: max |sym - full| = {np.abs(c1 - c2).max():.3e}, asym of full = {np.abs(c2 - c2.T).max():.3e}")
+    assert np.array_equal(c2, c2.T)
+    assert np.array_equal(c1, c2)
+    ref = A[:K].T @ A[:K]
+    assert np.abs(c1 - ref).max() <= 1e-13 * (1 + np.abs(ref).max()) * K
+
+
 @pytest.mark.parametrize("m,n", [(32, 40), (77, 120), (100, 200), (257, 300)])
 def test_spd_inverse(m, n):
     torch = need_gpu()
