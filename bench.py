@@ -3,18 +3,27 @@
 
 A step is one complete ``dfc_lrr_solve`` (Algorithm 1: D-step gather,
 factorisation of I + M M^T, all t blocks iterated to tolerance in batched
-launches, column-projection combine) on the m=500, n=2000, t=4 FP64 workload
-(20 rank-10 subspaces, l2-normalised columns, 5% corrupted columns).  The input
-is resident in HBM before the timed region.
+launches, column-projection combine).  The default workload is the one the
+mixed-precision comparison is defined on: m = 512, n = 20000, t = 40 blocks of
+500 (100 rank-20 subspaces, 10% replaced columns), timed in the FP64 plain form;
+the BF16x3 and FP32 forms are timed the same way and reported with their error
+against the FP64 form's Z.  The input is resident in HBM before every timed
+region, and no per-kernel timing runs inside the headline region.
 
-Prints one JSON line with solves/s (value), batched and per-block ALM
-iterations/s, the error against the stored FP64 oracle fingerprint, the
-roofline of the dominant kernel (its duration measured live with HIP events on
-the solve's stream) and the FP64 CPU oracle timed on a bounded sample.
+Per-kernel roofline figures come from a separate profiled region (one FP64
+solve, every launch bracketed by HIP events on the solve's stream): for the
+matrix products the algorithmic flops of each launch (2 M N K summed over the
+blocks it covers, from the host's descriptors) against the FP64 matrix peak, for
+the column kernels their algorithmic HBM bytes against 8 TB/s.
+
+Prints one JSON line.  The FP64 CPU oracle is timed on a bounded sample of the
+same workload (block 1, a few ALM iterations, scaled by the block-iterations of
+the full solve) and, single-threaded, on block 1 of the n = 2000 workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DFC-LRR solves/sec + ALM iters/sec at stated err vs FP64 plain form, 1 GPU"
 PEAK = {"mfma_f64": 78.6, "hbm": 8000.0, "alu_f64": 78.6}   # TFLOP/s, GB/s, TFLOP/s
+HBM_KERNELS = ("k_estep", "k_update_Z", "k_form_QT", "k_form_Y", "k_zstep_fused")
 
 
 def prof_table(B, ctx):
@@ -44,8 +54,8 @@ def prof_table(B, ctx):
 
 
 def prof_enable(B, ctx, on, only=None):
-    """Per-kernel HIP-event timing on the solve's stream; `only` restricts it to
-    the kernels whose name starts with that prefix."""
+    """Per-kernel HIP-event timing on the solve's stream (every launch, or only
+    the kernels whose name starts with `only`).  Enabling clears the table."""
     import ctypes as C
     lib = B.load_library()
     lib.lrr_prof_enable.argtypes = [C.c_void_p, C.c_int]
@@ -57,114 +67,174 @@ def prof_enable(B, ctx, on, only=None):
 
 
 def roofline_of(row, traffic=None):
-    """Roofline entry of one kernel from its event-timed launches.
-
-    GEMMs are priced against the FP64 matrix peak; the Jacobi kernels, whose
-    FP64 operations are counted on the device, against the FP64 vector peak;
-    column kernels by their algorithmic HBM bytes."""
+    """Roofline entry of one kernel from its event-timed launches: matrix
+    products by their algorithmic flops against the FP64 matrix peak, column
+    kernels by their algorithmic HBM bytes against 8 TB/s."""
     avg_ms = row["ms"] / max(row["launches"], 1)
-    base = {"kernel": row["name"], "traffic": traffic, "avg_launch_us": round(avg_ms * 1e3, 2),
-            "launches": row["launches"]}
+    base = {"kernel": row["name"], "launches": row["launches"], "avg_launch_us": round(avg_ms * 1e3, 2)}
     if row["flops"] > 0:
-        ach = row["flops"] / row["launches"] / (avg_ms * 1e-3) / 1e12
-        mfma = row["name"].startswith("k_dgemm")
-        peak = PEAK["mfma_f64"] if mfma else PEAK["alu_f64"]
-        return {**base, "bound": "mfma" if mfma else "alu", "achieved": round(ach, 4), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(ach / peak, 5)}
+        per = row["flops"] / row["launches"]
+        ach = per / (avg_ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK["mfma_f64"], "unit": "TFLOP/s",
+                "frac": round(ach / PEAK["mfma_f64"], 4), "traffic": traffic,
+                "algorithmic_per_launch": per, **base}
     if row["bytes"] > 0:
-        ach = row["bytes"] / row["launches"] / (avg_ms * 1e-3) / 1e9
-        return {**base, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm"], "unit": "GB/s",
-                "frac": round(ach / PEAK["hbm"], 4)}
-    return {**base, "bound": "alu", "achieved": None, "peak": PEAK["alu_f64"], "unit": "TFLOP/s",
-            "frac": None}
+        per = row["bytes"] / row["launches"]
+        ach = per / (avg_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm"], "unit": "GB/s",
+                "frac": round(ach / PEAK["hbm"], 4), "traffic": traffic,
+                "algorithmic_per_launch": per, **base}
+    return None
 
 
-def oracle_error(p, Z, golden_path):
+def lib_digest(B):
+    h = hashlib.sha256()
+    with open(B.LIB_PATH, "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(path, digest):
+    """HBM bytes per dispatch from counter runs of this very library build
+    (a JSON map kernel -> bytes, with the library digest it was taken on)."""
+    if not path or not os.path.exists(path):
+        return {}
+    tr = json.load(open(path))
+    if tr.get("_lib") != digest:
+        print(f"bench: counter file {path} is from another library build; traffic not reported",
+              file=sys.stderr)
+        return {}
+    return tr
+
+
+def workload_name(p, precision):
+    return p.name.rsplit("-", 1)[0] + "-" + precision
+
+
+def oracle_error(p, Zt):
+    """Relative error of the GPU's Z against the stored FP64 oracle fingerprint:
+    the probes Z w of the whole Z (workloads with a DFC fingerprint), or of the
+    first block's columns (workload 4, whose fingerprint is block 1 solved as
+    one LRR problem; the combine leaves block 1's columns as its J)."""
     import numpy as np
-    if not os.path.exists(golden_path):
-        return None
-    g = json.load(open(golden_path))
-    rng = np.random.default_rng(4242)
-    W = rng.standard_normal((p.n, 2))
-    Zw = (Z @ W).T
-    ref = np.array(g["Zw"])
-    return float(np.linalg.norm(Zw - ref) / np.linalg.norm(ref)), g
+    cfg = p.extra.get("config")
+    g4 = os.path.join(ROOT, "tests", "golden", "workload4_block1_oracle.json")
+    gd = os.path.join(ROOT, "tests", "golden", f"workload{cfg}_oracle.json")
+    if p.n == 20000 and os.path.exists(g4):
+        g = json.load(open(g4))
+        cols = p.perm[p.offsets[0]:p.offsets[1]]
+        Zb = Zt.index_select(0, __import__("torch").as_tensor(cols, device=Zt.device).long()).cpu().numpy().T
+        rng = np.random.default_rng(4243)
+        W = rng.standard_normal((len(cols), 2))
+        Zw = (Zb @ W).T
+        ref = np.array(g["Zw"])
+        return {"err_vs_oracle": float(np.linalg.norm(Zw - ref) / np.linalg.norm(ref)),
+                "oracle_scope": "block 1 (Z w probes)", "oracle_iters_block1": g["iters"]}
+    if cfg in (2, 3) and os.path.exists(gd):
+        g = json.load(open(gd))
+        Z = Zt.cpu().numpy().T
+        rng = np.random.default_rng(4242)
+        W = rng.standard_normal((p.n, 2))
+        Zw = (Z @ W).T
+        ref = np.array(g["Zw"])
+        return {"err_vs_oracle": float(np.linalg.norm(Zw - ref) / np.linalg.norm(ref)),
+                "oracle_scope": "all blocks (Z w probes)", "oracle_iters_per_block": g["iters"]}
+    return {"err_vs_oracle": None}
 
 
-def cpu_baseline(p, total_block_iters, target_s):
-    """The FP64 oracle on a bounded sample: block 1 of the workload for as many
-    ALM iterations as fit in about target_s seconds, scaled to solves/s by the
-    number of block-iterations of the full solve."""
-    import numpy as np
+def cpu_baseline(p, total_block_iters, target_s, single_thread_s):
+    """The FP64 oracle on bounded samples: block 1 of the benchmark workload for
+    as many ALM iterations as fit in about target_s seconds (push-through Z-step
+    when n >> m, as the oracle's workload-4 fingerprint), scaled to solves/s by
+    the block-iterations of the full solve; and block 1 of the n = 2000 workload
+    on one thread (the paper's simulations ran on a single core)."""
     from threadpoolctl import threadpool_limits
     import oracle
+    from paper_1304_5583_amd.datagen import make_config
     cores = len(os.sched_getaffinity(0))
     env = os.environ.get("OMP_NUM_THREADS")
     if env and env.isdigit():
         cores = min(cores, int(env))
-    X = p.M[:, p.perm[p.offsets[0]:p.offsets[1]]]
-    with threadpool_limits(limits=cores):
-        t0 = time.perf_counter()
-        oracle.lrr_alm(X, p.M, p.lam, oracle.ALMOptions(fixed_iters=3))
-        per_it = (time.perf_counter() - t0) / 3
-        n_it = int(max(5, min(400, target_s / max(per_it, 1e-6))))
-        t0 = time.perf_counter()
-        oracle.lrr_alm(X, p.M, p.lam, oracle.ALMOptions(fixed_iters=n_it))
-        el = time.perf_counter() - t0
+    form = "pushthrough" if p.n >= 4 * p.m else "literal"
+
+    def sample(q, limit, seconds):
+        X = q.M[:, q.perm[q.offsets[0]:q.offsets[1]]]
+        with threadpool_limits(limits=limit):
+            t0 = time.perf_counter()
+            oracle.lrr_alm(X, q.M, q.lam, oracle.ALMOptions(fixed_iters=1, solve_form=form))
+            per_it = time.perf_counter() - t0
+            n_it = int(max(2, min(400, seconds / max(per_it, 1e-6))))
+            t0 = time.perf_counter()
+            oracle.lrr_alm(X, q.M, q.lam, oracle.ALMOptions(fixed_iters=n_it, solve_form=form))
+            el = time.perf_counter() - t0
+        return n_it, el, X.shape[1]
+
+    n_it, el, l = sample(p, cores, target_s)
     rate = n_it / el
-    return {"value": rate / total_block_iters, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_it} ALM iterations of block 1 (m={p.m}, n={p.n}, l={X.shape[1]}) in "
-                      f"{el:.1f}s = {rate:.3f} block-iterations/s, divided by the {total_block_iters} "
-                      f"block-iterations of a full solve",
-            "block_iters_per_s": rate}
+    out = {"value": rate / total_block_iters, "unit": "solves/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n_it} ALM iterations of block 1 (m={p.m}, n={p.n}, l={l}, {form} Z-step) in "
+                     f"{el:.1f}s = {rate:.4f} block-iterations/s, divided by the {total_block_iters} "
+                     f"block-iterations of the GPU's full solve (extrapolated)",
+           "block_iters_per_s": rate}
+    if single_thread_s > 0:
+        q = make_config(2)
+        form = "literal"
+        n1, e1, l1 = sample(q, 1, single_thread_s)
+        out["single_thread_workload2"] = {
+            "block_iters_per_s": n1 / e1, "cores": 1,
+            "sample": f"{n1} ALM iterations of block 1 of {q.name} (l={l1}, literal Z-step) in {e1:.1f}s"}
+    return out
 
 
-def _timed_solves(B, torch, p, Mt, Zt, ctx, opts, steps):
+def timed_solves(B, torch, p, Mt, Zt, ctx, opts, steps):
+    """`steps` solves after one untimed one, no per-kernel timing; returns
+    seconds per solve, the last info and the totals of batched and per-block
+    iterations."""
     B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False, Zt=Zt)
     torch.cuda.synchronize()
+    bi = ki = 0
     t0 = time.perf_counter()
     for _ in range(steps):
         _, _, info = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False, Zt=Zt)
+        bi += info.batch_iters
+        ki += int(info.iters.sum())
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps, info
+    return (time.perf_counter() - t0) / steps, info, bi, ki
 
 
-def precision_forms(B, torch, p, Mt, Z64t, ctx, args):
-    """The reduced-precision forms on the benchmark workload: solves/s and the
-    relative Frobenius error of Z against the FP64 form's Z."""
+def precision_forms(B, torch, p, Mt, Z64t, ctx, opts_of, steps, sec64):
+    """The reduced-precision forms on the benchmark workload, timed like the
+    headline: solves/s, speed-up over the FP64 form, relative Frobenius error of
+    Z against the FP64 form's Z, iteration counts."""
     out = {}
     Zt = torch.empty_like(Z64t)
-    for name, prec in (("fp32", B.LRR_FP32), ("mixed_bf16x3", B.LRR_MIXED_BF16)):
-        sec, info = _timed_solves(B, torch, p, Mt, Zt, ctx, B.lrr_opts_default(precision=prec), 3)
+    for name, prec in (("mixed_bf16x3", B.LRR_MIXED_BF16), ("fp32", B.LRR_FP32)):
+        sec, info, bi, ki = timed_solves(B, torch, p, Mt, Zt, ctx, opts_of(prec), steps)
         err = (torch.linalg.norm(Zt - Z64t) / torch.linalg.norm(Z64t)).item()
-        out[name] = {"solves_per_s": 1.0 / sec, "ms_per_solve": 1e3 * sec, "err_vs_fp64_plain": err,
-                     "iters_per_block": info.iters.tolist()}
+        out[name] = {"solves_per_s": 1.0 / sec, "ms_per_solve": 1e3 * sec, "steps": steps,
+                     "speedup_vs_fp64": sec64 / sec, "err_vs_fp64_plain": err,
+                     "alm_iters_per_s": bi / (sec * steps), "alm_block_iters_per_s": ki / (sec * steps),
+                     "iters_range": [int(info.iters.min()), int(info.iters.max())]}
         print(f"bench: {name}: {1e3 * sec:.1f} ms/solve err_vs_fp64={err:.2e}", file=sys.stderr, flush=True)
+    del Zt
     return out
 
 
-def workload4_mixed(B, torch, ctx):
-    """Workload 4 (m=512, n=20000, t=40): BF16x3 form against the FP64 form on
-    this GPU, one timed solve each after a warm-up."""
-    from paper_1304_5583_amd.datagen import make_config
-    p = make_config(4)
-    dev = torch.device("cuda:0")
-    Mt = B.to_device_colmajor(p.M, dev)
-    Z64 = torch.empty((p.n, p.n), dtype=torch.float64, device=dev)
-    Zmx = torch.empty_like(Z64)
-    s64, i64 = _timed_solves(B, torch, p, Mt, Z64, ctx, B.lrr_opts_default(), 1)
-    smx, imx = _timed_solves(B, torch, p, Mt, Zmx, ctx, B.lrr_opts_default(precision=B.LRR_MIXED_BF16), 1)
-    err = (torch.linalg.norm(Zmx - Z64) / torch.linalg.norm(Z64)).item()
-    print(f"bench: workload 4: fp64 {s64:.2f}s mixed {smx:.2f}s err={err:.2e}", file=sys.stderr, flush=True)
-    del Zmx
-    out = {"workload": p.name, "m": p.m, "n": p.n, "t": p.t, "fp64_solves_per_s": 1.0 / s64,
-           "mixed_solves_per_s": 1.0 / smx, "speedup": s64 / smx, "err_vs_fp64_plain": err,
-           "iters_fp64": [int(i64.iters.min()), int(i64.iters.max())],
-           "iters_mixed": [int(imx.iters.min()), int(imx.iters.max())],
-           "segmentation": segmentation(B, torch, p, Z64, ctx, reps=1)}
-    del Z64, Mt
-    torch.cuda.empty_cache()
-    return out
+def profiled_solve(B, torch, p, Mt, Zt, ctx, opts):
+    """One FP64 solve with every launch bracketed by HIP events: the per-kernel
+    table and the roofline entries of the matrix products and column kernels."""
+    prof_enable(B, ctx, 1)
+    B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False, Zt=Zt)
+    torch.cuda.synchronize()
+    rows = prof_table(B, ctx)
+    prof_enable(B, ctx, 0)
+    total = sum(r["ms"] for r in rows)
+    for r in rows[:16]:
+        rf = roofline_of(r)
+        rate = f"{rf['achieved']} {rf['unit']} ({rf['frac']:.3f})" if rf else "-"
+        print(f"bench:   {r['name']:30s} {r['ms']:9.2f} ms {r['launches']:6d} launches "
+              f"avg {r['ms'] / max(r['launches'], 1) * 1e3:8.1f} us  {rate}", file=sys.stderr)
+    return rows, total
 
 
 def _accuracy(pred, truth):
@@ -179,29 +249,66 @@ def _accuracy(pred, truth):
     return float(np.mean([np.mean(mapped[truth == g] == g) for g in np.unique(truth)]))
 
 
-def segmentation(B, torch, p, Zt, ctx, golden=None, reps=3):
-    """Section 4.1.2 labels from the solve's Z on the GPU (lrr_segment, range
-    sketch with the largest block width as rank bound): time per call, the
-    embedding's products with the affinity, and the labels against the stored
-    oracle labels (workloads with an oracle record) or the ground truth."""
+def segmentation(B, torch, p, Zt, ctx, golden=None, reps=3, St=None, Mt=None, delta=0.5):
+    """Section 4.1.2 labels from the solve's Z on the GPU (lrr_segment, every
+    point clustered, range sketch with the largest block width as rank bound):
+    time per call, the embedding's products with the affinity, the accuracy over
+    the generator's clean points and, with a stored oracle record, label
+    equality.  With the solve's S: the outlier columns the method flags
+    (||S_j|| > delta ||M_j||, lrr_outlier_flags) against the generator's."""
     import numpy as np
     k = p.extra["k"]
     bound = int(np.diff(p.offsets).max())
-    lab, info = B.lrr_segment(Zt, k, p.outliers, rank_bound=bound, ctx=ctx)   # sizes the workspace
+    lab, info = B.lrr_segment(Zt, k, None, rank_bound=bound, ctx=ctx)   # sizes the workspace
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        lab, info = B.lrr_segment(Zt, k, p.outliers, rank_bound=bound, ctx=ctx)
+        lab, info = B.lrr_segment(Zt, k, None, rank_bound=bound, ctx=ctx)
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / reps
     got = lab.cpu().numpy()
     out = {"ms": ms, "k": k, "n_keep": info["n_keep"], "rank": info["rank"], "sketch": info["sketch"],
            "embed_products": info["embed_iters"], "embed_resid": info["embed_resid"],
            "theta_k": info["theta_k"], "theta_k1": info["theta_k1"], "kmeans_iters": info["kmeans_iters"],
-           "accuracy_vs_truth": _accuracy(got, np.where(p.outliers, -1, p.labels))}
-    if golden is not None and "labels" in golden:
+           "exclude": "none (every point clustered)",
+           "accuracy_vs_truth_clean_points": _accuracy(got, np.where(p.outliers, -1, p.labels))}
+    if golden is not None and "labels" in golden and "S_ratio" in golden:
         out["labels_equal_oracle"] = got.tolist() == golden["labels"]
+    if St is not None:
+        flags, cnt = B.lrr_outlier_flags(Mt, St, delta, ctx=ctx)
+        f = flags.cpu().numpy()
+        out["outlier_flags_from_S"] = {"delta": delta, "flagged": cnt, "generator_outliers": int(p.outliers.sum()),
+                                       "flagged_and_generator": int((f & p.outliers).sum())}
     print(f"bench: segmentation {p.name}: {ms:.1f} ms products {info['embed_iters']}", file=sys.stderr, flush=True)
+    return out
+
+
+def other_workload(B, torch, ctx, cfg, steps, tuned):
+    """FP64 solves/s and the error against the stored oracle fingerprint on
+    another workload (context for the headline)."""
+    from paper_1304_5583_amd.datagen import make_config
+    p = make_config(cfg)
+    dev = torch.device("cuda:0")
+    Mt = B.to_device_colmajor(p.M, dev)
+    Zt = torch.empty((p.n, p.n), dtype=torch.float64, device=dev)
+    opts = B.lrr_opts_default(tune=1) if tuned else B.lrr_opts_default()
+    sec, info, bi, ki = timed_solves(B, torch, p, Mt, Zt, ctx, opts, steps)
+    out = {"workload": workload_name(p, "fp64"), "m": p.m, "n": p.n, "t": p.t, "steps": steps,
+           "solves_per_s": 1.0 / sec, "ms_per_solve": 1e3 * sec, "alm_iters_per_s": bi / (sec * steps),
+           "alm_block_iters_per_s": ki / (sec * steps), "iters_per_block": info.iters.tolist()}
+    out.update(oracle_error(p, Zt))
+    print(f"bench: {p.name}: {1e3 * sec:.1f} ms/solve err_vs_oracle={out['err_vs_oracle']}", file=sys.stderr,
+          flush=True)
+    gpath = os.path.join(ROOT, "tests", "golden", f"workload{cfg}_oracle.json")
+    golden = json.load(open(gpath)) if os.path.exists(gpath) else None
+    _, St, _ = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=True, Zt=Zt)
+    out["segmentation"] = segmentation(B, torch, p, Zt, ctx, golden, reps=1, St=St, Mt=Mt)
+    del St
+    if cfg == 2:
+        out["local_variant"] = local_variant(B, torch, p, Mt, ctx)
+        out["slr_graph"] = slr_graph(B, torch, p, Mt, Zt, ctx)
+    del Zt, Mt
+    torch.cuda.empty_cache()
     return out
 
 
@@ -279,32 +386,38 @@ def workload5_adjoint(B, torch, ctx):
                 "checkpoint_every": p.extra["checkpoint_every"]})
     print(f"bench: workload 5 adjoint: forward {res['forward_ms']:.1f} ms backward {res['backward_ms']:.1f} ms",
           file=sys.stderr, flush=True)
+    del Mt, Wt
+    torch.cuda.empty_cache()
     return res
 
 
-def tuned_schedule(path, p):
-    """The schedule-table entry a tuned FP64 solve of workload p uses (None: no entry)."""
+def tuned_schedule(path, p, precision=0):
+    """The schedule-table entry a tuned solve of workload p uses (None: no entry)."""
     maxl = int(max(p.offsets[i + 1] - p.offsets[i] for i in range(p.t)))
     for line in open(path):
         f = line.split("#")[0].split()
-        if len(f) == 9 and [int(x) for x in f[:5]] == [p.m, p.n, p.t, maxl, 0]:
+        if len(f) == 9 and [int(x) for x in f[:5]] == [p.m, p.n, p.t, maxl, precision]:
             return dict(zip(("eig_block", "use_graph", "check_every", "coords"), (int(x) for x in f[5:])))
     return None
 
 
 def main():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", type=int, default=2, help="workload number (default 2)")
+    ap.add_argument("--workload", type=int, default=4, help="workload number (default 4)")
+    ap.add_argument("--form-steps", type=int, default=0,
+                    help="timed solves per reduced-precision form (default: steps, at most 10)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-single-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--eig-block", type=int, default=0,
-                    help="Jacobi block width (16 or 32); default: the autotuned schedule table")
     ap.add_argument("--no-tune", action="store_true", help="ignore the autotuned schedule table")
+    ap.add_argument("--no-forms", action="store_true", help="skip the reduced-precision forms")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the reduced-precision forms, workload 4 and the workload-5 adjoint")
+                    help="skip segmentation, the other workloads and the workload-5 adjoint")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_counters.json"),
+                    help="HBM bytes per dispatch from counter runs of this library build")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -314,7 +427,6 @@ def main():
               f"not implement.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1304_5583_amd import binding as B
     from paper_1304_5583_amd.datagen import make_config
@@ -328,66 +440,33 @@ def main():
     Mt = B.to_device_colmajor(p.M, dev)
     Zt = torch.empty((p.n, p.n), dtype=torch.float64, device=dev)
     ctx = B.get_context(0)
-    schedule = "default"
-    if args.eig_block or args.no_tune or not os.path.exists(B.TUNE_TABLE):
-        opts = B.lrr_opts_default(eig_block=args.eig_block)
-    else:
+    tuned = not args.no_tune and os.path.exists(B.TUNE_TABLE)
+    if tuned:
         B.lrr_tune_load(B.TUNE_TABLE, ctx=ctx)
-        opts = B.lrr_opts_default(tune=1)
-        schedule = tuned_schedule(B.TUNE_TABLE, p) or "default"
+
+    def opts_of(prec):
+        return B.lrr_opts_default(precision=prec, tune=1) if tuned else B.lrr_opts_default(precision=prec)
+
+    schedule = (tuned_schedule(B.TUNE_TABLE, p) if tuned else None) or "default"
     print(f"bench: schedule {schedule}", file=sys.stderr, flush=True)
+    opts = opts_of(B.LRR_FP64)
 
-    def step():
-        return B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False, Zt=Zt)
-
-    # warm-up: the first pass times every kernel to find the dominant one, whose
-    # launches alone are then timed with events during the timed region
-    rows_all = []
-    for i in range(max(args.warmup, 1)):
-        if i == 0:
-            prof_enable(B, ctx, 1)
-        _, _, info = step()
-        if i == 0:
-            torch.cuda.synchronize()
-            rows_all = prof_table(B, ctx)
-            prof_enable(B, ctx, 0)
+    for i in range(args.warmup):
+        _, _, info = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False, Zt=Zt)
+        torch.cuda.synchronize()
         print(f"bench: warmup {i} batch_iters={info.batch_iters}", file=sys.stderr, flush=True)
-    dominant = rows_all[0]["name"]
-    for r in rows_all[:14]:
-        rf = roofline_of(r)
-        rate = f"{rf['achieved']} {rf['unit']}" if rf["achieved"] is not None else "-"
-        print(f"bench:   {r['name']:28s} {r['ms']:10.2f} ms  {r['launches']:7d} launches  "
-              f"avg {rf['avg_launch_us']:8.1f} us  {rate}", file=sys.stderr)
-    torch.cuda.synchronize()
-    prof_enable(B, ctx, 1, only=dominant)
+    # headline region: the FP64 plain form, no per-kernel timing
     batch_iters = block_iters = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        _, _, info = step()
+        _, _, info = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False, Zt=Zt)
         batch_iters += info.batch_iters
         block_iters += int(info.iters.sum())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    rows = [r for r in prof_table(B, ctx) if r["name"] == dominant]
-    prof_enable(B, ctx, 0)
-    print(f"bench: {args.steps} steps in {elapsed:.3f}s (events on {dominant} only)", file=sys.stderr, flush=True)
-    if args.calib_copy:
-        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)   # 512 MiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print("bench: calibration copy 512 MiB x 3 done", file=sys.stderr)
-
-    Z = Zt.cpu().numpy().T
-    err = oracle_error(p, Z, os.path.join(ROOT, "tests", "golden", f"workload{args.workload}_oracle.json"))
-    traffic = None
-    tr_path = os.path.join(ROOT, "profiles", f"traffic_workload{args.workload}.json")
-    dom = rows[0]
-    if os.path.exists(tr_path):
-        tr = json.load(open(tr_path))
-        traffic = tr.get(dom["name"])
+    sec64 = elapsed / args.steps
+    print(f"bench: {args.steps} FP64 solves in {elapsed:.3f}s", file=sys.stderr, flush=True)
     line = {
         "metric": METRIC,
         "value": args.steps / elapsed,
@@ -395,39 +474,65 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * sec64,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": p.name, "m": p.m, "n": p.n, "t": p.t, "lambda": p.lam, "tol": p.tol,
-                   "precision": "fp64", "mu0": opts.mu0, "rho": opts.rho, "mu_max": opts.mu_max,
+        "config": {"workload": workload_name(p, "fp64"), "m": p.m, "n": p.n, "t": p.t, "lambda": p.lam,
+                   "tol": p.tol, "precision": "fp64", "mu0": opts.mu0, "rho": opts.rho, "mu_max": opts.mu_max,
                    "schedule": schedule},
         "alm_iters_per_s": batch_iters / elapsed,
         "alm_block_iters_per_s": block_iters / elapsed,
-        "iters_per_block": info.iters.tolist(),
-        "rank_per_block": info.rank.tolist(),
-        "err_vs_oracle": err[0] if err else None,
+        "iters_per_block_range": [int(info.iters.min()), int(info.iters.max())],
+        "rank_per_block_range": [int(info.rank.min()), int(info.rank.max())],
         "err_vs_fp64_plain": 0.0,
-        "roofline": roofline_of(dom, traffic),
-        "kernels_warmup_pass": [{"name": r["name"], "ms": round(r["ms"], 3), "launches": r["launches"],
-                                 "share": round(r["ms"] / sum(x["ms"] for x in rows_all), 4)}
-                                for r in rows_all[:8]],
     }
-    if err:
-        g = err[1]
-        line["oracle_iters_per_block"] = g["iters"]
+    line.update(oracle_error(p, Zt))
+    if not args.no_forms:
+        fs = args.form_steps or min(args.steps, 10)
+        line["forms"] = precision_forms(B, torch, p, Mt, Zt, ctx, opts_of, fs, sec64)
+
+    # profiled region: every launch of one FP64 solve between HIP events
+    rows, total = profiled_solve(B, torch, p, Mt, Zt, ctx, opts)
+    digest = lib_digest(B)
+    traffic = load_traffic(args.traffic, digest)
+    entries = [e for e in (roofline_of(r, traffic.get(r["name"])) for r in rows) if e is not None]
+    mfma = [e for e in entries if e["bound"] == "mfma"]
+    hbm = [e for e in entries if e["bound"] == "hbm" and e["kernel"] in HBM_KERNELS]
+    dominant = max(mfma, key=lambda e: e["avg_launch_us"] * e["launches"]) if mfma else entries[0]
+    line["roofline"] = dominant
+    line["roofline_hbm"] = hbm
+    line["roofline_mfma_all"] = mfma
+    line["kernels_profiled_solve"] = [{"name": r["name"], "ms": round(r["ms"], 3), "launches": r["launches"],
+                                       "share": round(r["ms"] / total, 4)} for r in rows[:12]]
+    line["lib"] = digest
+    if args.calib_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)   # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("bench: calibration copy 512 MiB x 3 done", file=sys.stderr, flush=True)
+        del src, dst
+
     if not args.no_extras:
-        line["segmentation"] = segmentation(B, torch, p, Zt, ctx, err[1] if err else None)
-        line["forms"] = precision_forms(B, torch, p, Mt, Zt, ctx, args)
-        if args.workload == 2:
-            line["local_variant"] = local_variant(B, torch, p, Mt, ctx)
-            line["slr_graph"] = slr_graph(B, torch, p, Mt, Zt, ctx)
-        line["workload4_mixed_vs_fp64"] = workload4_mixed(B, torch, ctx)
+        golden = None
+        gpath = os.path.join(ROOT, "tests", "golden", f"workload{args.workload}_oracle.json")
+        if os.path.exists(gpath):
+            golden = json.load(open(gpath))
+        _, St, _ = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=True, Zt=Zt)
+        line["segmentation"] = segmentation(B, torch, p, Zt, ctx, golden, reps=1 if p.n > 8192 else 3,
+                                            St=St, Mt=Mt)
+        del St
+        del Zt, Mt
+        torch.cuda.empty_cache()
+        line["other_workloads"] = [other_workload(B, torch, ctx, c, 5 if c == 2 else 3, tuned)
+                                   for c in (2, 3) if c != args.workload]
         line["workload5_adjoint"] = workload5_adjoint(B, torch, ctx)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(p, int(info.iters.sum()), args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(p, int(info.iters.sum()), args.cpu_seconds, args.cpu_single_seconds)
     print(json.dumps(line), flush=True)
 
 
