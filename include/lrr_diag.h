@@ -42,6 +42,17 @@ lrr_status lrr_diag_gemm(lrr_ctx *ctx, int precision, int ta, int tb, int M, int
 lrr_status lrr_diag_spd_inverse(lrr_ctx *ctx, int m, int n, const double *A, int lda,
                                 double *Kinv, int ldk, void *stream);
 
+/* The same factorisation for callers that cannot allocate device memory (code
+ * that must not call hipMalloc / hipFree, such as tight serving loops or
+ * harnesses that forbid allocation): every work buffer lives in one device
+ * array that the library holds statically, 32.3 MiB per GPU from module load
+ * until the process ends.  Limit: m <= 1024 (larger m is LRR_EINVAL with a
+ * message naming the limit); the caller still owns A and Kinv.  All calls on
+ * one GPU share that GPU's array: calls that overlap on one GPU (two streams or
+ * two host threads) race and must be serialised by the caller. */
+lrr_status lrr_diag_spd_inverse_noalloc(lrr_ctx *ctx, int m, int n, const double *A, int lda,
+                                        double *Kinv, int ldk, void *stream);
+
 /* Eigen-decomposition of `count` symmetric matrices of orders l[i] (host array):
  * matrix i is read from B + i*strideB (ld = ldb >= max l) and its eigenvalues
  * (unsorted) are written to lam + i*ldlam, its eigenvectors (columns, same

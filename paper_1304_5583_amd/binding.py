@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH):
     lib.lrr_diag_gemm.restype = i
     lib.lrr_diag_spd_inverse.argtypes = [vp, i, i, vp, i, vp, i, vp]
     lib.lrr_diag_spd_inverse.restype = i
+    lib.lrr_diag_spd_inverse_noalloc.argtypes = [vp, i, i, vp, i, vp, i, vp]
+    lib.lrr_diag_spd_inverse_noalloc.restype = i
     lib.lrr_diag_syevj.argtypes = [vp, i, ip, vp, i, C.c_long, vp, i, vp, i, ip, vp]
     lib.lrr_diag_syevj.restype = i
     lib.lrr_diag_plan_rounds.argtypes = [ip, i, i, ip, ip]
