@@ -117,9 +117,19 @@ typedef struct {
     int save_for_backward;   /* record what dfc_lrr_backward needs                  */
     int checkpoint_every;    /* adjoint checkpoint spacing k (default 20)           */
     int eig_block;           /* Jacobi block width: 0 auto, 16 or 32                */
-    int use_graph;           /* 1 (default): replay each iteration's Z- and E-step  */
-                             /* launches from a captured HIP graph; 0: launch them  */
-                             /* one by one (always so while profiling is enabled)   */
+    int use_graph;           /* how an iteration is issued:                         */
+                             /*  0: the J-step's decisions (blocks to threshold,    */
+                             /*     refinement steps, Jacobi passes and rounds) on  */
+                             /*     the host, every launch one by one;              */
+                             /*  1 (default): as 0, the Z-/E-step launches replayed */
+                             /*     from a captured HIP graph;                      */
+                             /*  2: every decision on the device (the refinement    */
+                             /*     steps gated by per-block flags, the Jacobi pass */
+                             /*     loop in one persistent launch), one graph per   */
+                             /*     iteration, flags read back every check_every    */
+                             /*     iterations; 3: the launches of 2 one by one.    */
+                             /* All four give the same iterates.  Profiling always  */
+                             /* launches one by one.                                */
     int coords;              /* lrr_coords: coordinates of the n-row iterates       */
     int tune;                /* 1: take eig_block, use_graph, check_every, coords   */
                              /* from the ctx's schedule table entry for this shape  */

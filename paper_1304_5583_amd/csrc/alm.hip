@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_estep(double* __restrict__ E, const dou
         mx = fmax(mx, fabs(r1));
     }
     mx = block_max256(mx, red);
-    if (threadIdx.x == 0) atomic_max_nonneg(&bs.r1max[b], mx);
+    if (threadIdx.x == 0) bs.colr1[j] = mx;
 }
 
 // The same E-step with one wavefront per column and the column held in
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void k_estep_w(double* __restrict__ E, const d
         st2<VEC>(Y1 + o, i, m, yn[0], yn[1]);
     }
     mx = wave_max(mx);
-    if (lane == 0) atomic_max_nonneg(&bs.r1max[b], mx);
+    if (lane == 0) bs.colr1[j] = mx;
 }
 
 // k_update_Z with one wavefront per column (no workgroup barriers, 16-byte
@@ -390,12 +390,37 @@ __global__ __launch_bounds__(256) void k_update_Z_w(const double* __restrict__ Q
             if (R2r) st2<VEC>(R2r + o, i, n, r2[0], r2[1]);
         }
     }
+    // per-column results (one store per wave; the per-block maxima follow in
+    // k_block_colmax, without atomics on t addresses from every column)
     if (R2r) {
         ss = wave_sum(ss);
-        if (lane == 0) atomic_max_nonneg(&r2nrm[b], sqrt(ss));
+        if (lane == 0) bs.colr2[j] = sqrt(ss);
     } else {
         mx = wave_max(mx);
-        if (lane == 0) atomic_max_nonneg(&bs.r2max[b], mx);
+        if (lane == 0) bs.colr2[j] = mx;
+    }
+}
+
+// per block: the largest per-column value of its columns, as the bit pattern of
+// a non-negative double (one workgroup per block)
+__global__ __launch_bounds__(256) void k_block_colmax(const double* __restrict__ col,
+                                                       const double* __restrict__ col2,
+                                                       const int* __restrict__ boff, BlockState bs,
+                                                       unsigned long long* __restrict__ out,
+                                                       unsigned long long* __restrict__ out2) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    if (!bs.active[b]) return;
+    double mx = 0.0, mx2 = 0.0;
+    for (int c = boff[b] + threadIdx.x; c < boff[b + 1]; c += 256) {
+        mx = fmax(mx, col[c]);
+        if (col2) mx2 = fmax(mx2, col2[c]);
+    }
+    mx = block_max256(mx, red);
+    if (col2) mx2 = block_max256(mx2, red);
+    if (threadIdx.x == 0) {
+        out[b] = dbl_bits(mx);
+        if (col2) out2[b] = dbl_bits(mx2);
     }
 }
 
@@ -512,6 +537,10 @@ void launch_update_Z(const double* Q, const double* MtV, const double* J, double
     else
         hipLaunchKernelGGL((k_update_Z_w<false>), grid, dim3(256), 0, s, Q, MtV, J, Z, Y2, R2r, r2nrm, n, ld, ncols,
                            colblk, bs, it);
+}
+void launch_block_colmax(const double* col, const int* boff, int t, BlockState bs, unsigned long long* out,
+                         hipStream_t s, const double* col2, unsigned long long* out2) {
+    hipLaunchKernelGGL(k_block_colmax, dim3(t), dim3(256), 0, s, col, col2, boff, bs, out, out2);
 }
 void launch_r2_decide(BlockState bs, unsigned long long* r2nrm, int* expand, int t, double tol, double sqrt_n,
                       hipStream_t s) {

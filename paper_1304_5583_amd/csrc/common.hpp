@@ -56,6 +56,8 @@ struct BlockState {
     double* res2;       // ||Z - J||_max of the last iteration
     unsigned long long* r1max;  // running max (bit pattern of a non-negative double)
     unsigned long long* r2max;
+    double* colr1;      // per column: max |R1| of the column (E-step)
+    double* colr2;      // per column: max |R2|, or the coefficient residual's 2-norm
 };
 
 // Eigensolver descriptor of one symmetric matrix (padded size L, ld = L).
@@ -90,6 +92,23 @@ struct EigDesc {
     const int* sched;   // (may be null) explicit rounds: entry r * (L/bs/2) + P is the pair
                         // p | q << 16 of slot P in round r; every round pairs all L/bs blocks
 };
+
+// Control block of the persistent eigensolve (k_jacobi_solve): its grid-wide
+// barrier, an error flag (a barrier wait that ran out), the open-matrix counts of
+// two consecutive passes.  Zeroed by a kernel before each launch.
+struct JacCtl {
+    unsigned bar_count;
+    unsigned bar_gen;
+    int err;
+    int n_open[2];
+    int pad[3];
+};
+
+// Gershgorin flag of one index: its disc lies below both tau^2 and the block's
+// cut nu * scale (pairs of two such indices are never rotated)
+__device__ __forceinline__ int lo_flag(double disc, double tau, double nu, double scale) {
+    return disc < fmin(tau * tau * (1.0 - 1e-9), nu * scale) ? 1 : 0;
+}
 
 // Warm-started eigenvector refinement of one Gram matrix (see refsyev.hip).
 struct RefDesc {

@@ -19,6 +19,8 @@
 // 44-47 TFLOP/s).  Whole K-tiles of interior workgroups are read with 16-byte
 // vector loads (7-10 % faster than element loads); loads at the matrix edges
 // are bounds-tested and zero-fill, so any M, N, K is legal.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -135,120 +137,139 @@ __device__ __forceinline__ void store_tile(const Frag<BM>& f, double (*As)[BM + 
 // chunk commute), so the computed product is exactly symmetric; only the tiles
 // with P <= Q run, and an off-diagonal tile also writes its transpose.
 template <int BM, bool TA, bool TB, bool SYM = false>
-__global__ __launch_bounds__(256) void k_dgemm(const GemmDesc* __restrict__ descs, int tiles_m, int tiles_n) {
+__global__ __launch_bounds__(256) void k_dgemm(const GemmDesc* __restrict__ descs, int tiles_m, int tiles_n,
+                                               int total) {
     constexpr int WM = BM / 2, TX = WM / 16, BK = Frag<BM>::BK;
     static_assert(!SYM || (TA && !TB && BM == BN), "symmetric tiles need C = A^T A with square tiles");
     const int per = SYM ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
-    // tiles in launch order: row tiles fastest, then column tiles, then products
-    // (placing each product's tiles on one XCD's L2 measured 3-5% slower)
-    const int tile = blockIdx.x;
-    const int z = tile / per, tin = tile - z * per;
-    const GemmDesc d = descs[z];
-    if (d.active && d.active[0] == 0) return;
-    int tm_i, tn_i;
-    if (SYM) {
-        // upper-triangle index tin -> (P, Q), P <= Q, column by column
-        int q = (int)((sqrt(8.0 * tin + 1.0) - 1.0) * 0.5);
-        while (q * (q + 1) / 2 > tin) --q;
-        while ((q + 1) * (q + 2) / 2 <= tin) ++q;
-        tn_i = q;
-        tm_i = tin - q * (q + 1) / 2;
-    } else {
-        tm_i = tin % tiles_m;
-        tn_i = tin / tiles_m;
-    }
-    const int m0 = tm_i * BM, n0 = tn_i * BN;
-    if (m0 >= d.M || n0 >= d.N) return;
-
     // double-buffered operand tiles: As[buf][k][i] = op(A)(m0+i, k0+k)
     __shared__ double As[2][BK][BM + PAD];
     __shared__ double Bs[2][BK][BN + PAD];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wm = (wave >> 1) * WM, wn = (wave & 1) * 32;
-    const int lr = lane & 15, lk = lane >> 4;
-
-    dbl4 acc[TX][2];
-#pragma unroll
-    for (int x = 0; x < TX; ++x)
-        for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
-
-    const double* __restrict__ A = d.A;
-    const double* __restrict__ B = d.B;
-    const int M = d.M, N = d.N, K = d.K;
-    const long lda = d.lda, ldb = d.ldb;
-
-    // whole K-tiles of an interior workgroup with 16-byte aligned operands are
-    // read with unchecked vector loads; the rest (edges, a partial last K-tile,
-    // odd strides or offsets) with bounds-tested element loads
-    const bool vec = m0 + BM <= M && n0 + BN <= N && (lda & 1) == 0 && (ldb & 1) == 0 &&
-                     (reinterpret_cast<unsigned long>(A) & 15) == 0 &&
-                     (reinterpret_cast<unsigned long>(B) & 15) == 0;
-    const int kvec = vec ? (K / BK) * BK : 0;
-
-    Frag<BM> f;
-    if (BK <= kvec) load_tile_vec<BM, TA, TB>(f, A, lda, B, ldb, m0, n0, 0, tid);
-    else load_tile<BM, TA, TB>(f, A, lda, B, ldb, M, N, K, m0, n0, 0, tid);
-    store_tile<BM, TA, TB>(f, As[0], Bs[0], tid);
-    __syncthreads();
-    int cur = 0;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        const int kn = k0 + BK;
-        // the next tile's global loads are in flight while this one is multiplied
-        if (kn < K) {
-            if (kn + BK <= kvec) load_tile_vec<BM, TA, TB>(f, A, lda, B, ldb, m0, n0, kn, tid);
-            else load_tile<BM, TA, TB>(f, A, lda, B, ldb, M, N, K, m0, n0, kn, tid);
+    // The grid is at most a few workgroups per CU; each takes the tiles
+    // blockIdx.x, blockIdx.x + gridDim.x, ...  in launch order: row tiles
+    // fastest, then column tiles, then products (placing each product's tiles
+    // on one XCD's L2 measured 3-5% slower).  A tile of a product whose block
+    // is not active is skipped after one descriptor read, so a launch with no
+    // active block costs little more than its dispatch.
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const int z = tile / per, tin = tile - z * per;
+        const GemmDesc d = descs[z];
+        if (d.active && d.active[0] == 0) continue;
+        int tm_i, tn_i;
+        if (SYM) {
+            // upper-triangle index tin -> (P, Q), P <= Q, column by column
+            int q = (int)((sqrt(8.0 * tin + 1.0) - 1.0) * 0.5);
+            while (q * (q + 1) / 2 > tin) --q;
+            while ((q + 1) * (q + 2) / 2 <= tin) ++q;
+            tn_i = q;
+            tm_i = tin - q * (q + 1) / 2;
+        } else {
+            tm_i = tin % tiles_m;
+            tn_i = tin / tiles_m;
         }
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            const int kr = kk + lk;
-            double a[TX];
-#pragma unroll
-            for (int x = 0; x < TX; ++x) a[x] = As[cur][kr][wm + 16 * x + lr];
-            const double b0 = Bs[cur][kr][wn + lr], b1 = Bs[cur][kr][wn + 16 + lr];
-#pragma unroll
-            for (int x = 0; x < TX; ++x) {
-                acc[x][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b0, acc[x][0], 0, 0, 0);
-                acc[x][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b1, acc[x][1], 0, 0, 0);
-            }
-        }
-        if (kn < K) store_tile<BM, TA, TB>(f, As[cur ^ 1], Bs[cur ^ 1], tid);
+        const int m0 = tm_i * BM, n0 = tn_i * BN;
+        if (m0 >= d.M || n0 >= d.N) continue;
+
+        const int tid = threadIdx.x;
+        const int lane = tid & 63;
+        const int wave = tid >> 6;
+        const int wm = (wave >> 1) * WM, wn = (wave & 1) * 32;
+        const int lr = lane & 15, lk = lane >> 4;
+
+        dbl4 acc[TX][2];
+    #pragma unroll
+        for (int x = 0; x < TX; ++x)
+            for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+        const double* __restrict__ A = d.A;
+        const double* __restrict__ B = d.B;
+        const int M = d.M, N = d.N, K = d.K;
+        const long lda = d.lda, ldb = d.ldb;
+
+        // whole K-tiles of an interior workgroup with 16-byte aligned operands are
+        // read with unchecked vector loads; the rest (edges, a partial last K-tile,
+        // odd strides or offsets) with bounds-tested element loads
+        const bool vec = m0 + BM <= M && n0 + BN <= N && (lda & 1) == 0 && (ldb & 1) == 0 &&
+                         (reinterpret_cast<unsigned long>(A) & 15) == 0 &&
+                         (reinterpret_cast<unsigned long>(B) & 15) == 0;
+        const int kvec = vec ? (K / BK) * BK : 0;
+
+        Frag<BM> f;
+        if (BK <= kvec) load_tile_vec<BM, TA, TB>(f, A, lda, B, ldb, m0, n0, 0, tid);
+        else load_tile<BM, TA, TB>(f, A, lda, B, ldb, M, N, K, m0, n0, 0, tid);
+        store_tile<BM, TA, TB>(f, As[0], Bs[0], tid);
         __syncthreads();
-        cur ^= 1;
-    }
+        int cur = 0;
+        for (int k0 = 0; k0 < K; k0 += BK) {
+            const int kn = k0 + BK;
+            // the next tile's global loads are in flight while this one is multiplied
+            if (kn < K) {
+                if (kn + BK <= kvec) load_tile_vec<BM, TA, TB>(f, A, lda, B, ldb, m0, n0, kn, tid);
+                else load_tile<BM, TA, TB>(f, A, lda, B, ldb, M, N, K, m0, n0, kn, tid);
+            }
+    #pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                const int kr = kk + lk;
+                double a[TX];
+    #pragma unroll
+                for (int x = 0; x < TX; ++x) a[x] = As[cur][kr][wm + 16 * x + lr];
+                const double b0 = Bs[cur][kr][wn + lr], b1 = Bs[cur][kr][wn + 16 + lr];
+    #pragma unroll
+                for (int x = 0; x < TX; ++x) {
+                    acc[x][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b0, acc[x][0], 0, 0, 0);
+                    acc[x][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b1, acc[x][1], 0, 0, 0);
+                }
+            }
+            if (kn < K) store_tile<BM, TA, TB>(f, As[cur ^ 1], Bs[cur ^ 1], tid);
+            __syncthreads();
+            cur ^= 1;
+        }
 
-    // accumulator layout of v_mfma_f64_16x16x4f64: register v of a lane holds
-    // row lane/16 + 4v, column lane%16 of the 16 x 16 tile
-    const double alpha = d.alpha, beta = d.beta;
-    const long ldc = d.ldc;
-#pragma unroll
-    for (int x = 0; x < TX; ++x) {
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-            const int gj = n0 + wn + y * 16 + lr;
-            if (gj >= N) continue;
-            const int cj = d.colmap ? d.colmap[gj] : gj;
-            double* __restrict__ Cc = d.C + (long)cj * ldc;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int gi = m0 + wm + x * 16 + lk + 4 * v;
-                if (gi < M) {
-                    double r = alpha * acc[x][y][v];
-                    if (beta != 0.0) r += beta * Cc[gi];
-                    Cc[gi] = r;
-                    if (SYM && tm_i != tn_i) {
-                        // the mirrored element (gj, gi); beta applies to it as well
-                        double* __restrict__ Cm = d.C + (long)gi * ldc;
-                        double rm = alpha * acc[x][y][v];
-                        if (beta != 0.0) rm += beta * Cm[gj];
-                        Cm[gj] = rm;
+        // accumulator layout of v_mfma_f64_16x16x4f64: register v of a lane holds
+        // row lane/16 + 4v, column lane%16 of the 16 x 16 tile
+        const double alpha = d.alpha, beta = d.beta;
+        const long ldc = d.ldc;
+    #pragma unroll
+        for (int x = 0; x < TX; ++x) {
+    #pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int gj = n0 + wn + y * 16 + lr;
+                if (gj >= N) continue;
+                const int cj = d.colmap ? d.colmap[gj] : gj;
+                double* __restrict__ Cc = d.C + (long)cj * ldc;
+    #pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int gi = m0 + wm + x * 16 + lk + 4 * v;
+                    if (gi < M) {
+                        double r = alpha * acc[x][y][v];
+                        if (beta != 0.0) r += beta * Cc[gi];
+                        Cc[gi] = r;
+                        if (SYM && tm_i != tn_i) {
+                            // the mirrored element (gj, gi); beta applies to it as well
+                            double* __restrict__ Cm = d.C + (long)gi * ldc;
+                            double rm = alpha * acc[x][y][v];
+                            if (beta != 0.0) rm += beta * Cm[gj];
+                            Cm[gj] = rm;
+                        }
                     }
                 }
             }
         }
+        // the next tile's first LDS stores wait for every wave of this one
+        __syncthreads();
     }
+}
+
+// workgroups of a GEMM launch: four per CU (the LDS of a 64-row tile allows four)
+int gemm_grid_cap() {
+    static int cap = 0;
+    if (cap == 0) {
+        int dev = 0, cus = 0;
+        LRR_HIP(hipGetDevice(&dev));
+        LRR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        cap = 4 * std::max(cus, 1);
+    }
+    return cap;
 }
 
 template <int BM>
@@ -256,12 +277,13 @@ void launch_bm(const GemmDesc* d_descs, int count, int maxM, int maxN, bool ta, 
     const int tm = (maxM + BM - 1) / BM, tn = (maxN + BN - 1) / BN;
     const long total = (long)tm * tn * count;
     if (total > 0x7fffffffL) throw HipError("GEMM grid too large");
-    dim3 grid((unsigned)total);
+    dim3 grid((unsigned)std::min<long>(total, gemm_grid_cap()));
     dim3 block(256);
-    if (!ta && !tb) hipLaunchKernelGGL((k_dgemm<BM, false, false>), grid, block, 0, stream, d_descs, tm, tn);
-    else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<BM, true, false>), grid, block, 0, stream, d_descs, tm, tn);
-    else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<BM, false, true>), grid, block, 0, stream, d_descs, tm, tn);
-    else hipLaunchKernelGGL((k_dgemm<BM, true, true>), grid, block, 0, stream, d_descs, tm, tn);
+    const int tt = (int)total;
+    if (!ta && !tb) hipLaunchKernelGGL((k_dgemm<BM, false, false>), grid, block, 0, stream, d_descs, tm, tn, tt);
+    else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<BM, true, false>), grid, block, 0, stream, d_descs, tm, tn, tt);
+    else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<BM, false, true>), grid, block, 0, stream, d_descs, tm, tn, tt);
+    else hipLaunchKernelGGL((k_dgemm<BM, true, true>), grid, block, 0, stream, d_descs, tm, tn, tt);
 }
 
 }  // namespace
@@ -270,6 +292,8 @@ bool dgemm_sym_tiles(int count, int maxN) {
     const long tm = (maxN + BN - 1) / BN;
     return tm * tm * count >= 512;
 }
+
+int gemm_grid(void) { return gemm_grid_cap(); }
 
 void launch_dgemm_sym(const GemmDesc* d_descs, int count, int maxN, hipStream_t stream, bool always) {
     if (count <= 0 || maxN <= 0) return;
@@ -282,8 +306,8 @@ void launch_dgemm_sym(const GemmDesc* d_descs, int count, int maxN, hipStream_t 
     }
     const long total = (long)tm * (tm + 1) / 2 * count;
     if (total > 0x7fffffffL) throw HipError("GEMM grid too large");
-    hipLaunchKernelGGL((k_dgemm<BN, true, false, true>), dim3((unsigned)total), dim3(256), 0, stream, d_descs, tm,
-                       tm);
+    hipLaunchKernelGGL((k_dgemm<BN, true, false, true>), dim3((unsigned)std::min<long>(total, gemm_grid_cap())),
+                       dim3(256), 0, stream, d_descs, tm, tm, (int)total);
 }
 
 void launch_dgemm(const GemmDesc* d_descs, int count, int maxM, int maxN, bool ta, bool tb,

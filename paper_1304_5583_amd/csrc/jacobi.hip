@@ -62,23 +62,38 @@ __device__ __forceinline__ void round_pair(const EigDesc& d, int nb, int round, 
     }
 }
 
+// LDS of one pair solve
+template <int BS>
+struct PairLds {
+    static constexpr int PB = 2 * BS, NP = BS;
+    double S[PB][PB + 1];
+    double R[PB][PB + 1];
+    double csc[NP], css[NP], cst[NP], csd[NP], cse[NP];
+    int any;
+    int LO[PB];
+};
+
+// Phase A for slot P of a round, by the NT threads of a workgroup: one cyclic
+// sweep of the 2BS x 2BS sub-matrix in LDS, the rotation written to R_P.
+// wslot spreads the operation counter over its slots.  Every thread returns
+// through the same path (the branches depend on LDS values only).
 template <int BS, int NT>
-__global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__ descs, int round, int sched) {
+__device__ void pair_solve(const EigDesc& d, int round, int P, int sched, int wslot, PairLds<BS>& sm) {
     constexpr int PB = 2 * BS;
     constexpr int NP = PB / 2;   // rotations per inner round
-    const EigDesc d = descs[blockIdx.y];
-    if (d.run[0] == 0 || d.st[0] != 0) return;
     const int nb = d.L / BS;
-    const int P = blockIdx.x;
-    if (P >= nb / 2 || round >= nb - 1) return;
     int p, q;
     round_pair(d, nb, round, P, sched, p, q);
 
-    __shared__ double S[PB][PB + 1];
-    __shared__ double R[PB][PB + 1];
-    __shared__ double csc[NP], css[NP], cst[NP], csd[NP], cse[NP];
-    __shared__ int any;
-    __shared__ int LO[PB];
+    auto& S = sm.S;
+    auto& R = sm.R;
+    auto& csc = sm.csc;
+    auto& css = sm.css;
+    auto& cst = sm.cst;
+    auto& csd = sm.csd;
+    auto& cse = sm.cse;
+    auto& any = sm.any;
+    auto& LO = sm.LO;
 
     const int tid = threadIdx.x;
     const long L = d.L;
@@ -182,7 +197,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
     if (tid == 0 && d.work) {
         // per round: NP angles (~30 operations), (NP^2 - NP) 2x2 updates (24), PB*NP rotations of R (6)
         const unsigned long long per_round = 30ull * NP + 24ull * (NP * NP - NP) + 6ull * PB * NP;
-        atomicAdd(&d.work[work_slot(0, blockIdx.x + blockIdx.y * gridDim.x)], per_round * (PB - 1));
+        atomicAdd(&d.work[work_slot(0, wslot)], per_round * (PB - 1));
     }
     double* Rg = d.R + (long)P * PB * PB;
     for (int idx = tid; idx < PB * PB; idx += NT) {
@@ -190,6 +205,17 @@ __global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__
         Rg[i + (long)j * PB] = R[i][j];
     }
     if (tid == 0) d.prot[P] = rotated;
+}
+
+template <int BS, int NT>
+__global__ __launch_bounds__(NT) void k_jacobi_pairs(const EigDesc* __restrict__ descs, int round, int sched) {
+    const EigDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0 || d.st[0] != 0) return;
+    const int nb = d.L / BS;
+    const int P = blockIdx.x;
+    if (P >= nb / 2 || round >= nb - 1) return;
+    __shared__ PairLds<BS> sm;
+    pair_solve<BS, NT>(d, round, P, sched, blockIdx.x + blockIdx.y * gridDim.x, sm);
 }
 
 // C (PB x PB, into LDS) = op(A) B for PB x PB operands in LDS (row stride PB + 1),
@@ -217,24 +243,37 @@ __device__ __forceinline__ void mm_lds(const double (*A)[PB + 1], const double (
     }
 }
 
-// phase B: tiles of B and row chunks of W
+// LDS of one phase-B item
 template <int BS>
-__global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict__ descs, int round, int sched) {
+struct ApplyLds {
+    static constexpr int PB = 2 * BS;
+    double X[PB][PB + 1];
+    double RP[PB][PB + 1];
+    double RQ[PB][PB + 1];
+    double T[PB][PB + 1];
+};
+
+constexpr int kApplyRows = 64;   // rows of W per phase-B item
+
+template <int BS>
+__device__ __forceinline__ int apply_items(int L) {
+    const int npair = L / BS / 2;
+    return npair * (npair + 1) / 2 + ((L + kApplyRows - 1) / kApplyRows) * npair;
+}
+
+// phase B, item `item` of a round (256 threads): a tile pair of B or a row
+// chunk of W
+template <int BS>
+__device__ void apply_item(const EigDesc& d, int round, int item, int sched, int wslot, ApplyLds<BS>& sm) {
     constexpr int PB = 2 * BS;
-    constexpr int RC = 64;   // rows of W per workgroup
-    const EigDesc d = descs[blockIdx.y];
-    if (d.run[0] == 0 || d.st[0] != 0) return;
+    constexpr int RC = kApplyRows;
     const int nb = d.L / BS;
     const int npair = nb / 2;
     const int ntri = npair * (npair + 1) / 2;
-    const int nchunks = (d.L + RC - 1) / RC;
-    const int item = blockIdx.x;
-    if (item >= ntri + nchunks * npair || round >= nb - 1) return;
-
-    __shared__ double X[PB][PB + 1];
-    __shared__ double RP[PB][PB + 1];
-    __shared__ double RQ[PB][PB + 1];
-    __shared__ double T[PB][PB + 1];
+    auto& X = sm.X;
+    auto& RP = sm.RP;
+    auto& RQ = sm.RQ;
+    auto& T = sm.T;
     const int tid = threadIdx.x;
     const long L = d.L;
 
@@ -245,7 +284,7 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
         const int Q = P + rem;
         if (!d.prot[P] && !d.prot[Q]) return;
         if (tid == 0 && d.work)   // two PB^3 products
-            atomicAdd(&d.work[work_slot(1, blockIdx.x + blockIdx.y * gridDim.x)], 4ull * PB * PB * PB);
+            atomicAdd(&d.work[work_slot(1, wslot)], 4ull * PB * PB * PB);
         int p1, q1, p2, q2;
         round_pair(d, nb, round, P, sched, p1, q1);
         round_pair(d, nb, round, Q, sched, p2, q2);
@@ -285,7 +324,7 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
         const int P = w % npair, chunk = w / npair;
         if (!d.prot[P]) return;
         if (tid == 0 && d.work)   // RC x PB times PB x PB
-            atomicAdd(&d.work[work_slot(1, blockIdx.x + blockIdx.y * gridDim.x)], 2ull * RC * PB * PB);
+            atomicAdd(&d.work[work_slot(1, wslot)], 2ull * RC * PB * PB);
         int p1, q1;
         round_pair(d, nb, round, P, sched, p1, q1);
         const double* RgP = d.R + (long)P * PB * PB;
@@ -311,6 +350,17 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
             __syncthreads();
         }
     }
+}
+
+template <int BS>
+__global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict__ descs, int round, int sched) {
+    const EigDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0 || d.st[0] != 0) return;
+    const int nb = d.L / BS;
+    const int item = blockIdx.x;
+    if (item >= apply_items<BS>(d.L) || round >= nb - 1) return;
+    __shared__ ApplyLds<BS> sm;
+    apply_item<BS>(d, round, item, sched, blockIdx.x + blockIdx.y * gridDim.x, sm);
 }
 
 // start of an eigensolve: reset flags, scale = max |diag|
@@ -389,6 +439,341 @@ __global__ void k_jacobi_eigvals(const EigDesc* __restrict__ descs) {
         d.lam[i] = (i < d.l) ? d.B[i + (long)i * d.L] : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Persistent eigensolve: the whole pass loop of the batched block-Jacobi method
+// in one launch.  Each pass: Gershgorin flags of every open matrix, the check of
+// every off-diagonal entry (marking the index-block pairs that still need a
+// rotation), closing converged matrices, and either a targeted pass (rounds of
+// perfect matchings covering the marked pairs, planned per matrix on the
+// device) or a full circle sweep; then the rounds, each a pair phase and an
+// apply phase.  Phases are separated by grid-wide barriers; every workgroup
+// takes the same decisions from the same global values, so the control flow
+// is uniform across the grid.  The results are those of the launch-per-phase
+// kernels above (same device functions, same order of operations).
+//
+// The grid must fit on the chip at once (the host sizes it from the occupancy
+// of this kernel).  Each barrier wait is bounded: a wait that runs out sets
+// JacCtl::err and every workgroup leaves at its next barrier, so the kernel
+// always ends; the host reports the flag as an error.
+// ---------------------------------------------------------------------------
+constexpr int kSolveThreads = 256;
+constexpr long kSpinLimit = 1L << 23;   // s_sleep(1) waits of one barrier (~0.4 s)
+constexpr int kChecksPerMatrix = 64;    // check items per matrix (as the check launch's grid)
+constexpr int kPlanMaxNb = 64;          // index blocks the device planner handles (bit masks)
+
+// all workgroups of the grid reach this point; false once any wait ran out
+__device__ bool grid_sync(JacCtl* ctl, unsigned nwg, unsigned& gen) {
+    __syncthreads();
+    __shared__ int bad;
+    if (threadIdx.x == 0) {
+        const unsigned g = gen;
+        const unsigned a = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == nwg - 1) {
+            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->bar_gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long spins = 0;
+            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kSpinLimit) {
+                    __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                // another workgroup's wait ran out: leave at once
+                if ((spins & 1023) == 0 && __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    break;
+            }
+        }
+        gen = g + 1;
+        bad = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return bad == 0;
+}
+
+// block b of item `item` given the prefix counts off[0..t]
+__device__ __forceinline__ int item_block(const int* __restrict__ off, int t, int item) {
+    int b = 0;
+    while (b + 1 < t && off[b + 1] <= item) ++b;
+    return b;
+}
+
+struct PlanLds {
+    unsigned short pp[kPlanMaxNb * (kPlanMaxNb - 1) / 2];
+    unsigned short qq[kPlanMaxNb * (kPlanMaxNb - 1) / 2];
+    unsigned char cov[kPlanMaxNb * (kPlanMaxNb - 1) / 2];
+    int cnt[kSolveThreads + 1];
+    unsigned long long inner;
+};
+
+// Targeted rounds of one matrix (the device form of the host planner
+// plan_rounds): the marked pairs p < q in p-major order are covered greedily,
+// round by round, each round completed to a perfect matching of the nb index
+// blocks (a block marked inside goes with a free partner, preferring another
+// such block; the rest pair up in order).  Returns the number of rounds, or -1
+// when more than cap would be needed (or nb exceeds the bit masks).
+__device__ int plan_device(const int* __restrict__ need, int nb, int cap, int* __restrict__ sched, PlanLds& pl) {
+    const int tid = threadIdx.x;
+    if (nb > kPlanMaxNb) return -1;
+    const int total = nb * nb;
+    const int per = (total + kSolveThreads - 1) / kSolveThreads;
+    const int i0 = tid * per, i1 = min(total, i0 + per);
+    if (tid == 0) pl.inner = 0ull;
+    __syncthreads();
+    int c = 0;
+    unsigned long long inner = 0ull;
+    for (int idx = i0; idx < i1; ++idx) {
+        const int p = idx / nb, q = idx % nb;
+        if (q < p || !need[idx]) continue;
+        if (p == q) inner |= 1ull << p;
+        else ++c;
+    }
+    pl.cnt[tid + 1] = c;
+    if (inner) atomicOr(&pl.inner, inner);
+    __syncthreads();
+    if (tid == 0) {
+        pl.cnt[0] = 0;
+        for (int k = 1; k <= kSolveThreads; ++k) pl.cnt[k] += pl.cnt[k - 1];
+    }
+    __syncthreads();
+    int w = pl.cnt[tid];
+    for (int idx = i0; idx < i1; ++idx) {
+        const int p = idx / nb, q = idx % nb;
+        if (q <= p || !need[idx]) continue;
+        pl.pp[w] = (unsigned short)p;
+        pl.qq[w] = (unsigned short)q;
+        pl.cov[w] = 0;
+        ++w;
+    }
+    __syncthreads();
+    const int npend = pl.cnt[kSolveThreads];
+    int rounds = 0;
+    if (tid == 0) {
+        unsigned long long in = pl.inner;
+        const unsigned long long all = (nb == 64) ? ~0ull : ((1ull << nb) - 1ull);
+        int left = npend;
+        if (npend > cap * (nb / 2)) {
+            rounds = -1;   // each round covers at most nb / 2 pairs
+        } else {
+            for (;;) {
+                if (left == 0 && in == 0ull) break;
+                if (rounds == cap) { rounds = -1; break; }
+                int* slot = sched + (long)rounds * (nb / 2);
+                int ns = 0;
+                unsigned long long used = 0ull;
+                for (int e = 0; e < npend; ++e) {
+                    if (pl.cov[e]) continue;
+                    const int p = pl.pp[e], q = pl.qq[e];
+                    const unsigned long long bits = (1ull << p) | (1ull << q);
+                    if (used & bits) continue;
+                    slot[ns++] = p | (q << 16);
+                    used |= bits;
+                    in &= ~bits;   // a pair solve also sweeps inside both blocks
+                    pl.cov[e] = 1;
+                    --left;
+                }
+                for (int p = 0; p < nb; ++p) {
+                    if (!((in >> p) & 1ull) || ((used >> p) & 1ull)) continue;
+                    const unsigned long long fr = all & ~used & ~(1ull << p);
+                    const unsigned long long fri = fr & in;
+                    const int q = fri ? __ffsll((long long)fri) - 1 : __ffsll((long long)fr) - 1;
+                    if (q < 0) break;   // cannot happen (nb is even, so a free partner exists)
+                    const int a = min(p, q), b = max(p, q);
+                    slot[ns++] = a | (b << 16);
+                    const unsigned long long bits = (1ull << p) | (1ull << q);
+                    used |= bits;
+                    in &= ~bits;
+                }
+                int u = -1;
+                for (int x = 0; x < nb; ++x) {
+                    if ((used >> x) & 1ull) continue;
+                    if (u < 0) u = x;
+                    else { slot[ns++] = u | (x << 16); u = -1; }
+                }
+                ++rounds;
+            }
+        }
+        pl.cnt[0] = rounds;
+    }
+    __syncthreads();
+    rounds = pl.cnt[0];
+    __syncthreads();
+    return rounds;
+}
+
+template <int BS>
+__global__ __launch_bounds__(kSolveThreads) void k_jacobi_solve(const EigDesc* __restrict__ descs, int t,
+                                                                 const int* __restrict__ offs, int* brounds,
+                                                                 JacCtl* ctl, const DevIter* it, int max_sweeps,
+                                                                 int max_targeted, int nb_max, int* need_all,
+                                                                 long need_total) {
+    __shared__ union {
+        PairLds<BS> p;
+        ApplyLds<BS> a;
+        PlanLds pl;
+    } sm;
+    __shared__ double red[4];
+    const unsigned G = gridDim.x;
+    const int wg = blockIdx.x, tid = threadIdx.x;
+    const int* off_rows = offs;
+    const int* off_pairs = offs + (t + 1);
+    const int* off_apply = offs + 2 * (t + 1);
+    unsigned gen = 0;
+
+    // start of the eigensolve: scale = max |diag|, flags cleared
+    for (int b = wg; b < t; b += G) {
+        const EigDesc d = descs[b];
+        if (d.run[0] == 0) continue;
+        double mx = 0.0;
+        for (int i = tid; i < d.l; i += kSolveThreads) mx = fmax(mx, fabs(d.B[i + (long)i * d.L]));
+        mx = wave_max(mx);
+        if ((tid & 63) == 0) red[tid >> 6] = mx;
+        __syncthreads();
+        if (tid == 0) {
+            d.scale[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+            d.st[0] = 0;
+            d.st[1] = 0;
+        }
+        __syncthreads();
+    }
+    if (!grid_sync(ctl, G, gen)) return;
+
+    const double tau = it->tau;
+    const int full_all = it->full;
+    int full = 0, targeted = 0, pass = 0;
+    bool counted = true;
+    for (;;) {
+        // Gershgorin flags of the open matrices; the marks are cleared
+        for (long k = (long)wg * kSolveThreads + tid; k < need_total; k += (long)G * kSolveThreads) need_all[k] = 0;
+        for (int item = wg; item < off_rows[t]; item += G) {
+            const int b = item_block(off_rows, t, item);
+            const EigDesc d = descs[b];
+            if (d.run[0] == 0 || d.st[0] != 0) continue;
+            const int i = item - off_rows[b];
+            const long L = d.L;
+            double rs = 0.0;   // column i of the symmetric matrix, contiguous
+            for (int j = tid; j < d.l; j += kSolveThreads)
+                if (j != i) rs += fabs(d.B[j + i * L]);
+            rs = wave_sum(rs);
+            if ((tid & 63) == 0) red[tid >> 6] = rs;
+            __syncthreads();
+            if (tid == 0) {
+                const double r = (red[0] + red[1]) + (red[2] + red[3]);
+                d.lo[i] = (i >= d.l) ? 1 : (full_all ? 0 : lo_flag(d.B[i + i * L] + r, tau, d.cut[0], d.scale[0]));
+                if (i == 0 && counted) d.passes[0] += 1;
+            }
+            __syncthreads();
+        }
+        if (!grid_sync(ctl, G, gen)) return;
+        // check: does any off-diagonal entry still need a rotation; mark its blocks
+        for (int item = wg; item < t * kChecksPerMatrix; item += G) {
+            const int b = item / kChecksPerMatrix, part = item % kChecksPerMatrix;
+            const EigDesc d = descs[b];
+            if (d.run[0] == 0 || d.st[0] != 0) continue;
+            const long L = d.L;
+            const long total = (long)d.l * d.l;
+            const double floor_abs = kAbsFloor * d.scale[0];
+            const int nb = d.L / BS;
+            int need = 0;
+            for (long idx = (long)part * kSolveThreads + tid; idx < total; idx += (long)kChecksPerMatrix * kSolveThreads) {
+                const int i = (int)(idx % d.l), j = (int)(idx / d.l);
+                if (i < j && !(d.lo[i] && d.lo[j])) {
+                    const double a = d.B[i + j * L];
+                    if (fabs(a) > fmax(kRelTol * sqrt(fabs(d.B[i + i * L] * d.B[j + j * L])), floor_abs)) {
+                        need = 1;
+                        d.need[(i / BS) * nb + j / BS] = 1;   // every writer stores 1
+                    }
+                }
+            }
+            if (__syncthreads_or(need) && tid == 0) atomicOr(&d.st[1], 1);
+        }
+        if (!grid_sync(ctl, G, gen)) return;
+        // close converged matrices, count the open ones, plan targeted rounds
+        for (int b = wg; b < t; b += G) {
+            const EigDesc d = descs[b];
+            const int nbb = d.L / BS;
+            int open = 0;
+            if (d.run[0] != 0 && d.st[0] == 0) {
+                open = d.st[1] != 0;
+                __syncthreads();
+                if (tid == 0) {
+                    if (!open) d.st[0] = 1;
+                    else atomicAdd(&ctl->n_open[pass & 1], 1);
+                    d.st[1] = 0;
+                }
+            }
+            int rb = 0;
+            if (open && targeted < max_targeted)
+                rb = plan_device(d.need, nbb, min((nb_max - 1) / 2, nbb - 1), const_cast<int*>(d.sched), sm.pl);
+            if (tid == 0) brounds[b] = rb;
+            __syncthreads();
+        }
+        if (!grid_sync(ctl, G, gen)) return;
+        // the same decision in every workgroup
+        const int nopen = __hip_atomic_load(&ctl->n_open[pass & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (wg == 0 && tid == 0) ctl->n_open[(pass + 1) & 1] = 0;
+        if (nopen == 0 || full == max_sweeps) break;
+        int rounds = targeted < max_targeted ? 0 : -1;
+        for (int b = 0; b < t && rounds >= 0; ++b) {
+            const int rb = brounds[b];
+            rounds = rb < 0 ? -1 : max(rounds, rb);
+        }
+        int sched;
+        if (rounds > 0) {
+            // matrices that need fewer rounds get circle rounds (any perfect matching is valid)
+            for (int b = wg; b < t; b += G) {
+                const EigDesc d = descs[b];
+                const int nbb = d.L / BS, np = nbb / 2;
+                const int r0 = brounds[b], r1 = min(rounds, nbb - 1);
+                int* sc = const_cast<int*>(d.sched);
+                for (int k = tid; k < (r1 - r0) * np; k += kSolveThreads) {
+                    const int r = r0 + k / np, P = k % np;
+                    int a0, b0;
+                    rr_pair(nbb, r, P, a0, b0);
+                    sc[r * np + P] = a0 | (b0 << 16);
+                }
+            }
+            if (!grid_sync(ctl, G, gen)) return;
+            ++targeted;
+            counted = false;
+            sched = 1;
+        } else {
+            rounds = nb_max - 1;
+            ++full;
+            counted = true;
+            sched = 0;
+        }
+        for (int r = 0; r < rounds; ++r) {
+            for (int item = wg; item < off_pairs[t]; item += G) {
+                const int b = item_block(off_pairs, t, item);
+                const EigDesc d = descs[b];
+                if (d.run[0] == 0 || d.st[0] != 0 || r >= d.L / BS - 1) continue;
+                pair_solve<BS, kSolveThreads>(d, r, item - off_pairs[b], sched, wg, sm.p);
+                __syncthreads();
+            }
+            if (!grid_sync(ctl, G, gen)) return;
+            for (int item = wg; item < off_apply[t]; item += G) {
+                const int b = item_block(off_apply, t, item);
+                const EigDesc d = descs[b];
+                if (d.run[0] == 0 || d.st[0] != 0 || r >= d.L / BS - 1) continue;
+                apply_item<BS>(d, r, item - off_apply[b], sched, wg, sm.a);
+                __syncthreads();
+            }
+            if (!grid_sync(ctl, G, gen)) return;
+        }
+        ++pass;
+    }
+}
+
+// before each launch; the error flag stays set once raised (the host clears it
+// at the start of a solve and reads it with the convergence flags)
+__global__ void k_jacobi_ctl_reset(JacCtl* ctl) {
+    ctl->bar_count = 0u;
+    ctl->bar_gen = 0u;
+    ctl->n_open[0] = 0;
+    ctl->n_open[1] = 0;
+}
+
 }  // namespace
 
 void launch_jacobi_init(const EigDesc* d_descs, int count, hipStream_t s) {
@@ -432,6 +817,39 @@ void launch_jacobi_check(const EigDesc* d_descs, int count, int maxL, int* d_ope
 
 void launch_jacobi_sweep_end(const EigDesc* d_descs, int count, int* d_any, hipStream_t s) {
     hipLaunchKernelGGL(k_jacobi_sweep_end, dim3((count + 63) / 64), dim3(64), 0, s, d_descs, count, d_any);
+}
+
+int jacobi_solve_grid(int bs) {
+    static int grid[2] = {0, 0};
+    int& g = grid[bs == 32 ? 1 : 0];
+    if (g == 0) {
+        int dev = 0, cus = 0, per = 0;
+        LRR_HIP(hipGetDevice(&dev));
+        LRR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        if (bs == 32)
+            LRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_jacobi_solve<32>, kSolveThreads, 0));
+        else
+            LRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_jacobi_solve<16>, kSolveThreads, 0));
+        if (per < 1) throw HipError("the persistent eigensolve does not fit on a CU");
+        // one workgroup per CU: a grid barrier costs each workgroup an L2
+        // write-back and invalidation at agent scope (measured 15-24 us with 256
+        // workgroups, 67-93 us with 1024)
+        g = std::max(cus, 1);
+    }
+    return g;
+}
+
+void launch_jacobi_solve(const EigDesc* d_descs, int count, const int* d_offs, int* d_brounds, JacCtl* ctl,
+                         const DevIter* it, int max_sweeps, int max_targeted, int nb_max, int bs, int* need_all,
+                         long need_total, hipStream_t s) {
+    hipLaunchKernelGGL(k_jacobi_ctl_reset, dim3(1), dim3(1), 0, s, ctl);
+    const dim3 grid(jacobi_solve_grid(bs));
+    if (bs == 32)
+        hipLaunchKernelGGL((k_jacobi_solve<32>), grid, dim3(kSolveThreads), 0, s, d_descs, count, d_offs, d_brounds,
+                           ctl, it, max_sweeps, max_targeted, nb_max, need_all, need_total);
+    else
+        hipLaunchKernelGGL((k_jacobi_solve<16>), grid, dim3(kSolveThreads), 0, s, d_descs, count, d_offs, d_brounds,
+                           ctl, it, max_sweeps, max_targeted, nb_max, need_all, need_total);
 }
 
 void launch_jacobi_eigvals(const EigDesc* d_descs, int count, hipStream_t s) {

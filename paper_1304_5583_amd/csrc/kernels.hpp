@@ -14,6 +14,8 @@ void launch_dgemm(const GemmDesc* d_descs, int count, int maxM, int maxN, bool t
 void launch_dgemm_sym(const GemmDesc* d_descs, int count, int maxN, hipStream_t stream, bool always = false);
 // whether launch_dgemm_sym runs the triangle of tiles for this batch
 bool dgemm_sym_tiles(int count, int maxN);
+// workgroups of a GEMM launch (looked up once; call before a stream capture)
+int gemm_grid(void);
 
 // xgemm.hip: the same contract with the arithmetic chosen by `mode` (GemmMode)
 void launch_xgemm(const GemmDesc* d_descs, int count, int maxM, int maxN, bool ta, bool tb, int mode,
@@ -38,13 +40,23 @@ void launch_jacobi_apply(const EigDesc* d_descs, int count, int maxL, int bs, in
 void launch_jacobi_check(const EigDesc* d_descs, int count, int maxL, int* d_open, hipStream_t s, int bs = 0);
 void launch_jacobi_sweep_end(const EigDesc* d_descs, int count, int* d_any, hipStream_t s);
 void launch_jacobi_eigvals(const EigDesc* d_descs, int count, hipStream_t s);
+// The whole block-Jacobi pass loop of `count` matrices (bs = 16 or 32) in
+// one persistent launch (after a reset of ctl): d_offs holds the prefix counts
+// of the matrices' rows, pair slots and apply items (3 x (count + 1)); d_brounds
+// count ints of scratch; need_all the marks of all matrices (need_total ints,
+// EigDesc::need points into it).  ctl->err != 0 afterwards: a barrier wait ran
+// out (the grid did not fit on the chip); the decompositions are then invalid.
+void launch_jacobi_solve(const EigDesc* d_descs, int count, const int* d_offs, int* d_brounds, JacCtl* ctl,
+                         const DevIter* it, int max_sweeps, int max_targeted, int nb_max, int bs, int* need_all,
+                         long need_total, hipStream_t s);
+int jacobi_solve_grid(int bs);
 
 // refsyev.hip
 void launch_ref_begin(const RefDesc* d, int count, int maxL, const int* svt_run, const int* warm, hipStream_t s);
 void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, hipStream_t s);
 void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s);
 void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s);
-void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, int* n_open, hipStream_t s);
+void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, hipStream_t s);
 void launch_ref_next(const RefDesc* d, int count, hipStream_t s);
 void launch_orth_guard(const RefDesc* d, int count, int maxL, const int* warm, hipStream_t s);
 // count_pass: count this pass of the sweep loop toward the block's switch rule
@@ -77,6 +89,10 @@ void launch_sub_cols(double* T, const double* A, int m, long ld, int ncols, cons
 void launch_update_Z(const double* Q, const double* MtV, const double* J, double* Z, double* Y2, double* R2r,
                      unsigned long long* r2nrm, int n, long ld, int ncols, const int* colblk, BlockState bs,
                      const DevIter* it, hipStream_t s);
+// out[b] = max over block b's columns of col (active blocks only); with col2,
+// out2[b] likewise in the same launch
+void launch_block_colmax(const double* col, const int* boff, int t, BlockState bs, unsigned long long* out,
+                         hipStream_t s, const double* col2 = nullptr, unsigned long long* out2 = nullptr);
 void launch_r2_decide(BlockState bs, unsigned long long* r2nrm, int* expand, int t, double tol, double sqrt_n,
                       hipStream_t s);
 void launch_colmax(const double* A, int n, long ld, int ncols, const int* colblk, const int* expand,

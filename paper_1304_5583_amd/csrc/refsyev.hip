@@ -37,6 +37,8 @@ namespace {
 
 constexpr double kLinCap = 0.1;
 constexpr long kStatGroups = 64;         // workgroups per matrix of the kernels that also reduce statistics
+constexpr long kStreamGroups = 128;      // workgroups per matrix of the element-wise passes (grid-stride)
+constexpr int kRowGroups = 64;           // workgroups per matrix of the row pass
 constexpr double kFirstStepCap = 0.1;    // largest correction accepted in the first step
 constexpr double kOrthTol = 1e-6;         // |I - X^T X| above this after one step: restart cold
 constexpr double kRelTol = 1e-15;
@@ -44,18 +46,10 @@ constexpr double kAbsFloor = 1e-14;
 constexpr double kLoCut = 1e-2;           // cut factor after the switch
 constexpr int kSwitchSweeps = 8;          // warm sweeps that trigger it
 
-// lo flag of one index from its Gershgorin disc: skipped only below both tau^2
-// and the block's cut
-__device__ __forceinline__ int lo_flag(double disc, double tau, double nu, double scale) {
-    return disc < fmin(tau * tau * (1.0 - 1e-9), nu * scale) ? 1 : 0;
-}
 
 // row pass: lambda_i, Gershgorin flag lo_i of S (padding: lambda 0, lo 1)
-__global__ __launch_bounds__(256) void k_ref_rows(const RefDesc* __restrict__ descs, const DevIter* it) {
-    const RefDesc d = descs[blockIdx.y];
-    if (d.run[0] == 0) return;
-    const int i = blockIdx.x;
-    if (i >= d.L) return;
+// one row of k_ref_rows: lambda_i and the Gershgorin flag lo_i of S
+__device__ void ref_row(const RefDesc& d, int i, const DevIter* it) {
     const long L = d.L;
     const double* S = d.SG;
     const double* G = d.SG + L * L;
@@ -79,6 +73,12 @@ __global__ __launch_bounds__(256) void k_ref_rows(const RefDesc* __restrict__ de
             d.lo[i] = 1;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_ref_rows(const RefDesc* __restrict__ descs, const DevIter* it) {
+    const RefDesc d = descs[blockIdx.y];
+    if (d.run[0] == 0) return;
+    for (int i = blockIdx.x; i < d.L; i += gridDim.x) ref_row(d, i, it);
 }
 
 // correction matrix E and per-matrix statistics
@@ -143,15 +143,13 @@ __global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs
 __global__ __launch_bounds__(256) void k_ref_add(const RefDesc* __restrict__ descs) {
     const RefDesc d = descs[blockIdx.y];
     if (d.run[0] == 0) return;
-    const long L = d.L;
-    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    if (idx < L * L) d.X[idx] += d.XE[idx];
+    const long n = (long)d.L * d.L;
+    for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < n; idx += (long)gridDim.x * 256) d.X[idx] += d.XE[idx];
 }
 
 // after E is formed and before it is applied: apply the step only while the
 // corrections do not grow; stop (without applying) otherwise
-__global__ void k_ref_update(const RefDesc* __restrict__ descs, int count, int step, int max_steps,
-                             int* n_open) {
+__global__ void k_ref_update(const RefDesc* __restrict__ descs, int count, int step, int max_steps) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= count) return;
     const RefDesc d = descs[b];
@@ -168,7 +166,6 @@ __global__ void k_ref_update(const RefDesc* __restrict__ descs, int count, int s
     d.unres[0] = 0;
     d.run[0] = apply ? 1 : 0;
     d.cont[0] = cont ? 1 : 0;
-    if (cont) atomicAdd(n_open, 1);
 }
 
 // after the step is applied: continue only where the update asked for it
@@ -275,8 +272,8 @@ __global__ __launch_bounds__(256) void k_orth_guard(const RefDesc* __restrict__ 
     const double dev = __longlong_as_double((long long)d.emax[0]);
     if (!(dev <= kOrthTol)) {
         const long L = d.L;
-        const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-        if (idx < L * L) d.X[idx] = warm[d.block] ? d.Xb[idx] : (((idx % L) == (idx / L)) ? 1.0 : 0.0);
+        for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < L * L; idx += (long)gridDim.x * 256)
+            d.X[idx] = warm[d.block] ? d.Xb[idx] : (((idx % L) == (idx / L)) ? 1.0 : 0.0);
     }
 }
 
@@ -284,9 +281,8 @@ __global__ __launch_bounds__(256) void k_orth_guard(const RefDesc* __restrict__ 
 __global__ __launch_bounds__(256) void k_ref_backup(const RefDesc* __restrict__ descs) {
     const RefDesc d = descs[blockIdx.y];
     if (d.run[0] == 0) return;
-    const long L = d.L;
-    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    if (idx < L * L) d.Xb[idx] = d.X[idx];
+    const long n = (long)d.L * d.L;
+    for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < n; idx += (long)gridDim.x * 256) d.Xb[idx] = d.X[idx];
 }
 
 __global__ void k_orth_reset(const RefDesc* __restrict__ descs, int count) {
@@ -318,7 +314,8 @@ void launch_orth_E(const RefDesc* d, int count, int maxL, hipStream_t s) {
 }
 void launch_orth_guard(const RefDesc* d, int count, int maxL, const int* warm, hipStream_t s) {
     const long n = (long)maxL * maxL;
-    hipLaunchKernelGGL(k_orth_guard, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d, warm);
+    hipLaunchKernelGGL(k_orth_guard, dim3((unsigned)std::min<long>((n + 255) / 256, kStreamGroups), count), dim3(256),
+                       0, s, d, warm);
 }
 void launch_ref_next(const RefDesc* d, int count, hipStream_t s) {
     hipLaunchKernelGGL(k_ref_next, dim3((count + 63) / 64), dim3(64), 0, s, d, count);
@@ -337,10 +334,11 @@ void launch_ref_begin(const RefDesc* d, int count, int maxL, const int* svt_run,
     const long n = (long)maxL * maxL;
     hipLaunchKernelGGL(k_ref_begin, dim3((count + 63) / 64), dim3(64), 0, s, d, count, svt_run, warm);
     hipLaunchKernelGGL(k_ref_scale, dim3(count), dim3(256), 0, s, d);
-    hipLaunchKernelGGL(k_ref_backup, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_ref_backup, dim3((unsigned)std::min<long>((n + 255) / 256, kStreamGroups), count), dim3(256),
+                       0, s, d);
 }
 void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, hipStream_t s) {
-    hipLaunchKernelGGL(k_ref_rows, dim3(maxL, count), dim3(256), 0, s, d, it);
+    hipLaunchKernelGGL(k_ref_rows, dim3(std::min(maxL, kRowGroups), count), dim3(256), 0, s, d, it);
 }
 void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s) {
     const long n = (long)maxL * maxL;
@@ -349,10 +347,11 @@ void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s) {
 }
 void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s) {
     const long n = (long)maxL * maxL;
-    hipLaunchKernelGGL(k_ref_add, dim3((unsigned)((n + 255) / 256), count), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_ref_add, dim3((unsigned)std::min<long>((n + 255) / 256, kStreamGroups), count), dim3(256), 0,
+                       s, d);
 }
-void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, int* n_open, hipStream_t s) {
-    hipLaunchKernelGGL(k_ref_update, dim3((count + 63) / 64), dim3(64), 0, s, d, count, step, max_steps, n_open);
+void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, hipStream_t s) {
+    hipLaunchKernelGGL(k_ref_update, dim3((count + 63) / 64), dim3(64), 0, s, d, count, step, max_steps);
 }
 void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hipStream_t s, bool count_pass) {
     hipLaunchKernelGGL(k_lo_rows, dim3(maxL, count), dim3(256), 0, s, d, it, (int)count_pass);

@@ -210,11 +210,14 @@ struct Buffers {
     std::vector<int*> prot;
     double *res1, *res2, *eigscale;
     unsigned long long *r1max, *r2max;
+    double *colr1, *colr2;       // per-column residual maxima (reduced per block without atomics)
     DevIter* it;
     std::vector<double*> Bm, Wm, Wg, Pm, Rm, lam, h, TX, SG, Eb, XE, Bq;
     std::vector<int*> lo;
     int *warm, *ref_run, *ref_unres, *ref_cont, *passes;
     int *need_all, *sched_all;   // targeted Jacobi rounds: check marks and round schedules, all blocks
+    int *jac_offs, *jac_brounds; // persistent eigensolve: per-block item prefixes, planned rounds
+    lrr::JacCtl* jac_ctl;
     double* locut;
     double *ref_eprev, *ref_scale;
     unsigned long long* ref_emax;
@@ -335,6 +338,8 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.eigscale = a.take<double>(t);
     b.r1max = a.take<unsigned long long>(t);
     b.r2max = a.take<unsigned long long>(t);
+    b.colr1 = a.take<double>(c);
+    b.colr2 = a.take<double>(c);
     b.it = a.take<DevIter>(1);
     for (auto* v : {&b.Bm, &b.Wm, &b.Wg, &b.Pm, &b.Rm, &b.lam, &b.h, &b.TX, &b.SG, &b.Eb, &b.XE, &b.Bq})
         v->assign(t, nullptr);
@@ -367,6 +372,9 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
         b.need_all = a.take<int>(nneed);
         b.sched_all = a.take<int>(nsched);
     }
+    b.jac_offs = a.take<int>(3 * (t + 1));
+    b.jac_brounds = a.take<int>(t);
+    b.jac_ctl = a.take<lrr::JacCtl>(1);
     b.warm = a.take<int>(t);
     b.passes = a.take<int>(t);
     b.locut = a.take<double>(t);
@@ -494,7 +502,7 @@ bool opts_valid(const lrr_opts& o, std::string& why) {
         why = "negative count"; return false;
     }
     if (o.eig_block != 0 && o.eig_block != 16 && o.eig_block != 32) { why = "eig_block must be 0, 16 or 32"; return false; }
-    if (o.use_graph != 0 && o.use_graph != 1) { why = "use_graph must be 0 or 1"; return false; }
+    if (o.use_graph < 0 || o.use_graph > 3) { why = "use_graph must be 0, 1, 2 or 3"; return false; }
     if (o.coords < 0 || o.coords > 2) { why = "unknown coords"; return false; }
     if (o.tune != 0 && o.tune != 1) { why = "tune must be 0 or 1"; return false; }
     if (o.solve_form == LRR_SOLVE_LITERAL) {
@@ -538,7 +546,7 @@ bool parse_tune(const char* path, std::vector<TuneEntry>& out, std::string& why)
         const int k = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %c", &e.m, &e.n, &e.t, &e.maxl, &e.precision,
                                   &e.eig_block, &e.use_graph, &e.check_every, &e.coords, &extra);
         if (k != 9 || e.m < 1 || e.n < 1 || e.t < 1 || e.maxl < 1 || e.precision < 0 || e.precision > 2 ||
-            (e.eig_block != 16 && e.eig_block != 32) || (e.use_graph != 0 && e.use_graph != 1) ||
+            (e.eig_block != 16 && e.eig_block != 32) || e.use_graph < 0 || e.use_graph > 3 ||
             e.check_every < 1 || e.coords < 0 || e.coords > 2) {
             why = std::string(path) + ": malformed entry on line " + std::to_string(no);
             ok = false;
@@ -853,6 +861,18 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
 
     up(b.g_KK, gKK.data(), sizeof(GemmDesc) * gKK.size());
     up(b.eig, eig.data(), sizeof(EigDesc) * t);
+    {
+        // item prefixes of the persistent eigensolve: rows, pair slots, apply items
+        std::vector<int> offs(3 * (t + 1), 0);
+        for (int bb = 0; bb < t; ++bb) {
+            const int L = p.L[bb], nbb = L / p.bs, np = nbb / 2;
+            offs[bb + 1] = offs[bb] + L;
+            offs[(t + 1) + bb + 1] = offs[(t + 1) + bb] + np;
+            offs[2 * (t + 1) + bb + 1] = offs[2 * (t + 1) + bb] + np * (np + 1) / 2 + ((L + 63) / 64) * np;
+        }
+        up(b.jac_offs, offs.data(), sizeof(int) * offs.size());
+        LRR_HIP(hipStreamSynchronize(s));   // the host table goes out of scope
+    }
     up(b.svt, svt.data(), sizeof(SvtDesc) * t);
     if (pr.perm) up(b.perm, pr.perm, sizeof(int) * c);
 
@@ -886,6 +906,7 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
     LRR_HIP(hipMemsetAsync(b.iters, 0, sizeof(int) * t, s));
     LRR_HIP(hipMemsetAsync(b.warm, 0, sizeof(int) * t, s));
     LRR_HIP(hipMemsetAsync(b.passes, 0, sizeof(int) * t, s));
+    LRR_HIP(hipMemsetAsync(b.jac_ctl, 0, sizeof(lrr::JacCtl), s));
     LRR_HIP(hipMemsetAsync(b.locut, 0, sizeof(double) * t, s));   // every eigenpair resolved at first
     LRR_HIP(hipMemsetAsync(b.rank, 0, sizeof(int) * t, s));
     LRR_HIP(hipMemsetAsync(b.r1max, 0, sizeof(unsigned long long) * t, s));
@@ -936,6 +957,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         need_off[bb + 1] = need_off[bb] + nbb * nbb;
         sched_off[bb + 1] = sched_off[bb] + (nbb - 1) * (nbb / 2);
     }
+    const size_t need_total = need_off[t];
     // pinned host area: the flags, the check marks (read back every pass) and the
     // round schedules (uploaded by targeted passes; rewritten only after the next
     // pass's synchronisation, when the previous upload has completed)
@@ -944,7 +966,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     int* hp = static_cast<int*>(ensure_pinned(ctx, flag_bytes + need_bytes + sizeof(int) * sched_off[t]));
     int* h_need = reinterpret_cast<int*>(reinterpret_cast<char*>(hp) + flag_bytes);
     int* h_sched = reinterpret_cast<int*>(reinterpret_cast<char*>(hp) + flag_bytes + need_bytes);
-    BlockState bst{b.active, b.svt_run, b.iters, b.rank, b.res1, b.res2, b.r1max, b.r2max};
+    BlockState bst{b.active, b.svt_run, b.iters, b.rank, b.res1, b.res2, b.r1max, b.r2max, b.colr1, b.colr2};
     const ProductModes& pm = p.pm;
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
     const int check_every = o.check_every > 0 ? o.check_every : 1;
@@ -967,7 +989,13 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     long long sweeps_total = 0;
     std::vector<int> block_rounds(t, 0);
     const double D = sizeof(double);
-    // one iteration's Z-step and E-step launches on stream st
+    // use_graph 0, 1: the J-step's decisions on the host (refinement steps, Jacobi
+    // passes); 2, 3: every decision on the device, one launch sequence per
+    // iteration (2: replayed from a graph, 3: launched one by one)
+    const bool device_loop = o.use_graph >= 2;
+    // device queries of the launch shapes, made before any stream capture
+    (void)lrr::gemm_grid();
+    if (device_loop) (void)lrr::jacobi_solve_grid(p.bs);
     auto zstep = [&](hipStream_t st, bool anchor, auto&& tm, double cact) {
         tm("k_form_QT", 0.0, ((pm.dMQ ? 5.0 : 3.0) * n + 4.0 * m) * cact * D, [&] {
             lrr::launch_form_QT(b.J, b.Y2, b.Q, pm.dMQ ? b.Dn : nullptr, n, n, b.X, b.E, b.Y1, b.T, m, m, c,
@@ -993,6 +1021,9 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             });
             tm("k_estep", 0.0, 5.0 * m * cact * D, [&] {
                 lrr::launch_estep(b.E, b.T, b.Y1, m, m, c, pr.lam, b.colblk, bst, b.it, st);
+            });
+            tm("k_block_colmax", 0.0, 0.0, [&] {
+                lrr::launch_block_colmax(b.colr1, b.boff, t, bst, b.r1max, st, b.colr2, b.r2max);
             });
             tm("k_check", 0.0, 0.0, [&] {
                 lrr::launch_check(bst, t, b.it, b.mu_sched, o.tol, fixed, b.n_active, st);
@@ -1026,6 +1057,9 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         });
         if (p.reduced) {
             // max-norm of R2 = Qm R2r: decided by the column 2-norm bounds, else expanded
+            tm("k_block_colmax", 0.0, 0.0, [&] {
+                lrr::launch_block_colmax(b.colr2, b.boff, t, bst, b.r2nrm, st);
+            });
             tm("k_r2_decide", 0.0, 0.0, [&] {
                 lrr::launch_r2_decide(bst, b.r2nrm, b.expand, t, o.tol, std::sqrt((double)nfull), st);
             });
@@ -1039,33 +1073,110 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         tm("k_estep", 0.0, 5.0 * m * cact * D, [&] {
             lrr::launch_estep(b.E, b.V, b.Y1, m, m, c, pr.lam, b.colblk, bst, b.it, st);
         });
+        tm("k_block_colmax", 0.0, 0.0, [&] {
+            if (p.reduced) lrr::launch_block_colmax(b.colr1, b.boff, t, bst, b.r1max, st);
+            else lrr::launch_block_colmax(b.colr1, b.boff, t, bst, b.r1max, st, b.colr2, b.r2max);
+        });
         tm("k_check", 0.0, 0.0, [&] {
             lrr::launch_check(bst, t, b.it, b.mu_sched, o.tol, fixed, b.n_active, st);
         });
     };
-    auto untimed = [](const char*, double, double, auto&& f) { f(); };
-    // graphs of the chain (plain and re-anchoring iterations); per-kernel
-    // timing needs the launches one by one, so profiling runs them eagerly
-    const bool chain_timed = prof.wants("k_form_QT") || prof.wants(lrr::xgemm_name(pm.MQ, false, false)) ||
-                             prof.wants("k_dgemm<false, false>") || prof.wants(lrr::xgemm_name(pm.MtV, true, false)) ||
-                             prof.wants("k_sub_cols") || prof.wants("k_update_Z") || prof.wants("k_r2_decide") ||
-                             prof.wants("k_colmax") || prof.wants("k_estep") || prof.wants("k_check");
-    const bool use_graph = o.use_graph != 0 && !chain_timed;
-    hipGraphExec_t g_plain = nullptr, g_anchor = nullptr;
-    hipStream_t cs = use_graph ? ctx_capture_stream(ctx) : nullptr;
-    struct GraphGuard {
-        hipGraphExec_t* a;
-        hipGraphExec_t* b;
-        ~GraphGuard() {
-            if (*a) (void)hipGraphExecDestroy(*a);
-            if (*b) (void)hipGraphExecDestroy(*b);
+    // One iteration's J-step: every decision is taken on the device from per-block
+    // flags (which blocks threshold, which refinement steps apply, how the
+    // eigensolve proceeds), so the launches are the same in every iteration.
+    // Only while profiling (`tm` times launches, prof.on) are the flags read back,
+    // to price each launch with the flops of the blocks it actually covers.
+    auto jstep = [&](hipStream_t st, auto&& tm, double cact) {
+        const bool price = prof.on;
+        auto read_flags = [&](int* dst, const int* src) {
+            if (!price) return;
+            LRR_HIP(hipMemcpyAsync(dst, src, sizeof(int) * t, hipMemcpyDeviceToHost, st));
+            sync();
+        };
+        // J-step input and the exact zero test
+        tm("k_form_Y", 0.0, 3.0 * n * cact * D, [&] {
+            lrr::launch_form_Y(b.Z, b.Y2, b.Y, b.colsq, n, n, c, b.colblk, b.active, b.it, st);
+        });
+        tm("k_block_fro", 0.0, cact * D, [&] { lrr::launch_block_fro(b.colsq, b.boff, t, bst, b.it, st); });
+        tm("k_zero_J", 0.0, 0.0, [&] { lrr::launch_zero_J(b.J, n, n, c, b.colblk, bst, st); });
+        read_flags(h_run, b.svt_run);
+        double f_gram = 0, f_P = 0, f_J = 0, f_L3 = 0;
+        for (int bb = 0; bb < t && price; ++bb) {
+            if (!h_run[bb]) continue;
+            const double l = p.boff[bb + 1] - p.boff[bb], L = p.L[bb];
+            f_gram += 2.0 * l * l * n;
+            f_P += 2.0 * l * l * L;
+            f_J += 2.0 * n * l * l;
+            f_L3 += 2.0 * L * L * L;
         }
-    } graph_guard{&g_plain, &g_anchor};
-    int k = k0;
-    for (k = k0; k < k1; ++k) {
-        if (hooks && hooks->begin) hooks->begin(k);
-        double cact = 0.0;   // columns of blocks still iterating
-        for (int bb = 0; bb < t; ++bb) if (h_act[bb]) cact += p.boff[bb + 1] - p.boff[bb];
+        // the symmetric kernel computes the tiles on and above the diagonal
+        const double hg = lrr::dgemm_sym_tiles(t, p.maxl) ? 0.5 : 1.0, hL = lrr::dgemm_sym_tiles(t, p.maxL) ? 0.5 : 1.0;
+        // Gram matrix of each block that thresholds (FP64 in every precision form)
+        tm("k_dgemm_sym", hg * f_gram, 0.0, [&] { lrr::launch_dgemm_sym(b.g_gram, t, p.maxl, st); });
+        // Newton refinement of the previous iteration's eigenvectors: a fixed
+        // number of steps, each applied only where the per-block flags allow
+        tm("k_ref_begin", 0.0, 0.0, [&] { lrr::launch_ref_begin(b.ref, t, p.maxL, b.svt_run, b.warm, st); });
+        for (int step = 0; step < kRefSteps; ++step) {
+            read_flags(h_ref, b.ref_run);
+            double fl = 0.0;
+            for (int bb = 0; bb < t && price; ++bb)
+                if (h_ref[bb]) fl += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
+            tm("k_dgemm<false, false>", fl, 0.0, [&] {
+                lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, st);
+            });
+            tm("k_dgemm<true, false>", fl, 0.0, [&] {
+                lrr::launch_dgemm(b.g_refSG, t, p.maxL, p.maxL, true, false, st);
+            });
+            tm("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, st); });
+            tm("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, st); });
+            tm("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, st); });
+            // decide before applying: only quadratically shrinking corrections
+            tm("k_ref_update", 0.0, 0.0, [&] { lrr::launch_ref_update(b.ref, t, step, kRefSteps, st); });
+            tm("k_dgemm<false, false>", fl, 0.0, [&] {
+                lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, st);
+            });
+            tm("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, st); });
+            tm("k_ref_next", 0.0, 0.0, [&] { lrr::launch_ref_next(b.ref, t, st); });
+        }
+        // two Newton-Schulz steps X <- X (I + (I - X^T X)/2); an estimate that is
+        // still far from orthonormal before the second step restarts from I
+        tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run(b.ref, t, b.svt_run, st); });
+        for (int ns = 0; ns < 2; ++ns) {
+            tm("k_dgemm_sym", hL * f_L3, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, st); });
+            tm("k_orth_E", 0.0, 0.0, [&] { lrr::launch_orth_E(b.ref, t, p.maxL, st); });
+            tm("k_dgemm<false, false>", f_L3, 0.0, [&] {
+                lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, st);
+            });
+            tm("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, st); });
+        }
+        tm("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, b.warm, st); });
+        tm("k_dgemm<false, false>", f_L3, 0.0, [&] {
+            lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, st);
+        });
+        tm("k_dgemm<true, false>", f_L3, 0.0, [&] {
+            lrr::launch_dgemm(b.g_Bq, t, p.maxL, p.maxL, true, false, st);
+        });
+        // block-Jacobi passes for the couplings the refinement left (the whole
+        // decomposition on a block's first thresholding step): one persistent launch
+        tm("k_jacobi_solve", 0.0, 0.0, [&] {
+            lrr::launch_jacobi_solve(b.eig, t, b.jac_offs, b.jac_brounds, b.jac_ctl, b.it, max_sweeps, kMaxTargeted,
+                                     p.maxL / p.bs, p.bs, b.need_all, (long)need_total, st);
+        });
+        tm("k_svt_weights", 0.0, 0.0, [&] { lrr::launch_svt_weights(b.svt, t, p.maxL, b.it, bst, st); });
+        tm("k_dgemm<false, true>", f_P, 0.0, [&] {
+            lrr::launch_dgemm(b.g_P, t, p.maxl, p.maxl, false, true, st);
+        });
+        tm("k_dgemm<false, false>", f_J, 0.0, [&] {
+            lrr::launch_dgemm(b.g_J, t, n, p.maxl, false, false, st);
+        });
+        tm("k_lo_mode", 0.0, 0.0, [&] { lrr::launch_lo_mode(b.svt_run, b.warm, b.passes, b.locut, t, st); });
+        tm("k_mark_warm", 0.0, 0.0, [&] { lrr::launch_mark_warm(b.svt_run, b.warm, t, st); });
+    };
+    auto untimed = [](const char*, double, double, auto&& f) { f(); };
+    // The J-step with its decisions on the host: which blocks threshold (one
+    // read-back), each refinement step (a read-back of the continue flags), each
+    // Jacobi pass (a read-back of the check marks, the round plan from the host).
+    auto host_jstep = [&](double cact) {
         // J-step input and the exact zero test
         timed("k_form_Y", 0.0, 3.0 * n * cact * D, [&] {
             lrr::launch_form_Y(b.Z, b.Y2, b.Y, b.colsq, n, n, c, b.colblk, b.active, b.it, s);
@@ -1110,10 +1221,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 timed("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, s); });
                 timed("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, s); });
                 // decide before applying: only quadratically shrinking corrections
-                LRR_HIP(hipMemsetAsync(b.eig_any, 0, sizeof(int), s));
-                timed("k_ref_update", 0.0, 0.0, [&] {
-                    lrr::launch_ref_update(b.ref, t, step, kRefSteps, b.eig_any, s);
-                });
+                timed("k_ref_update", 0.0, 0.0, [&] { lrr::launch_ref_update(b.ref, t, step, kRefSteps, s); });
                 timed("k_dgemm<false, false>", fl, 0.0, [&] {
                     lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, s);
                 });
@@ -1145,8 +1253,8 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             });
             // block-Jacobi sweeps for the couplings the refinement left (the
             // whole decomposition on a block's first thresholding step)
-            timed("k_jacobi_init", 0.0, 0.0, [&] { lrr::launch_jacobi_init(b.eig, t, s); });
             const int nb = p.maxL / p.bs;
+            timed("k_jacobi_init", 0.0, 0.0, [&] { lrr::launch_jacobi_init(b.eig, t, s); });
             // A pass checks every matrix, then runs a full sweep (nb - 1 circle
             // rounds) or, when the marked index-block pairs fit into at most
             // (nb - 1) / 2 perfect matchings for every block, only those rounds.
@@ -1216,14 +1324,42 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             timed("k_lo_mode", 0.0, 0.0, [&] { lrr::launch_lo_mode(b.svt_run, b.warm, b.passes, b.locut, t, s); });
             timed("k_mark_warm", 0.0, 0.0, [&] { lrr::launch_mark_warm(b.svt_run, b.warm, t, s); });
         }
-        // Z-step (push-through) and E-step: the same launches in every iteration
-        // (the penalty is read from DevIter), replayed from a captured graph
+    };
+    // use_graph 1: the Z-/E-step chain of an iteration is captured once per solve
+    // (plain and re-anchoring iterations) and replayed with hipGraphLaunch;
+    // use_graph 2: one whole iteration (J-step, Z-step, E-step, multipliers, stop
+    // test) is captured and replayed, and the host reads the device flags back
+    // only every check_every iterations.  Per-kernel timing launches one by one
+    // (the same launches).
+    const bool chain_timed = prof.wants("k_form_QT") || prof.wants(lrr::xgemm_name(pm.MQ, false, false)) ||
+                             prof.wants("k_dgemm<false, false>") || prof.wants(lrr::xgemm_name(pm.MtV, true, false)) ||
+                             prof.wants("k_sub_cols") || prof.wants("k_update_Z") || prof.wants("k_r2_decide") ||
+                             prof.wants("k_colmax") || prof.wants("k_estep") || prof.wants("k_check") ||
+                             prof.wants("k_block_colmax");
+    const bool use_graph = device_loop ? (o.use_graph == 2 && !prof.on) : (o.use_graph == 1 && !chain_timed);
+    hipGraphExec_t g_plain = nullptr, g_anchor = nullptr;
+    hipStream_t cs = use_graph ? ctx_capture_stream(ctx) : nullptr;
+    struct GraphGuard {
+        hipGraphExec_t* a;
+        hipGraphExec_t* b;
+        ~GraphGuard() {
+            if (*a) (void)hipGraphExecDestroy(*a);
+            if (*b) (void)hipGraphExecDestroy(*b);
+        }
+    } graph_guard{&g_plain, &g_anchor};
+    int k = k0;
+    for (k = k0; k < k1; ++k) {
+        if (hooks && hooks->begin) hooks->begin(k);
+        double cact = 0.0;   // columns of blocks still iterating (as of the last read-back)
+        for (int bb = 0; bb < t; ++bb) if (h_act[bb]) cact += p.boff[bb + 1] - p.boff[bb];
         const bool anchor = pm.dMQ && k > 0 && k % kAnchorEvery == 0;
+        if (!device_loop) host_jstep(cact);
         if (use_graph) {
             hipGraphExec_t& ex = anchor ? g_anchor : g_plain;
             if (!ex) {
                 hipGraph_t graph = nullptr;
                 LRR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                if (device_loop) jstep(cs, untimed, cact);
                 zstep(cs, anchor, untimed, cact);
                 LRR_HIP(hipStreamEndCapture(cs, &graph));
                 const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
@@ -1232,13 +1368,16 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             }
             LRR_HIP(hipGraphLaunch(ex, s));
         } else {
+            if (device_loop) jstep(s, timed, cact);
             zstep(s, anchor, timed, cact);
         }
         if (hooks && hooks->end) hooks->end(k);
         if (!fixed && ((k + 1) % check_every == 0 || k + 1 == p.n_iter)) {
             LRR_HIP(hipMemcpyAsync(h_misc + 1, b.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
             LRR_HIP(hipMemcpyAsync(h_act, b.active, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+            LRR_HIP(hipMemcpyAsync(h_misc + 2, &b.jac_ctl->err, sizeof(int), hipMemcpyDeviceToHost, s));
             sync();
+            if (h_misc[2] != 0) throw lrr::HipError("eigensolver: a grid barrier wait ran out");
             if (h_misc[1] == 0) { ++k; break; }
         }
     }
@@ -1254,6 +1393,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         for (auto& e : prof.entries) {
             if (e.name.rfind("k_jacobi_pairs" + sfx, 0) == 0) e.flops += (double)hw[0];
             if (e.name.rfind("k_jacobi_apply" + sfx, 0) == 0) e.flops += (double)hw[1];
+            if (e.name == "k_jacobi_solve") e.flops += (double)(hw[0] + hw[1]);
         }
     }
     res.batch_iters = k - k0;
@@ -1264,7 +1404,10 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     LRR_HIP(hipMemcpyAsync(res.res1.data(), b.res1, sizeof(double) * t, hipMemcpyDeviceToHost, s));
     LRR_HIP(hipMemcpyAsync(res.res2.data(), b.res2, sizeof(double) * t, hipMemcpyDeviceToHost, s));
     LRR_HIP(hipMemcpyAsync(act.data(), b.active, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+    int jac_err = 0;
+    LRR_HIP(hipMemcpyAsync(&jac_err, &b.jac_ctl->err, sizeof(int), hipMemcpyDeviceToHost, s));
     LRR_HIP(hipStreamSynchronize(s));
+    if (jac_err != 0) throw lrr::HipError("eigensolver: a grid barrier wait ran out");
     res.converged = true;
     if (!fixed)
         for (int bb = 0; bb < t; ++bb) if (act[bb]) res.converged = false;

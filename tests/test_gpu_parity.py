@@ -246,6 +246,52 @@ def test_graph_replay_matches_eager_launches(prec):
             assert bool((Zt == ref[0]).all()) and bool((St == ref[1]).all())
 
 
+@pytest.mark.parametrize("case", ["uneven", "wide-reduced", "full-32"])
+def test_device_loop_whole_iteration_graph(case):
+    """use_graph = 2: every decision of the J-step on the device (refinement steps
+    gated by per-block flags, the Jacobi pass loop in one persistent launch) and
+    one graph per iteration, the flags read back every check_every iterations.
+    Bitwise the same solve as its launches one by one (use_graph = 3) and as the
+    host-decided schedule (use_graph = 0, 1) -- the same device functions and
+    decisions -- over repeated solves on one context, and within 1e-6 of the
+    oracle."""
+    import oracle
+    from paper_1304_5583_amd import binding as B
+    from paper_1304_5583_amd.datagen import small_problem
+    need_gpu()
+    if case == "uneven":
+        p = small_problem(41, m=64, k=3, r=4, ns=40, n_replace=8, t=3, lam=0.3, uneven=(35, 45))
+        kw = {}
+    elif case == "wide-reduced":
+        p = small_problem(42, m=40, k=4, r=3, ns=40, n_replace=8, t=4, lam=0.3)
+        kw = dict(coords=B.LRR_COORDS_REDUCED, check_every=4)
+    else:
+        p = small_problem(43, m=80, k=3, r=4, ns=50, n_replace=10, t=2, lam=0.3)
+        kw = dict(eig_block=32, coords=B.LRR_COORDS_FULL)
+    say(f"[device loop {case}] m={p.m} n={p.n} t={p.t}")
+    Mt = B.to_device_colmajor(p.M)
+    ctx = B.Context(0)
+    out = {}
+    for g in (2, 3, 2, 1, 0, 2):
+        o = B.lrr_opts_default(use_graph=g, **kw)
+        Zt, St, info = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=o, ctx=ctx)
+        assert info.status == 0
+        out.setdefault(g, []).append((Zt.clone(), St.clone(), info.iters.tolist(), info.rank.tolist()))
+    ref = out[2][0]
+    for g, runs in out.items():
+        for Zt, St, it, rk in runs:
+            same = bool((Zt == ref[0]).all()) and bool((St == ref[1]).all())
+            say(f"  use_graph={g}: iters {it} rank {rk} bitwise equal {same} "
+                f"max diff {float((Zt - ref[0]).abs().max()):.2e}")
+            assert it == ref[2] and rk == ref[3]
+            assert same
+    with one_thread():
+        refo = oracle.dfc_lrr(p.M, p.lam, p.perm, p.offsets)
+    Z = B.from_device_colmajor(ref[0])
+    say(f"  vs oracle {rel(Z, refo.Z):.2e}")
+    assert rel(Z, refo.Z) <= TOL_Z
+
+
 @pytest.mark.parametrize("coords", [1, 2])
 @pytest.mark.parametrize("seed,m,t,uneven", [(51, 40, 3, (30, 44)), (52, 150, 4, None)])
 def test_full_and_reduced_coordinates_vs_oracle(coords, seed, m, t, uneven):
