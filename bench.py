@@ -202,6 +202,25 @@ def timed_solves(B, torch, p, Mt, Zt, ctx, opts, steps):
     return (time.perf_counter() - t0) / steps, info, bi, ki
 
 
+def device_loop(B, torch, p, Mt, Zref, ctx, schedule, steps):
+    """The same FP64 solve with every J-step decision on the device and one
+    graph per ALM iteration (use_graph = 2: one host synchronisation per
+    check_every iterations): solves/s and bitwise equality with the
+    host-driven solve's Z."""
+    sched = schedule if isinstance(schedule, dict) else {}
+    o = B.lrr_opts_default(use_graph=2, eig_block=sched.get("eig_block", 0),
+                           check_every=sched.get("check_every", 0), coords=sched.get("coords", 0))
+    Zt = torch.empty_like(Zref)
+    sec, info, bi, _ = timed_solves(B, torch, p, Mt, Zt, ctx, o, steps)
+    out = {"use_graph": 2, "check_every": int(o.check_every) or None, "steps": steps, "solves_per_s": 1.0 / sec,
+           "ms_per_solve": 1e3 * sec, "host_syncs": "one per check_every iterations",
+           "bitwise_equal_to_host_driven": bool(torch.equal(Zt, Zref))}
+    print(f"bench: device-driven J-step {p.name}: {1e3 * sec:.1f} ms/solve "
+          f"bitwise={out['bitwise_equal_to_host_driven']}", file=sys.stderr, flush=True)
+    del Zt
+    return out
+
+
 def precision_forms(B, torch, p, Mt, Z64t, ctx, opts_of, steps, sec64):
     """The reduced-precision forms on the benchmark workload, timed like the
     headline: solves/s, speed-up over the FP64 form, relative Frobenius error of
@@ -299,6 +318,8 @@ def other_workload(B, torch, ctx, cfg, steps, tuned):
     out.update(oracle_error(p, Zt))
     print(f"bench: {p.name}: {1e3 * sec:.1f} ms/solve err_vs_oracle={out['err_vs_oracle']}", file=sys.stderr,
           flush=True)
+    sched = tuned_schedule(B.TUNE_TABLE, p) if tuned else None
+    out["device_loop"] = device_loop(B, torch, p, Mt, Zt, ctx, sched, steps)
     gpath = os.path.join(ROOT, "tests", "golden", f"workload{cfg}_oracle.json")
     golden = json.load(open(gpath)) if os.path.exists(gpath) else None
     _, St, _ = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=True, Zt=Zt)
@@ -490,6 +511,8 @@ def main():
         "err_vs_fp64_plain": 0.0,
     }
     line.update(oracle_error(p, Zt))
+    if not args.no_extras:
+        line["device_loop"] = device_loop(B, torch, p, Mt, Zt, ctx, schedule, min(args.steps, 5))
     if not args.no_forms:
         fs = args.form_steps or min(args.steps, 10)
         line["forms"] = precision_forms(B, torch, p, Mt, Zt, ctx, opts_of, fs, sec64)

@@ -20,8 +20,8 @@
  *
  * Arguments
  *   ctx        a context from lrr_ctx_create
- *   m, n       M is m x n (DEVICE, double, column-major, ldm >= m); n <= 4096
- *   Z, ldz     DEVICE, double, n x n, column-major, ldz >= n
+ *   m, n       M is m x n (DEVICE, double, column-major, ldm >= m), n >= 2
+ *   Z, ldz     DEVICE, double, n x n, column-major, ldz >= n, finite entries
  *   nk         neighbours per sample, 1 <= nk <= min(n - 1, 1024)
  *   alpha      l1 weight, alpha > 0 (Section 4.2.2 uses 0.05)
  *   nbr        DEVICE int32, n x nk, sample-major: nbr[i * nk + a] (output)
@@ -33,8 +33,10 @@
  * The Lasso is solved by a finite active-set method (Lawson and Hanson's, with
  * the free columns kept independent); a sample whose support would exceed 64
  * neighbours, or that exceeds 10 n_k + 20 steps, stops there.  The work runs on
- * `stream` in the ctx's segmentation workspace (not the solver's); the call
- * returns when the outputs are complete.  LRR_NOT_CONVERGED: outputs written,
+ * `stream` in the ctx's segmentation workspace (not the solver's), which holds
+ * one n x n FP64 matrix (first the affinities, then M^T M: 3.2 GB at
+ * n = 20000); the call returns when the outputs are complete.  LRR_ENOMEM: the
+ * workspace could not be allocated.  LRR_NOT_CONVERGED: outputs written,
  * but some sample stopped early (info->not_converged).
  */
 #ifndef LRR_SLR_H

@@ -28,22 +28,30 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["slr_neighbors", "nn_lasso", "nn_lasso_objective", "slr_graph"]
+__all__ = ["slr_neighbors", "slr_neighbors_rows", "nn_lasso", "nn_lasso_objective", "slr_graph"]
 
 
 def slr_neighbors(Z: np.ndarray, nk: int) -> np.ndarray:
     """(n, nk) int64: row i lists the nk samples j != i with the largest
     |Z_ij| + |Z_ji|, by decreasing affinity, ties to the lower index."""
     Z = np.asarray(Z, dtype=np.float64)
+    return slr_neighbors_rows(Z, nk, range(Z.shape[0]))
+
+
+def slr_neighbors_rows(Z: np.ndarray, nk: int, rows) -> np.ndarray:
+    """The rows `rows` of slr_neighbors(Z, nk), each formed on its own (for
+    sampled checks at sizes where all n rows would take too long)."""
+    Z = np.asarray(Z, dtype=np.float64)
     n = Z.shape[0]
     if not 1 <= nk <= n - 1:
         raise ValueError("need 1 <= nk <= n - 1")
-    A = np.abs(Z) + np.abs(Z).T
-    out = np.empty((n, nk), dtype=np.int64)
-    for i in range(n):
+    rows = list(rows)
+    out = np.empty((len(rows), nk), dtype=np.int64)
+    for r, i in enumerate(rows):
+        a = np.abs(Z[i, :]) + np.abs(Z[:, i])        # a[j] = |Z_ij| + |Z_ji|
         cand = [j for j in range(n) if j != i]
-        cand.sort(key=lambda j: (-A[i, j], j))
-        out[i] = cand[:nk]
+        cand.sort(key=lambda j: (-a[j], j))
+        out[r] = cand[:nk]
     return out
 
 

@@ -1,11 +1,16 @@
 // SLR-graph construction (Section 4.2.2) on the GPU.
 //
-//   neighbours   one workgroup per sample: the affinities |Z_ij| + |Z_ji| of
-//                all j go to LDS with their indices and are ordered by a
-//                bitonic network (decreasing affinity, ties by index); the
-//                first n_k indices are the sample's basis;
-//   Gram         G = M^T M once (FP64 MFMA GEMM); D_i^T D_i and D_i^T x_i are
-//                gathers from G;
+//   affinity     W = |Z| + |Z|^T formed once (tiled transpose through LDS), so
+//                the affinities of sample i are the contiguous column i of W;
+//   neighbours   one workgroup per sample: a most-significant-digit radix
+//                selection over the IEEE bit patterns of column i (non-negative
+//                doubles order like their bit patterns) finds the n_k-th
+//                largest affinity T; the keys above T and the lowest-indexed
+//                keys equal to T (ties to the lower index) are gathered into
+//                LDS and ordered by a bitonic network (decreasing affinity,
+//                ties by index), which is the full ordering's first n_k;
+//   Gram         G = M^T M once (FP64 MFMA GEMM) into the buffer W occupied;
+//                D_i^T D_i and D_i^T x_i are gathers from G;
 //   Lasso        one workgroup per sample: the Lawson-Hanson active set on
 //                w^T G_i w - 2 b^T w + alpha 1^T w, w >= 0, with the free set
 //                P kept independent (a dependent entering column is pivoted
@@ -40,46 +45,151 @@ void ctx_prof_flush(lrr_ctx* ctx);
 
 namespace {
 
-constexpr int kMaxN = 4096;          // affinity row held in LDS for the ordering
 constexpr int kMaxNk = 1024;
 constexpr double kTol = 1e-12;       // optimality tolerance relative to the sample's scale
 constexpr double kDepTol = 1e-10;    // Cholesky pivot / max diagonal below which a column is dependent
 constexpr int kMaxP = 64;            // largest free set (Lasso support) held in LDS
+constexpr int kTile = 64;            // affinity transpose tile
 
-// neighbours of sample i = blockIdx.x: P = power of two >= n entries in LDS
-__global__ __launch_bounds__(256) void k_slr_select(const double* __restrict__ Z, long ldz, int n, int P, int nk,
-                                                    int* __restrict__ nbr) {
-    extern __shared__ char smem[];
-    double* key = reinterpret_cast<double*>(smem);
-    int* idx = reinterpret_cast<int*>(key + P);
-    const int i = blockIdx.x;
-    for (int j = threadIdx.x; j < P; j += 256) {
-        double v = -1.0;                       // below every affinity: padding and the sample itself
-        if (j < n && j != i) v = fabs(Z[j + (long)i * ldz]) + fabs(Z[i + (long)j * ldz]);
-        key[j] = v;
-        idx[j] = j;
+// W(r, c) = |Z(r, c)| + |Z(c, r)| (one FP64 addition, so W is exactly symmetric)
+__global__ __launch_bounds__(256) void k_slr_affinity(const double* __restrict__ Z, long ldz, int n,
+                                                      double* __restrict__ W, long ldw) {
+    __shared__ double t[kTile][kTile + 1];
+    const int r0 = blockIdx.x * kTile, c0 = blockIdx.y * kTile;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    // t[a][b] = |Z(c0 + a, r0 + b)|: the mirrored tile, read along its columns
+    for (int k = ty; k < kTile; k += 4) {
+        const int row = c0 + tx, col = r0 + k;
+        t[tx][k] = (row < n && col < n) ? fabs(Z[row + (long)col * ldz]) : 0.0;
     }
     __syncthreads();
-    // bitonic network; "before" = larger key, or equal key and smaller index
+    for (int k = ty; k < kTile; k += 4) {
+        const int row = r0 + tx, col = c0 + k;
+        if (row < n && col < n) W[row + (long)col * ldw] = fabs(Z[row + (long)col * ldz]) + t[k][tx];
+    }
+}
+
+// Digits of the radix selection, most significant first: five of 12 bits and
+// one of 4 (bits 63..52, 51..40, 39..28, 27..16, 15..4, 3..0).
+__device__ __forceinline__ int digit_shift(int pass) { return pass < 5 ? 52 - 12 * pass : 0; }
+__device__ __forceinline__ int digit_bins(int pass) { return pass < 5 ? 4096 : 16; }
+
+// Neighbours of sample i = blockIdx.x from column i of W (entries j != i).
+// Invariant of the selection: the keys whose masked bits exceed `prefix`
+// number nk - need, and at least `need` keys have masked bits equal to it.
+__global__ __launch_bounds__(256) void k_slr_select(const double* __restrict__ W, long ldw, int n, int nk,
+                                                    int* __restrict__ nbr) {
+    __shared__ unsigned hist[4096];
+    __shared__ double skey[kMaxNk];
+    __shared__ int sidx[kMaxNk];
+    __shared__ int s_bin, s_need, s_cnt, s_gt, s_ties;
+    __shared__ int wtot[4];
+    const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double* col = W + (long)i * ldw;
+    unsigned long long prefix = 0, mask = 0;
+    int need = nk;
+    bool exact = true;   // false once the prefix alone isolates exactly nk keys (every key >= prefix)
+    for (int pass = 0; pass < 6; ++pass) {
+        const int shift = digit_shift(pass), nb = digit_bins(pass);
+        for (int b = tid; b < nb; b += 256) hist[b] = 0u;
+        __syncthreads();
+        for (int j = tid; j < n; j += 256) {
+            if (j == i) continue;
+            const unsigned long long k = (unsigned long long)__double_as_longlong(col[j]);
+            if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & (unsigned long long)(nb - 1)], 1u);
+        }
+        __syncthreads();
+        if (wv == 0) {
+            // lane l owns bins [lo, hi) counted from the top; the first lane whose
+            // inclusive count reaches `need` walks its bins downwards
+            const int chunk = (nb + 63) / 64;
+            const int hi = nb - lane * chunk, lo = max(0, hi - chunk);
+            int sum = 0;
+            for (int b = lo; b < hi; ++b) sum += (int)hist[b];
+            int incl = sum;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += v;
+            }
+            const unsigned long long ball = __ballot(incl >= need);
+            const int L = __ffsll((long long)ball) - 1;
+            if (lane == L) {
+                int above = incl - sum, b = hi - 1;
+                for (; b > lo; --b) {
+                    if (above + (int)hist[b] >= need) break;
+                    above += (int)hist[b];
+                }
+                s_bin = b;
+                s_need = need - above;
+                s_cnt = (int)hist[b];
+            }
+        }
+        __syncthreads();
+        prefix |= (unsigned long long)s_bin << shift;
+        mask |= (unsigned long long)(nb - 1) << shift;
+        need = s_need;
+        const int cnt = s_cnt;
+        __syncthreads();
+        if (cnt == need) { exact = false; break; }
+    }
+    // gather: keys above the threshold in any order, then the `need` lowest
+    // indices whose key equals it (exact case), in index order
+    if (tid == 0) { s_gt = 0; s_ties = 0; }
+    __syncthreads();
+    const int n_gt = exact ? nk - need : nk;
+    for (int base = 0; base < n; base += 256) {
+        const int j = base + tid;
+        const bool in = j < n && j != i;
+        const double v = in ? col[j] : 0.0;
+        const unsigned long long k = (unsigned long long)__double_as_longlong(v);
+        const bool gt = in && (exact ? k > prefix : k >= prefix);
+        const bool tie = in && exact && k == prefix;
+        if (gt) {
+            const int slot = atomicAdd(&s_gt, 1);
+            skey[slot] = v;
+            sidx[slot] = j;
+        }
+        const unsigned long long bt = __ballot(tie);
+        if (lane == 0) wtot[wv] = (int)__popcll(bt);
+        __syncthreads();
+        int r = s_ties + (int)__popcll(bt & ((1ull << lane) - 1ull));
+        for (int q = 0; q < wv; ++q) r += wtot[q];
+        if (tie && r < need) {
+            skey[n_gt + r] = v;
+            sidx[n_gt + r] = j;
+        }
+        __syncthreads();
+        if (tid == 0) s_ties += wtot[0] + wtot[1] + wtot[2] + wtot[3];
+        __syncthreads();
+    }
+    // bitonic network over the nk gathered keys; "before" = larger key, or
+    // equal key and smaller index; padding (key -1, below every affinity) sinks
+    int P = 1;
+    while (P < nk) P <<= 1;
+    for (int a = nk + tid; a < P; a += 256) {
+        skey[a] = -1.0;
+        sidx[a] = INT_MAX;
+    }
+    __syncthreads();
     for (int k = 2; k <= P; k <<= 1) {
-        for (int s = k >> 1; s > 0; s >>= 1) {
-            for (int a = threadIdx.x; a < P; a += 256) {
-                const int b = a ^ s;
+        for (int st = k >> 1; st > 0; st >>= 1) {
+            for (int a = tid; a < P; a += 256) {
+                const int b = a ^ st;
                 if (b > a) {
-                    const bool up = (a & k) == 0;          // this run is ordered "before" first
-                    const double ka = key[a], kb = key[b];
-                    const int ia = idx[a], ib = idx[b];
+                    const bool up = (a & k) == 0;
+                    const double ka = skey[a], kb = skey[b];
+                    const int ia = sidx[a], ib = sidx[b];
                     const bool b_first = kb > ka || (kb == ka && ib < ia);
                     if (b_first == up) {
-                        key[a] = kb; key[b] = ka;
-                        idx[a] = ib; idx[b] = ia;
+                        skey[a] = kb; skey[b] = ka;
+                        sidx[a] = ib; sidx[b] = ia;
                     }
                 }
             }
             __syncthreads();
         }
     }
-    for (int a = threadIdx.x; a < nk; a += 256) nbr[(long)i * nk + a] = idx[a];
+    for (int a = tid; a < nk; a += 256) nbr[(long)i * nk + a] = sidx[a];
 }
 
 // deterministic max over the 256 threads
@@ -373,7 +483,6 @@ extern "C" lrr_status lrr_slr_graph(lrr_ctx* ctx, int m, int n, const void* Mv, 
     if (!ctx) return lrr::ctx_fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
     if (m < 1 || n < 2 || !Mv || !Zv || ldm < m || ldz < n || !nbr || !w)
         return lrr::ctx_fail(ctx, LRR_EINVAL, "bad M / Z / output arguments");
-    if (n > kMaxN) return lrr::ctx_fail(ctx, LRR_EINVAL, "n > 4096 is not supported by the neighbour ordering");
     if (nk < 1 || nk > n - 1 || nk > kMaxNk) return lrr::ctx_fail(ctx, LRR_EINVAL, "nk must lie in [1, min(n-1, 1024)]");
     if (!(alpha > 0.0) || !std::isfinite(alpha)) return lrr::ctx_fail(ctx, LRR_EINVAL, "alpha must be positive");
     const double* M = static_cast<const double*>(Mv);
@@ -382,9 +491,7 @@ extern "C" lrr_status lrr_slr_graph(lrr_ctx* ctx, int m, int n, const void* Mv, 
     try {
         if (hipSetDevice(lrr::ctx_device(ctx)) != hipSuccess)
             return lrr::ctx_fail(ctx, LRR_EDEVICE, "hipSetDevice failed");
-        int P = 1;
-        while (P < n) P <<= 1;
-        // workspace: G (n x n), per-sample step counts and violations, one descriptor
+        // workspace: W, then G (n x n, one buffer), per-sample step counts and violations, one descriptor
         const size_t offG = 0, offS = offG + sizeof(double) * (size_t)n * n;
         const size_t offK = (offS + sizeof(int) * (size_t)n + 255) & ~size_t(255);
         const size_t offD = (offK + sizeof(double) * (size_t)n + 255) & ~size_t(255);
@@ -395,9 +502,12 @@ extern "C" lrr_status lrr_slr_graph(lrr_ctx* ctx, int m, int n, const void* Mv, 
         double* kkt = reinterpret_cast<double*>(base + offK);
         lrr::GemmDesc* gd = reinterpret_cast<lrr::GemmDesc*>(base + offD);
 
-        lrr::ctx_timed(ctx, s, "k_slr_select", 0.0, 16.0 * n * (double)n, [&] {
-            hipLaunchKernelGGL(k_slr_select, dim3(n), dim3(256), (size_t)P * (sizeof(double) + sizeof(int)), s, Z,
-                               (long)ldz, n, P, nk, nbr);
+        const unsigned tiles = (unsigned)((n + kTile - 1) / kTile);
+        lrr::ctx_timed(ctx, s, "k_slr_affinity", 0.0, 24.0 * n * (double)n, [&] {
+            hipLaunchKernelGGL(k_slr_affinity, dim3(tiles, tiles), dim3(256), 0, s, Z, (long)ldz, n, G, (long)n);
+        });
+        lrr::ctx_timed(ctx, s, "k_slr_select", 0.0, 8.0 * n * (double)n, [&] {
+            hipLaunchKernelGGL(k_slr_select, dim3(n), dim3(256), 0, s, G, (long)n, n, nk, nbr);
         });
         lrr::GemmDesc h{M, M, G, n, n, m, ldm, ldm, n, 1.0, 0.0, nullptr, nullptr};
         LRR_HIP(hipMemcpyAsync(gd, &h, sizeof(h), hipMemcpyHostToDevice, s));

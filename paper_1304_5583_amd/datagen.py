@@ -33,6 +33,8 @@ __all__ = [
     "union_of_subspaces",
     "paper_simulation",
     "make_config",
+    "small_problem",
+    "synthetic_coefficients",
     "CONFIG_NAMES",
 ]
 
@@ -272,3 +274,25 @@ def small_problem(seed: int, m: int = 40, k: int = 3, r: int = 3, ns: int = 30,
     return Problem(name=f"small-s{seed}-m{m}-n{n}-t{t}", M=np.ascontiguousarray(M),
                    labels=labels, outliers=outl, perm=perm, offsets=offsets, lam=lam,
                    extra={"k": k})
+
+
+def synthetic_coefficients(labels: np.ndarray, seed: int, quantum: float | None = 2.0 ** -10,
+                           noise: float = 0.01, within: float = 0.1) -> np.ndarray:
+    """Seeded n x n stand-in for a low-rank coefficient matrix with the block
+    structure of a union of subspaces (input of the SLR-graph stage): every
+    entry N(0, noise^2), plus |N(0, within^2)| between samples with one label,
+    rounded to multiples of `quantum` so that equal affinities (ties) occur.
+    Built in column panels to bound the temporaries at n = 20000."""
+    labels = np.asarray(labels)
+    rng = np.random.default_rng(seed)
+    n = labels.shape[0]
+    Z = np.empty((n, n), dtype=np.float64)
+    for c0 in range(0, n, 2048):
+        c1 = min(n, c0 + 2048)
+        blk = noise * rng.standard_normal((n, c1 - c0))
+        same = labels[:, None] == labels[None, c0:c1]
+        blk += np.where(same, within * np.abs(rng.standard_normal((n, c1 - c0))), 0.0)
+        if quantum:
+            blk = np.round(blk / quantum) * quantum
+        Z[:, c0:c1] = blk
+    return Z

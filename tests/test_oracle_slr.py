@@ -98,6 +98,22 @@ def test_neighbors_are_the_top_affinities_with_index_ties():
         assert all(j > max(q for q in lst if A[i, q] == edge) for j in rest if A[i, j] == edge)
 
 
+def test_neighbor_rows_match_a_lexicographic_sort():
+    """slr_neighbors_rows on a tie-heavy matrix equals numpy's lexicographic
+    sort on (-affinity, index) of each row, and slr_neighbors' rows."""
+    rng = np.random.default_rng(11)
+    n, nk = 300, 40
+    Z = np.round(rng.standard_normal((n, n)) * 4) / 4       # many exact ties
+    rows = [0, 7, 150, 299]
+    got = slr.slr_neighbors_rows(Z, nk, rows)
+    for r, i in enumerate(rows):
+        a = np.abs(Z[i, :]) + np.abs(Z[:, i])
+        j = np.array([q for q in range(n) if q != i])
+        order = j[np.lexsort((j, -a[j]))]
+        assert np.array_equal(got[r], order[:nk])
+    assert np.array_equal(got, slr.slr_neighbors(Z, nk)[rows])
+
+
 def test_slr_graph_weights_satisfy_optimality():
     """End to end on a small union of subspaces: each sample's weights are
     non-negative and optimal for its neighbour basis."""
