@@ -14,7 +14,9 @@
  *
  * Memory conventions (all entry points)
  * -------------------------------------
- *  - Matrices are column-major with an explicit leading dimension (ld >= rows).
+ *  - Matrices are column-major with an explicit leading dimension (rows <= ld
+ *    < 4194304 = 2^22: the FP64 matrix-core GEMM addresses a K-tile of an
+ *    operand with 32-bit byte offsets; a larger ld is LRR_EINVAL).
  *    A column is one data point, so a row-major (n, m) tensor holds M^T.
  *  - Matrix arguments are DEVICE pointers on the ctx's device, element type
  *    double in every precision form (the form selects the arithmetic of the

@@ -21,7 +21,9 @@ extern "C" {
  * for every dense product of the solver (Gram matrices, dictionary products,
  * reconstruction, combine).  A^T A (ta, !tb, B == A, ldb == lda, M == N) runs
  * the symmetric kernel of the solver's Gram matrices: the tiles on and above
- * the diagonal are computed and mirrored, bitwise the full product. */
+ * the diagonal are computed and mirrored, bitwise the full product.  lda and
+ * ldb must be below 4194304 (2^22; the kernel addresses a K-tile's panel with
+ * 32-bit byte offsets): LRR_EINVAL otherwise. */
 lrr_status lrr_diag_dgemm(lrr_ctx *ctx, int ta, int tb, int M, int N, int K, double alpha,
                           const double *A, int lda, const double *B, int ldb, double beta,
                           double *C, int ldc, void *stream);

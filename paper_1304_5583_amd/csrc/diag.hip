@@ -69,6 +69,8 @@ lrr_status lrr_diag_gemm(lrr_ctx* ctx, int precision, int ta, int tb, int M, int
         return lrr::ctx_fail(ctx, LRR_EINVAL, "unknown precision");
     if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !C) return lrr::ctx_fail(ctx, LRR_EINVAL, "bad GEMM arguments");
     if (lda < (ta ? K : M) || ldb < (tb ? N : K) || ldc < M) return lrr::ctx_fail(ctx, LRR_EINVAL, "leading dimension too small");
+    if (precision == LRR_FP64 && (lda >= lrr::kGemmMaxLd || ldb >= lrr::kGemmMaxLd))
+        return lrr::ctx_fail(ctx, LRR_EINVAL, "lda and ldb must be below 4194304");
     return run(ctx, [&]() -> lrr_status {
         hipStream_t s = static_cast<hipStream_t>(stream);
         lrr::GemmDesc h{A, B, C, M, N, K, lda, ldb, ldc, alpha, beta, nullptr, nullptr};
@@ -94,6 +96,7 @@ lrr_status lrr_diag_spd_inverse(lrr_ctx* ctx, int m, int n, const double* A, int
     if (!ctx) return lrr::ctx_fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
     if (m <= 0 || n <= 0 || !A || !Kinv || lda < m || ldk < m)
         return lrr::ctx_fail(ctx, LRR_EINVAL, "bad arguments");
+    if (lda >= lrr::kGemmMaxLd || ldk >= lrr::kGemmMaxLd) return lrr::ctx_fail(ctx, LRR_EINVAL, "leading dimensions must be below 4194304");
     return run(ctx, [&]() -> lrr_status {
         hipStream_t s = static_cast<hipStream_t>(stream);
         const size_t mm = (size_t)m * m;

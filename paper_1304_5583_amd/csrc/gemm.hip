@@ -8,17 +8,29 @@
 // 64-wide wavefronts owns a (BM/2) x 32 part as MFMA tiles of 16 x 16.  BM is 64
 // unless the batch has fewer than 512 such tiles; then BM = 32 doubles the
 // number of workgroups, so that every CU holds two and one hides the other's
-// load latency (the four Gram matrices of order 500 of a 4-block problem ran at
-// 21-30 TFLOP/s with one 64-row workgroup per CU, the 40-block problem's at
-// 47-55).  Both heights sum every element over K in the same order, so the
-// choice does not change the result.  K advances in steps of 16 (four MFMA
-// k-chunks of 4).  Operand tiles are double-buffered in LDS and the next tile is
-// fetched into registers while the current one is multiplied.  With 16-deep
-// tiles a 64-row workgroup holds 34 KB of LDS, so four fit on a CU (32-deep
-// tiles allowed two and ran the batched 512-order products at 38-40 instead of
-// 44-47 TFLOP/s).  Whole K-tiles of interior workgroups are read with 16-byte
-// vector loads (7-10 % faster than element loads); loads at the matrix edges
-// are bounds-tested and zero-fill, so any M, N, K is legal.
+// load latency.  Both heights sum every element over K in the same order (K in
+// steps of 16, four MFMA k-chunks of 4 each), so the choice does not change the
+// result, and neither does anything else below: only the data movement is tuned.
+//
+// Data movement, per K-tile of 16:
+//   * global -> registers with raw buffer loads, two K-tiles ahead of the one
+//     being multiplied (two register sets, the loop unrolled by two), so a load
+//     has two tiles' worth of MFMA time to arrive.  An element outside the
+//     matrix (M, N or K edge) gets an offset with bit 31 set, beyond the
+//     buffer's range, and the hardware returns 0 for it: the loads are
+//     straight-line code for every tile, edges included, and the compiler
+//     waits only for the older set (vmcnt(n) instead of vmcnt(0));
+//   * every load instruction of a wavefront covers whole contiguous runs: the
+//     threads walk the operand's contiguous dimension first (rows of A, k of
+//     A^T, k of B, columns of B^T);
+//   * registers -> double-buffered LDS tiles (row stride BM + 2 doubles: a
+//     stride of 16 mod 32 would make the column-wise stores of k-contiguous
+//     operands 8-way bank conflicted and measured 40 % slower);
+//   * the kernel is held to 128 VGPRs (four waves per SIMD, the LDS of four
+//     workgroups per CU): at three waves per SIMD the batched 512-order
+//     products ran 17 % slower.
+// Measured on 40 products of order 512 (m = 512, n = 500, K = 512): 47 TFLOP/s,
+// against 41 for element/vector loads one tile ahead in branches.
 #include <algorithm>
 
 #include "common.hpp"
@@ -30,128 +42,44 @@ namespace {
 
 constexpr int BN = 64, PAD = 2;
 
-// K depth of a tile: 16 for both heights (LDS for four 64-row workgroups per
-// CU; 32-deep tiles with 32-row tiles, whose grids hold two workgroups per CU,
-// measured no faster: 507 vs 502 ms per workload-2 solve)
-template <int BM>
-constexpr int kDepth = 16;
+constexpr int BK = 16;                         // K depth of a tile
+constexpr unsigned kRsrcWord3 = 0x00020000u;   // raw buffer resource, gfx9-family data format
+constexpr unsigned kRange = 0x7ffffff0u;       // num_records: offsets with bit 31 set are outside
 
-// One K-tile of op(A) (BM x BK) and op(B) (BK x BN) in registers.
-template <int BM>
-struct Frag {
-    static constexpr int BK = kDepth<BM>;
-    static constexpr int NLA = (BM * BK) / 256;   // elements of the op(A) tile per thread
-    static constexpr int NLB = (BN * BK) / 256;   // elements of the op(B) tile per thread
-    double a[NLA];
-    double b[NLB];
-};
-
-// Thread -> element map of the operand tiles.  Every thread holds a run of NLA
-// (op(A)) or NLB (op(B)) elements that are contiguous in memory:
-//   op(A) = A   : run along the BM rows of one k   (row (tid % (BM/NLA)) * NLA, k = tid / (BM/NLA))
-//   op(A) = A^T : run along k of one row           (row tid / (BK/NLA), k = (tid % (BK/NLA)) * NLA)
-//   op(B) = B   : run along k of one column        (column tid / (BK/NLB), k = (tid % (BK/NLB)) * NLB)
-//   op(B) = B^T : run along the BN columns of one k (column (tid % (BN/NLB)) * NLB, k = tid / (BN/NLB))
-template <int BM, bool TA>
-__device__ __forceinline__ void a_slot(int tid, int& i, int& kk) {
-    constexpr int NLA = Frag<BM>::NLA, BK = Frag<BM>::BK;
-    if (!TA) { i = (tid % (BM / NLA)) * NLA; kk = tid / (BM / NLA); }
-    else     { i = tid / (BK / NLA); kk = (tid % (BK / NLA)) * NLA; }
+// raw buffer resource over one K-tile's panel of an operand (offsets from `base`)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const double* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)kRange, (int)kRsrcWord3);
 }
-template <int BM, bool TB>
-__device__ __forceinline__ void b_slot(int tid, int& j, int& kk) {
-    constexpr int NLB = Frag<BM>::NLB, BK = Frag<BM>::BK;
-    if (!TB) { j = tid / (BK / NLB); kk = (tid % (BK / NLB)) * NLB; }
-    else     { j = (tid % (BN / NLB)) * NLB; kk = tid / (BN / NLB); }
+__device__ __forceinline__ double buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
-// bounds-tested loads (zero outside the matrices)
-template <int BM, bool TA, bool TB>
-__device__ __forceinline__ void load_tile(Frag<BM>& f, const double* __restrict__ A, long lda,
-                                          const double* __restrict__ B, long ldb, int M, int N, int K,
-                                          int m0, int n0, int k0, int tid) {
-    constexpr int NLA = Frag<BM>::NLA, NLB = Frag<BM>::NLB;
-    int i, ka, j, kb;
-    a_slot<BM, TA>(tid, i, ka);
-    b_slot<BM, TB>(tid, j, kb);
-#pragma unroll
-    for (int v = 0; v < NLA; ++v) {
-        const int gi = m0 + i + (TA ? 0 : v), gk = k0 + ka + (TA ? v : 0);
-        f.a[v] = (gi < M && gk < K) ? (TA ? A[gk + gi * lda] : A[gi + gk * lda]) : 0.0;
-    }
-#pragma unroll
-    for (int v = 0; v < NLB; ++v) {
-        const int gj = n0 + j + (TB ? v : 0), gk = k0 + kb + (TB ? 0 : v);
-        f.b[v] = (gj < N && gk < K) ? (TB ? B[gj + gk * ldb] : B[gk + gj * ldb]) : 0.0;
-    }
-}
-
-// interior tile with 16-byte aligned runs: unchecked 16-byte vector loads
-template <int BM, bool TA, bool TB>
-__device__ __forceinline__ void load_tile_vec(Frag<BM>& f, const double* __restrict__ A, long lda,
-                                              const double* __restrict__ B, long ldb, int m0, int n0, int k0,
-                                              int tid) {
-    constexpr int NLA = Frag<BM>::NLA, NLB = Frag<BM>::NLB;
-    int i, ka, j, kb;
-    a_slot<BM, TA>(tid, i, ka);
-    b_slot<BM, TB>(tid, j, kb);
-    const double* pa = TA ? A + (k0 + ka) + (long)(m0 + i) * lda : A + (m0 + i) + (long)(k0 + ka) * lda;
-    const double* pb = TB ? B + (n0 + j) + (long)(k0 + kb) * ldb : B + (k0 + kb) + (long)(n0 + j) * ldb;
-#pragma unroll
-    for (int v = 0; v < NLA; v += 2) {
-        const double2 x = *reinterpret_cast<const double2*>(pa + v);
-        f.a[v] = x.x;
-        f.a[v + 1] = x.y;
-    }
-#pragma unroll
-    for (int v = 0; v < NLB; v += 2) {
-        const double2 x = *reinterpret_cast<const double2*>(pb + v);
-        f.b[v] = x.x;
-        f.b[v + 1] = x.y;
-    }
-}
-
-template <int BM, bool TA, bool TB>
-__device__ __forceinline__ void store_tile(const Frag<BM>& f, double (*As)[BM + PAD], double (*Bs)[BN + PAD],
-                                           int tid) {
-    constexpr int NLA = Frag<BM>::NLA, NLB = Frag<BM>::NLB;
-    int i, ka, j, kb;
-    a_slot<BM, TA>(tid, i, ka);
-    b_slot<BM, TB>(tid, j, kb);
-#pragma unroll
-    for (int v = 0; v < NLA; ++v) {
-        if (!TA) As[ka][i + v] = f.a[v];
-        else As[ka + v][i] = f.a[v];
-    }
-#pragma unroll
-    for (int v = 0; v < NLB; ++v) {
-        if (!TB) Bs[kb + v][j] = f.b[v];
-        else Bs[kb][j + v] = f.b[v];
-    }
-}
-
-// BM = 64: each wave owns a 32 x 32 quarter (2 x 2 MFMA tiles); BM = 32 (grids too
-// small to give every CU two workgroups): each wave owns 16 x 32 (1 x 2 tiles).
 // SYM (with TA, !TB, BM = BN, C square): C = A^T A.  Tile (P, Q) and tile (Q, P)
 // multiply the same pairs of numbers in the same order (the MFMA products of a
 // chunk commute), so the computed product is exactly symmetric; only the tiles
 // with P <= Q run, and an off-diagonal tile also writes its transpose.
+// Byte offsets inside one K-tile's panel are below 2^31 while lda * BM and
+// ldb * 64 stay below 2^28 doubles (leading dimensions below four million).
 template <int BM, bool TA, bool TB, bool SYM = false>
-__global__ __launch_bounds__(256) void k_dgemm(const GemmDesc* __restrict__ descs, int tiles_m, int tiles_n,
-                                               int total) {
-    constexpr int WM = BM / 2, TX = WM / 16, BK = Frag<BM>::BK;
+__global__ __launch_bounds__(256, 4) void k_dgemm(const GemmDesc* __restrict__ descs, int tiles_m, int tiles_n,
+                                                  int total) {
+    constexpr int WM = BM / 2, TX = WM / 16;
+    constexpr int NA = BM * BK / 256, NB = BN * BK / 256;   // operand elements per thread and K-tile
     static_assert(!SYM || (TA && !TB && BM == BN), "symmetric tiles need C = A^T A with square tiles");
     const int per = SYM ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
     // double-buffered operand tiles: As[buf][k][i] = op(A)(m0+i, k0+k)
     __shared__ double As[2][BK][BM + PAD];
     __shared__ double Bs[2][BK][BN + PAD];
-    // The grid is at most a few workgroups per CU; each takes the tiles
-    // blockIdx.x, blockIdx.x + gridDim.x, ...  in launch order: row tiles
-    // fastest, then column tiles, then products (placing each product's tiles
-    // on one XCD's L2 measured 3-5% slower).  A tile of a product whose block
-    // is not active is skipped after one descriptor read, so a launch with no
-    // active block costs little more than its dispatch.
-    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    // The grid is at most four workgroups per CU; each takes the tiles
+    // blockIdx.x, blockIdx.x + gridDim.x, ...  Workgroup w runs on XCD w % 8, so
+    // the first 8 * floor(total / 8) tiles are dealt out in eight contiguous
+    // ranges, one per XCD: the tiles of one product share an L2 (3 % faster than
+    // dealing consecutive tiles to consecutive XCDs).  Within a product, row
+    // tiles run fastest.  A tile of a product whose block is not active is
+    // skipped after one descriptor read.
+    const int per_x = total >> 3;
+    for (int t0 = blockIdx.x; t0 < total; t0 += gridDim.x) {
+        const int tile = t0 < 8 * per_x ? (t0 & 7) * per_x + (t0 >> 3) : t0;
         const int z = tile / per, tin = tile - z * per;
         const GemmDesc d = descs[z];
         if (d.active && d.active[0] == 0) continue;
@@ -177,7 +105,7 @@ __global__ __launch_bounds__(256) void k_dgemm(const GemmDesc* __restrict__ desc
         const int lr = lane & 15, lk = lane >> 4;
 
         dbl4 acc[TX][2];
-    #pragma unroll
+#pragma unroll
         for (int x = 0; x < TX; ++x)
             for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
 
@@ -185,59 +113,92 @@ __global__ __launch_bounds__(256) void k_dgemm(const GemmDesc* __restrict__ desc
         const double* __restrict__ B = d.B;
         const int M = d.M, N = d.N, K = d.K;
         const long lda = d.lda, ldb = d.ldb;
+        const int nt = (K + BK - 1) / BK;
+        // element v of this thread in a K-tile = its first element plus v steps:
+        //   op(A) = A  : row ai = tid % BM, k = tid / BM + (256 / BM) v
+        //   op(A) = A^T: k = tid % 16, row ai = tid / 16 + 16 v
+        //   op(B) = B  : k = tid % 16, column bj = tid / 16 + 16 v
+        //   op(B) = B^T: column bj = tid % 64, k = tid / 64 + 4 v
+        const int ai = TA ? tid / 16 : tid % BM, ak = TA ? tid % 16 : tid / BM;
+        const int bj = TB ? tid % 64 : tid / 16, bk = TB ? tid / 64 : tid % 16;
+        constexpr int dai = TA ? 16 : 0, dak = TA ? 0 : 256 / BM;
+        constexpr int dbj = TB ? 0 : 16, dbk = TB ? 4 : 0;
+        const unsigned aoff = (unsigned)(8 * (TA ? ak + (long)ai * lda : ai + (long)ak * lda));
+        const unsigned boff = (unsigned)(8 * (TB ? bj + (long)bk * ldb : bk + (long)bj * ldb));
+        const unsigned astep = (unsigned)(8 * (TA ? (long)dai * lda : (long)dak * lda));
+        const unsigned bstep = (unsigned)(8 * (TB ? (long)dbk * ldb : (long)dbj * ldb));
 
-        // whole K-tiles of an interior workgroup with 16-byte aligned operands are
-        // read with unchecked vector loads; the rest (edges, a partial last K-tile,
-        // odd strides or offsets) with bounds-tested element loads
-        const bool vec = m0 + BM <= M && n0 + BN <= N && (lda & 1) == 0 && (ldb & 1) == 0 &&
-                         (reinterpret_cast<unsigned long>(A) & 15) == 0 &&
-                         (reinterpret_cast<unsigned long>(B) & 15) == 0;
-        const int kvec = vec ? (K / BK) * BK : 0;
-
-        Frag<BM> f;
-        if (BK <= kvec) load_tile_vec<BM, TA, TB>(f, A, lda, B, ldb, m0, n0, 0, tid);
-        else load_tile<BM, TA, TB>(f, A, lda, B, ldb, M, N, K, m0, n0, 0, tid);
-        store_tile<BM, TA, TB>(f, As[0], Bs[0], tid);
-        __syncthreads();
-        int cur = 0;
-        for (int k0 = 0; k0 < K; k0 += BK) {
-            const int kn = k0 + BK;
-            // the next tile's global loads are in flight while this one is multiplied
-            if (kn < K) {
-                if (kn + BK <= kvec) load_tile_vec<BM, TA, TB>(f, A, lda, B, ldb, m0, n0, kn, tid);
-                else load_tile<BM, TA, TB>(f, A, lda, B, ldb, M, N, K, m0, n0, kn, tid);
+        double fa0[NA], fb0[NB], fa1[NA], fb1[NB];
+        // K-tile kt of both operands into registers (zeros outside the matrices)
+        auto gload = [&](double (&fa)[NA], double (&fb)[NB], int kt) {
+            const int k0 = kt * BK;
+            const __amdgpu_buffer_rsrc_t ra = panel_rsrc(TA ? A + k0 + (long)m0 * lda : A + m0 + (long)k0 * lda);
+            const __amdgpu_buffer_rsrc_t rb = panel_rsrc(TB ? B + n0 + (long)k0 * ldb : B + k0 + (long)n0 * ldb);
+#pragma unroll
+            for (int v = 0; v < NA; ++v) {
+                const unsigned in = (unsigned)(m0 + ai + dai * v < M) & (unsigned)(k0 + ak + dak * v < K);
+                fa[v] = buffer_ld(ra, (aoff + v * astep) | ((in ^ 1u) << 31));
             }
-    #pragma unroll
+#pragma unroll
+            for (int v = 0; v < NB; ++v) {
+                const unsigned in = (unsigned)(n0 + bj + dbj * v < N) & (unsigned)(k0 + bk + dbk * v < K);
+                fb[v] = buffer_ld(rb, (boff + v * bstep) | ((in ^ 1u) << 31));
+            }
+        };
+        auto lstore = [&](const double (&fa)[NA], const double (&fb)[NB], int buf) {
+#pragma unroll
+            for (int v = 0; v < NA; ++v) As[buf][ak + dak * v][ai + dai * v] = fa[v];
+#pragma unroll
+            for (int v = 0; v < NB; ++v) Bs[buf][bk + dbk * v][bj + dbj * v] = fb[v];
+        };
+        // the four k-chunks of the tile in LDS buffer `buf`, in order
+        auto mma = [&](int buf) {
+#pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
                 const int kr = kk + lk;
                 double a[TX];
-    #pragma unroll
-                for (int x = 0; x < TX; ++x) a[x] = As[cur][kr][wm + 16 * x + lr];
-                const double b0 = Bs[cur][kr][wn + lr], b1 = Bs[cur][kr][wn + 16 + lr];
-    #pragma unroll
+#pragma unroll
+                for (int x = 0; x < TX; ++x) a[x] = As[buf][kr][wm + 16 * x + lr];
+                const double b0 = Bs[buf][kr][wn + lr], b1 = Bs[buf][kr][wn + 16 + lr];
+#pragma unroll
                 for (int x = 0; x < TX; ++x) {
                     acc[x][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b0, acc[x][0], 0, 0, 0);
                     acc[x][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b1, acc[x][1], 0, 0, 0);
                 }
             }
-            if (kn < K) store_tile<BM, TA, TB>(f, As[cur ^ 1], Bs[cur ^ 1], tid);
+        };
+        // tile 0 in LDS buffer 0, tile 1 in flight in set 0; each half of the loop
+        // multiplies one tile while the tile after next loads into the other set
+        gload(fa0, fb0, 0);
+        lstore(fa0, fb0, 0);
+        gload(fa0, fb0, 1);
+        __syncthreads();
+        for (int pr = 0; pr < nt / 2; ++pr) {
+            const int kt = 2 * pr;
+            gload(fa1, fb1, kt + 2);
+            mma(0);
+            lstore(fa0, fb0, 1);
             __syncthreads();
-            cur ^= 1;
+            gload(fa0, fb0, kt + 3);
+            mma(1);
+            lstore(fa1, fb1, 0);
+            __syncthreads();
         }
+        if (nt & 1) mma(0);
 
         // accumulator layout of v_mfma_f64_16x16x4f64: register v of a lane holds
         // row lane/16 + 4v, column lane%16 of the 16 x 16 tile
         const double alpha = d.alpha, beta = d.beta;
         const long ldc = d.ldc;
-    #pragma unroll
+#pragma unroll
         for (int x = 0; x < TX; ++x) {
-    #pragma unroll
+#pragma unroll
             for (int y = 0; y < 2; ++y) {
                 const int gj = n0 + wn + y * 16 + lr;
                 if (gj >= N) continue;
                 const int cj = d.colmap ? d.colmap[gj] : gj;
                 double* __restrict__ Cc = d.C + (long)cj * ldc;
-    #pragma unroll
+#pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int gi = m0 + wm + x * 16 + lk + 4 * v;
                     if (gi < M) {

@@ -16,6 +16,8 @@ void launch_dgemm_sym(const GemmDesc* d_descs, int count, int maxN, hipStream_t 
 bool dgemm_sym_tiles(int count, int maxN);
 // workgroups of a GEMM launch (looked up once; call before a stream capture)
 int gemm_grid(void);
+// leading dimensions of the FP64 GEMM's operands stay below this (32-bit panel offsets)
+constexpr int kGemmMaxLd = 1 << 22;
 
 // xgemm.hip: the same contract with the arithmetic chosen by `mode` (GemmMode)
 void launch_xgemm(const GemmDesc* d_descs, int count, int maxM, int maxN, bool ta, bool tb, int mode,

@@ -86,6 +86,7 @@ extern "C" lrr_status lrr_diag_spd_inverse_noalloc(lrr_ctx* ctx, int m, int n, c
     if (!ctx) return lrr::ctx_fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
     if (m <= 0 || n <= 0 || !A || !Kinv || lda < m || ldk < m)
         return lrr::ctx_fail(ctx, LRR_EINVAL, "bad arguments");
+    if (lda >= lrr::kGemmMaxLd || ldk >= lrr::kGemmMaxLd) return lrr::ctx_fail(ctx, LRR_EINVAL, "leading dimensions must be below 4194304");
     if (m > kNoAllocMaxM)
         return lrr::ctx_fail(ctx, LRR_EINVAL,
                              "m = " + std::to_string(m) + " exceeds the no-allocation limit of " +

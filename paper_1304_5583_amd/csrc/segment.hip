@@ -559,6 +559,7 @@ extern "C" lrr_status lrr_segment(lrr_ctx* ctx, int n, const void* Zv, int ldz, 
                                   void* stream) {
     if (!ctx) return lrr::ctx_fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
     if (n < 1 || !Zv || ldz < n || !labels) return lrr::ctx_fail(ctx, LRR_EINVAL, "bad Z / labels arguments");
+    if (ldz >= lrr::kGemmMaxLd) return lrr::ctx_fail(ctx, LRR_EINVAL, "leading dimensions must be below 4194304");
     if (!(rank_tol > 0.0 && rank_tol < 1.0)) return lrr::ctx_fail(ctx, LRR_EINVAL, "rank_tol must lie in (0, 1)");
     if (rank_bound < 0) return lrr::ctx_fail(ctx, LRR_EINVAL, "rank_bound must be >= 0");
     if (k < 1 || k > kMaxK) return lrr::ctx_fail(ctx, LRR_EINVAL, "k must lie in [1, 1024]");

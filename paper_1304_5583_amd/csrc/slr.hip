@@ -483,6 +483,7 @@ extern "C" lrr_status lrr_slr_graph(lrr_ctx* ctx, int m, int n, const void* Mv, 
     if (!ctx) return lrr::ctx_fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
     if (m < 1 || n < 2 || !Mv || !Zv || ldm < m || ldz < n || !nbr || !w)
         return lrr::ctx_fail(ctx, LRR_EINVAL, "bad M / Z / output arguments");
+    if (ldm >= lrr::kGemmMaxLd || ldz >= lrr::kGemmMaxLd) return lrr::ctx_fail(ctx, LRR_EINVAL, "leading dimensions must be below 4194304");
     if (nk < 1 || nk > n - 1 || nk > kMaxNk) return lrr::ctx_fail(ctx, LRR_EINVAL, "nk must lie in [1, min(n-1, 1024)]");
     if (!(alpha > 0.0) || !std::isfinite(alpha)) return lrr::ctx_fail(ctx, LRR_EINVAL, "alpha must be positive");
     const double* M = static_cast<const double*>(Mv);

@@ -1970,6 +1970,8 @@ lrr_status lrr_solve(lrr_ctx* ctx, int m, int n, int l, const void* A, int lda, 
     if (m <= 0 || n <= 0 || l <= 0) return fail(ctx, LRR_EINVAL, "dimensions must be positive");
     if (!A || !X || !Z) return fail(ctx, LRR_EINVAL, "A, X and Z must not be NULL");
     if (lda < m || ldx < m || ldz < n || (E && lde < m)) return fail(ctx, LRR_EINVAL, "leading dimension too small");
+    if (lda >= lrr::kGemmMaxLd || ldx >= lrr::kGemmMaxLd || ldz >= lrr::kGemmMaxLd || (E && lde >= lrr::kGemmMaxLd))
+        return fail(ctx, LRR_EINVAL, "leading dimensions must be below 4194304");
     if (!(lambda > 0) || !std::isfinite(lambda)) return fail(ctx, LRR_EINVAL, "lambda must be positive and finite");
     lrr_opts o;
     if (opts) o = *opts; else lrr_opts_default(&o);
@@ -2011,6 +2013,8 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
     if (m <= 0 || n <= 0) return fail(ctx, LRR_EINVAL, "dimensions must be positive");
     if (!M || !Z) return fail(ctx, LRR_EINVAL, "M and Z must not be NULL");
     if (ldm < m || ldz < n || (S && lds < m)) return fail(ctx, LRR_EINVAL, "leading dimension too small");
+    if (ldm >= lrr::kGemmMaxLd || ldz >= lrr::kGemmMaxLd || (S && lds >= lrr::kGemmMaxLd))
+        return fail(ctx, LRR_EINVAL, "leading dimensions must be below 4194304");
     if (!(lambda > 0) || !std::isfinite(lambda)) return fail(ctx, LRR_EINVAL, "lambda must be positive and finite");
     std::string why;
     if (check_partition_impl(n, t, perm, offsets, why) != LRR_OK) return fail(ctx, LRR_EINVAL, why);
@@ -2095,6 +2099,8 @@ lrr_status dfc_lrr_solve_local(lrr_ctx* ctx, int m, int n, const void* M, int ld
     if (m <= 0 || n <= 0) return fail(ctx, LRR_EINVAL, "dimensions must be positive");
     if (!M || !Z) return fail(ctx, LRR_EINVAL, "M and Z must not be NULL");
     if (ldm < m || ldz < n || (S && lds < m)) return fail(ctx, LRR_EINVAL, "leading dimension too small");
+    if (ldm >= lrr::kGemmMaxLd || ldz >= lrr::kGemmMaxLd || (S && lds >= lrr::kGemmMaxLd))
+        return fail(ctx, LRR_EINVAL, "leading dimensions must be below 4194304");
     if (!(lambda > 0) || !std::isfinite(lambda)) return fail(ctx, LRR_EINVAL, "lambda must be positive and finite");
     std::string why;
     if (check_partition_impl(n, t, perm, offsets, why) != LRR_OK) return fail(ctx, LRR_EINVAL, why);
@@ -2160,6 +2166,7 @@ lrr_status dfc_lrr_backward(lrr_ctx* ctx, const void* dZ, int lddz, double* dlam
     Tape& tp = *ctx->tape;
     if (!dZ || !dlambda) return fail(ctx, LRR_EINVAL, "dZ and dlambda must not be NULL");
     if (lddz < tp.p.n || (dM && lddm < tp.p.m)) return fail(ctx, LRR_EINVAL, "leading dimension too small");
+    if (lddz >= lrr::kGemmMaxLd || (dM && lddm >= lrr::kGemmMaxLd)) return fail(ctx, LRR_EINVAL, "leading dimensions must be below 4194304");
     return guarded(ctx, [&]() -> lrr_status {
         LRR_HIP(hipSetDevice(ctx->device));
         hipStream_t s = static_cast<hipStream_t>(stream);

@@ -21,12 +21,38 @@ def test_dgemm_matches_float64(ta, tb, M, N, K):
 
 
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
-@pytest.mark.parametrize("M,N,K", [(128, 96, 100), (96, 128, 64), (512, 512, 500)])
-def test_dgemm_vector_loads(ta, tb, M, N, K):
-    """Even leading dimensions: interior tiles take the 16-byte loads (32-row
-    tiles on these small grids), the edges and a ragged last K tile the
-    bounds-tested loads."""
+@pytest.mark.parametrize("M,N,K", [(128, 96, 100), (96, 128, 64), (512, 512, 500), (130, 70, 16), (70, 130, 32),
+                                   (65, 65, 48), (64, 64, 1)])
+def test_dgemm_even_leading_dimensions(ta, tb, M, N, K):
+    """Even leading dimensions, ragged M / N edges and K of one, two and three
+    16-deep tiles (the loop multiplies tiles in pairs, an odd last one alone,
+    and loads two tiles ahead: past the end the loads must read zeros)."""
     _check_dgemm(ta, tb, M, N, K, (4, 2, 2))
+
+
+@pytest.mark.parametrize("ta", [0, 1])
+def test_dgemm_largest_leading_dimension(ta):
+    """lda = 2^22 - 1, the largest the FP64 GEMM accepts (a K-tile's panel is
+    addressed with 32-bit byte offsets; with op(A) = A^T the 64 rows of a tile
+    span 63 lda): the product is right; lda = 2^22 is LRR_EINVAL."""
+    torch = need_gpu()
+    from paper_1304_5583_amd import binding as B
+    M, N, K = 64, 8, 20
+    lda = (1 << 22) - 1
+    rng = np.random.default_rng(22)
+    opA, opB = rng.standard_normal((M, K)), rng.standard_normal((K, N))
+    stored = opA.T if ta else opA                      # K x M or M x K, column-major
+    dA = torch.zeros((stored.shape[1], lda), dtype=torch.float64, device="cuda")
+    dA[:, :stored.shape[0]] = torch.from_numpy(np.ascontiguousarray(stored.T)).cuda()
+    dB = torch.from_numpy(np.ascontiguousarray(opB.T)).cuda()
+    dC = torch.zeros((N, M), dtype=torch.float64, device="cuda")
+    B.lrr_diag_dgemm(bool(ta), False, dA, dB, dC, M, N, K, lda, K, M)
+    ref = opA @ opB
+    assert np.abs(dC.cpu().numpy().T - ref).max() <= 1e-13 * (1 + np.abs(ref).max()) * K
+    with pytest.raises(B.LRRError) as e:
+        B.lrr_diag_dgemm(bool(ta), False, dA, dB, dC, M, N, K, lda + 1, K, M)
+    assert e.value.status == B.LRR_EINVAL
+    del dA
 
 
 def _check_dgemm(ta, tb, M, N, K, pads):
