@@ -107,6 +107,70 @@ def load_traffic(path, digest):
     return tr
 
 
+def lib_kernel_name(rocprof_name):
+    """The library's timing-table name of a kernel from its rocprof name
+    ("void lrr::(anonymous namespace)::k_dgemm<64, false, false, false>(...)"
+    -> "k_dgemm<false, false>"); None for kernels outside the roofline set."""
+    import re
+    n = re.sub(r"^void ", "", rocprof_name).replace("(anonymous namespace)::", "")
+    n = re.sub(r"\(.*$", "", n)
+    n = n.split("::")[-1]
+    m = re.match(r"k_dgemm<(\d+), (true|false), (true|false), (true|false)>", n)
+    if m:
+        return "k_dgemm_sym" if m.group(4) == "true" else f"k_dgemm<{m.group(2)}, {m.group(3)}>"
+    base = re.sub(r"<.*$", "", n)
+    base = {"k_update_Z_w": "k_update_Z", "k_estep_w": "k_estep"}.get(base, base)
+    return base if base in HBM_KERNELS or base.startswith("k_") else None
+
+
+def traffic_from_pmc(fetch_csv, write_csv, out_path, digest):
+    """HBM bytes per dispatch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE; KiB per dispatch, summed over the rows of a dispatch), each
+    scaled by what the same counter reads for the 512 MiB device copy that
+    --calib-copy adds (the copy's last dispatch), averaged per kernel name."""
+    import csv
+    from collections import defaultdict
+
+    def per_dispatch(path, counter):
+        vals, names = defaultdict(float), {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            d = int(r["Dispatch_Id"])
+            vals[d] += float(r["Counter_Value"])
+            names[d] = r["Kernel_Name"]
+        return vals, names
+
+    fv, fn = per_dispatch(fetch_csv, "FETCH_SIZE")
+    wv, wn = per_dispatch(write_csv, "WRITE_SIZE")
+    copy_kib = 512 * 1024.0
+    fcopy = [fv[d] for d in fv if "copyBuffer" in fn[d] and fv[d] > 0.25 * copy_kib]
+    wcopy = [wv[d] for d in wv if "copyBuffer" in wn[d] and wv[d] > 0.25 * copy_kib]
+    if not fcopy or not wcopy:
+        raise SystemExit("no 512 MiB calibration copy in the counter runs (run bench.py with --calib-copy)")
+    fscale, wscale = copy_kib / fcopy[-1], copy_kib / wcopy[-1]
+    acc = defaultdict(lambda: [0.0, 0.0, 0, 0])
+    for d, v in fv.items():
+        k = lib_kernel_name(fn[d])
+        if k:
+            acc[k][0] += v * fscale * 1024.0
+            acc[k][2] += 1
+    for d, v in wv.items():
+        k = lib_kernel_name(wn[d])
+        if k:
+            acc[k][1] += v * wscale * 1024.0
+            acc[k][3] += 1
+    out = {"_lib": digest, "_scale": {"fetch": fscale, "write": wscale},
+           "_source": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, one FP64 solve each, scaled by a 512 MiB copy"}
+    for k, (fb, wb, nf, nw) in sorted(acc.items()):
+        if nf and nw:
+            out[k] = round(fb / nf + wb / nw)
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"bench: wrote {out_path} ({len(out) - 3} kernels, scale fetch {fscale:.3f} write {wscale:.3f})",
+          file=sys.stderr)
+
+
 def workload_name(p, precision):
     return p.name.rsplit("-", 1)[0] + "-" + precision
 
@@ -441,7 +505,13 @@ def main():
                     help="HBM bytes per dispatch from counter runs of this library build")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM counters)")
+    ap.add_argument("--traffic-from-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write --traffic from two rocprofv3 counter-collection files and exit")
     args = ap.parse_args()
+    if args.traffic_from_pmc:
+        from paper_1304_5583_amd import binding as B
+        traffic_from_pmc(args.traffic_from_pmc[0], args.traffic_from_pmc[1], args.traffic, lib_digest(B))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the DFC blocks would "
               f"shard across GPUs with no communication until the combine, which this build does "
