@@ -119,7 +119,7 @@ def lib_kernel_name(rocprof_name):
     if m:
         return "k_dgemm_sym" if m.group(4) == "true" else f"k_dgemm<{m.group(2)}, {m.group(3)}>"
     base = re.sub(r"<.*$", "", n)
-    base = {"k_update_Z_w": "k_update_Z", "k_estep_w": "k_estep"}.get(base, base)
+    base = {"k_update_Z_w": "k_update_Z", "k_estep_w": "k_estep", "k_form_Y_w": "k_form_Y"}.get(base, base)
     return base if base in HBM_KERNELS or base.startswith("k_") else None
 
 
