@@ -1138,8 +1138,9 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             tm("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, st); });
             tm("k_ref_next", 0.0, 0.0, [&] { lrr::launch_ref_next(b.ref, t, st); });
         }
-        // two Newton-Schulz steps X <- X (I + (I - X^T X)/2); an estimate that is
-        // still far from orthonormal before the second step restarts from I
+        // up to two Newton-Schulz steps X <- X (I + (I - X^T X)/2), the second
+        // only where the first started above 1e-8; an estimate that is still far
+        // from orthonormal before its last step restarts from I
         tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run(b.ref, t, b.svt_run, st); });
         for (int ns = 0; ns < 2; ++ns) {
             tm("k_dgemm_sym", hL * f_L3, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, st); });
@@ -1148,8 +1149,10 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, st);
             });
             tm("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, st); });
+            if (ns == 0) tm("k_orth_decide", 0.0, 0.0, [&] { lrr::launch_orth_decide(b.ref, t, st); });
         }
         tm("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, b.warm, st); });
+        tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run(b.ref, t, b.svt_run, st); });
         tm("k_dgemm<false, false>", f_L3, 0.0, [&] {
             lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, st);
         });
@@ -1230,8 +1233,9 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
                 sync();
             }
-            // two Newton-Schulz steps X <- X (I + (I - X^T X)/2); an estimate that is
-            // still far from orthonormal before the second step restarts from I
+            // up to two Newton-Schulz steps X <- X (I + (I - X^T X)/2), the second
+            // only where the first started above 1e-8; an estimate that is still far
+            // from orthonormal before its last step restarts from I
             double f_L3 = 0.0;
             for (int bb = 0; bb < t; ++bb)
                 if (h_run[bb]) f_L3 += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
@@ -1243,8 +1247,10 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                     lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, s);
                 });
                 timed("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, s); });
+                if (ns == 0) timed("k_orth_decide", 0.0, 0.0, [&] { lrr::launch_orth_decide(b.ref, t, s); });
             }
             timed("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, b.warm, s); });
+            timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run(b.ref, t, b.svt_run, s); });
             timed("k_dgemm<false, false>", f_L3, 0.0, [&] {
                 lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, s);
             });
