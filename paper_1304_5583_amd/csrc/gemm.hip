@@ -54,10 +54,12 @@ __device__ __forceinline__ double buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned o
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
-// SYM (with TA, !TB, BM = BN, C square): C = A^T A.  Tile (P, Q) and tile (Q, P)
-// multiply the same pairs of numbers in the same order (the MFMA products of a
-// chunk commute), so the computed product is exactly symmetric; only the tiles
-// with P <= Q run, and an off-diagonal tile also writes its transpose.
+// SYM (with TA, !TB, BM = BN, C square): C = A^T B for a product that is
+// symmetric in exact arithmetic (A^T A, or X^T (B X) with B symmetric); only the
+// tiles with P <= Q run, and an off-diagonal tile also writes its transpose, so
+// the result is exactly symmetric.  For A^T A it is bitwise the full product:
+// tile (P, Q) and tile (Q, P) multiply the same pairs of numbers in the same
+// order (the MFMA products of a chunk commute).
 // Byte offsets inside one K-tile's panel are below 2^31 while lda * BM and
 // ldb * 64 stay below 2^28 doubles (leading dimensions below four million).
 template <int BM, bool TA, bool TB, bool SYM = false>
@@ -65,7 +67,7 @@ __global__ __launch_bounds__(256, 4) void k_dgemm(const GemmDesc* __restrict__ d
                                                   int total) {
     constexpr int WM = BM / 2, TX = WM / 16;
     constexpr int NA = BM * BK / 256, NB = BN * BK / 256;   // operand elements per thread and K-tile
-    static_assert(!SYM || (TA && !TB && BM == BN), "symmetric tiles need C = A^T A with square tiles");
+    static_assert(!SYM || (TA && !TB && BM == BN), "symmetric tiles need C = A^T B with square tiles");
     const int per = SYM ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
     // double-buffered operand tiles: As[buf][k][i] = op(A)(m0+i, k0+k)
     __shared__ double As[2][BK][BM + PAD];

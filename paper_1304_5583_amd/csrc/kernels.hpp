@@ -8,9 +8,10 @@ namespace lrr {
 // gemm.hip
 void launch_dgemm(const GemmDesc* d_descs, int count, int maxM, int maxN, bool ta, bool tb,
                   hipStream_t stream);
-// C = A^T A for square C (descriptors with M = N): only the tiles on and above
-// the diagonal are computed, the others mirrored (bitwise the full product);
-// batches of fewer than 512 full tiles take the full kernel unless `always`
+// C = A^T B for square C (descriptors with M = N) known to be symmetric (A^T A,
+// X^T (B X)): only the tiles on and above the diagonal are computed, the others
+// mirrored (for A^T A bitwise the full product); batches of fewer than 512 full
+// tiles take the full kernel unless `always`
 void launch_dgemm_sym(const GemmDesc* d_descs, int count, int maxN, hipStream_t stream, bool always = false);
 // whether launch_dgemm_sym runs the triangle of tiles for this batch
 bool dgemm_sym_tiles(int count, int maxN);

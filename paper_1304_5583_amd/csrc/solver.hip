@@ -1124,9 +1124,8 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             tm("k_dgemm<false, false>", fl, 0.0, [&] {
                 lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, st);
             });
-            tm("k_dgemm<true, false>", fl, 0.0, [&] {
-                lrr::launch_dgemm(b.g_refSG, t, p.maxL, p.maxL, true, false, st);
-            });
+            // S = X^T (B X) is symmetric: upper tiles, mirrored
+            tm("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_refSG, t, p.maxL, st); });
             tm("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, st); });
             tm("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, st); });
             tm("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, st); });
@@ -1156,9 +1155,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         tm("k_dgemm<false, false>", f_L3, 0.0, [&] {
             lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, st);
         });
-        tm("k_dgemm<true, false>", f_L3, 0.0, [&] {
-            lrr::launch_dgemm(b.g_Bq, t, p.maxL, p.maxL, true, false, st);
-        });
+        tm("k_dgemm_sym", hL * f_L3, 0.0, [&] { lrr::launch_dgemm_sym(b.g_Bq, t, p.maxL, st); });
         // block-Jacobi passes for the couplings the refinement left (the whole
         // decomposition on a block's first thresholding step): one persistent launch
         tm("k_jacobi_solve", 0.0, 0.0, [&] {
@@ -1217,9 +1214,8 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 timed("k_dgemm<false, false>", fl, 0.0, [&] {
                     lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, s);
                 });
-                timed("k_dgemm<true, false>", fl, 0.0, [&] {
-                    lrr::launch_dgemm(b.g_refSG, t, p.maxL, p.maxL, true, false, s);
-                });
+                // S = X^T (B X) is symmetric: upper tiles, mirrored
+                timed("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_refSG, t, p.maxL, s); });
                 timed("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, s); });
                 timed("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, s); });
                 timed("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, s); });
@@ -1254,9 +1250,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             timed("k_dgemm<false, false>", f_L3, 0.0, [&] {
                 lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, s);
             });
-            timed("k_dgemm<true, false>", f_L3, 0.0, [&] {
-                lrr::launch_dgemm(b.g_Bq, t, p.maxL, p.maxL, true, false, s);
-            });
+            timed("k_dgemm_sym", hL * f_L3, 0.0, [&] { lrr::launch_dgemm_sym(b.g_Bq, t, p.maxL, s); });
             // block-Jacobi sweeps for the couplings the refinement left (the
             // whole decomposition on a block's first thresholding step)
             const int nb = p.maxL / p.bs;
