@@ -619,6 +619,7 @@ def main():
         line["segmentation"] = segmentation(B, torch, p, Zt, ctx, golden, reps=1 if p.n > 8192 else 3,
                                             St=St, Mt=Mt)
         del St
+        line["slr_graph"] = slr_graph(B, torch, p, Mt, Zt, ctx, reps=1 if p.n > 8192 else 3)
         del Zt, Mt
         torch.cuda.empty_cache()
         line["other_workloads"] = [other_workload(B, torch, ctx, c, 5 if c == 2 else 3, tuned)

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblrr.so")
-SOURCES = ["gemm.hip", "xgemm.hip", "jacobi.hip", "refsyev.hip", "chol.hip", "alm.hip", "adjoint.hip", "solver.hip", "diag.hip", "segment.hip", "slr.hip", "noalloc.hip"]
+SOURCES = ["gemm.hip", "xgemm.hip", "jacobi.hip", "refsyev.hip", "chol.hip", "alm.hip", "adjoint.hip", "solver.hip", "diag.hip", "segment.hip", "slr.hip", "noalloc.hip", "host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

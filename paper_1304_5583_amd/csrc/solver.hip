@@ -35,6 +35,7 @@
 #include "kernels.hpp"
 #include "../../include/lrr.h"
 #include "../../include/lrr_diag.h"
+#include "host.hpp"
 
 // Opt-in per-kernel timing with HIP events on the solve's stream.
 struct LrrProf {
@@ -109,11 +110,6 @@ struct LrrProf {
 struct Tape;   // record of the last dfc_lrr_solve for dfc_lrr_backward
 
 // One line of the autotuner's schedule table.
-struct TuneEntry {
-    int m, n, t, maxl, precision;     // the problem shape the entry is for
-    int eig_block, use_graph, check_every, coords;
-};
-
 struct lrr_ctx {
     LrrProf prof;
     int device = 0;
@@ -128,7 +124,7 @@ struct lrr_ctx {
     hipStream_t capture = nullptr;         // private stream for graph capture
     void* seg_ws = nullptr;                // workspace of lrr_segment (kept apart from the solver's)
     size_t seg_bytes = 0;
-    std::vector<TuneEntry> tune;           // schedule table (lrr_tune_load)
+    std::vector<lrr::host::TuneEntry> tune;           // schedule table (lrr_tune_load)
 };
 
 namespace {
@@ -240,59 +236,6 @@ int jacobi_bs(int maxl, int requested) {
 }
 
 int round_up(int x, int a) { return ((x + a - 1) / a) * a; }
-
-// Targeted Jacobi rounds.  need (nb x nb, p <= q at p * nb + q) marks the
-// index-block pairs that still hold an entry needing a rotation (p == q: inside
-// block p).  Greedy maximal matchings of the marked pairs, each completed to a
-// perfect matching of the nb blocks (a block inside which something is marked
-// goes with any free partner; the rest pair up in order), are written to out as
-// p | q << 16 per slot, nb / 2 slots per round.  Returns the number of rounds,
-// or -1 if more than cap would be needed.
-int plan_rounds(const int* need, int nb, int cap, int* out) {
-    std::vector<std::pair<int, int>> pend, keep;
-    std::vector<char> inner(nb, 0), used(nb);
-    for (int p = 0; p < nb; ++p)
-        for (int q = p; q < nb; ++q)
-            if (need[p * nb + q]) {
-                if (p == q) inner[p] = 1;
-                else pend.emplace_back(p, q);
-            }
-    int rounds = 0;
-    for (;;) {
-        bool left = !pend.empty();
-        for (int p = 0; p < nb && !left; ++p) left = inner[p] != 0;
-        if (!left) return rounds;
-        if (rounds == cap) return -1;
-        int* slot = out + (size_t)rounds * (nb / 2);
-        int ns = 0;
-        std::fill(used.begin(), used.end(), 0);
-        auto put = [&](int p, int q) {
-            slot[ns++] = std::min(p, q) | (std::max(p, q) << 16);
-            used[p] = used[q] = 1;
-            inner[p] = inner[q] = 0;   // a pair solve also sweeps inside both blocks
-        };
-        keep.clear();
-        for (const auto& e : pend) {
-            if (!used[e.first] && !used[e.second]) put(e.first, e.second);
-            else keep.push_back(e);
-        }
-        pend.swap(keep);
-        for (int p = 0; p < nb; ++p) {
-            if (!inner[p] || used[p]) continue;
-            int q = -1;
-            for (int x = 0; x < nb; ++x)
-                if (x != p && !used[x] && (q < 0 || (inner[x] && !inner[q]))) q = x;
-            put(p, q);   // nb is even, so a free partner exists
-        }
-        int u = -1;
-        for (int x = 0; x < nb; ++x) {
-            if (used[x]) continue;
-            if (u < 0) u = x;
-            else { put(u, x); u = -1; }
-        }
-        ++rounds;
-    }
-}
 
 // Lay out every buffer; with a null base only the size is computed.
 size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need_X) {
@@ -517,7 +460,7 @@ bool opts_valid(const lrr_opts& o, std::string& why) {
 // the schedule of a tuned solve: the table entry for this shape, if any
 void apply_tune(const lrr_ctx* ctx, lrr_opts& o, int m, int n, int t, int maxl) {
     if (!o.tune) return;
-    for (const TuneEntry& e : ctx->tune) {
+    for (const lrr::host::TuneEntry& e : ctx->tune) {
         if (e.m == m && e.n == n && e.t == t && e.maxl == maxl && e.precision == o.precision) {
             o.eig_block = e.eig_block;
             o.use_graph = e.use_graph;
@@ -526,51 +469,6 @@ void apply_tune(const lrr_ctx* ctx, lrr_opts& o, int m, int n, int t, int maxl) 
             return;
         }
     }
-}
-
-// parse a schedule table; returns false with a message naming the line
-bool parse_tune(const char* path, std::vector<TuneEntry>& out, std::string& why) {
-    FILE* f = std::fopen(path, "r");
-    if (!f) { why = std::string("cannot open ") + path; return false; }
-    char line[512];
-    int no = 0;
-    bool ok = true;
-    while (std::fgets(line, sizeof(line), f)) {
-        ++no;
-        if (char* c = std::strchr(line, '#')) *c = '\0';
-        bool blank = true;
-        for (const char* c = line; *c; ++c) if (!std::isspace((unsigned char)*c)) { blank = false; break; }
-        if (blank) continue;
-        TuneEntry e;
-        char extra;
-        const int k = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %c", &e.m, &e.n, &e.t, &e.maxl, &e.precision,
-                                  &e.eig_block, &e.use_graph, &e.check_every, &e.coords, &extra);
-        if (k != 9 || e.m < 1 || e.n < 1 || e.t < 1 || e.maxl < 1 || e.precision < 0 || e.precision > 2 ||
-            (e.eig_block != 16 && e.eig_block != 32) || e.use_graph < 0 || e.use_graph > 3 ||
-            e.check_every < 1 || e.coords < 0 || e.coords > 2) {
-            why = std::string(path) + ": malformed entry on line " + std::to_string(no);
-            ok = false;
-            break;
-        }
-        out.push_back(e);
-    }
-    std::fclose(f);
-    return ok;
-}
-
-lrr_status check_partition_impl(int n, int t, const int* perm, const int* offsets, std::string& why) {
-    if (n <= 0 || t <= 0 || t > n) { why = "need 0 < t <= n"; return LRR_EINVAL; }
-    if (!perm || !offsets) { why = "perm and offsets must not be NULL"; return LRR_EINVAL; }
-    if (offsets[0] != 0 || offsets[t] != n) { why = "offsets must start at 0 and end at n"; return LRR_EINVAL; }
-    for (int i = 0; i < t; ++i)
-        if (offsets[i + 1] <= offsets[i]) { why = "offsets must be strictly increasing"; return LRR_EINVAL; }
-    std::vector<char> seen(n, 0);
-    for (int j = 0; j < n; ++j) {
-        const int v = perm[j];
-        if (v < 0 || v >= n || seen[v]) { why = "perm is not a permutation of 0..n-1"; return LRR_EINVAL; }
-        seen[v] = 1;
-    }
-    return LRR_OK;
 }
 
 struct Problem {
@@ -1279,7 +1177,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 for (int bb = 0; bb < t && rounds >= 0; ++bb) {
                     const int nbb = p.L[bb] / p.bs;
                     // the block's schedule holds nbb - 1 rounds
-                    const int rb = plan_rounds(h_need + need_off[bb], nbb, std::min((nb - 1) / 2, nbb - 1),
+                    const int rb = lrr::host::plan_rounds(h_need + need_off[bb], nbb, std::min((nb - 1) / 2, nbb - 1),
                                                h_sched + sched_off[bb]);
                     rounds = rb < 0 ? -1 : std::max(rounds, rb);
                     block_rounds[bb] = rb;
@@ -1905,9 +1803,9 @@ lrr_status lrr_ctx_create(int device, lrr_ctx** out) {
     lrr_ctx* c = new lrr_ctx();
     c->device = device;
     if (const char* path = std::getenv("LRR_TUNE_TABLE")) {
-        std::vector<TuneEntry> t;
+        std::vector<lrr::host::TuneEntry> t;
         std::string why;
-        if (parse_tune(path, t, why)) c->tune = std::move(t);
+        if (lrr::host::parse_tune(path, t, why)) c->tune = std::move(t);
     }
     *out = c;
     return LRR_OK;
@@ -1916,9 +1814,9 @@ lrr_status lrr_ctx_create(int device, lrr_ctx** out) {
 lrr_status lrr_tune_load(lrr_ctx* ctx, const char* path) {
     if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
     if (!path) { ctx->tune.clear(); return LRR_OK; }
-    std::vector<TuneEntry> t;
+    std::vector<lrr::host::TuneEntry> t;
     std::string why;
-    if (!parse_tune(path, t, why)) return fail(ctx, LRR_EINVAL, why);
+    if (!lrr::host::parse_tune(path, t, why)) return fail(ctx, LRR_EINVAL, why);
     ctx->tune = std::move(t);
     return LRR_OK;
 }
@@ -1946,7 +1844,7 @@ const char* lrr_last_error(const lrr_ctx* ctx) {
 
 lrr_status lrr_check_partition(int n, int t, const int* perm, const int* offsets) {
     std::string why;
-    lrr_status st = check_partition_impl(n, t, perm, offsets, why);
+    lrr_status st = lrr::host::check_partition(n, t, perm, offsets, why);
     if (st != LRR_OK) return fail(nullptr, st, why);
     return LRR_OK;
 }
@@ -2017,7 +1915,7 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
         return fail(ctx, LRR_EINVAL, "leading dimensions must be below 4194304");
     if (!(lambda > 0) || !std::isfinite(lambda)) return fail(ctx, LRR_EINVAL, "lambda must be positive and finite");
     std::string why;
-    if (check_partition_impl(n, t, perm, offsets, why) != LRR_OK) return fail(ctx, LRR_EINVAL, why);
+    if (lrr::host::check_partition(n, t, perm, offsets, why) != LRR_OK) return fail(ctx, LRR_EINVAL, why);
     lrr_opts o;
     if (opts) o = *opts; else lrr_opts_default(&o);
     if (!opts_valid(o, why)) return fail(ctx, LRR_EINVAL, why);
@@ -2103,7 +2001,7 @@ lrr_status dfc_lrr_solve_local(lrr_ctx* ctx, int m, int n, const void* M, int ld
         return fail(ctx, LRR_EINVAL, "leading dimensions must be below 4194304");
     if (!(lambda > 0) || !std::isfinite(lambda)) return fail(ctx, LRR_EINVAL, "lambda must be positive and finite");
     std::string why;
-    if (check_partition_impl(n, t, perm, offsets, why) != LRR_OK) return fail(ctx, LRR_EINVAL, why);
+    if (lrr::host::check_partition(n, t, perm, offsets, why) != LRR_OK) return fail(ctx, LRR_EINVAL, why);
     lrr_opts o;
     if (opts) o = *opts; else lrr_opts_default(&o);
     if (!opts_valid(o, why)) return fail(ctx, LRR_EINVAL, why);
@@ -2177,7 +2075,7 @@ lrr_status dfc_lrr_backward(lrr_ctx* ctx, const void* dZ, int lddz, double* dlam
 
 lrr_status lrr_diag_plan_rounds(const int* need, int nb, int cap, int* out, int* rounds) {
     if (!need || !out || !rounds || nb < 2 || nb > 65534 || (nb & 1) || cap < 0) return LRR_EINVAL;
-    *rounds = plan_rounds(need, nb, cap, out);
+    *rounds = lrr::host::plan_rounds(need, nb, cap, out);
     return LRR_OK;
 }
 
