@@ -19,8 +19,13 @@
  *    operand with 32-bit byte offsets; a larger ld is LRR_EINVAL).
  *    A column is one data point, so a row-major (n, m) tensor holds M^T.
  *  - Matrix arguments are DEVICE pointers on the ctx's device, element type
- *    double in every precision form (the form selects the arithmetic of the
- *    large products, not the storage).
+ *    double by default in every precision form (the form selects the
+ *    arithmetic of the large products, not the storage).  With opts.io_type =
+ *    LRR_IO_FP32 the forward entry points (lrr_solve, dfc_lrr_solve,
+ *    dfc_lrr_solve_local) take and return float buffers instead: the inputs
+ *    are widened to FP64 copies in the ctx, the iteration state stays FP64, and
+ *    the outputs are rounded to FP32 once at the end (extra ctx memory: one FP64
+ *    copy of every matrix argument).
  *    Index arrays (perm, offsets) and the info arrays are HOST pointers.
  *  - The caller owns every argument buffer.  The library owns its workspace,
  *    which lives in the ctx and is reused (and grown) across calls.
@@ -69,6 +74,12 @@ typedef enum {
     LRR_MIXED_BF16 = 2       /* operands split x = hi + lo in BF16, three BF16     */
                              /* MFMA products (hi hi + hi lo + lo hi), FP32 accum. */
 } lrr_precision;
+
+/* Element type of the matrix arguments of the forward entry points. */
+typedef enum {
+    LRR_IO_FP64 = 0,         /* double buffers (default)                            */
+    LRR_IO_FP32 = 1          /* float buffers; FP64 state inside (see above)        */
+} lrr_io_type;
 
 /* The Z-step solves (I + A^T A) Z = A^T (X - E + Y1/mu) + J - Y2/mu (Eq. 2's
  * augmented Lagrangian).  Literal: the n x n matrix is factored (FP64 Cholesky)
@@ -136,7 +147,9 @@ typedef struct {
     int tune;                /* 1: take eig_block, use_graph, check_every, coords   */
                              /* from the ctx's schedule table entry for this shape  */
                              /* (lrr_tune_load), if there is one; 0 (default): not  */
-    int reserved[4];         /* must be zero                                        */
+    int io_type;             /* lrr_io_type of the matrix arguments (forward entry  */
+                             /* points; not with save_for_backward)                 */
+    int reserved[3];         /* must be zero                                        */
 } lrr_opts;
 
 /* Per-block results; every pointer may be NULL, each non-NULL array has t entries. */

@@ -27,6 +27,7 @@ LRR_EINVAL, LRR_ENOMEM, LRR_EDEVICE, LRR_ENUMERIC, LRR_ENOTAPE = -1, -2, -3, -4,
 LRR_FP64, LRR_FP32, LRR_MIXED_BF16 = 0, 1, 2
 LRR_COORDS_AUTO, LRR_COORDS_FULL, LRR_COORDS_REDUCED = 0, 1, 2
 LRR_SOLVE_AUTO, LRR_SOLVE_LITERAL, LRR_SOLVE_PUSHTHROUGH = 0, 1, 2
+LRR_IO_FP64, LRR_IO_FP32 = 0, 1
 STATUS_NAMES = {0: "LRR_OK", 1: "LRR_NOT_CONVERGED", -1: "LRR_EINVAL", -2: "LRR_ENOMEM",
                 -3: "LRR_EDEVICE", -4: "LRR_ENUMERIC", -5: "LRR_ENOTAPE"}
 
@@ -38,7 +39,7 @@ class lrr_opts(C.Structure):
         ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("check_every", C.c_int),
         ("max_sweeps", C.c_int), ("save_for_backward", C.c_int), ("checkpoint_every", C.c_int),
         ("eig_block", C.c_int), ("use_graph", C.c_int), ("coords", C.c_int), ("tune", C.c_int),
-        ("reserved", C.c_int * 4),
+        ("io_type", C.c_int), ("reserved", C.c_int * 3),
     ]
 
 
@@ -241,20 +242,37 @@ def _require_cuda_f64(torch, *ts):
             raise TypeError("expected contiguous float64 CUDA tensors")
 
 
+def _io(torch, opts, *ts):
+    """Element type of a forward call from its input tensors: float64 (the
+    default) or float32 (opts.io_type = LRR_IO_FP32, float32 outputs); returns
+    (opts to pass, output dtype)."""
+    dts = {t.dtype for t in ts if t is not None}
+    if dts == {torch.float32}:
+        o = lrr_opts()
+        C.pointer(o)[0] = opts
+        o.io_type = LRR_IO_FP32
+        for t in ts:
+            if t is not None and (not t.is_cuda or not t.is_contiguous()):
+                raise TypeError("expected contiguous float32 CUDA tensors")
+        return o, torch.float32
+    _require_cuda_f64(torch, *ts)
+    return opts, torch.float64
+
+
 def lrr_solve(At, Xt, lam: float, opts: lrr_opts | None = None, ctx: Context | None = None,
               want_E: bool = True):
     """Eq. (2) with one block.  At: (n, m) tensor holding A (m x n); Xt: (l, m)
-    holding X (m x l).  Returns (Zt (l, n) holding Z, Et (l, m) or None, info)."""
+    holding X (m x l).  Returns (Zt (l, n) holding Z, Et (l, m) or None, info).
+    float32 A and X select FP32 I/O (float32 outputs, FP64 state)."""
     import torch
-    _require_cuda_f64(torch, At, Xt)
+    opts, odt = _io(torch, opts or lrr_opts_default(), At, Xt)
     n, m = At.shape
     l, m2 = Xt.shape
     if m2 != m:
         raise ValueError("A and X must have the same number of rows")
     ctx = ctx or get_context(At.device.index or 0)
-    opts = opts or lrr_opts_default()
-    Zt = torch.empty((l, n), dtype=torch.float64, device=At.device)
-    Et = torch.empty((l, m), dtype=torch.float64, device=At.device) if want_E else None
+    Zt = torch.empty((l, n), dtype=odt, device=At.device)
+    Et = torch.empty((l, m), dtype=odt, device=At.device) if want_E else None
     info, arrs = _make_info(1)
     st = load_library().lrr_solve(ctx.handle, m, n, l, C.c_void_p(At.data_ptr()), m,
                                   C.c_void_p(Xt.data_ptr()), m, float(lam), C.byref(opts),
@@ -268,18 +286,20 @@ def lrr_solve(At, Xt, lam: float, opts: lrr_opts | None = None, ctx: Context | N
 def dfc_lrr_solve(Mt, lam: float, perm, offsets, opts: lrr_opts | None = None,
                   ctx: Context | None = None, want_S: bool = True, Zt=None):
     """Algorithm 1.  Mt: (n, m) tensor holding M (m x n).  Returns
-    (Zt (n, n) holding Z, St (n, m) holding S or None, info)."""
+    (Zt (n, n) holding Z, St (n, m) holding S or None, info).  A float32 Mt
+    selects FP32 I/O (float32 outputs, FP64 state inside)."""
     import torch
-    _require_cuda_f64(torch, Mt)
+    opts, odt = _io(torch, opts or lrr_opts_default(), Mt)
     n, m = Mt.shape
     perm = np.ascontiguousarray(perm, dtype=np.int32)
     offsets = np.ascontiguousarray(offsets, dtype=np.int32)
     t = len(offsets) - 1
     ctx = ctx or get_context(Mt.device.index or 0)
-    opts = opts or lrr_opts_default()
     if Zt is None:
-        Zt = torch.empty((n, n), dtype=torch.float64, device=Mt.device)
-    St = torch.empty((n, m), dtype=torch.float64, device=Mt.device) if want_S else None
+        Zt = torch.empty((n, n), dtype=odt, device=Mt.device)
+    elif Zt.dtype != odt or Zt.shape != (n, n) or not Zt.is_contiguous():
+        raise TypeError("Zt must be a contiguous (n, n) tensor of the input's dtype")
+    St = torch.empty((n, m), dtype=odt, device=Mt.device) if want_S else None
     info, arrs = _make_info(t)
     st = load_library().dfc_lrr_solve(ctx.handle, m, n, C.c_void_p(Mt.data_ptr()), m, float(lam), t,
                                       _ip(perm), _ip(offsets), C.byref(opts),
@@ -295,16 +315,17 @@ def dfc_lrr_solve_local(Mt, lam: float, perm, offsets, combine_rank: int = 0, op
     """Footnote variant of Section 2.2 (every block its own dictionary, truncated-SVD
     combine of diag(J_1..J_t)).  Same tensors and return value as dfc_lrr_solve."""
     import torch
-    _require_cuda_f64(torch, Mt)
+    opts, odt = _io(torch, opts or lrr_opts_default(), Mt)
     n, m = Mt.shape
     perm = np.ascontiguousarray(perm, dtype=np.int32)
     offsets = np.ascontiguousarray(offsets, dtype=np.int32)
     t = len(offsets) - 1
     ctx = ctx or get_context(Mt.device.index or 0)
-    opts = opts or lrr_opts_default()
     if Zt is None:
-        Zt = torch.empty((n, n), dtype=torch.float64, device=Mt.device)
-    St = torch.empty((n, m), dtype=torch.float64, device=Mt.device) if want_S else None
+        Zt = torch.empty((n, n), dtype=odt, device=Mt.device)
+    elif Zt.dtype != odt or Zt.shape != (n, n) or not Zt.is_contiguous():
+        raise TypeError("Zt must be a contiguous (n, n) tensor of the input's dtype")
+    St = torch.empty((n, m), dtype=odt, device=Mt.device) if want_S else None
     info, arrs = _make_info(t)
     st = load_library().dfc_lrr_solve_local(ctx.handle, m, n, C.c_void_p(Mt.data_ptr()), m, float(lam), t,
                                             _ip(perm), _ip(offsets), int(combine_rank), C.byref(opts),

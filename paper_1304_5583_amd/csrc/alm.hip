@@ -69,6 +69,15 @@ __global__ __launch_bounds__(256) void k_copy_cols(const double* __restrict__ X,
     for (int i = threadIdx.x; i < m; i += 256) Y[i + j * ldy] = X[i + j * ldx];
 }
 
+// element-type conversion of a column-major matrix (one workgroup per column):
+// FP32 -> FP64 is exact, FP64 -> FP32 rounds to nearest
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_convert_cols(const TI* __restrict__ src, long lds, TO* __restrict__ dst,
+                                                      long ldd, int rows) {
+    const long j = blockIdx.x;
+    for (int i = threadIdx.x; i < rows; i += 256) dst[i + j * ldd] = static_cast<TO>(src[i + j * lds]);
+}
+
 __global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ M, long ldm, int m,
                                                     int* flag) {
     const int j = blockIdx.x;
@@ -498,6 +507,14 @@ void launch_scatter_cols(const double* X, long ldx, double* S, long lds, int m, 
 }
 void launch_copy_cols(const double* X, long ldx, double* Y, long ldy, int m, int ncols, hipStream_t s) {
     hipLaunchKernelGGL(k_copy_cols, dim3(ncols), dim3(256), 0, s, X, ldx, Y, ldy, m);
+}
+void launch_widen_cols(const float* src, long lds, double* dst, long ldd, int rows, int cols, hipStream_t s) {
+    if (rows > 0 && cols > 0)
+        hipLaunchKernelGGL((k_convert_cols<float, double>), dim3(cols), dim3(256), 0, s, src, lds, dst, ldd, rows);
+}
+void launch_narrow_cols(const double* src, long lds, float* dst, long ldd, int rows, int cols, hipStream_t s) {
+    if (rows > 0 && cols > 0)
+        hipLaunchKernelGGL((k_convert_cols<double, float>), dim3(cols), dim3(256), 0, s, src, lds, dst, ldd, rows);
 }
 void launch_nonfinite(const double* M, long ldm, int m, int n, int* d_flag, hipStream_t s) {
     hipLaunchKernelGGL(k_nonfinite, dim3(n), dim3(256), 0, s, M, ldm, m, d_flag);

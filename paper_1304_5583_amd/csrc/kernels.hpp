@@ -78,6 +78,9 @@ void launch_gather_cols(const double* M, long ldm, double* X, long ldx, int m, i
 void launch_scatter_cols(const double* X, long ldx, double* S, long lds, int m, int ncols,
                          const int* d_perm, hipStream_t s);
 void launch_copy_cols(const double* X, long ldx, double* Y, long ldy, int m, int ncols, hipStream_t s);
+// FP32 <-> FP64 copies of a column-major matrix
+void launch_widen_cols(const float* src, long lds, double* dst, long ldd, int rows, int cols, hipStream_t s);
+void launch_narrow_cols(const double* src, long lds, float* dst, long ldd, int rows, int cols, hipStream_t s);
 void launch_nonfinite(const double* M, long ldm, int m, int n, int* d_flag, hipStream_t s);
 void launch_form_Y(const double* Z, const double* Y2, double* Y, double* colsq, int n, long ld, int ncols,
                    const int* colblk, const int* active, const DevIter* it, hipStream_t s);

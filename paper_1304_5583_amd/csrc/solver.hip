@@ -25,6 +25,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
+#include <initializer_list>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -123,6 +124,8 @@ struct lrr_ctx {
     Tape* tape = nullptr;
     hipStream_t capture = nullptr;         // private stream for graph capture
     void* seg_ws = nullptr;                // workspace of lrr_segment (kept apart from the solver's)
+    void* io_ws = nullptr;                 // FP64 copies of FP32 arguments (opts.io_type)
+    size_t io_bytes = 0;
     size_t seg_bytes = 0;
     std::vector<lrr::host::TuneEntry> tune;           // schedule table (lrr_tune_load)
 };
@@ -452,6 +455,11 @@ bool opts_valid(const lrr_opts& o, std::string& why) {
         if (o.precision != LRR_FP64) { why = "the literal solve form runs in FP64 only"; return false; }
         if (o.coords == LRR_COORDS_REDUCED) { why = "the literal solve form needs full coordinates"; return false; }
         if (o.save_for_backward) { why = "the reverse mode records the push-through solve form"; return false; }
+    }
+    if (o.io_type != LRR_IO_FP64 && o.io_type != LRR_IO_FP32) { why = "unknown io_type"; return false; }
+    if (o.io_type == LRR_IO_FP32 && o.save_for_backward) {
+        why = "the reverse mode takes FP64 buffers (io_type must be LRR_IO_FP64 with save_for_backward)";
+        return false;
     }
     for (int r : o.reserved) if (r != 0) { why = "reserved fields must be zero"; return false; }
     return true;
@@ -1827,6 +1835,7 @@ void lrr_ctx_destroy(lrr_ctx* ctx) {
         ctx->prof.release();
         if (ctx->ws) (void)hipFree(ctx->ws);
         if (ctx->seg_ws) (void)hipFree(ctx->seg_ws);
+        if (ctx->io_ws) (void)hipFree(ctx->io_ws);
         if (ctx->dflag) (void)hipFree(ctx->dflag);
         if (ctx->dwork) (void)hipFree(ctx->dwork);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -1861,7 +1870,7 @@ lrr_status lrr_workspace_bytes(int m, int n, int t, const int* offsets, const lr
     return LRR_OK;
 }
 
-lrr_status lrr_solve(lrr_ctx* ctx, int m, int n, int l, const void* A, int lda, const void* X, int ldx,
+static lrr_status lrr_solve_f64(lrr_ctx* ctx, int m, int n, int l, const void* A, int lda, const void* X, int ldx,
                      double lambda, const lrr_opts* opts, void* Z, int ldz, void* E, int lde,
                      lrr_info* info, void* stream) {
     if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
@@ -1904,7 +1913,7 @@ lrr_status lrr_solve(lrr_ctx* ctx, int m, int n, int l, const void* A, int lda, 
     });
 }
 
-lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, double lambda, int t,
+static lrr_status dfc_lrr_solve_f64(lrr_ctx* ctx, int m, int n, const void* M, int ldm, double lambda, int t,
                          const int* perm, const int* offsets, const lrr_opts* opts, void* Z, int ldz,
                          void* S, int lds, lrr_info* info, void* stream) {
     if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
@@ -1990,7 +1999,7 @@ lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, dou
     });
 }
 
-lrr_status dfc_lrr_solve_local(lrr_ctx* ctx, int m, int n, const void* M, int ldm, double lambda, int t,
+static lrr_status dfc_lrr_solve_local_f64(lrr_ctx* ctx, int m, int n, const void* M, int ldm, double lambda, int t,
                                const int* perm, const int* offsets, int combine_rank, const lrr_opts* opts,
                                void* Z, int ldz, void* S, int lds, lrr_info* info, void* stream) {
     if (!ctx) return fail(nullptr, LRR_EINVAL, "ctx must not be NULL");
@@ -2077,6 +2086,114 @@ lrr_status lrr_diag_plan_rounds(const int* need, int nb, int cap, int* out, int*
     if (!need || !out || !rounds || nb < 2 || nb > 65534 || (nb & 1) || cap < 0) return LRR_EINVAL;
     *rounds = lrr::host::plan_rounds(need, nb, cap, out);
     return LRR_OK;
+}
+
+// ---------------------------------------------------------------- FP32 I/O
+// The forward entry points with opts.io_type = LRR_IO_FP32: FP32 inputs are
+// widened into FP64 copies in the ctx's I/O area, the FP64 entry point runs on
+// them, and its FP64 outputs (also in the I/O area) are rounded into the
+// caller's FP32 buffers.
+
+static bool io_args_ok(lrr_ctx* ctx, std::initializer_list<std::pair<int, int>> ld_rows) {
+    for (const auto& lr : ld_rows)
+        if (lr.first < lr.second || lr.first >= lrr::kGemmMaxLd) {
+            fail(ctx, LRR_EINVAL, "leading dimension too small or not below 4194304");
+            return false;
+        }
+    return true;
+}
+
+static double* io_area(lrr_ctx* ctx, size_t doubles) {
+    const size_t bytes = doubles * sizeof(double);
+    if (ctx->io_bytes < bytes) {
+        if (ctx->io_ws) { (void)hipFree(ctx->io_ws); ctx->io_ws = nullptr; ctx->io_bytes = 0; }
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) throw std::bad_alloc();
+        ctx->io_ws = p;
+        ctx->io_bytes = bytes;
+    }
+    return static_cast<double*>(ctx->io_ws);
+}
+
+lrr_status lrr_solve(lrr_ctx* ctx, int m, int n, int l, const void* A, int lda, const void* X, int ldx,
+                     double lambda, const lrr_opts* opts, void* Z, int ldz, void* E, int lde,
+                     lrr_info* info, void* stream) {
+    if (!opts || opts->io_type == LRR_IO_FP64 || !ctx || m <= 0 || n <= 0 || l <= 0 || !A || !X || !Z)
+        return lrr_solve_f64(ctx, m, n, l, A, lda, X, ldx, lambda, opts, Z, ldz, E, lde, info, stream);
+    lrr_opts o = *opts;
+    std::string why;
+    if (!opts_valid(o, why)) return fail(ctx, LRR_EINVAL, why);
+    if (!io_args_ok(ctx, {{lda, m}, {ldx, m}, {ldz, n}, {E ? lde : m, m}})) return LRR_EINVAL;
+    o.io_type = LRR_IO_FP64;
+    return guarded(ctx, [&]() -> lrr_status {
+        LRR_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const size_t mn = (size_t)m * n, ml = (size_t)m * l, nl = (size_t)n * l;
+        double* A64 = io_area(ctx, mn + 2 * ml + nl);
+        double* X64 = A64 + mn;
+        double* Z64 = X64 + ml;
+        double* E64 = Z64 + nl;
+        lrr::launch_widen_cols(static_cast<const float*>(A), lda, A64, m, m, n, s);
+        lrr::launch_widen_cols(static_cast<const float*>(X), ldx, X64, m, m, l, s);
+        const lrr_status st = lrr_solve_f64(ctx, m, n, l, A64, m, X64, m, lambda, &o, Z64, n, E ? E64 : nullptr, m,
+                                            info, stream);
+        if (st != LRR_OK && st != LRR_NOT_CONVERGED) return st;
+        lrr::launch_narrow_cols(Z64, n, static_cast<float*>(Z), ldz, n, l, s);
+        if (E) lrr::launch_narrow_cols(E64, m, static_cast<float*>(E), lde, m, l, s);
+        LRR_HIP(hipStreamSynchronize(s));
+        return st;
+    });
+}
+
+// dfc_lrr_solve and dfc_lrr_solve_local share the FP32 I/O path
+extern "C++" template <typename F>
+static lrr_status dfc_io32(lrr_ctx* ctx, int m, int n, const void* M, int ldm, void* Z, int ldz, void* S, int lds,
+                           const lrr_opts* opts, void* stream, F&& solve64) {
+    lrr_opts o = *opts;
+    std::string why;
+    if (!opts_valid(o, why)) return fail(ctx, LRR_EINVAL, why);
+    if (!io_args_ok(ctx, {{ldm, m}, {ldz, n}, {S ? lds : m, m}})) return LRR_EINVAL;
+    o.io_type = LRR_IO_FP64;
+    return guarded(ctx, [&]() -> lrr_status {
+        LRR_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const size_t mn = (size_t)m * n, nn = (size_t)n * n;
+        double* M64 = io_area(ctx, 2 * mn + nn);
+        double* S64 = M64 + mn;
+        double* Z64 = S64 + mn;
+        lrr::launch_widen_cols(static_cast<const float*>(M), ldm, M64, m, m, n, s);
+        const lrr_status st = solve64(M64, &o, Z64, S ? S64 : nullptr);
+        if (st != LRR_OK && st != LRR_NOT_CONVERGED) return st;
+        lrr::launch_narrow_cols(Z64, n, static_cast<float*>(Z), ldz, n, n, s);
+        if (S) lrr::launch_narrow_cols(S64, m, static_cast<float*>(S), lds, m, n, s);
+        LRR_HIP(hipStreamSynchronize(s));
+        return st;
+    });
+}
+
+lrr_status dfc_lrr_solve(lrr_ctx* ctx, int m, int n, const void* M, int ldm, double lambda, int t,
+                         const int* perm, const int* offsets, const lrr_opts* opts, void* Z, int ldz,
+                         void* S, int lds, lrr_info* info, void* stream) {
+    if (!opts || opts->io_type == LRR_IO_FP64 || !ctx || m <= 0 || n <= 0 || !M || !Z)
+        return dfc_lrr_solve_f64(ctx, m, n, M, ldm, lambda, t, perm, offsets, opts, Z, ldz, S, lds, info, stream);
+    return dfc_io32(ctx, m, n, M, ldm, Z, ldz, S, lds, opts, stream,
+                    [&](const double* M64, const lrr_opts* o, double* Z64, double* S64) {
+                        return dfc_lrr_solve_f64(ctx, m, n, M64, m, lambda, t, perm, offsets, o, Z64, n, S64, m,
+                                                 info, stream);
+                    });
+}
+
+lrr_status dfc_lrr_solve_local(lrr_ctx* ctx, int m, int n, const void* M, int ldm, double lambda, int t,
+                               const int* perm, const int* offsets, int combine_rank, const lrr_opts* opts,
+                               void* Z, int ldz, void* S, int lds, lrr_info* info, void* stream) {
+    if (!opts || opts->io_type == LRR_IO_FP64 || !ctx || m <= 0 || n <= 0 || !M || !Z)
+        return dfc_lrr_solve_local_f64(ctx, m, n, M, ldm, lambda, t, perm, offsets, combine_rank, opts, Z, ldz, S,
+                                       lds, info, stream);
+    return dfc_io32(ctx, m, n, M, ldm, Z, ldz, S, lds, opts, stream,
+                    [&](const double* M64, const lrr_opts* o, double* Z64, double* S64) {
+                        return dfc_lrr_solve_local_f64(ctx, m, n, M64, m, lambda, t, perm, offsets, combine_rank, o,
+                                                       Z64, n, S64, m, info, stream);
+                    });
 }
 
 }  // extern "C"

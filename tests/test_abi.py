@@ -35,7 +35,8 @@ def test_opts_default_values():
     o = B.lrr_opts_default()
     assert o.precision == B.LRR_FP64 and o.mu0 == 1e-6 and o.rho == 1.1
     assert o.mu_max == 1e10 and o.tol == 1e-8 and o.max_iter == 1000
-    assert o.fixed_iters == 0 and o.checkpoint_every == 20 and list(o.reserved) == [0] * 4 and o.tune == 0
+    assert o.fixed_iters == 0 and o.checkpoint_every == 20 and list(o.reserved) == [0] * 3 and o.tune == 0
+    assert o.io_type == B.LRR_IO_FP64
     assert o.coords == 0
     assert o.use_graph == 1
     assert "gfx950" in B.lrr_version()
