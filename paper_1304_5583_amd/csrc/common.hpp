@@ -189,13 +189,27 @@ __host__ __device__ __forceinline__ void rr_pair(int N, int r, int k, int& a, in
 
 }  // namespace lrr
 
+// a failing call throws; its error is also taken out of HIP's last-error
+// state, so that it cannot surface at a later, unrelated error check
 #define LRR_HIP(call)                                                         \
     do {                                                                      \
         hipError_t _e = (call);                                               \
         if (_e != hipSuccess) {                                               \
+            (void)hipGetLastError();                                          \
             throw lrr::HipError(std::string(#call) + ": " + hipGetErrorString(_e)); \
         }                                                                     \
     } while (0)
+
+namespace lrr {
+// device allocation for the workspaces: false (and no HIP error left behind)
+// when the memory is not there, which the entry points report as LRR_ENOMEM
+inline bool try_device_alloc(void** p, size_t bytes) {
+    if (hipMalloc(p, bytes) == hipSuccess) return true;
+    *p = nullptr;
+    (void)hipGetLastError();
+    return false;
+}
+}  // namespace lrr
 
 namespace lrr {
 struct HipError {

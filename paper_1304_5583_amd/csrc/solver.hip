@@ -501,7 +501,7 @@ void ensure_ws(lrr_ctx* ctx, size_t bytes) {
     if (ctx->ws_bytes >= bytes) return;
     if (ctx->ws) { (void)hipFree(ctx->ws); ctx->ws = nullptr; ctx->ws_bytes = 0; }
     void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) throw std::bad_alloc();
+    if (!lrr::try_device_alloc(&p, bytes)) throw std::bad_alloc();
     ctx->ws = p;
     ctx->ws_bytes = bytes;
 }
@@ -1536,10 +1536,7 @@ static void tape_begin(lrr_ctx* ctx, const Problem& pr, const Plan& p) {
     const size_t need = tape_layout(tp, nullptr);
     if (need > tp.bytes) {
         tape_free(&tp);
-        if (hipMalloc(&tp.mem, need) != hipSuccess) {
-            tp.mem = nullptr;
-            throw std::bad_alloc();
-        }
+        if (!lrr::try_device_alloc(&tp.mem, need)) throw std::bad_alloc();
         tp.bytes = need;
     }
     tape_layout(tp, static_cast<char*>(tp.mem));
@@ -1762,7 +1759,7 @@ void* ctx_seg_workspace(lrr_ctx* ctx, size_t bytes) {
     if (ctx->seg_bytes < bytes) {
         if (ctx->seg_ws) { (void)hipFree(ctx->seg_ws); ctx->seg_ws = nullptr; ctx->seg_bytes = 0; }
         void* p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) throw std::bad_alloc();
+        if (!lrr::try_device_alloc(&p, bytes)) throw std::bad_alloc();
         ctx->seg_ws = p;
         ctx->seg_bytes = bytes;
     }
@@ -2108,7 +2105,7 @@ static double* io_area(lrr_ctx* ctx, size_t doubles) {
     if (ctx->io_bytes < bytes) {
         if (ctx->io_ws) { (void)hipFree(ctx->io_ws); ctx->io_ws = nullptr; ctx->io_bytes = 0; }
         void* p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) throw std::bad_alloc();
+        if (!lrr::try_device_alloc(&p, bytes)) throw std::bad_alloc();
         ctx->io_ws = p;
         ctx->io_bytes = bytes;
     }

@@ -164,3 +164,32 @@ def test_slr_graph_edges_and_errors():
         with pytest.raises(B.LRRError) as e:
             B.lrr_slr_graph(Mt, Zt, **kw)
         assert e.value.status == B.LRR_EINVAL
+
+
+def test_slr_graph_workspace_out_of_memory():
+    """A workspace the device cannot hold (the n x n affinity / Gram buffer at
+    n = 4 000 000, 128 TB) is LRR_ENOMEM before any kernel runs, and the same
+    context then serves a normal call (the failed allocation leaves no HIP
+    error behind)."""
+    torch = need_gpu()
+    import ctypes as C
+    from oracle import slr
+    from paper_1304_5583_amd import binding as B
+    n, nk = 4_000_000, 1
+    assert torch.cuda.get_device_properties(0).total_memory < 8.0 * n * n   # the request cannot fit
+    ctx = B.get_context(0)
+    Mt = torch.zeros((n, 1), dtype=torch.float64, device="cuda")
+    Zdummy = torch.zeros(16, dtype=torch.float64, device="cuda")   # never read: allocation fails first
+    nbr = torch.empty((n, nk), dtype=torch.int32, device="cuda")
+    w = torch.empty((n, nk), dtype=torch.float64, device="cuda")
+    info = B.lrr_slr_info()
+    st = B.load_library().lrr_slr_graph(ctx.handle, 1, n, C.c_void_p(Mt.data_ptr()), 1,
+                                        C.c_void_p(Zdummy.data_ptr()), n, nk, 0.1, C.c_void_p(nbr.data_ptr()),
+                                        C.c_void_p(w.data_ptr()), None, C.byref(info),
+                                        C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == B.LRR_ENOMEM, B.lrr_last_error(ctx)
+    del Mt, nbr, w
+    rng = np.random.default_rng(9)
+    M, Z = rng.standard_normal((8, 20)), rng.standard_normal((20, 20))
+    nb, _, _, inf = B.lrr_slr_graph(B.to_device_colmajor(M), B.to_device_colmajor(Z), 3, 0.1, ctx=ctx)
+    assert inf["converged"] and np.array_equal(nb.cpu().numpy(), slr.slr_neighbors(Z, 3))
