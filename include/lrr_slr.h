@@ -31,13 +31,20 @@
  *   stream     hipStream_t (NULL: the null stream)
  *
  * The Lasso is solved by a finite active-set method (Lawson and Hanson's, with
- * the free columns kept independent); a sample whose support would exceed 64
- * neighbours, or that exceeds 10 n_k + 20 steps, stops there.  The work runs on
- * `stream` in the ctx's segmentation workspace (not the solver's), which holds
- * one n x n FP64 matrix (first the affinities, then M^T M: 3.2 GB at
- * n = 20000); the call returns when the outputs are complete.  LRR_ENOMEM: the
- * workspace could not be allocated.  LRR_NOT_CONVERGED: outputs written,
- * but some sample stopped early (info->not_converged).
+ * the free columns kept independent, so a support never exceeds min(m, n_k));
+ * a sample that exceeds 10 n_k + 20 steps stops there.  Supports up to 64 are
+ * solved with their factorisations in on-chip memory; a sample whose support
+ * grows beyond that is solved again by a second pass that keeps the Cholesky
+ * factor of its free set in device memory and updates it as indices enter and
+ * leave.  The work runs on `stream` in the ctx's segmentation workspace (not
+ * the solver's), which holds one n x n FP64 matrix (first the affinities, then
+ * M^T M: 3.2 GB at n = 20000); the second pass, when needed, allocates
+ * (2 min(m, n_k)^2 + n_k^2) doubles per concurrently resident sample (at most
+ * the samples it has, and what the device can keep resident: about 6 GB at
+ * n_k = 500) and frees it before returning.  The call returns when the
+ * outputs are complete.  LRR_ENOMEM: a workspace could not be allocated.
+ * LRR_NOT_CONVERGED: outputs written, but some sample stopped early
+ * (info->not_converged).
  */
 #ifndef LRR_SLR_H
 #define LRR_SLR_H
@@ -52,6 +59,8 @@ typedef struct lrr_slr_info {
     int max_steps;       /* most active-set steps any sample needed             */
     int not_converged;   /* samples that stopped without meeting the conditions  */
     double max_kkt;      /* largest final optimality violation / sample scale   */
+    int large_support;   /* samples solved by the large-support pass            */
+    int max_support;     /* largest number of positive weights of any sample     */
 } lrr_slr_info;
 
 lrr_status lrr_slr_graph(lrr_ctx* ctx, int m, int n, const void* M, int ldm, const void* Z, int ldz, int nk,

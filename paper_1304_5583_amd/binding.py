@@ -52,7 +52,8 @@ class lrr_seg_info(C.Structure):
 
 
 class lrr_slr_info(C.Structure):
-    _fields_ = [("max_steps", C.c_int), ("not_converged", C.c_int), ("max_kkt", C.c_double)]
+    _fields_ = [("max_steps", C.c_int), ("not_converged", C.c_int), ("max_kkt", C.c_double),
+                ("large_support", C.c_int), ("max_support", C.c_int)]
 
 
 class lrr_info(C.Structure):

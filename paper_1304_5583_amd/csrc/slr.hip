@@ -18,7 +18,10 @@
 //                coordinates is one gathered row of G per free index, the
 //                factorisations of G_PP (|P| <= 64) run in LDS with all
 //                threads, the triangular solves in one wave with the unknowns
-//                in registers.
+//                in registers;
+//   large        samples whose free set outgrows 64 are solved again by a
+//                second pass that keeps the Cholesky factor of G_PP in device
+//                memory and updates it as indices enter and leave.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -294,7 +297,8 @@ __device__ void backward_w0(const double* A, int ldA, int p, const double* y, do
 __global__ __launch_bounds__(256) void k_slr_lasso(const double* __restrict__ G, long ldg, int nk, double alpha,
                                                    const int* __restrict__ nbr, double* __restrict__ wout,
                                                    double* __restrict__ obj, int* __restrict__ steps_out,
-                                                   double* __restrict__ kkt_out) {
+                                                   double* __restrict__ kkt_out, int* __restrict__ sup_out,
+                                                   int* __restrict__ big_list, int* __restrict__ big_count) {
     extern __shared__ char smem[];
     double* g = reinterpret_cast<double*>(smem);
     double* b = g + nk;
@@ -325,7 +329,7 @@ __global__ __launch_bounds__(256) void k_slr_lasso(const double* __restrict__ G,
     const double tol = kTol * scale, thr = kDepTol * dmax;
     int steps = 0;
     double viol = 0.0;
-    int status = 0;                          // 0 running, 1 optimal, 2 gave up
+    int status = 0;                          // 0 running, 1 optimal, 2 gave up, 3 support above kMaxP
     while (status == 0) {
         if (threadIdx.x == 0) state = 0;
         __syncthreads();
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(256) void k_slr_lasso(const double* __restrict__ G,
         block_argmin256(gmin, jmin, rv, ri, gj, j);
         if (!(gj < 0.0)) j = -1;             // only free coordinates violate: solve the face again
         if (j >= 0) {
-            if (p + 1 > kMaxP) { status = 2; break; }
+            if (p + 1 > kMaxP) { status = 3; break; }   // handed to the large-support pass
             // factor G over P + {j}; the last pivot decides dependence
             for (int e = threadIdx.x; e < (p + 1) * (p + 1); e += 256) {
                 const int r = e % (p + 1), c = e / (p + 1);
@@ -453,10 +457,14 @@ __global__ __launch_bounds__(256) void k_slr_lasso(const double* __restrict__ G,
         if (state == 2) { status = 2; break; }
     }
     // weights, optimal objective, statistics
+    double ns = 0.0;
     for (int a = threadIdx.x; a < nk; a += 256) {
         const int q = pos[a];
-        wout[(long)i * nk + a] = q >= 0 ? wP[q] : 0.0;
+        const double wa = q >= 0 ? wP[q] : 0.0;
+        wout[(long)i * nk + a] = wa;
+        ns += wa > 0.0 ? 1.0 : 0.0;
     }
+    const double nsup = block_sum256(ns, red);
     if (obj) {
         // w^T G w = w^T (g + 2 b - alpha) / 2 with the last gradient of the free set
         double t = 0.0;
@@ -470,6 +478,357 @@ __global__ __launch_bounds__(256) void k_slr_lasso(const double* __restrict__ G,
     if (threadIdx.x == 0) {
         steps_out[i] = steps;
         kkt_out[i] = status == 1 ? viol / scale : INFINITY;
+        sup_out[i] = (int)nsup;
+        if (status == 3) big_list[atomicAdd(big_count, 1)] = i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Large supports.  A sample whose free set outgrows kMaxP is solved again from
+// the start by k_slr_lasso_big with the same steps, one workgroup per sample
+// over a fixed set of slots.  Each slot owns, in device memory, two pmax x pmax
+// buffers for the Cholesky factor L of G_PP (column-major, ld = pmax; the
+// second receives the factor after a removal) and the n_k x n_k columns of G_i
+// gathered when their index first enters P.  The factor is kept up to date
+// instead of recomputed: an entering index appends the row L^-1 G_Pj and its
+// pivot; a leaving index is cut out and the trailing block takes a rank-one
+// update with the removed column (Golub and Van Loan, Matrix Computations,
+// Section 6.5.4).  z = L^-1 (b_P - alpha/2) is kept as well, so a face solve
+// is one backward substitution.
+
+constexpr int kDB = 32;          // diagonal block of the triangular solves
+constexpr int kDBld = kDB + 1;   // its LDS leading dimension (odd: no bank conflicts)
+
+__device__ double block_min256(double v, double* red) { return -block_max256(-v, red); }
+
+// L[o:o+nb, o:o+nb] (lower part) into D
+__device__ void stage_diag(const double* L, long ld, int o, int nb, double* D) {
+    for (int e = threadIdx.x; e < kDB * kDB; e += 256) {
+        const int r = e % kDB, c = e / kDB;
+        if (r < nb && c <= r) D[r + c * kDBld] = L[(o + r) + (long)(o + c) * ld];
+    }
+    __syncthreads();
+}
+
+// x = L^-1 x over the entries [k0, p), in place, given the entries [0, k0)
+// already solved: the rows below each diagonal block are updated by all
+// threads (one row per thread, coalesced down the columns), the block itself
+// is solved by wave 0 from LDS
+__device__ void big_forward(const double* L, long ld, int p, int k0, double* x, double* D) {
+    const int tid = threadIdx.x;
+    if (k0 > 0 && k0 < p) {
+        for (int i = k0 + tid; i < p; i += 256) {
+            double t = 0.0;
+            for (int c = 0; c < k0; ++c) t += L[i + (long)c * ld] * x[c];
+            x[i] -= t;
+        }
+        __syncthreads();
+    }
+    for (int o = k0; o < p; o += kDB) {
+        const int nb = min(kDB, p - o);
+        stage_diag(L, ld, o, nb, D);
+        if (tid < 64) forward_w0(D, kDBld, nb, x + o, x + o);
+        __syncthreads();
+        if (o + nb < p) {
+            for (int i = o + nb + tid; i < p; i += 256) {
+                double t = 0.0;
+                for (int c = 0; c < nb; ++c) t += L[i + (long)(o + c) * ld] * x[o + c];
+                x[i] -= t;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// x = L^-T x over the leading p entries, in place: blocks from the bottom; the
+// entries above a solved block take its contribution as 32-lane dot products
+// down their columns
+__device__ void big_backward(const double* L, long ld, int p, double* x, double* D) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (p <= 0) return;
+    for (int o = ((p - 1) / kDB) * kDB; o >= 0; o -= kDB) {
+        const int nb = min(kDB, p - o);
+        stage_diag(L, ld, o, nb, D);
+        if (tid < 64) backward_w0(D, kDBld, nb, x + o, x + o);
+        __syncthreads();
+        if (o > 0) {
+            const int r = lane & 31;
+            for (int c0 = 2 * wv; c0 < o; c0 += 8) {
+                const int c = c0 + (lane >> 5);
+                double t = (c < o && r < nb) ? L[o + r + (long)c * ld] * x[o + r] : 0.0;
+                for (int off = 16; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+                if (r == 0 && c < o) x[c] -= t;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// appends index j at free position p with weight w0, given y = L^-1 G_Pj and
+// the pivot d2 = G_jj - |y|^2 > 0; z gains its entry p
+__device__ void big_append(double* L, long ld, int& p, int j, double w0, double d2, const double* y, short* P,
+                           double* wP, short* pos, double* z, const double* b, double alpha, double* red) {
+    const double piv = sqrt(d2);
+    double t = 0.0;
+    for (int q = threadIdx.x; q < p; q += 256) {
+        L[p + (long)q * ld] = y[q];
+        t += y[q] * z[q];
+    }
+    const double dot = block_sum256(t, red);
+    if (threadIdx.x == 0) {
+        L[p + (long)p * ld] = piv;
+        P[p] = (short)j;
+        wP[p] = w0;
+        pos[j] = (short)p;
+        z[p] = (b[j] - 0.5 * alpha - dot) / piv;
+    }
+    __syncthreads();
+    ++p;
+}
+
+// removes free position k: P, wP and pos close the gap, and Lo receives the
+// factor of G_PP without row and column k (then L and Lo trade places).  v is
+// LDS scratch of pmax entries.
+__device__ void big_delete(double*& L, double*& Lo, long ld, int& p, int k, short* P, double* wP, short* pos,
+                           double* v) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int pn = p - 1;
+    const int leaving = P[k];
+    for (int r = k + 1 + tid; r < p; r += 256) v[r - k - 1] = L[r + (long)k * ld];
+    for (int c = wv; c < pn; c += 4) {
+        const long cs = (long)(c + (c >= k)) * ld;
+        for (int r = c + lane; r < pn; r += 64) Lo[r + (long)c * ld] = L[(r + (r >= k)) + cs];
+    }
+    short pr[4];
+    double wr[4];
+    for (int u = 0; u < 4; ++u) {
+        const int q = k + tid + 256 * u;
+        if (q < pn) { pr[u] = P[q + 1]; wr[u] = wP[q + 1]; }
+    }
+    __syncthreads();
+    for (int u = 0; u < 4; ++u) {
+        const int q = k + tid + 256 * u;
+        if (q < pn) { P[q] = pr[u]; wP[q] = wr[u]; pos[pr[u]] = (short)q; }
+    }
+    if (tid == 0) pos[leaving] = -1;
+    __syncthreads();
+    // Lo33 Lo33^T = L33 L33^T + v v^T, one column at a time
+    for (int c = k; c < pn; ++c) {
+        const double lcc = Lo[c + (long)c * ld], vc = v[c - k];
+        const double rr = hypot(lcc, vc), cs = rr / lcc, sn = vc / lcc;
+        for (int r = c + 1 + tid; r < pn; r += 256) {
+            const double ln = (Lo[r + (long)c * ld] + sn * v[r - k]) / cs;
+            v[r - k] = cs * v[r - k] - sn * ln;
+            Lo[r + (long)c * ld] = ln;
+        }
+        __syncthreads();                     // every thread has read this pivot
+        if (tid == 0) Lo[c + (long)c * ld] = rr;
+    }
+    __syncthreads();
+    double* t = L;
+    L = Lo;
+    Lo = t;
+    p = pn;
+}
+
+// z = L^-1 (b_P - alpha/2) from position k0 on
+__device__ void big_refresh_z(const double* L, long ld, int p, int k0, const short* P, const double* b, double alpha,
+                              double* z, double* D) {
+    for (int q = k0 + threadIdx.x; q < p; q += 256) z[q] = b[P[q]] - 0.5 * alpha;
+    __syncthreads();
+    big_forward(L, ld, p, k0, z, D);
+}
+
+// the samples in list[0 .. *count), one per workgroup at a time; slot s of
+// `scratch` (slot_doubles each) belongs to workgroup s
+__global__ __launch_bounds__(256) void k_slr_lasso_big(const double* __restrict__ G, long ldg, int nk, int pmax,
+                                                       double alpha, const int* __restrict__ nbr,
+                                                       const int* __restrict__ list, const int* __restrict__ count,
+                                                       double* __restrict__ scratch, long slot_doubles,
+                                                       double* __restrict__ wout, double* __restrict__ obj,
+                                                       int* __restrict__ steps_out, double* __restrict__ kkt_out,
+                                                       int* __restrict__ sup_out) {
+    extern __shared__ char smem[];
+    double* b = reinterpret_cast<double*>(smem);
+    double* wP = b + nk;
+    double* z = wP + pmax;
+    double* y = z + pmax;
+    int* nb = reinterpret_cast<int*>(y + pmax);
+    short* pos = reinterpret_cast<short*>(nb + nk);
+    short* P = pos + nk;
+    unsigned char* have = reinterpret_cast<unsigned char*>(P + pmax);
+    unsigned char* keep = have + nk;
+    __shared__ double D[kDB * kDBld];
+    __shared__ double rv[256];
+    __shared__ int ri[256];
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    const long ld = pmax;
+    double* L = scratch + (long)blockIdx.x * slot_doubles;
+    double* Lo = L + ld * pmax;
+    double* Gc = Lo + ld * pmax;             // column a: G_i(:, a) once a has entered P
+    const int total = *count;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int i = list[item];
+        const int* my = nbr + (long)i * nk;
+        double sc = 1.0, dm = 0.0;
+        for (int a = tid; a < nk; a += 256) {
+            const int q = my[a];
+            nb[a] = q;
+            b[a] = G[q + (long)i * ldg];
+            pos[a] = -1;
+            have[a] = 0;
+            const double d = G[q + (long)q * ldg];
+            sc = fmax(sc, fmax(fabs(2.0 * b[a] - alpha), 2.0 * d));
+            dm = fmax(dm, d);
+        }
+        const double scale = block_max256(sc, red);
+        const double dmax = block_max256(dm, red);
+        const double tol = kTol * scale, thr = kDepTol * dmax;
+        int p = 0, steps = 0, status = 0;
+        double viol = 0.0;
+        double ga[4];                        // gradient of the coordinates tid + 256 u
+        while (status == 0) {
+            for (int u = 0; u < 4; ++u) {
+                const int a = tid + 256 * u;
+                ga[u] = a < nk ? alpha - 2.0 * b[a] : 0.0;
+            }
+            for (int r = 0; r < p; ++r) {
+                const double wr = 2.0 * wP[r];
+                const double* col = Gc + (long)P[r] * nk;
+                for (int u = 0; u < 4; ++u) {
+                    const int a = tid + 256 * u;
+                    if (a < nk) ga[u] += wr * col[a];
+                }
+            }
+            double v = 0.0, gmin = 0.0;
+            int jmin = INT_MAX;
+            for (int u = 0; u < 4; ++u) {
+                const int a = tid + 256 * u;
+                if (a >= nk) continue;
+                if (pos[a] >= 0) v = fmax(v, fabs(ga[u]));
+                else {
+                    v = fmax(v, fmax(0.0, -ga[u]));
+                    if (ga[u] < gmin || (ga[u] == gmin && ga[u] < 0.0 && a < jmin)) { gmin = ga[u]; jmin = a; }
+                }
+            }
+            viol = block_max256(v, red);
+            if (viol <= tol) { status = 1; break; }
+            if (++steps > 10 * nk + 20) { status = 2; break; }
+            double gj;
+            int j;
+            block_argmin256(gmin, jmin, rv, ri, gj, j);
+            if (!(gj < 0.0)) j = -1;
+            if (j >= 0) {
+                double* cj = Gc + (long)j * nk;
+                if (!have[j]) {
+                    const double* src = G + (long)nb[j] * ldg;
+                    for (int a = tid; a < nk; a += 256) cj[a] = src[nb[a]];
+                    __syncthreads();
+                    if (tid == 0) have[j] = 1;
+                }
+                for (int q = tid; q < p; q += 256) y[q] = cj[P[q]];
+                __syncthreads();
+                big_forward(L, ld, p, 0, y, D);
+                double t2 = 0.0;
+                for (int q = tid; q < p; q += 256) t2 += y[q] * y[q];
+                const double d2 = cj[j] - block_sum256(t2, red);
+                if (!(d2 > thr)) {
+                    // D_j = D_P beta, beta = L^-T y: w_P -= t beta, w_j = t, until the
+                    // first weight with beta > 0 reaches zero; that index leaves
+                    if (p == 0) { status = 2; break; }
+                    big_backward(L, ld, p, y, D);
+                    double tb = INFINITY;
+                    int ib = INT_MAX;
+                    for (int q = tid; q < p; q += 256) {
+                        if (y[q] > 0.0) {
+                            const double r = wP[q] / y[q];
+                            if (r < tb || (r == tb && P[q] < ib)) { tb = r; ib = P[q]; }
+                        }
+                    }
+                    double t;
+                    int out;
+                    block_argmin256(tb, ib, rv, ri, t, out);
+                    if (out == INT_MAX) { status = 2; break; }
+                    for (int q = tid; q < p; q += 256) wP[q] -= t * y[q];
+                    __syncthreads();
+                    const int kd = pos[out];
+                    big_delete(L, Lo, ld, p, kd, P, wP, pos, y);
+                    big_refresh_z(L, ld, p, kd, P, b, alpha, z, D);
+                    for (int q = tid; q < p; q += 256) y[q] = cj[P[q]];
+                    __syncthreads();
+                    big_forward(L, ld, p, 0, y, D);
+                    t2 = 0.0;
+                    for (int q = tid; q < p; q += 256) t2 += y[q] * y[q];
+                    const double d2b = cj[j] - block_sum256(t2, red);
+                    if (!(d2b > 0.0)) { status = 2; break; }
+                    big_append(L, ld, p, j, t, d2b, y, P, wP, pos, z, b, alpha, red);
+                } else {
+                    if (p + 1 > pmax) { status = 2; break; }   // more independent columns than rows
+                    big_append(L, ld, p, j, 0.0, d2, y, P, wP, pos, z, b, alpha, red);
+                }
+            }
+            // face solve G_PP s = b_P - alpha/2 (s = L^-T z), stepping back while a
+            // weight would turn non-positive
+            for (int inner = 0; inner < pmax + 1 && p > 0; ++inner) {
+                for (int q = tid; q < p; q += 256) y[q] = z[q];
+                __syncthreads();
+                big_backward(L, ld, p, y, D);
+                double bad = 0.0;
+                for (int q = tid; q < p; q += 256) bad = fmax(bad, y[q] > 0.0 ? 0.0 : 1.0);
+                if (block_max256(bad, red) == 0.0) {
+                    for (int q = tid; q < p; q += 256) wP[q] = y[q];
+                    __syncthreads();
+                    break;
+                }
+                double tq = INFINITY;
+                for (int q = tid; q < p; q += 256) {
+                    if (y[q] <= 0.0) {
+                        const double den = wP[q] - y[q];
+                        tq = fmin(tq, den > 0.0 ? wP[q] / den : 0.0);
+                    }
+                }
+                const double t = block_min256(tq, red);
+                if (!(t < INFINITY)) { status = 2; break; }     // the face solution is not finite
+                double kmin = (double)p;
+                for (int q = tid; q < p; q += 256) {
+                    bool gone = false;
+                    if (y[q] <= 0.0) {
+                        const double den = wP[q] - y[q];
+                        gone = (den > 0.0 ? wP[q] / den : 0.0) == t;
+                    }
+                    const double wn = wP[q] + t * (y[q] - wP[q]);
+                    const bool kp = !(gone || !(wn > 0.0));
+                    keep[q] = kp ? 1 : 0;
+                    if (kp) wP[q] = wn;
+                    else kmin = fmin(kmin, (double)q);
+                }
+                const int k0 = (int)block_min256(kmin, red);
+                for (int q = p - 1; q >= k0; --q)
+                    if (!keep[q]) big_delete(L, Lo, ld, p, q, P, wP, pos, y);
+                if (p > 0) big_refresh_z(L, ld, p, k0, P, b, alpha, z, D);
+            }
+        }
+        // weights, optimal objective, statistics
+        double ns = 0.0, to = 0.0;
+        for (int u = 0; u < 4; ++u) {
+            const int a = tid + 256 * u;
+            if (a >= nk) continue;
+            const int q = pos[a];
+            const double wa = q >= 0 ? wP[q] : 0.0;
+            wout[(long)i * nk + a] = wa;
+            ns += wa > 0.0 ? 1.0 : 0.0;
+            if (q >= 0) to += wP[q] * (0.5 * (ga[u] + 2.0 * b[a] - alpha) - 2.0 * b[a] + alpha);
+        }
+        const double nsup = block_sum256(ns, red);
+        const double s = block_sum256(to, red);
+        if (tid == 0) {
+            if (obj) obj[i] = s + G[i + (long)i * ldg];
+            steps_out[i] = steps;
+            kkt_out[i] = status == 1 ? viol / scale : INFINITY;
+            sup_out[i] = (int)nsup;
+        }
+        __syncthreads();
     }
 }
 
@@ -492,15 +851,24 @@ extern "C" lrr_status lrr_slr_graph(lrr_ctx* ctx, int m, int n, const void* Mv, 
     try {
         if (hipSetDevice(lrr::ctx_device(ctx)) != hipSuccess)
             return lrr::ctx_fail(ctx, LRR_EDEVICE, "hipSetDevice failed");
-        // workspace: W, then G (n x n, one buffer), per-sample step counts and violations, one descriptor
+        // workspace: W, then G (n x n, one buffer); per-sample step counts, violations and
+        // support sizes; the list of samples for the large-support pass and its length;
+        // one GEMM descriptor
+        auto up = [](size_t o) { return (o + 255) & ~size_t(255); };
         const size_t offG = 0, offS = offG + sizeof(double) * (size_t)n * n;
-        const size_t offK = (offS + sizeof(int) * (size_t)n + 255) & ~size_t(255);
-        const size_t offD = (offK + sizeof(double) * (size_t)n + 255) & ~size_t(255);
+        const size_t offK = up(offS + sizeof(int) * (size_t)n);
+        const size_t offU = up(offK + sizeof(double) * (size_t)n);
+        const size_t offL = up(offU + sizeof(int) * (size_t)n);
+        const size_t offC = up(offL + sizeof(int) * (size_t)n);
+        const size_t offD = up(offC + sizeof(int));
         const size_t bytes = offD + sizeof(lrr::GemmDesc);
         char* base = static_cast<char*>(lrr::ctx_seg_workspace(ctx, bytes));
         double* G = reinterpret_cast<double*>(base + offG);
         int* steps = reinterpret_cast<int*>(base + offS);
         double* kkt = reinterpret_cast<double*>(base + offK);
+        int* sup = reinterpret_cast<int*>(base + offU);
+        int* big_list = reinterpret_cast<int*>(base + offL);
+        int* big_count = reinterpret_cast<int*>(base + offC);
         lrr::GemmDesc* gd = reinterpret_cast<lrr::GemmDesc*>(base + offD);
 
         const unsigned tiles = (unsigned)((n + kTile - 1) / kTile);
@@ -514,22 +882,53 @@ extern "C" lrr_status lrr_slr_graph(lrr_ctx* ctx, int m, int n, const void* Mv, 
         LRR_HIP(hipMemcpyAsync(gd, &h, sizeof(h), hipMemcpyHostToDevice, s));
         lrr::ctx_timed(ctx, s, "k_dgemm<true, false>", 2.0 * n * (double)n * m, 0.0,
                        [&] { lrr::launch_dgemm(gd, 1, n, n, true, false, s); });
+        LRR_HIP(hipMemsetAsync(big_count, 0, sizeof(int), s));
         const size_t lds = (size_t)nk * (2 * sizeof(double) + 2 * sizeof(int));
         lrr::ctx_timed(ctx, s, "k_slr_lasso", 0.0, 0.0, [&] {
             hipLaunchKernelGGL(k_slr_lasso, dim3(n), dim3(256), lds, s, G, (long)n, nk, alpha, nbr, w, obj, steps,
-                               kkt);
+                               kkt, sup, big_list, big_count);
         });
         LRR_HIP(hipGetLastError());
-        std::vector<int> hs(n);
+        int nbig = 0;
+        LRR_HIP(hipMemcpyAsync(&nbig, big_count, sizeof(int), hipMemcpyDeviceToHost, s));
+        LRR_HIP(hipStreamSynchronize(s));
+        if (nbig > 0) {
+            // supports above kMaxP: independent free sets hold at most min(m, nk) indices
+            const int pmax = std::min(m, nk);
+            const size_t lds_big = sizeof(double) * ((size_t)nk + 3 * (size_t)pmax) + sizeof(int) * (size_t)nk +
+                                   sizeof(short) * ((size_t)nk + pmax) + (size_t)nk + pmax;
+            int per_cu = 0, cus = 0;
+            LRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_slr_lasso_big, 256, lds_big));
+            LRR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, lrr::ctx_device(ctx)));
+            long slots = std::min<long>(nbig, std::max(1, per_cu) * (long)std::max(1, cus));
+            const long slot_doubles = ((2L * pmax * pmax + (long)nk * nk) + 31) / 32 * 32;
+            void* scratch = nullptr;
+            while (slots >= 1 && !lrr::try_device_alloc(&scratch, sizeof(double) * slot_doubles * slots)) slots /= 2;
+            if (!scratch) return lrr::ctx_fail(ctx, LRR_ENOMEM, "SLR-graph large-support workspace allocation failed");
+            struct Free {
+                void* p;
+                ~Free() { (void)hipFree(p); }
+            } release{scratch};
+            lrr::ctx_timed(ctx, s, "k_slr_lasso_big", 0.0, 0.0, [&] {
+                hipLaunchKernelGGL(k_slr_lasso_big, dim3((unsigned)slots), dim3(256), lds_big, s, G, (long)n, nk,
+                                   pmax, alpha, nbr, big_list, big_count, static_cast<double*>(scratch),
+                                   slot_doubles, w, obj, steps, kkt, sup);
+            });
+            LRR_HIP(hipGetLastError());
+            LRR_HIP(hipStreamSynchronize(s));
+        }
+        std::vector<int> hs(n), hu(n);
         std::vector<double> hk(n);
         LRR_HIP(hipMemcpyAsync(hs.data(), steps, sizeof(int) * n, hipMemcpyDeviceToHost, s));
         LRR_HIP(hipMemcpyAsync(hk.data(), kkt, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        LRR_HIP(hipMemcpyAsync(hu.data(), sup, sizeof(int) * n, hipMemcpyDeviceToHost, s));
         LRR_HIP(hipStreamSynchronize(s));
         lrr::ctx_prof_flush(ctx);
-        int smax = 0, nc = 0;
+        int smax = 0, nc = 0, umax = 0;
         double kmax = 0.0;
         for (int i = 0; i < n; ++i) {
             smax = std::max(smax, hs[i]);
+            umax = std::max(umax, hu[i]);
             if (hk[i] <= kTol) kmax = std::max(kmax, hk[i]);
             if (!(hk[i] <= kTol)) ++nc;
         }
@@ -537,6 +936,8 @@ extern "C" lrr_status lrr_slr_graph(lrr_ctx* ctx, int m, int n, const void* Mv, 
             info->max_steps = smax;
             info->not_converged = nc;
             info->max_kkt = kmax;
+            info->large_support = nbig;
+            info->max_support = umax;
         }
         return nc ? LRR_NOT_CONVERGED : LRR_OK;
     } catch (const lrr::HipError& e) {

@@ -2,14 +2,16 @@
 
 The coefficient matrix Z given to both sides is a seeded synthetic stand-in
 with the block structure of a union of subspaces, rounded so that equal
-affinities occur (datagen.synthetic_coefficients), not a GPU solve's output.
+affinities occur (datagen.synthetic_coefficients), or Gaussian; one test takes
+the Z of the workload-4 solve and checks it by properties and sampled rows.
 
 Neighbour lists are integer work and must equal the oracle's bit for bit (both
 sides form |Z_ij| + |Z_ji| with one FP64 addition and order by it, ties to the
 lower index).  The non-negative Lasso has a unique optimal value but, when a
 sample's neighbours span fewer dimensions than their number, not unique
 weights; so per sample the test compares the optimal objective with the
-oracle's (relative 1e-9), checks the GPU weights against the optimality
+oracle's (relative 1e-9, plus the gap that both sides' final optimality
+violations allow by convexity), checks the GPU weights against the optimality
 conditions computed here in FP64 (1e-9 of the sample's scale), recomputes the
 objective from the weights, and where D_i^T D_i is positive definite compares
 the weights themselves (1e-7).
@@ -31,9 +33,22 @@ def _check_sample(M, i, nbr_i, w_i, obj_i, alpha, ref_obj=None, ref_w=None):
     f = float(np.sum((x - D @ w_i) ** 2) + alpha * w_i.sum())
     assert np.all(w_i >= 0)
     assert kkt <= 1e-9 * scale, kkt / scale
-    assert abs(obj_i - f) <= 1e-10 * max(1.0, f)
+    # the reported objective is x^T x + sum_q w_q ((g_q + 2 b_q - alpha)/2 - 2 b_q + alpha): a
+    # difference of terms of size x^T x and 2 b^T w, so its rounding error scales with those
+    # (low-rank bases with a small alpha cancel five orders of magnitude)
+    terms = float(x @ x + 2.0 * np.abs(b) @ w_i)
+    assert abs(obj_i - f) <= 1e-10 * max(1.0, f) + 1e-13 * terms, (obj_i, f, terms)
     if ref_obj is not None:
-        assert abs(f - ref_obj) <= 1e-9 * max(1.0, ref_obj), (f, ref_obj)
+        # both sides stop at optimality violations eps_gpu, eps_ref of 1e-12 of the scale; by
+        # convexity f(u) >= f(v) + g(v)^T (u - v) >= f(v) - eps_v (|u|_1 + |v|_1) for feasible
+        # u, v, so the two objectives may differ by max(eps) (|w|_1 + |w_ref|_1), which on
+        # rank-deficient bases with a large scale exceeds the plain 1e-9 relative bound
+        slack = 0.0
+        if ref_w is not None:
+            gr = 2 * G @ ref_w - 2 * b + alpha
+            kkt_ref = np.max(np.where(ref_w > 0, np.abs(gr), np.maximum(0.0, -gr)))
+            slack = max(kkt, kkt_ref) * (w_i.sum() + ref_w.sum())
+        assert abs(f - ref_obj) <= 1e-9 * max(1.0, ref_obj) + slack, (f, ref_obj, slack)
     if ref_w is not None and np.linalg.eigvalsh(G)[0] > 1e-8 * np.linalg.eigvalsh(G)[-1]:
         assert np.abs(w_i - ref_w).max() <= 1e-7 * max(1.0, np.abs(ref_w).max())
 
@@ -118,11 +133,11 @@ def _check_neighbour_property(Z, nbr, rows):
 def test_slr_graph_workload4_size():
     """Workload 4's size (m = 512, n = 20000), n_k = 500, alpha = 0.05: the
     neighbour lists of 24 seeded samples equal the oracle's bit for bit, every
-    sample's list has the top-affinity property (checked here with numpy), and
-    48 seeded inlier samples meet the Lasso's optimality conditions.  The 2000
-    replaced columns (random vectors of norm ~23) need supports of ~250
-    neighbours (oracle), beyond the kernel's 64, so they stop early and the
-    call reports them as not converged."""
+    sample's list has the top-affinity property (checked here with numpy),
+    every sample converges, 48 seeded inliers and 48 seeded replaced columns
+    meet the optimality conditions, and on 3 replaced columns (supports of
+    ~250 neighbours, solved by the large-support pass) the optimal objective
+    equals the oracle's."""
     need_gpu()
     from oracle import slr
     from paper_1304_5583_amd import binding as B
@@ -133,7 +148,8 @@ def test_slr_graph_workload4_size():
     nk, alpha = 500, 0.05
     nbr, w, obj, info = B.lrr_slr_graph(Mt, Zt, nk, alpha)
     del Zt
-    say(f"[slr wl4] steps<={info['max_steps']} kkt={info['max_kkt']:.1e} not_converged={info['not_converged']}")
+    say(f"[slr wl4] steps<={info['max_steps']} kkt={info['max_kkt']:.1e} not_converged={info['not_converged']} "
+        f"large={info['large_support']} max_support={info['max_support']}")
     nbr, w, obj = nbr.cpu().numpy(), w.cpu().numpy(), obj.cpu().numpy()
     rng = np.random.default_rng(404)
     rows = rng.choice(p.n, 24, replace=False)
@@ -141,9 +157,99 @@ def test_slr_graph_workload4_size():
         rn = slr.slr_neighbors_rows(Zg, nk, rows)
     assert np.array_equal(nbr[rows], rn)
     _check_neighbour_property(Zg, nbr, np.arange(p.n))
-    assert info["not_converged"] <= int(p.outliers.sum())
+    assert info["converged"] and info["max_kkt"] <= 1e-12
+    assert info["large_support"] >= int(p.outliers.sum()) and info["max_support"] > 64
     for i in rng.choice(np.where(~p.outliers)[0], 48, replace=False):
         _check_sample(p.M, i, nbr[i], w[i], obj[i], alpha)
+    outl = np.where(p.outliers)[0]
+    for i in rng.choice(outl, 48, replace=False):
+        _check_sample(p.M, i, nbr[i], w[i], obj[i], alpha)
+    for i in rng.choice(outl, 3, replace=False):
+        D = p.M[:, nbr[i]]
+        G, b = D.T @ D, D.T @ p.M[:, i]
+        with one_thread():
+            rw = slr.nn_lasso(G, b, alpha)
+        robj = slr.nn_lasso_objective(G, b, float(p.M[:, i] @ p.M[:, i]), alpha, rw)
+        _check_sample(p.M, i, nbr[i], w[i], obj[i], alpha, robj, rw)
+
+
+@pytest.mark.parametrize("seed,m,r,n,nk,alpha", [(71, 100, 100, 160, 150, 0.05), (72, 120, 80, 160, 150, 0.001),
+                                                 (72, 120, 72, 160, 150, 0.01)])
+def test_slr_graph_large_supports_match_oracle(seed, m, r, n, nk, alpha):
+    """Gaussian data of rank r whose Lasso supports exceed the 64 of the
+    on-chip pass, so (nearly) every sample goes through the large-support
+    pass (oracle counts: 150, 160 and 160 of the 160 samples, supports 61-87,
+    66-80 and 67-72).  With r < n_k the free sets reach the rank of D_i and
+    entering columns are dependent (the swap step: 243 and 1404 of them over
+    the last two cases), and the face steps remove indices (factor updates:
+    659, 4111 and 5288).  Every sample: neighbour list equal to the oracle's,
+    optimal objective equal to the oracle's (1e-9), optimality conditions."""
+    need_gpu()
+    from oracle import slr
+    from paper_1304_5583_amd import binding as B
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((m, r)) @ rng.standard_normal((r, n)) if r < m else rng.standard_normal((m, n))
+    Z = rng.standard_normal((n, n))
+    Mt, Zt = B.to_device_colmajor(M), B.to_device_colmajor(Z)
+    nbr, w, obj, info = B.lrr_slr_graph(Mt, Zt, nk, alpha)
+    say(f"[slr big s{seed}] m={m} r={r} nk={nk} steps<={info['max_steps']} kkt={info['max_kkt']:.1e} "
+        f"large={info['large_support']} max_support={info['max_support']}")
+    assert info["converged"]
+    assert info["large_support"] > n // 2 and info["max_support"] > 64
+    nbr, w, obj = nbr.cpu().numpy(), w.cpu().numpy(), obj.cpu().numpy()
+    with one_thread():
+        rn = slr.slr_neighbors(Z, nk)
+    assert np.array_equal(nbr, rn)
+    for i in range(n):
+        D = M[:, nbr[i]]
+        G, b = D.T @ D, D.T @ M[:, i]
+        with one_thread():
+            rw = slr.nn_lasso(G, b, alpha)
+        robj = slr.nn_lasso_objective(G, b, float(M[:, i] @ M[:, i]), alpha, rw)
+        _check_sample(M, i, nbr[i], w[i], obj[i], alpha, robj, rw)
+
+
+def test_slr_graph_workload4_solve():
+    """SLR-graph on the Z of the FP64 DFC-LRR solve of workload 4 (the
+    benchmark's input): the replaced columns take large weights in Z, so most
+    samples' neighbour lists are dominated by them and the supports run to
+    ~250.  Every sample converges; on 200 seeded samples the list has the
+    top-affinity property (affinity rows formed here from Z's rows and
+    columns) and the weights meet the optimality conditions; on 4 seeded
+    samples the optimal objective equals the oracle's."""
+    torch = need_gpu()
+    from oracle import slr
+    from paper_1304_5583_amd import binding as B
+    from paper_1304_5583_amd.datagen import make_config
+    p = make_config(4)
+    Mt = B.to_device_colmajor(p.M)
+    Zt = torch.empty((p.n, p.n), dtype=torch.float64, device="cuda")
+    B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, want_S=False, Zt=Zt)
+    nk, alpha = 500, 0.05
+    nbr, w, obj, info = B.lrr_slr_graph(Mt, Zt, nk, alpha)
+    say(f"[slr wl4 solve] steps<={info['max_steps']} kkt={info['max_kkt']:.1e} large={info['large_support']} "
+        f"max_support={info['max_support']}")
+    assert info["converged"] and info["max_kkt"] <= 1e-12
+    rng = np.random.default_rng(4040)
+    rows = np.sort(rng.choice(p.n, 200, replace=False))
+    rt = torch.from_numpy(rows).cuda()
+    # column-major Z: Zt[c] is column c, so Z[r, :] = Zt[:, r] and Z[:, r] = Zt[r]
+    A = (Zt[:, rt].abs().T + Zt[rt].abs()).cpu().numpy()
+    del Zt
+    torch.cuda.empty_cache()
+    A[np.arange(len(rows)), rows] = -1.0
+    nbr, w, obj = nbr.cpu().numpy(), w.cpu().numpy(), obj.cpu().numpy()
+    for k, i in enumerate(rows):
+        order = np.lexsort((np.arange(p.n), -A[k]))[:nk]
+        assert np.array_equal(nbr[i], order)
+        _check_sample(p.M, i, nbr[i], w[i], obj[i], alpha)
+    for i in rng.choice(rows, 4, replace=False):
+        D = p.M[:, nbr[i]]
+        G, b = D.T @ D, D.T @ p.M[:, i]
+        with one_thread():
+            rw = slr.nn_lasso(G, b, alpha)
+        robj = slr.nn_lasso_objective(G, b, float(p.M[:, i] @ p.M[:, i]), alpha, rw)
+        _check_sample(p.M, i, nbr[i], w[i], obj[i], alpha, robj, rw)
 
 
 def test_slr_graph_edges_and_errors():
