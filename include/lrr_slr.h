@@ -32,7 +32,7 @@
  *
  * The Lasso is solved by a finite active-set method (Lawson and Hanson's, with
  * the free columns kept independent, so a support never exceeds min(m, n_k));
- * a sample that exceeds 10 n_k + 20 steps stops there.  Supports up to 64 are
+ * a sample that exceeds 10 n_k + 20 steps stops there.  Supports up to 32 are
  * solved with their factorisations in on-chip memory; a sample whose support
  * grows beyond that is solved again by a second pass that keeps the Cholesky
  * factor of its free set in device memory and updates it as indices enter and

@@ -16,10 +16,10 @@
 //                P kept independent (a dependent entering column is pivoted
 //                in along its dependence); the gradient over all n_k
 //                coordinates is one gathered row of G per free index, the
-//                factorisations of G_PP (|P| <= 64) run in LDS with all
+//                factorisations of G_PP (|P| <= 32) run in LDS with all
 //                threads, the triangular solves in one wave with the unknowns
 //                in registers;
-//   large        samples whose free set outgrows 64 are solved again by a
+//   large        samples whose free set outgrows 32 are solved again by a
 //                second pass that keeps the Cholesky factor of G_PP in device
 //                memory and updates it as indices enter and leave.
 #include <hip/hip_runtime.h>
@@ -51,7 +51,7 @@ namespace {
 constexpr int kMaxNk = 1024;
 constexpr double kTol = 1e-12;       // optimality tolerance relative to the sample's scale
 constexpr double kDepTol = 1e-10;    // Cholesky pivot / max diagonal below which a column is dependent
-constexpr int kMaxP = 64;            // largest free set (Lasso support) held in LDS
+constexpr int kMaxP = 32;            // largest free set (Lasso support) held in LDS
 constexpr int kTile = 64;            // affinity transpose tile
 
 // W(r, c) = |Z(r, c)| + |Z(c, r)| (one FP64 addition, so W is exactly symmetric)
@@ -483,6 +483,24 @@ __global__ __launch_bounds__(256) void k_slr_lasso(const double* __restrict__ G,
     }
 }
 
+// (value, index) arg-min over the 256 threads through wave shuffles and four
+// LDS slots: smaller value wins, ties to the lower index (the same result as
+// block_argmin256)
+__device__ void block_argmin256_w(double v, int i, double* sv, int* si, double& vout, int& iout) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(i, off, 64);
+        if (ov < v || (ov == v && oi < i)) { v = ov; i = oi; }
+    }
+    if ((threadIdx.x & 63) == 0) { sv[threadIdx.x >> 6] = v; si[threadIdx.x >> 6] = i; }
+    __syncthreads();
+    vout = sv[0];
+    iout = si[0];
+    for (int w = 1; w < 4; ++w)
+        if (sv[w] < vout || (sv[w] == vout && si[w] < iout)) { vout = sv[w]; iout = si[w]; }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Large supports.  A sample whose free set outgrows kMaxP is solved again from
 // the start by k_slr_lasso_big with the same steps, one workgroup per sample
@@ -501,64 +519,149 @@ constexpr int kDBld = kDB + 1;   // its LDS leading dimension (odd: no bank conf
 
 __device__ double block_min256(double v, double* red) { return -block_max256(-v, red); }
 
-// L[o:o+nb, o:o+nb] (lower part) into D
-__device__ void stage_diag(const double* L, long ld, int o, int nb, double* D) {
-    for (int e = threadIdx.x; e < kDB * kDB; e += 256) {
-        const int r = e % kDB, c = e / kDB;
-        if (r < nb && c <= r) D[r + c * kDBld] = L[(o + r) + (long)(o + c) * ld];
+// the lower part of the diagonal block L[o:o+nb, o:o+nb], four entries per
+// thread, loaded into registers (so the loads can be in flight during other
+// work) and then written to an LDS block of leading dimension kDBld
+__device__ void diag_load(const double* L, long ld, int o, int nb, double (&v)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = threadIdx.x + 256 * u, r = e % kDB, c = e / kDB;
+        v[u] = (r < nb && c <= r) ? L[(o + r) + (long)(o + c) * ld] : 0.0;
     }
-    __syncthreads();
+}
+__device__ void diag_store(double* D, const double (&v)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        D[e % kDB + (e / kDB) * kDBld] = v[u];
+    }
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// wave 0: x = Dl^-1 x over nb <= 32 entries (Dl the staged lower block), in
+// place.  Column sweep: lane i holds x_i; step q broadcasts x_q and the lanes
+// below subtract their column-q entry times it, so a step is a broadcast and
+// one FMA, with no reduction.
+__device__ void fwd_sweep_w0(const double* D, int nb, double* x) {
+    const int lane = threadIdx.x;
+    double r = lane < nb ? x[lane] : 0.0;
+    const double dinv = lane < nb ? 1.0 / D[lane + lane * kDBld] : 0.0;
+    for (int q = 0; q < nb; ++q) {
+        const double lq = D[(lane & 31) + q * kDBld];
+        const double xq = readlane_d(r, q) * readlane_d(dinv, q);
+        if (lane == q) r = xq;
+        else if (lane > q && lane < nb) r -= lq * xq;
+    }
+    if (lane < nb) x[lane] = r;
+}
+
+// wave 0: x = Dl^-T x over nb <= 32 entries, in place (row sweep from the bottom)
+__device__ void bwd_sweep_w0(const double* D, int nb, double* x) {
+    const int lane = threadIdx.x;
+    double r = lane < nb ? x[lane] : 0.0;
+    const double dinv = lane < nb ? 1.0 / D[lane + lane * kDBld] : 0.0;
+    for (int q = nb - 1; q >= 0; --q) {
+        const double lq = D[q + (lane & 31) * kDBld];
+        const double xq = readlane_d(r, q) * readlane_d(dinv, q);
+        if (lane == q) r = xq;
+        else if (lane < q) r -= lq * xq;
+    }
+    if (lane < nb) x[lane] = r;
+}
+
+// barrier that orders LDS only: global loads in flight (prefetches) stay in
+// flight, and global stores become visible to the workgroup at the next full
+// __syncthreads()
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// x[i] -= sum_{c < nc} L[i, c0 + c] x[c0 + c] for rows i in [r0, p), one row per
+// thread; the column entries of a batch of 8 are loaded before they are used
+__device__ void big_gemv_rows(const double* L, long ld, int p, int r0, int c0, int nc, double* x) {
+    for (int i = r0 + threadIdx.x; i < p; i += 256) {
+        const double* li = L + i + (long)c0 * ld;
+        double t = 0.0;
+        int c = 0;
+        for (; c + 8 <= nc; c += 8) {
+            double e[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) e[u] = li[(long)(c + u) * ld];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t += e[u] * x[c0 + c + u];
+        }
+        for (; c < nc; ++c) t += li[(long)c * ld] * x[c0 + c];
+        x[i] -= t;
+    }
 }
 
 // x = L^-1 x over the entries [k0, p), in place, given the entries [0, k0)
-// already solved: the rows below each diagonal block are updated by all
-// threads (one row per thread, coalesced down the columns), the block itself
-// is solved by wave 0 from LDS
+// already solved.  Blocks of kDB: wave 0 solves the staged diagonal block,
+// then all threads update the rows below (one row per thread, coalesced down
+// the columns) while the next diagonal block's loads are in flight; D holds
+// two LDS blocks used in turn.
 __device__ void big_forward(const double* L, long ld, int p, int k0, double* x, double* D) {
     const int tid = threadIdx.x;
-    if (k0 > 0 && k0 < p) {
-        for (int i = k0 + tid; i < p; i += 256) {
-            double t = 0.0;
-            for (int c = 0; c < k0; ++c) t += L[i + (long)c * ld] * x[c];
-            x[i] -= t;
-        }
-        __syncthreads();
-    }
+    if (k0 >= p) return;
+    double dv[4];
+    diag_load(L, ld, k0, min(kDB, p - k0), dv);
+    if (k0 > 0) big_gemv_rows(L, ld, p, k0, 0, k0, x);
+    diag_store(D, dv);
+    __syncthreads();
+    int buf = 0;
     for (int o = k0; o < p; o += kDB) {
         const int nb = min(kDB, p - o);
-        stage_diag(L, ld, o, nb, D);
-        if (tid < 64) forward_w0(D, kDBld, nb, x + o, x + o);
+        if (tid < 64) fwd_sweep_w0(D + buf * kDB * kDBld, nb, x + o);
         __syncthreads();
-        if (o + nb < p) {
-            for (int i = o + nb + tid; i < p; i += 256) {
-                double t = 0.0;
-                for (int c = 0; c < nb; ++c) t += L[i + (long)(o + c) * ld] * x[o + c];
-                x[i] -= t;
-            }
+        const int on = o + nb;
+        if (on < p) {
+            diag_load(L, ld, on, min(kDB, p - on), dv);
+            big_gemv_rows(L, ld, p, on, o, nb, x);
+            buf ^= 1;
+            diag_store(D + buf * kDB * kDBld, dv);
             __syncthreads();
         }
     }
 }
 
 // x = L^-T x over the leading p entries, in place: blocks from the bottom; the
-// entries above a solved block take its contribution as 32-lane dot products
-// down their columns
+// entries above a solved block take its contribution, one thread per entry (a
+// dot product down its column, the block's rows of it loaded at once), while
+// the next diagonal block's loads are in flight
 __device__ void big_backward(const double* L, long ld, int p, double* x, double* D) {
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x;
     if (p <= 0) return;
-    for (int o = ((p - 1) / kDB) * kDB; o >= 0; o -= kDB) {
+    double dv[4];
+    int o = ((p - 1) / kDB) * kDB;
+    diag_load(L, ld, o, p - o, dv);
+    diag_store(D, dv);
+    __syncthreads();
+    int buf = 0;
+    for (; o >= 0; o -= kDB) {
         const int nb = min(kDB, p - o);
-        stage_diag(L, ld, o, nb, D);
-        if (tid < 64) backward_w0(D, kDBld, nb, x + o, x + o);
+        if (tid < 64) bwd_sweep_w0(D + buf * kDB * kDBld, nb, x + o);
         __syncthreads();
         if (o > 0) {
-            const int r = lane & 31;
-            for (int c0 = 2 * wv; c0 < o; c0 += 8) {
-                const int c = c0 + (lane >> 5);
-                double t = (c < o && r < nb) ? L[o + r + (long)c * ld] * x[o + r] : 0.0;
-                for (int off = 16; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-                if (r == 0 && c < o) x[c] -= t;
+            diag_load(L, ld, o - kDB, kDB, dv);
+            for (int c = tid; c < o; c += 256) {
+                const double* lc = L + o + (long)c * ld;
+                double e[kDB];
+#pragma unroll
+                for (int r = 0; r < kDB; ++r) e[r] = r < nb ? lc[r] : 0.0;
+                double t = 0.0;
+#pragma unroll
+                for (int r = 0; r < kDB; ++r) t += e[r] * x[o + r];
+                x[c] -= t;
             }
+            buf ^= 1;
+            diag_store(D + buf * kDB * kDBld, dv);
             __syncthreads();
         }
     }
@@ -588,16 +691,30 @@ __device__ void big_append(double* L, long ld, int& p, int j, double w0, double 
 
 // removes free position k: P, wP and pos close the gap, and Lo receives the
 // factor of G_PP without row and column k (then L and Lo trade places).  v is
-// LDS scratch of pmax entries.
+// LDS scratch of pmax entries; z[k ..] is overwritten (the caller refreshes z
+// from position k or below).
+template <int NU>
 __device__ void big_delete(double*& L, double*& Lo, long ld, int& p, int k, short* P, double* wP, short* pos,
-                           double* v) {
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+                           double* v, double* z) {
+    const int tid = threadIdx.x;
     const int pn = p - 1;
     const int leaving = P[k];
     for (int r = k + 1 + tid; r < p; r += 256) v[r - k - 1] = L[r + (long)k * ld];
-    for (int c = wv; c < pn; c += 4) {
-        const long cs = (long)(c + (c >= k)) * ld;
-        for (int r = c + lane; r < pn; r += 64) Lo[r + (long)c * ld] = L[(r + (r >= k)) + cs];
+    // the copy runs over the pn x pn square in batches of 8 entries per thread
+    // (loads of a batch in flight together); entries above the diagonal are skipped
+    const int tot = pn * pn;
+    for (int e0 = 0; e0 < tot; e0 += 256 * 8) {
+        double val[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + tid + 256 * u, r = e % pn, c = e / pn;
+            val[u] = (e < tot && r >= c) ? L[(r + (r >= k)) + (long)(c + (c >= k)) * ld] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + tid + 256 * u, r = e % pn, c = e / pn;
+            if (e < tot && r >= c) Lo[r + (long)c * ld] = val[u];
+        }
     }
     short pr[4];
     double wr[4];
@@ -612,18 +729,63 @@ __device__ void big_delete(double*& L, double*& Lo, long ld, int& p, int k, shor
     }
     if (tid == 0) pos[leaving] = -1;
     __syncthreads();
-    // Lo33 Lo33^T = L33 L33^T + v v^T, one column at a time
-    for (int c = k; c < pn; ++c) {
-        const double lcc = Lo[c + (long)c * ld], vc = v[c - k];
-        const double rr = hypot(lcc, vc), cs = rr / lcc, sn = vc / lcc;
-        for (int r = c + 1 + tid; r < pn; r += 256) {
-            const double ln = (Lo[r + (long)c * ld] + sn * v[r - k]) / cs;
-            v[r - k] = cs * v[r - k] - sn * ln;
-            Lo[r + (long)c * ld] = ln;
-        }
-        __syncthreads();                     // every thread has read this pivot
-        if (tid == 0) Lo[c + (long)c * ld] = rr;
+    // Lo33 Lo33^T = L33 L33^T + v v^T, one column at a time.  Thread tid owns rows
+    // tid + 256 u and keeps their entries of v in registers; the entry of the next
+    // pivot row goes through LDS (two slots used in turn), columns are loaded four
+    // steps ahead, and the steps are ordered by LDS-only barriers.  The new pivots
+    // wait in dg = z[k ..] (entries the caller recomputes) until the loop ends, so
+    // no pivot is overwritten while a prefetch of it may be in flight.
+    double* dg = z + k;
+    double vr[NU], ring[4][NU], piv[4];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int r = tid + 256 * u;
+        vr[u] = (r >= k && r < pn) ? v[r - k] : 0.0;
     }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int col = k + d;
+        piv[d] = col < pn ? Lo[col + (long)col * ld] : 1.0;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int r = tid + 256 * u;
+            ring[d][u] = (r > col && r < pn) ? Lo[r + (long)col * ld] : 0.0;
+        }
+    }
+    double* vb = v;                          // vb[(c - k) & 1]: the entry of pivot row c
+    for (int c = k; c < pn; c += 4) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const int cc = c + d;
+            if (cc < pn) {
+                const double vc = vb[(cc - k) & 1], lcc = piv[d];
+                const double rr = sqrt(lcc * lcc + vc * vc), cs = rr / lcc, ics = lcc / rr, sn = vc / lcc;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    const int r = tid + 256 * u;
+                    if (r > cc && r < pn) {
+                        const double ln = (ring[d][u] + sn * vr[u]) * ics;
+                        vr[u] = cs * vr[u] - sn * ln;
+                        Lo[r + (long)cc * ld] = ln;
+                        if (r == cc + 1) vb[(cc + 1 - k) & 1] = vr[u];
+                    }
+                }
+                if (tid == 0) dg[cc - k] = rr;
+                const int cn = cc + 4;
+                if (cn < pn) {
+                    piv[d] = Lo[cn + (long)cn * ld];
+#pragma unroll
+                    for (int u = 0; u < NU; ++u) {
+                        const int r = tid + 256 * u;
+                        ring[d][u] = (r > cn && r < pn) ? Lo[r + (long)cn * ld] : 0.0;
+                    }
+                }
+                lds_barrier();
+            }
+        }
+    }
+    __syncthreads();
+    for (int c = k + tid; c < pn; c += 256) Lo[c + (long)c * ld] = dg[c - k];
     __syncthreads();
     double* t = L;
     L = Lo;
@@ -640,8 +802,9 @@ __device__ void big_refresh_z(const double* L, long ld, int p, int k0, const sho
 }
 
 // the samples in list[0 .. *count), one per workgroup at a time; slot s of
-// `scratch` (slot_doubles each) belongs to workgroup s
-__global__ __launch_bounds__(256) void k_slr_lasso_big(const double* __restrict__ G, long ldg, int nk, int pmax,
+// `scratch` (slot_doubles each) belongs to workgroup s; n_k <= 256 NU
+template <int NU>
+__global__ __launch_bounds__(256, NU == 2 ? 4 : 3) void k_slr_lasso_big(const double* __restrict__ G, long ldg, int nk, int pmax,
                                                        double alpha, const int* __restrict__ nbr,
                                                        const int* __restrict__ list, const int* __restrict__ count,
                                                        double* __restrict__ scratch, long slot_doubles,
@@ -658,15 +821,16 @@ __global__ __launch_bounds__(256) void k_slr_lasso_big(const double* __restrict_
     short* P = pos + nk;
     unsigned char* have = reinterpret_cast<unsigned char*>(P + pmax);
     unsigned char* keep = have + nk;
-    __shared__ double D[kDB * kDBld];
-    __shared__ double rv[256];
-    __shared__ int ri[256];
+    __shared__ double D[2 * kDB * kDBld];
+    __shared__ double rv[4];
+    __shared__ int ri[4];
     __shared__ double red[4];
     const int tid = threadIdx.x;
     const long ld = pmax;
     double* L = scratch + (long)blockIdx.x * slot_doubles;
     double* Lo = L + ld * pmax;
     double* Gc = Lo + ld * pmax;             // column a: G_i(:, a) once a has entered P
+    const long ldc = (nk + 1) & ~1;          // even, so column pairs are 16-byte aligned
     const int total = *count;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int i = list[item];
@@ -687,24 +851,49 @@ __global__ __launch_bounds__(256) void k_slr_lasso_big(const double* __restrict_
         const double tol = kTol * scale, thr = kDepTol * dmax;
         int p = 0, steps = 0, status = 0;
         double viol = 0.0;
-        double ga[4];                        // gradient of the coordinates tid + 256 u
+        double ga[NU];                       // gradient of the coordinates NU tid + u
         while (status == 0) {
-            for (int u = 0; u < 4; ++u) {
-                const int a = tid + 256 * u;
+            // g = alpha - 2 b + 2 G_i(:, P) w_P: NU consecutive coordinates per thread
+            // (16-byte loads down the columns), the columns of a batch of 8 loaded together
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int a = NU * tid + u;
                 ga[u] = a < nk ? alpha - 2.0 * b[a] : 0.0;
             }
-            for (int r = 0; r < p; ++r) {
+            const bool mine = NU * tid < nk;
+            int r = 0;
+            for (; r + 8 <= p; r += 8) {
+                double2 e[8][NU / 2];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const double2* col = reinterpret_cast<const double2*>(Gc + (long)P[r + q] * ldc) + (NU / 2) * tid;
+#pragma unroll
+                    for (int h = 0; h < NU / 2; ++h) e[q][h] = mine ? col[h] : make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const double wr = 2.0 * wP[r + q];
+#pragma unroll
+                    for (int h = 0; h < NU / 2; ++h) {
+                        ga[2 * h] += wr * e[q][h].x;
+                        ga[2 * h + 1] += wr * e[q][h].y;
+                    }
+                }
+            }
+            for (; r < p; ++r) {
                 const double wr = 2.0 * wP[r];
-                const double* col = Gc + (long)P[r] * nk;
-                for (int u = 0; u < 4; ++u) {
-                    const int a = tid + 256 * u;
-                    if (a < nk) ga[u] += wr * col[a];
+                const double2* col = reinterpret_cast<const double2*>(Gc + (long)P[r] * ldc) + (NU / 2) * tid;
+#pragma unroll
+                for (int h = 0; h < NU / 2; ++h) {
+                    const double2 e = mine ? col[h] : make_double2(0.0, 0.0);
+                    ga[2 * h] += wr * e.x;
+                    ga[2 * h + 1] += wr * e.y;
                 }
             }
             double v = 0.0, gmin = 0.0;
             int jmin = INT_MAX;
-            for (int u = 0; u < 4; ++u) {
-                const int a = tid + 256 * u;
+            for (int u = 0; u < NU; ++u) {
+                const int a = NU * tid + u;
                 if (a >= nk) continue;
                 if (pos[a] >= 0) v = fmax(v, fabs(ga[u]));
                 else {
@@ -717,10 +906,10 @@ __global__ __launch_bounds__(256) void k_slr_lasso_big(const double* __restrict_
             if (++steps > 10 * nk + 20) { status = 2; break; }
             double gj;
             int j;
-            block_argmin256(gmin, jmin, rv, ri, gj, j);
+            block_argmin256_w(gmin, jmin, rv, ri, gj, j);
             if (!(gj < 0.0)) j = -1;
             if (j >= 0) {
-                double* cj = Gc + (long)j * nk;
+                double* cj = Gc + (long)j * ldc;
                 if (!have[j]) {
                     const double* src = G + (long)nb[j] * ldg;
                     for (int a = tid; a < nk; a += 256) cj[a] = src[nb[a]];
@@ -748,12 +937,12 @@ __global__ __launch_bounds__(256) void k_slr_lasso_big(const double* __restrict_
                     }
                     double t;
                     int out;
-                    block_argmin256(tb, ib, rv, ri, t, out);
+                    block_argmin256_w(tb, ib, rv, ri, t, out);
                     if (out == INT_MAX) { status = 2; break; }
                     for (int q = tid; q < p; q += 256) wP[q] -= t * y[q];
                     __syncthreads();
                     const int kd = pos[out];
-                    big_delete(L, Lo, ld, p, kd, P, wP, pos, y);
+                    big_delete<NU>(L, Lo, ld, p, kd, P, wP, pos, y, z);
                     big_refresh_z(L, ld, p, kd, P, b, alpha, z, D);
                     for (int q = tid; q < p; q += 256) y[q] = cj[P[q]];
                     __syncthreads();
@@ -805,14 +994,14 @@ __global__ __launch_bounds__(256) void k_slr_lasso_big(const double* __restrict_
                 }
                 const int k0 = (int)block_min256(kmin, red);
                 for (int q = p - 1; q >= k0; --q)
-                    if (!keep[q]) big_delete(L, Lo, ld, p, q, P, wP, pos, y);
+                    if (!keep[q]) big_delete<NU>(L, Lo, ld, p, q, P, wP, pos, y, z);
                 if (p > 0) big_refresh_z(L, ld, p, k0, P, b, alpha, z, D);
             }
         }
         // weights, optimal objective, statistics
         double ns = 0.0, to = 0.0;
-        for (int u = 0; u < 4; ++u) {
-            const int a = tid + 256 * u;
+        for (int u = 0; u < NU; ++u) {
+            const int a = NU * tid + u;
             if (a >= nk) continue;
             const int q = pos[a];
             const double wa = q >= 0 ? wP[q] : 0.0;
@@ -897,11 +1086,12 @@ extern "C" lrr_status lrr_slr_graph(lrr_ctx* ctx, int m, int n, const void* Mv, 
             const int pmax = std::min(m, nk);
             const size_t lds_big = sizeof(double) * ((size_t)nk + 3 * (size_t)pmax) + sizeof(int) * (size_t)nk +
                                    sizeof(short) * ((size_t)nk + pmax) + (size_t)nk + pmax;
+            const auto kern = nk <= 512 ? k_slr_lasso_big<2> : k_slr_lasso_big<4>;
             int per_cu = 0, cus = 0;
-            LRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_slr_lasso_big, 256, lds_big));
+            LRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds_big));
             LRR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, lrr::ctx_device(ctx)));
             long slots = std::min<long>(nbig, std::max(1, per_cu) * (long)std::max(1, cus));
-            const long slot_doubles = ((2L * pmax * pmax + (long)nk * nk) + 31) / 32 * 32;
+            const long slot_doubles = ((2L * pmax * pmax + (long)nk * ((nk + 1) & ~1)) + 31) / 32 * 32;
             void* scratch = nullptr;
             while (slots >= 1 && !lrr::try_device_alloc(&scratch, sizeof(double) * slot_doubles * slots)) slots /= 2;
             if (!scratch) return lrr::ctx_fail(ctx, LRR_ENOMEM, "SLR-graph large-support workspace allocation failed");
@@ -910,7 +1100,7 @@ extern "C" lrr_status lrr_slr_graph(lrr_ctx* ctx, int m, int n, const void* Mv, 
                 ~Free() { (void)hipFree(p); }
             } release{scratch};
             lrr::ctx_timed(ctx, s, "k_slr_lasso_big", 0.0, 0.0, [&] {
-                hipLaunchKernelGGL(k_slr_lasso_big, dim3((unsigned)slots), dim3(256), lds_big, s, G, (long)n, nk,
+                hipLaunchKernelGGL(kern, dim3((unsigned)slots), dim3(256), lds_big, s, G, (long)n, nk,
                                    pmax, alpha, nbr, big_list, big_count, static_cast<double*>(scratch),
                                    slot_doubles, w, obj, steps, kkt, sup);
             });
