@@ -435,7 +435,8 @@ def slr_graph(B, torch, p, Mt, Zt, ctx, nk=500, alpha=0.05, reps=3):
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / reps
     out = {"ms": ms, "nk": nk, "alpha": alpha, "max_steps": info["max_steps"], "max_kkt": info["max_kkt"],
-           "not_converged": info["not_converged"], "edges_per_sample": float((w > 0).sum().item()) / p.n}
+           "not_converged": info["not_converged"], "large_support": info["large_support"],
+           "max_support": info["max_support"], "edges_per_sample": float((w > 0).sum().item()) / p.n}
     print(f"bench: SLR-graph {p.name}: {ms:.1f} ms", file=sys.stderr, flush=True)
     return out
 

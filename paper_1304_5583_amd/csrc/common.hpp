@@ -91,6 +91,9 @@ struct EigDesc {
                         // at p * (L/bs) + q) holding an entry that still needs a rotation
     const int* sched;   // (may be null) explicit rounds: entry r * (L/bs/2) + P is the pair
                         // p | q << 16 of slot P in round r; every round pairs all L/bs blocks
+    const int* done;    // (may be null) done[0] set: the refinement left nothing to rotate; B
+                        // was not formed, its diagonal is taken from lam and the matrix is
+                        // closed at the start of the eigensolve
 };
 
 // Control block of the persistent eigensolve (k_jacobi_solve): its grid-wide
@@ -128,6 +131,8 @@ struct RefDesc {
     double* Xb;         // L x L copy of X before the refinement (restored if it fails)
     const double* cut;  // cut factor of the block (as EigDesc::cut)
     int L, l, block;
+    int* clean;         // the last applied step corrected by < kCleanCorr with no unresolvable
+                        // coupling, and the orthogonalisation found |I - X^T X| <= kCleanDev
 };
 
 // One block's small matrices in the reverse sweep of the thresholding step.

@@ -367,6 +367,11 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const EigDesc* __restrict_
 __global__ __launch_bounds__(256) void k_jacobi_init(const EigDesc* __restrict__ descs) {
     const EigDesc d = descs[blockIdx.x];
     if (d.run[0] == 0) return;
+    const bool done = d.done && d.done[0];
+    if (done) {
+        for (int i = threadIdx.x; i < d.l; i += 256) d.B[i + (long)i * d.L] = d.lam[i];
+        __syncthreads();
+    }
     double mx = 0.0;
     for (int i = threadIdx.x; i < d.l; i += 256) mx = fmax(mx, fabs(d.B[i + (long)i * d.L]));
     mx = wave_max(mx);
@@ -375,7 +380,7 @@ __global__ __launch_bounds__(256) void k_jacobi_init(const EigDesc* __restrict__
     __syncthreads();
     if (threadIdx.x == 0) {
         d.scale[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-        d.st[0] = 0;
+        d.st[0] = done ? 1 : 0;
         d.st[1] = 0;
     }
 }
@@ -624,6 +629,11 @@ __global__ __launch_bounds__(kSolveThreads) void k_jacobi_solve(const EigDesc* _
     for (int b = wg; b < t; b += G) {
         const EigDesc d = descs[b];
         if (d.run[0] == 0) continue;
+        const bool done = d.done && d.done[0];
+        if (done) {
+            for (int i = tid; i < d.l; i += kSolveThreads) d.B[i + (long)i * d.L] = d.lam[i];
+            __syncthreads();
+        }
         double mx = 0.0;
         for (int i = tid; i < d.l; i += kSolveThreads) mx = fmax(mx, fabs(d.B[i + (long)i * d.L]));
         mx = wave_max(mx);
@@ -631,7 +641,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_jacobi_solve(const EigDesc* _
         __syncthreads();
         if (tid == 0) {
             d.scale[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-            d.st[0] = 0;
+            d.st[0] = done ? 1 : 0;
             d.st[1] = 0;
         }
         __syncthreads();

@@ -67,6 +67,8 @@ void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hi
                     bool count_pass = true);
 void launch_orth_E(const RefDesc* d, int count, int maxL, hipStream_t s);
 void launch_ref_set_run(const RefDesc* d, int count, const int* svt_run, hipStream_t s);
+// the Jacobi matrix is formed only for the blocks that need a decomposition and are not clean
+void launch_ref_set_run_jac(const RefDesc* d, int count, const int* svt_run, hipStream_t s);
 // after the first orthogonalisation step: the second runs where |I - X^T X| exceeded 1e-8
 void launch_orth_decide(const RefDesc* d, int count, hipStream_t s);
 void launch_lo_mode(const int* svt_run, const int* warm, int* passes, double* cut, int t, hipStream_t s);

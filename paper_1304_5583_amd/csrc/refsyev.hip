@@ -46,6 +46,19 @@ constexpr double kAbsFloor = 1e-14;
 constexpr double kLoCut = 1e-2;           // cut factor after the switch
 constexpr int kSwitchSweeps = 8;          // warm sweeps that trigger it
 constexpr double kNSSecond = 1e-8;        // |I - X^T X| above which the second orthogonalisation step runs
+// A block is clean (its Jacobi matrix X^T B X is not formed) when the last
+// applied step's largest correction e was below kCleanCorr with no unresolvable
+// coupling above the Jacobi tolerance, and the first orthogonalisation step
+// found |I - X^T X| = d <= kCleanDev (so no second step).  Write X = V (I + H)
+// with V orthonormal eigenvectors up to the step's residual: the step leaves
+// couplings of order e^2 times the eigenvalue gaps, and the non-orthogonality
+// H (|H| ~ d / 2) couples i and j by (lambda_i + lambda_j) H_ij; the
+// orthogonalisation X (I + (I - X^T X)/2) = V (I - H^2 + ...) leaves O(d^2).
+// Both are below the Jacobi check's floor of 1e-14 max |diag|, and the
+// Rayleigh quotients of the step's S differ from those of the final X by
+// terms of the same second order.
+constexpr double kCleanCorr = 1e-10;
+constexpr double kCleanDev = 1e-8;
 
 
 // row pass: lambda_i, Gershgorin flag lo_i of S (padding: lambda 0, lo 1)
@@ -158,6 +171,7 @@ __global__ void k_ref_update(const RefDesc* __restrict__ descs, int count, int s
     const double e = __longlong_as_double((long long)d.emax[0]);
     const double limit = (step == 0) ? kFirstStepCap : d.eprev[0];
     const bool apply = (e <= limit);
+    d.clean[0] = (apply && e < kCleanCorr && d.unres[0] == 0) ? 1 : 0;
     // after a correction below 1e-10 the next one (quadratic in it) would be at
     // the rounding level; what such a step would remove is left to the Jacobi
     // check, whose tolerance decides convergence
@@ -185,6 +199,7 @@ __global__ void k_ref_begin(const RefDesc* __restrict__ descs, int count, const 
     const RefDesc d = descs[b];
     d.run[0] = (svt_run[d.block] && warm[d.block]) ? 1 : 0;
     d.cont[0] = 0;
+    d.clean[0] = 0;
     d.eprev[0] = 1.0;
     d.emax[0] = 0ull;
     d.unres[0] = 0;
@@ -305,6 +320,7 @@ __global__ void k_orth_decide(const RefDesc* __restrict__ descs, int count, doub
     if (d.run[0] == 0) return;
     const double dev = __longlong_as_double((long long)d.emax[0]);
     d.run[0] = dev > thr ? 1 : 0;
+    if (!(dev <= kCleanDev)) d.clean[0] = 0;
 }
 
 // the steps after the refinement run on every matrix that needs a decomposition
@@ -313,6 +329,15 @@ __global__ void k_ref_set_run(const RefDesc* __restrict__ descs, int count, cons
     if (b >= count) return;
     const RefDesc d = descs[b];
     d.run[0] = svt_run[d.block];
+}
+
+// the Jacobi matrix X^T B X is formed for the matrices that need a decomposition
+// and are not clean
+__global__ void k_ref_set_run_jac(const RefDesc* __restrict__ descs, int count, const int* __restrict__ svt_run) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const RefDesc d = descs[b];
+    d.run[0] = (svt_run[d.block] && !d.clean[0]) ? 1 : 0;
 }
 
 __global__ void k_mark_warm(const int* __restrict__ svt_run, int* __restrict__ warm, int t) {
@@ -341,6 +366,9 @@ void launch_orth_decide(const RefDesc* d, int count, hipStream_t s) {
 }
 void launch_ref_set_run(const RefDesc* d, int count, const int* svt_run, hipStream_t s) {
     hipLaunchKernelGGL(k_ref_set_run, dim3((count + 63) / 64), dim3(64), 0, s, d, count, svt_run);
+}
+void launch_ref_set_run_jac(const RefDesc* d, int count, const int* svt_run, hipStream_t s) {
+    hipLaunchKernelGGL(k_ref_set_run_jac, dim3((count + 63) / 64), dim3(64), 0, s, d, count, svt_run);
 }
 void launch_lo_mode(const int* svt_run, const int* warm, int* passes, double* cut, int t, hipStream_t s) {
     hipLaunchKernelGGL(k_lo_mode, dim3((t + 63) / 64), dim3(64), 0, s, svt_run, warm, passes, cut, t);

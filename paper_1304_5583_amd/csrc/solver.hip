@@ -213,7 +213,7 @@ struct Buffers {
     DevIter* it;
     std::vector<double*> Bm, Wm, Wg, Pm, Rm, lam, h, TX, SG, Eb, XE, Bq;
     std::vector<int*> lo;
-    int *warm, *ref_run, *ref_unres, *ref_cont, *passes;
+    int *warm, *ref_run, *ref_unres, *ref_cont, *ref_clean, *passes;
     int *need_all, *sched_all;   // targeted Jacobi rounds: check marks and round schedules, all blocks
     int *jac_offs, *jac_brounds; // persistent eigensolve: per-block item prefixes, planned rounds
     lrr::JacCtl* jac_ctl;
@@ -326,6 +326,7 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.locut = a.take<double>(t);
     b.ref_run = a.take<int>(t);
     b.ref_cont = a.take<int>(t);
+    b.ref_clean = a.take<int>(t);
     b.ref_unres = a.take<int>(t);
     b.ref_eprev = a.take<double>(t);
     b.ref_scale = a.take<double>(t);
@@ -721,11 +722,11 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
                                 0.0, b.expand + bb, nullptr};
         eig[bb] = EigDesc{b.Bq[bb], X, b.Rm[bb], b.lam[bb], L, l, run, b.eigst + 2 * bb,
                           b.eigscale + bb, b.prot[bb], b.lo[bb], ctx->dwork, b.locut + bb, b.passes + bb,
-                          b.need_all + need_off[bb], b.sched_all + sched_off[bb]};
+                          b.need_all + need_off[bb], b.sched_all + sched_off[bb], b.ref_clean + bb};
         svt[bb] = SvtDesc{b.Bq[bb], X, b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
         ref[bb] = RefDesc{b.Bm[bb], X, b.SG[bb], b.Eb[bb], b.XE[bb], b.lam[bb], b.lo[bb], b.ref_scale + bb,
                           b.ref_emax + bb, b.ref_unres + bb, b.ref_eprev + bb, b.ref_run + bb,
-                          b.ref_cont + bb, b.Bq[bb], b.locut + bb, L, l, bb};
+                          b.ref_cont + bb, b.Bq[bb], b.locut + bb, L, l, bb, b.ref_clean + bb};
     }
     std::vector<GemmDesc> gKK(p.local ? t : 1);
     if (p.literal)
@@ -1057,7 +1058,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             if (ns == 0) tm("k_orth_decide", 0.0, 0.0, [&] { lrr::launch_orth_decide(b.ref, t, st); });
         }
         tm("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, b.warm, st); });
-        tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run(b.ref, t, b.svt_run, st); });
+        tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_jac(b.ref, t, b.svt_run, st); });
         tm("k_dgemm<false, false>", f_L3, 0.0, [&] {
             lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, st);
         });
@@ -1152,7 +1153,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 if (ns == 0) timed("k_orth_decide", 0.0, 0.0, [&] { lrr::launch_orth_decide(b.ref, t, s); });
             }
             timed("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, b.warm, s); });
-            timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run(b.ref, t, b.svt_run, s); });
+            timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_jac(b.ref, t, b.svt_run, s); });
             timed("k_dgemm<false, false>", f_L3, 0.0, [&] {
                 lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, s);
             });
