@@ -508,6 +508,9 @@ def main():
                     help="also run a plain 512 MiB device copy (reference for HBM counters)")
     ap.add_argument("--traffic-from-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write --traffic from two rocprofv3 counter-collection files and exit")
+    ap.add_argument("--slr-only", action="store_true",
+                    help="after the warmup solves, time only the SLR-graph on the solve's Z (one JSON line of "
+                         "its statistics; for profiling that step)")
     args = ap.parse_args()
     if args.traffic_from_pmc:
         from paper_1304_5583_amd import binding as B
@@ -547,6 +550,13 @@ def main():
         _, _, info = B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False, Zt=Zt)
         torch.cuda.synchronize()
         print(f"bench: warmup {i} batch_iters={info.batch_iters}", file=sys.stderr, flush=True)
+    if args.slr_only:
+        if args.warmup == 0:
+            B.dfc_lrr_solve(Mt, p.lam, p.perm, p.offsets, opts=opts, ctx=ctx, want_S=False, Zt=Zt)
+        out = slr_graph(B, torch, p, Mt, Zt, ctx, reps=1)
+        out["workload"] = workload_name(p, "fp64")
+        print(json.dumps(out), flush=True)
+        return
     # headline region: the FP64 plain form, no per-kernel timing
     batch_iters = block_iters = 0
     torch.cuda.synchronize()

@@ -230,6 +230,7 @@ struct Buffers {
 };
 
 constexpr int kRefSteps = 10;  // cap on refinement steps per thresholding step
+constexpr int kBlindSteps = 3;   // refinement steps launched before the host reads the flags
 constexpr int kMaxTargeted = 60;   // cap on targeted Jacobi passes per eigensolve
 constexpr int kAnchorEvery = 16;   // FP64 re-anchoring period of the carried product M Q
 
@@ -1059,10 +1060,14 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         }
         tm("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, b.warm, st); });
         tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_jac(b.ref, t, b.svt_run, st); });
-        tm("k_dgemm<false, false>", f_L3, 0.0, [&] {
+        read_flags(h_ref, b.ref_run);
+        double f_jac = 0.0;   // the Jacobi matrix is formed for the blocks that are not clean
+        for (int bb = 0; bb < t && price; ++bb)
+            if (h_ref[bb]) f_jac += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
+        tm("k_dgemm<false, false>", f_jac, 0.0, [&] {
             lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, st);
         });
-        tm("k_dgemm_sym", hL * f_L3, 0.0, [&] { lrr::launch_dgemm_sym(b.g_Bq, t, p.maxL, st); });
+        tm("k_dgemm_sym", hL * f_jac, 0.0, [&] { lrr::launch_dgemm_sym(b.g_Bq, t, p.maxL, st); });
         // block-Jacobi passes for the couplings the refinement left (the whole
         // decomposition on a block's first thresholding step): one persistent launch
         tm("k_jacobi_solve", 0.0, 0.0, [&] {
@@ -1110,14 +1115,20 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             timed("k_dgemm_sym", hg * f_gram, 0.0, [&] { lrr::launch_dgemm_sym(b.g_gram, t, p.maxl, s); });
             // Newton refinement of the previous iteration's eigenvectors
             timed("k_ref_begin", 0.0, 0.0, [&] { lrr::launch_ref_begin(b.ref, t, p.maxL, b.svt_run, b.warm, s); });
-            LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
-            sync();
+            // the first kBlindSteps steps are launched without reading the flags back
+            // (a warm eigensolve takes about three; the device flags decide which
+            // blocks a step touches), later ones only while some block continues;
+            // a profiled solve reads them every step to price the products
             for (int step = 0; step < kRefSteps; ++step) {
                 double fl = 0.0;
-                int nref = 0;
-                for (int bb = 0; bb < t; ++bb)
-                    if (h_ref[bb]) { fl += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb]; ++nref; }
-                if (nref == 0) break;
+                if (step >= kBlindSteps || prof.on) {
+                    LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+                    sync();
+                    int nref = 0;
+                    for (int bb = 0; bb < t; ++bb)
+                        if (h_ref[bb]) { fl += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb]; ++nref; }
+                    if (nref == 0) break;
+                }
                 timed("k_dgemm<false, false>", fl, 0.0, [&] {
                     lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, s);
                 });
@@ -1133,8 +1144,6 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 });
                 timed("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, s); });
                 timed("k_ref_next", 0.0, 0.0, [&] { lrr::launch_ref_next(b.ref, t, s); });
-                LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
-                sync();
             }
             // up to two Newton-Schulz steps X <- X (I + (I - X^T X)/2), the second
             // only where the first started above 1e-8; an estimate that is still far
@@ -1154,10 +1163,18 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             }
             timed("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, b.warm, s); });
             timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_jac(b.ref, t, b.svt_run, s); });
-            timed("k_dgemm<false, false>", f_L3, 0.0, [&] {
+            double f_jac = f_L3;   // priced by the blocks that form the Jacobi matrix (not clean)
+            if (prof.on) {
+                LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+                sync();
+                f_jac = 0.0;
+                for (int bb = 0; bb < t; ++bb)
+                    if (h_ref[bb]) f_jac += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
+            }
+            timed("k_dgemm<false, false>", f_jac, 0.0, [&] {
                 lrr::launch_dgemm(b.g_refT, t, p.maxL, p.maxL, false, false, s);
             });
-            timed("k_dgemm_sym", hL * f_L3, 0.0, [&] { lrr::launch_dgemm_sym(b.g_Bq, t, p.maxL, s); });
+            timed("k_dgemm_sym", hL * f_jac, 0.0, [&] { lrr::launch_dgemm_sym(b.g_Bq, t, p.maxL, s); });
             // block-Jacobi sweeps for the couplings the refinement left (the
             // whole decomposition on a block's first thresholding step)
             const int nb = p.maxL / p.bs;
