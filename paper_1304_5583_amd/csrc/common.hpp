@@ -131,7 +131,7 @@ struct RefDesc {
     double* Xb;         // L x L copy of X before the refinement (restored if it fails)
     const double* cut;  // cut factor of the block (as EigDesc::cut)
     int L, l, block;
-    int* clean;         // the last applied step corrected by < kCleanCorr with no unresolvable
+    int* clean;         // the last applied step corrected by less than the stop with no unresolvable
                         // coupling, and the orthogonalisation found |I - X^T X| <= kCleanDev
 };
 

@@ -59,7 +59,8 @@ void launch_ref_begin(const RefDesc* d, int count, int maxL, const int* svt_run,
 void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, hipStream_t s);
 void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s);
 void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s);
-void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, hipStream_t s);
+// stop: a step whose largest correction falls below it is the last one
+void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, double stop, hipStream_t s);
 void launch_ref_next(const RefDesc* d, int count, hipStream_t s);
 void launch_orth_guard(const RefDesc* d, int count, int maxL, const int* warm, hipStream_t s);
 // count_pass: count this pass of the sweep loop toward the block's switch rule

@@ -47,7 +47,7 @@ constexpr double kLoCut = 1e-2;           // cut factor after the switch
 constexpr int kSwitchSweeps = 8;          // warm sweeps that trigger it
 constexpr double kNSSecond = 1e-8;        // |I - X^T X| above which the second orthogonalisation step runs
 // A block is clean (its Jacobi matrix X^T B X is not formed) when the last
-// applied step's largest correction e was below kCleanCorr with no unresolvable
+// applied step's largest correction e was below the stop (at most 1e-8) with no unresolvable
 // coupling above the Jacobi tolerance, and the first orthogonalisation step
 // found |I - X^T X| = d <= kCleanDev (so no second step).  Write X = V (I + H)
 // with V orthonormal eigenvectors up to the step's residual: the step leaves
@@ -57,7 +57,6 @@ constexpr double kNSSecond = 1e-8;        // |I - X^T X| above which the second 
 // Both are below the Jacobi check's floor of 1e-14 max |diag|, and the
 // Rayleigh quotients of the step's S differ from those of the final X by
 // terms of the same second order.
-constexpr double kCleanCorr = 1e-10;
 constexpr double kCleanDev = 1e-8;
 
 
@@ -163,7 +162,7 @@ __global__ __launch_bounds__(256) void k_ref_add(const RefDesc* __restrict__ des
 
 // after E is formed and before it is applied: apply the step only while the
 // corrections do not grow; stop (without applying) otherwise
-__global__ void k_ref_update(const RefDesc* __restrict__ descs, int count, int step, int max_steps) {
+__global__ void k_ref_update(const RefDesc* __restrict__ descs, int count, int step, int max_steps, double stop) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= count) return;
     const RefDesc d = descs[b];
@@ -171,11 +170,11 @@ __global__ void k_ref_update(const RefDesc* __restrict__ descs, int count, int s
     const double e = __longlong_as_double((long long)d.emax[0]);
     const double limit = (step == 0) ? kFirstStepCap : d.eprev[0];
     const bool apply = (e <= limit);
-    d.clean[0] = (apply && e < kCleanCorr && d.unres[0] == 0) ? 1 : 0;
-    // after a correction below 1e-10 the next one (quadratic in it) would be at
+    d.clean[0] = (apply && e < stop && d.unres[0] == 0) ? 1 : 0;
+    // after a correction below `stop` the next one (quadratic in it) would be at
     // the rounding level; what such a step would remove is left to the Jacobi
     // check, whose tolerance decides convergence
-    const bool cont = apply && e >= 1e-10 && step + 1 < max_steps;
+    const bool cont = apply && e >= stop && step + 1 < max_steps;
     d.eprev[0] = e;
     d.emax[0] = 0ull;
     d.unres[0] = 0;
@@ -397,8 +396,8 @@ void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s) {
     hipLaunchKernelGGL(k_ref_add, dim3((unsigned)std::min<long>((n + 255) / 256, kStreamGroups), count), dim3(256), 0,
                        s, d);
 }
-void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, hipStream_t s) {
-    hipLaunchKernelGGL(k_ref_update, dim3((count + 63) / 64), dim3(64), 0, s, d, count, step, max_steps);
+void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, double stop, hipStream_t s) {
+    hipLaunchKernelGGL(k_ref_update, dim3((count + 63) / 64), dim3(64), 0, s, d, count, step, max_steps, stop);
 }
 void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hipStream_t s, bool count_pass) {
     hipLaunchKernelGGL(k_lo_rows, dim3(maxL, count), dim3(256), 0, s, d, it, (int)count_pass);

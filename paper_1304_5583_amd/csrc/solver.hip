@@ -879,6 +879,13 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
     const int check_every = o.check_every > 0 ? o.check_every : 1;
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
+    // The refinement stops after a correction below ref_stop: the next one
+    // (quadratic in it) would be at the rounding level of the products.  A
+    // fixed-iteration solve, the form callers differentiate, uses 1e-10 so that
+    // its forward map stays smooth at the scale of a central difference
+    // (h = 1e-6); a solve that stops on the tolerance, whose iteration count is
+    // itself a step function of the data, uses 1e-8.
+    const double ref_stop = fixed ? 1e-10 : 1e-8;
     int* h_run = hp;            // t ints
     int* h_misc = hp + t;       // scalars
     int* h_ref = hp + t + 16;   // t ints: refinement still running, per block
@@ -1038,7 +1045,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             tm("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, st); });
             tm("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, st); });
             // decide before applying: only quadratically shrinking corrections
-            tm("k_ref_update", 0.0, 0.0, [&] { lrr::launch_ref_update(b.ref, t, step, kRefSteps, st); });
+            tm("k_ref_update", 0.0, 0.0, [&] { lrr::launch_ref_update(b.ref, t, step, kRefSteps, ref_stop, st); });
             tm("k_dgemm<false, false>", fl, 0.0, [&] {
                 lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, st);
             });
@@ -1138,7 +1145,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 timed("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, s); });
                 timed("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, s); });
                 // decide before applying: only quadratically shrinking corrections
-                timed("k_ref_update", 0.0, 0.0, [&] { lrr::launch_ref_update(b.ref, t, step, kRefSteps, s); });
+                timed("k_ref_update", 0.0, 0.0, [&] { lrr::launch_ref_update(b.ref, t, step, kRefSteps, ref_stop, s); });
                 timed("k_dgemm<false, false>", fl, 0.0, [&] {
                     lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, s);
                 });
