@@ -56,8 +56,9 @@ int jacobi_solve_grid(int bs);
 
 // refsyev.hip
 void launch_ref_begin(const RefDesc* d, int count, int maxL, const int* svt_run, const int* warm, hipStream_t s);
-void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, hipStream_t s);
-void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s);
+// gid: X^T X taken as the identity (G not read; the first step of a warm refinement)
+void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, hipStream_t s, bool gid = false);
+void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s, bool gid = false);
 void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s);
 // stop: a step whose largest correction falls below it is the last one
 void launch_ref_update(const RefDesc* d, int count, int step, int max_steps, double stop, hipStream_t s);

@@ -62,7 +62,7 @@ constexpr double kCleanDev = 1e-8;
 
 // row pass: lambda_i, Gershgorin flag lo_i of S (padding: lambda 0, lo 1)
 // one row of k_ref_rows: lambda_i and the Gershgorin flag lo_i of S
-__device__ void ref_row(const RefDesc& d, int i, const DevIter* it) {
+__device__ void ref_row(const RefDesc& d, int i, const DevIter* it, int gid) {
     const long L = d.L;
     const double* S = d.SG;
     const double* G = d.SG + L * L;
@@ -79,7 +79,7 @@ __device__ void ref_row(const RefDesc& d, int i, const DevIter* it) {
         const double tau = it->tau;
         if (i < d.l) {
             const double sii = S[i + i * L];
-            d.lam[i] = sii / G[i + i * L];
+            d.lam[i] = gid ? sii : sii / G[i + i * L];
             d.lo[i] = it->full ? 0 : lo_flag(sii + r, tau, d.cut[0], d.scale[0]);
         } else {
             d.lam[i] = 0.0;
@@ -88,14 +88,16 @@ __device__ void ref_row(const RefDesc& d, int i, const DevIter* it) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_ref_rows(const RefDesc* __restrict__ descs, const DevIter* it) {
+// gid: X^T X is taken as the identity (the first step of a warm refinement,
+// whose X left the previous iteration orthonormal to rounding), G not read
+__global__ __launch_bounds__(256) void k_ref_rows(const RefDesc* __restrict__ descs, const DevIter* it, int gid) {
     const RefDesc d = descs[blockIdx.y];
     if (d.run[0] == 0) return;
-    for (int i = blockIdx.x; i < d.L; i += gridDim.x) ref_row(d, i, it);
+    for (int i = blockIdx.x; i < d.L; i += gridDim.x) ref_row(d, i, it, gid);
 }
 
 // correction matrix E and per-matrix statistics
-__global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs) {
+__global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs, int gid) {
     const RefDesc d = descs[blockIdx.y];
     if (d.run[0] == 0) return;
     const long L = d.L;
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs
         const int i = (int)(idx % L), j = (int)(idx / L);
         const double* S = d.SG;
         const double* G = d.SG + L * L;
-        const double gij = G[i + j * L];
+        const double gij = gid ? (i == j ? 1.0 : 0.0) : G[i + j * L];
         double e;
         if (i == j) {
             e = 0.5 * (1.0 - gij);
@@ -383,13 +385,13 @@ void launch_ref_begin(const RefDesc* d, int count, int maxL, const int* svt_run,
     hipLaunchKernelGGL(k_ref_backup, dim3((unsigned)std::min<long>((n + 255) / 256, kStreamGroups), count), dim3(256),
                        0, s, d);
 }
-void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, hipStream_t s) {
-    hipLaunchKernelGGL(k_ref_rows, dim3(std::min(maxL, kRowGroups), count), dim3(256), 0, s, d, it);
+void launch_ref_rows(const RefDesc* d, int count, int maxL, const DevIter* it, hipStream_t s, bool gid) {
+    hipLaunchKernelGGL(k_ref_rows, dim3(std::min(maxL, kRowGroups), count), dim3(256), 0, s, d, it, (int)gid);
 }
-void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s) {
+void launch_ref_E(const RefDesc* d, int count, int maxL, hipStream_t s, bool gid) {
     const long n = (long)maxL * maxL;
     hipLaunchKernelGGL(k_ref_E, dim3((unsigned)std::min<long>((n + 255) / 256, kStatGroups), count), dim3(256), 0,
-                       s, d);
+                       s, d, (int)gid);
 }
 void launch_ref_add(const RefDesc* d, int count, int maxL, hipStream_t s) {
     const long n = (long)maxL * maxL;

@@ -1041,9 +1041,12 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             });
             // S = X^T (B X) is symmetric: upper tiles, mirrored
             tm("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_refSG, t, p.maxL, st); });
-            tm("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, st); });
-            tm("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, st); });
-            tm("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, st); });
+            // the first step takes X^T X = I: X left the previous iteration orthonormal
+            // to rounding (orthogonalised, or rotated by the Jacobi sweeps)
+            const bool gid = step == 0;
+            if (!gid) tm("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, st); });
+            tm("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, st, gid); });
+            tm("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, st, gid); });
             // decide before applying: only quadratically shrinking corrections
             tm("k_ref_update", 0.0, 0.0, [&] { lrr::launch_ref_update(b.ref, t, step, kRefSteps, ref_stop, st); });
             tm("k_dgemm<false, false>", fl, 0.0, [&] {
@@ -1141,9 +1144,11 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 });
                 // S = X^T (B X) is symmetric: upper tiles, mirrored
                 timed("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_refSG, t, p.maxL, s); });
-                timed("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, s); });
-                timed("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, s); });
-                timed("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, s); });
+                // the first step takes X^T X = I (X left the previous iteration orthonormal)
+                const bool gid = step == 0;
+                if (!gid) timed("k_dgemm_sym", hL * fl, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, s); });
+                timed("k_ref_rows", 0.0, 0.0, [&] { lrr::launch_ref_rows(b.ref, t, p.maxL, b.it, s, gid); });
+                timed("k_ref_E", 0.0, 0.0, [&] { lrr::launch_ref_E(b.ref, t, p.maxL, s, gid); });
                 // decide before applying: only quadratically shrinking corrections
                 timed("k_ref_update", 0.0, 0.0, [&] { lrr::launch_ref_update(b.ref, t, step, kRefSteps, ref_stop, s); });
                 timed("k_dgemm<false, false>", fl, 0.0, [&] {
