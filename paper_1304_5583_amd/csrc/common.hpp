@@ -131,6 +131,8 @@ struct RefDesc {
     double* Xb;         // L x L copy of X before the refinement (restored if it fails)
     const double* cut;  // cut factor of the block (as EigDesc::cut)
     int L, l, block;
+    unsigned long long* rdev;  // largest |I - X^T X| seen by the step (bits)
+    int* nsskip;        // the last applied step measured |I - X^T X| <= 1e-8: no orthogonalisation
     int* clean;         // the last applied step corrected by less than the stop with no unresolvable
                         // coupling, and the orthogonalisation found |I - X^T X| <= kCleanDev
 };

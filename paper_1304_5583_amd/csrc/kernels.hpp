@@ -69,6 +69,9 @@ void launch_lo_rows(const EigDesc* d, int count, int maxL, const DevIter* it, hi
                     bool count_pass = true);
 void launch_orth_E(const RefDesc* d, int count, int maxL, hipStream_t s);
 void launch_ref_set_run(const RefDesc* d, int count, const int* svt_run, hipStream_t s);
+// the orthogonalisation steps run for the blocks that need a decomposition and did not measure
+// |I - X^T X| <= 1e-8 in their last refinement step
+void launch_ref_set_run_ns(const RefDesc* d, int count, const int* svt_run, hipStream_t s);
 // the Jacobi matrix is formed only for the blocks that need a decomposition and are not clean
 void launch_ref_set_run_jac(const RefDesc* d, int count, const int* svt_run, hipStream_t s);
 // after the first orthogonalisation step: the second runs where |I - X^T X| exceeded 1e-8

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs
     if (d.run[0] == 0) return;
     const long L = d.L;
     if ((long)blockIdx.x * 256 >= L * L) return;   // whole workgroup past the matrix
-    double emax = 0.0;
+    double emax = 0.0, rdev = 0.0;
     int unres = 0;
     // a few workgroups stride over the matrix: one atomic per workgroup for the
     // statistics (one per 256 entries serialised on the two addresses)
@@ -111,6 +111,7 @@ __global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs
         const double* S = d.SG;
         const double* G = d.SG + L * L;
         const double gij = gid ? (i == j ? 1.0 : 0.0) : G[i + j * L];
+        rdev = fmax(rdev, fabs((i == j ? 1.0 : 0.0) - gij));
         double e;
         if (i == j) {
             e = 0.5 * (1.0 - gij);
@@ -137,16 +138,20 @@ __global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs
     }
     // one atomic per workgroup (per-wave atomics on one address serialise)
     emax = wave_max(emax);
+    rdev = wave_max(rdev);
     int u = unres;
     for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
-    __shared__ double wmax[4];
+    __shared__ double wmax[4], wdev[4];
     __shared__ int wsum[4];
     if ((threadIdx.x & 63) == 0) {
         wmax[threadIdx.x >> 6] = emax;
+        wdev[threadIdx.x >> 6] = rdev;
         wsum[threadIdx.x >> 6] = u;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        const double r4 = fmax(fmax(wdev[0], wdev[1]), fmax(wdev[2], wdev[3]));
+        if (r4 > 0.0) atomic_max_nonneg(d.rdev, r4);
         const double e4 = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
         const int u4 = wsum[0] + wsum[1] + wsum[2] + wsum[3];
         if (e4 > 0.0) atomic_max_nonneg(d.emax, e4);
@@ -173,6 +178,12 @@ __global__ void k_ref_update(const RefDesc* __restrict__ descs, int count, int s
     const double limit = (step == 0) ? kFirstStepCap : d.eprev[0];
     const bool apply = (e <= limit);
     d.clean[0] = (apply && e < stop && d.unres[0] == 0) ? 1 : 0;
+    // the step leaves |I - X^T X| of order |R| e + e^2 (E + E^T = R to first
+    // order): with G measured (not the first step) and |R| <= kNSSecond the
+    // orthogonalisation steps would only move rounding noise
+    const double rdev = __longlong_as_double((long long)d.rdev[0]);
+    d.nsskip[0] = (d.clean[0] && step > 0 && rdev <= kNSSecond) ? 1 : 0;
+    d.rdev[0] = 0ull;
     // after a correction below `stop` the next one (quadratic in it) would be at
     // the rounding level; what such a step would remove is left to the Jacobi
     // check, whose tolerance decides convergence
@@ -201,6 +212,8 @@ __global__ void k_ref_begin(const RefDesc* __restrict__ descs, int count, const 
     d.run[0] = (svt_run[d.block] && warm[d.block]) ? 1 : 0;
     d.cont[0] = 0;
     d.clean[0] = 0;
+    d.nsskip[0] = 0;
+    d.rdev[0] = 0ull;
     d.eprev[0] = 1.0;
     d.emax[0] = 0ull;
     d.unres[0] = 0;
@@ -332,6 +345,15 @@ __global__ void k_ref_set_run(const RefDesc* __restrict__ descs, int count, cons
     d.run[0] = svt_run[d.block];
 }
 
+// the orthogonalisation steps run for the matrices that need a decomposition,
+// except those whose last refinement step measured |I - X^T X| <= kNSSecond
+__global__ void k_ref_set_run_ns(const RefDesc* __restrict__ descs, int count, const int* __restrict__ svt_run) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const RefDesc d = descs[b];
+    d.run[0] = (svt_run[d.block] && !d.nsskip[0]) ? 1 : 0;
+}
+
 // the Jacobi matrix X^T B X is formed for the matrices that need a decomposition
 // and are not clean
 __global__ void k_ref_set_run_jac(const RefDesc* __restrict__ descs, int count, const int* __restrict__ svt_run) {
@@ -367,6 +389,9 @@ void launch_orth_decide(const RefDesc* d, int count, hipStream_t s) {
 }
 void launch_ref_set_run(const RefDesc* d, int count, const int* svt_run, hipStream_t s) {
     hipLaunchKernelGGL(k_ref_set_run, dim3((count + 63) / 64), dim3(64), 0, s, d, count, svt_run);
+}
+void launch_ref_set_run_ns(const RefDesc* d, int count, const int* svt_run, hipStream_t s) {
+    hipLaunchKernelGGL(k_ref_set_run_ns, dim3((count + 63) / 64), dim3(64), 0, s, d, count, svt_run);
 }
 void launch_ref_set_run_jac(const RefDesc* d, int count, const int* svt_run, hipStream_t s) {
     hipLaunchKernelGGL(k_ref_set_run_jac, dim3((count + 63) / 64), dim3(64), 0, s, d, count, svt_run);

@@ -213,7 +213,8 @@ struct Buffers {
     DevIter* it;
     std::vector<double*> Bm, Wm, Wg, Pm, Rm, lam, h, TX, SG, Eb, XE, Bq;
     std::vector<int*> lo;
-    int *warm, *ref_run, *ref_unres, *ref_cont, *ref_clean, *passes;
+    int *warm, *ref_run, *ref_unres, *ref_cont, *ref_clean, *ref_nsskip, *passes;
+    unsigned long long* ref_rdev;
     int *need_all, *sched_all;   // targeted Jacobi rounds: check marks and round schedules, all blocks
     int *jac_offs, *jac_brounds; // persistent eigensolve: per-block item prefixes, planned rounds
     lrr::JacCtl* jac_ctl;
@@ -328,6 +329,8 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.ref_run = a.take<int>(t);
     b.ref_cont = a.take<int>(t);
     b.ref_clean = a.take<int>(t);
+    b.ref_nsskip = a.take<int>(t);
+    b.ref_rdev = a.take<unsigned long long>(t);
     b.ref_unres = a.take<int>(t);
     b.ref_eprev = a.take<double>(t);
     b.ref_scale = a.take<double>(t);
@@ -727,7 +730,8 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         svt[bb] = SvtDesc{b.Bq[bb], X, b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
         ref[bb] = RefDesc{b.Bm[bb], X, b.SG[bb], b.Eb[bb], b.XE[bb], b.lam[bb], b.lo[bb], b.ref_scale + bb,
                           b.ref_emax + bb, b.ref_unres + bb, b.ref_eprev + bb, b.ref_run + bb,
-                          b.ref_cont + bb, b.Bq[bb], b.locut + bb, L, l, bb, b.ref_clean + bb};
+                          b.ref_cont + bb, b.Bq[bb], b.locut + bb, L, l, bb, b.ref_rdev + bb,
+                          b.ref_nsskip + bb, b.ref_clean + bb};
     }
     std::vector<GemmDesc> gKK(p.local ? t : 1);
     if (p.literal)
@@ -1058,11 +1062,21 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         // up to two Newton-Schulz steps X <- X (I + (I - X^T X)/2), the second
         // only where the first started above 1e-8; an estimate that is still far
         // from orthonormal before its last step restarts from I
-        tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run(b.ref, t, b.svt_run, st); });
+        tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_ns(b.ref, t, b.svt_run, st); });
+        read_flags(h_ref, b.ref_run);
+        double f_ns = 0.0;   // the orthogonalisation runs where the refinement did not measure it
+        for (int bb = 0; bb < t && price; ++bb)
+            if (h_ref[bb]) f_ns += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
         for (int ns = 0; ns < 2; ++ns) {
-            tm("k_dgemm_sym", hL * f_L3, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, st); });
+            if (ns == 1 && price) {   // the second step runs where the first started above 1e-8
+                read_flags(h_ref, b.ref_run);
+                f_ns = 0.0;
+                for (int bb = 0; bb < t; ++bb)
+                    if (h_ref[bb]) f_ns += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
+            }
+            tm("k_dgemm_sym", hL * f_ns, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, st); });
             tm("k_orth_E", 0.0, 0.0, [&] { lrr::launch_orth_E(b.ref, t, p.maxL, st); });
-            tm("k_dgemm<false, false>", f_L3, 0.0, [&] {
+            tm("k_dgemm<false, false>", f_ns, 0.0, [&] {
                 lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, st);
             });
             tm("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, st); });
@@ -1163,11 +1177,26 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             double f_L3 = 0.0;
             for (int bb = 0; bb < t; ++bb)
                 if (h_run[bb]) f_L3 += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
-            timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run(b.ref, t, b.svt_run, s); });
+            timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_ns(b.ref, t, b.svt_run, s); });
+            double f_ns = f_L3;   // priced by the blocks that still orthogonalise
+            if (prof.on) {
+                LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+                sync();
+                f_ns = 0.0;
+                for (int bb = 0; bb < t; ++bb)
+                    if (h_ref[bb]) f_ns += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
+            }
             for (int ns = 0; ns < 2; ++ns) {
-                timed("k_dgemm_sym", hL * f_L3, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, s); });
+                if (ns == 1 && prof.on) {   // the second step runs where the first started above 1e-8
+                    LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+                    sync();
+                    f_ns = 0.0;
+                    for (int bb = 0; bb < t; ++bb)
+                        if (h_ref[bb]) f_ns += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
+                }
+                timed("k_dgemm_sym", hL * f_ns, 0.0, [&] { lrr::launch_dgemm_sym(b.g_orthG, t, p.maxL, s); });
                 timed("k_orth_E", 0.0, 0.0, [&] { lrr::launch_orth_E(b.ref, t, p.maxL, s); });
-                timed("k_dgemm<false, false>", f_L3, 0.0, [&] {
+                timed("k_dgemm<false, false>", f_ns, 0.0, [&] {
                     lrr::launch_dgemm(b.g_refXE, t, p.maxL, p.maxL, false, false, s);
                 });
                 timed("k_ref_add", 0.0, 0.0, [&] { lrr::launch_ref_add(b.ref, t, p.maxL, s); });
