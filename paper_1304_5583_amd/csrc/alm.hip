@@ -124,6 +124,36 @@ __global__ __launch_bounds__(256) void k_block_fro(const double* __restrict__ co
     }
 }
 
+// Blocks that need an eigen-decomposition this iteration: those that threshold,
+// and, in an iteration where some block thresholds for the first time (a cold
+// eigensolve, many Jacobi sweeps), every other block not yet decomposed whose
+// ||Y||_F exceeds prewarm * tau: it is close to its own first thresholding
+// step, and decomposing it in the same launches costs little more than the
+// rounds already paid, while its later first step then starts warm.
+__global__ __launch_bounds__(256) void k_eig_select(const double* __restrict__ colsq, const int* __restrict__ boff,
+                                                     int t, const int* __restrict__ active,
+                                                     const int* __restrict__ svt_run, const int* __restrict__ warm,
+                                                     int* __restrict__ eig_run, const DevIter* it, double prewarm) {
+    __shared__ double red[4];
+    __shared__ int any_cold;
+    if (threadIdx.x == 0) any_cold = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < t; b += 256)
+        if (svt_run[b] && !warm[b]) any_cold = 1;   // every writer stores 1
+    __syncthreads();
+    const double tau = it->tau;
+    for (int b = 0; b < t; ++b) {
+        int e = svt_run[b];
+        if (!e && any_cold && prewarm > 0.0 && active[b] && !warm[b]) {
+            double s = 0.0;
+            for (int c = boff[b] + threadIdx.x; c < boff[b + 1]; c += 256) s += colsq[c];
+            s = block_sum256(s, red);
+            e = sqrt(s) > prewarm * tau ? 1 : 0;
+        }
+        if (threadIdx.x == 0) eig_run[b] = e;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_zero_J(double* __restrict__ J, int n, long ld,
                                                  const int* __restrict__ colblk, BlockState bs) {
     const int j = blockIdx.x;
@@ -526,6 +556,11 @@ void launch_form_Y(const double* Z, const double* Y2, double* Y, double* colsq, 
 void launch_block_fro(const double* colsq, const int* boff, int t, BlockState bs, const DevIter* it,
                       hipStream_t s) {
     hipLaunchKernelGGL(k_block_fro, dim3(t), dim3(256), 0, s, colsq, boff, bs, it);
+}
+void launch_eig_select(const double* colsq, const int* boff, int t, const int* active, const int* svt_run,
+                       const int* warm, int* eig_run, const DevIter* it, double prewarm, hipStream_t s) {
+    hipLaunchKernelGGL(k_eig_select, dim3(1), dim3(256), 0, s, colsq, boff, t, active, svt_run, warm, eig_run, it,
+                       prewarm);
 }
 void launch_zero_J(double* J, int n, long ld, int ncols, const int* colblk, BlockState bs, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_J, dim3(ncols), dim3(256), 0, s, J, n, ld, colblk, bs);

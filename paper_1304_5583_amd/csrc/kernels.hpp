@@ -93,6 +93,10 @@ void launch_form_Y(const double* Z, const double* Y2, double* Y, double* colsq, 
                    const int* colblk, const int* active, const DevIter* it, hipStream_t s);
 void launch_block_fro(const double* colsq, const int* boff, int t, BlockState bs, const DevIter* it,
                       hipStream_t s);
+// eig_run: the blocks that threshold, plus (prewarm > 0, in an iteration where some block
+// thresholds for the first time) the blocks not yet decomposed with ||Y||_F > prewarm * tau
+void launch_eig_select(const double* colsq, const int* boff, int t, const int* active, const int* svt_run,
+                       const int* warm, int* eig_run, const DevIter* it, double prewarm, hipStream_t s);
 void launch_zero_J(double* J, int n, long ld, int ncols, const int* colblk, BlockState bs, hipStream_t s);
 void launch_svt_weights(const SvtDesc* d, int count, int maxL, const DevIter* it, BlockState bs,
                         hipStream_t s);

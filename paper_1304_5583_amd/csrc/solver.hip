@@ -205,7 +205,7 @@ struct Buffers {
     EigDesc* eq;
     GemmDesc *g_red, *g_exp;
     int *colblk, *boff, *perm;
-    int *active, *svt_run, *iters, *rank, *eigst, *n_active, *eig_any, *flag;
+    int *active, *svt_run, *eig_run, *iters, *rank, *eigst, *n_active, *eig_any, *flag;
     std::vector<int*> prot;
     double *res1, *res2, *eigscale;
     unsigned long long *r1max, *r2max;
@@ -231,6 +231,7 @@ struct Buffers {
 };
 
 constexpr int kRefSteps = 10;  // cap on refinement steps per thresholding step
+constexpr double kPreWarm = 0.5;   // ||Y||_F / tau above which a block is decomposed ahead of time
 constexpr int kBlindSteps = 3;   // refinement steps launched before the host reads the flags
 constexpr int kMaxTargeted = 60;   // cap on targeted Jacobi passes per eigensolve
 constexpr int kAnchorEvery = 16;   // FP64 re-anchoring period of the carried product M Q
@@ -275,6 +276,7 @@ size_t layout(const Plan& p, char* base, Buffers& b, int with_combine, bool need
     b.perm = a.take<int>(c);
     b.active = a.take<int>(t);
     b.svt_run = a.take<int>(t);
+    b.eig_run = a.take<int>(t);
     b.iters = a.take<int>(t);
     b.rank = a.take<int>(t);
     b.eigst = a.take<int>(2 * t);
@@ -684,11 +686,12 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         const size_t LL = (size_t)L * L;
         double* Yb = b.Y + (size_t)p.boff[bb] * nr;
         double* Jb = b.J + (size_t)p.boff[bb] * nr;
-        const int* run = b.svt_run + bb;
+        const int* run = b.svt_run + bb;    // thresholds this iteration
+        const int* erun = b.eig_run + bb;   // needs an eigen-decomposition this iteration
         const int* rrun = b.ref_run + bb;
         double* X = b.Wm[bb];
         double* T = b.TX[bb];
-        gram[bb] = GemmDesc{Yb, Yb, b.Bm[bb], l, l, nr, nr, nr, L, 1.0, 0.0, run, nullptr};
+        gram[bb] = GemmDesc{Yb, Yb, b.Bm[bb], l, l, nr, nr, nr, L, 1.0, 0.0, erun, nullptr};
         // refinement: T = B X, S = X^T T, G = X^T X (symmetric kernel), XE = X E
         gRT[bb] = GemmDesc{b.Bm[bb], X, T, L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
         gRSG[bb] = GemmDesc{X, T, b.SG[bb], L, L, L, L, L, L, 1.0, 0.0, rrun, nullptr};
@@ -724,7 +727,7 @@ void setup_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStream_t
         if (p.reduced)   // expansion of the coupling residual: R2 = Qm R2r
             gExp[bb] = GemmDesc{b.Qm, b.R2r + o_n, b.R2full + (size_t)p.boff[bb] * n, n, l, nr, n, nr, n, 1.0,
                                 0.0, b.expand + bb, nullptr};
-        eig[bb] = EigDesc{b.Bq[bb], X, b.Rm[bb], b.lam[bb], L, l, run, b.eigst + 2 * bb,
+        eig[bb] = EigDesc{b.Bq[bb], X, b.Rm[bb], b.lam[bb], L, l, erun, b.eigst + 2 * bb,
                           b.eigscale + bb, b.prot[bb], b.lo[bb], ctx->dwork, b.locut + bb, b.passes + bb,
                           b.need_all + need_off[bb], b.sched_all + sched_off[bb], b.ref_clean + bb};
         svt[bb] = SvtDesc{b.Bq[bb], X, b.Wg[bb], b.lam[bb], b.h[bb], L, l, run, bb};
@@ -890,6 +893,12 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     // (h = 1e-6); a solve that stops on the tolerance, whose iteration count is
     // itself a step function of the data, uses 1e-8.
     const double ref_stop = fixed ? 1e-10 : 1e-8;
+    // Blocks decomposed ahead of their first thresholding step (k_eig_select):
+    // ||Y||_F above this fraction of tau when another block goes cold.  Off in
+    // fixed-iteration solves, whose recorded J-steps follow the thresholding
+    // blocks only.
+    const double prewarm = fixed ? 0.0 : kPreWarm;
+    int* h_svt = hp + 3 * t + 16;   // t ints: thresholding blocks (pricing of P and J)
     int* h_run = hp;            // t ints
     int* h_misc = hp + t;       // scalars
     int* h_ref = hp + t + 16;   // t ints: refinement still running, per block
@@ -1018,14 +1027,20 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         });
         tm("k_block_fro", 0.0, cact * D, [&] { lrr::launch_block_fro(b.colsq, b.boff, t, bst, b.it, st); });
         tm("k_zero_J", 0.0, 0.0, [&] { lrr::launch_zero_J(b.J, n, n, c, b.colblk, bst, st); });
-        read_flags(h_run, b.svt_run);
+        tm("k_eig_select", 0.0, 0.0, [&] {
+            lrr::launch_eig_select(b.colsq, b.boff, t, b.active, b.svt_run, b.warm, b.eig_run, b.it, prewarm, st);
+        });
+        read_flags(h_run, b.eig_run);
+        read_flags(h_svt, b.svt_run);
         double f_gram = 0, f_P = 0, f_J = 0, f_L3 = 0;
         for (int bb = 0; bb < t && price; ++bb) {
-            if (!h_run[bb]) continue;
             const double l = p.boff[bb + 1] - p.boff[bb], L = p.L[bb];
+            if (h_svt[bb]) {
+                f_P += 2.0 * l * l * L;
+                f_J += 2.0 * n * l * l;
+            }
+            if (!h_run[bb]) continue;
             f_gram += 2.0 * l * l * n;
-            f_P += 2.0 * l * l * L;
-            f_J += 2.0 * n * l * l;
             f_L3 += 2.0 * L * L * L;
         }
         // the symmetric kernel computes the tiles on and above the diagonal
@@ -1034,7 +1049,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         tm("k_dgemm_sym", hg * f_gram, 0.0, [&] { lrr::launch_dgemm_sym(b.g_gram, t, p.maxl, st); });
         // Newton refinement of the previous iteration's eigenvectors: a fixed
         // number of steps, each applied only where the per-block flags allow
-        tm("k_ref_begin", 0.0, 0.0, [&] { lrr::launch_ref_begin(b.ref, t, p.maxL, b.svt_run, b.warm, st); });
+        tm("k_ref_begin", 0.0, 0.0, [&] { lrr::launch_ref_begin(b.ref, t, p.maxL, b.eig_run, b.warm, st); });
         for (int step = 0; step < kRefSteps; ++step) {
             read_flags(h_ref, b.ref_run);
             double fl = 0.0;
@@ -1062,7 +1077,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         // up to two Newton-Schulz steps X <- X (I + (I - X^T X)/2), the second
         // only where the first started above 1e-8; an estimate that is still far
         // from orthonormal before its last step restarts from I
-        tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_ns(b.ref, t, b.svt_run, st); });
+        tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_ns(b.ref, t, b.eig_run, st); });
         read_flags(h_ref, b.ref_run);
         double f_ns = 0.0;   // the orthogonalisation runs where the refinement did not measure it
         for (int bb = 0; bb < t && price; ++bb)
@@ -1083,7 +1098,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             if (ns == 0) tm("k_orth_decide", 0.0, 0.0, [&] { lrr::launch_orth_decide(b.ref, t, st); });
         }
         tm("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, b.warm, st); });
-        tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_jac(b.ref, t, b.svt_run, st); });
+        tm("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_jac(b.ref, t, b.eig_run, st); });
         read_flags(h_ref, b.ref_run);
         double f_jac = 0.0;   // the Jacobi matrix is formed for the blocks that are not clean
         for (int bb = 0; bb < t && price; ++bb)
@@ -1105,8 +1120,8 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         tm("k_dgemm<false, false>", f_J, 0.0, [&] {
             lrr::launch_dgemm(b.g_J, t, n, p.maxl, false, false, st);
         });
-        tm("k_lo_mode", 0.0, 0.0, [&] { lrr::launch_lo_mode(b.svt_run, b.warm, b.passes, b.locut, t, st); });
-        tm("k_mark_warm", 0.0, 0.0, [&] { lrr::launch_mark_warm(b.svt_run, b.warm, t, st); });
+        tm("k_lo_mode", 0.0, 0.0, [&] { lrr::launch_lo_mode(b.eig_run, b.warm, b.passes, b.locut, t, st); });
+        tm("k_mark_warm", 0.0, 0.0, [&] { lrr::launch_mark_warm(b.eig_run, b.warm, t, st); });
     };
     auto untimed = [](const char*, double, double, auto&& f) { f(); };
     // The J-step with its decisions on the host: which blocks threshold (one
@@ -1119,17 +1134,23 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         });
         timed("k_block_fro", 0.0, cact * D, [&] { lrr::launch_block_fro(b.colsq, b.boff, t, bst, b.it, s); });
         timed("k_zero_J", 0.0, 0.0, [&] { lrr::launch_zero_J(b.J, n, n, c, b.colblk, bst, s); });
-        LRR_HIP(hipMemcpyAsync(h_run, b.svt_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+        timed("k_eig_select", 0.0, 0.0, [&] {
+            lrr::launch_eig_select(b.colsq, b.boff, t, b.active, b.svt_run, b.warm, b.eig_run, b.it, prewarm, s);
+        });
+        LRR_HIP(hipMemcpyAsync(h_run, b.eig_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+        LRR_HIP(hipMemcpyAsync(h_svt, b.svt_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
         sync();
         int any_run = 0;
         double f_gram = 0, f_P = 0, f_J = 0;
         for (int bb = 0; bb < t; ++bb) {
+            const double l = p.boff[bb + 1] - p.boff[bb];
+            if (h_svt[bb]) {
+                f_P += 2.0 * l * l * p.L[bb];
+                f_J += 2.0 * n * l * l;
+            }
             if (!h_run[bb]) continue;
             any_run = 1;
-            const double l = p.boff[bb + 1] - p.boff[bb], L = p.L[bb];
             f_gram += 2.0 * l * l * n;
-            f_P += 2.0 * l * l * L;
-            f_J += 2.0 * n * l * l;
         }
         if (any_run) {
             // Gram matrix of each block that needs a decomposition (FP64 in every
@@ -1138,7 +1159,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             const double hg = lrr::dgemm_sym_tiles(t, p.maxl) ? 0.5 : 1.0, hL = lrr::dgemm_sym_tiles(t, p.maxL) ? 0.5 : 1.0;
             timed("k_dgemm_sym", hg * f_gram, 0.0, [&] { lrr::launch_dgemm_sym(b.g_gram, t, p.maxl, s); });
             // Newton refinement of the previous iteration's eigenvectors
-            timed("k_ref_begin", 0.0, 0.0, [&] { lrr::launch_ref_begin(b.ref, t, p.maxL, b.svt_run, b.warm, s); });
+            timed("k_ref_begin", 0.0, 0.0, [&] { lrr::launch_ref_begin(b.ref, t, p.maxL, b.eig_run, b.warm, s); });
             // the first kBlindSteps steps are launched without reading the flags back
             // (a warm eigensolve takes about three; the device flags decide which
             // blocks a step touches), later ones only while some block continues;
@@ -1177,7 +1198,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             double f_L3 = 0.0;
             for (int bb = 0; bb < t; ++bb)
                 if (h_run[bb]) f_L3 += 2.0 * (double)p.L[bb] * p.L[bb] * p.L[bb];
-            timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_ns(b.ref, t, b.svt_run, s); });
+            timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_ns(b.ref, t, b.eig_run, s); });
             double f_ns = f_L3;   // priced by the blocks that still orthogonalise
             if (prof.on) {
                 LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
@@ -1203,7 +1224,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
                 if (ns == 0) timed("k_orth_decide", 0.0, 0.0, [&] { lrr::launch_orth_decide(b.ref, t, s); });
             }
             timed("k_orth_guard", 0.0, 0.0, [&] { lrr::launch_orth_guard(b.ref, t, p.maxL, b.warm, s); });
-            timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_jac(b.ref, t, b.svt_run, s); });
+            timed("k_ref_set_run", 0.0, 0.0, [&] { lrr::launch_ref_set_run_jac(b.ref, t, b.eig_run, s); });
             double f_jac = f_L3;   // priced by the blocks that form the Jacobi matrix (not clean)
             if (prof.on) {
                 LRR_HIP(hipMemcpyAsync(h_ref, b.ref_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
@@ -1286,8 +1307,8 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
             timed("k_dgemm<false, false>", f_J, 0.0, [&] {
                 lrr::launch_dgemm(b.g_J, t, n, p.maxl, false, false, s);
             });
-            timed("k_lo_mode", 0.0, 0.0, [&] { lrr::launch_lo_mode(b.svt_run, b.warm, b.passes, b.locut, t, s); });
-            timed("k_mark_warm", 0.0, 0.0, [&] { lrr::launch_mark_warm(b.svt_run, b.warm, t, s); });
+            timed("k_lo_mode", 0.0, 0.0, [&] { lrr::launch_lo_mode(b.eig_run, b.warm, b.passes, b.locut, t, s); });
+            timed("k_mark_warm", 0.0, 0.0, [&] { lrr::launch_mark_warm(b.eig_run, b.warm, t, s); });
         }
     };
     // use_graph 1: the Z-/E-step chain of an iteration is captured once per solve
