@@ -1127,6 +1127,7 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
     // The J-step with its decisions on the host: which blocks threshold (one
     // read-back), each refinement step (a read-back of the continue flags), each
     // Jacobi pass (a read-back of the check marks, the round plan from the host).
+    bool eig_seen = false;   // some block has been decomposed in this solve
     auto host_jstep = [&](double cact) {
         // J-step input and the exact zero test
         timed("k_form_Y", 0.0, 3.0 * n * cact * D, [&] {
@@ -1137,22 +1138,31 @@ Result iterate_alm(lrr_ctx* ctx, const Problem& pr, Plan& p, Buffers& b, hipStre
         timed("k_eig_select", 0.0, 0.0, [&] {
             lrr::launch_eig_select(b.colsq, b.boff, t, b.active, b.svt_run, b.warm, b.eig_run, b.it, prewarm, s);
         });
-        LRR_HIP(hipMemcpyAsync(h_run, b.eig_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
-        LRR_HIP(hipMemcpyAsync(h_svt, b.svt_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
-        sync();
-        int any_run = 0;
+        // Which blocks decompose is read back until the first eigensolve; from then
+        // on the blocks keep thresholding (||Y||_F grows while tau shrinks), so the
+        // J-step is launched without the read-back and the device flags gate every
+        // kernel (a block that does not run is skipped, bitwise as before).  A
+        // profiled solve reads them every iteration to price the products.
+        int any_run = 1;
         double f_gram = 0, f_P = 0, f_J = 0;
-        for (int bb = 0; bb < t; ++bb) {
-            const double l = p.boff[bb + 1] - p.boff[bb];
-            if (h_svt[bb]) {
-                f_P += 2.0 * l * l * p.L[bb];
-                f_J += 2.0 * n * l * l;
+        if (!eig_seen || prof.on) {
+            LRR_HIP(hipMemcpyAsync(h_run, b.eig_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+            LRR_HIP(hipMemcpyAsync(h_svt, b.svt_run, sizeof(int) * t, hipMemcpyDeviceToHost, s));
+            sync();
+            any_run = 0;
+            for (int bb = 0; bb < t; ++bb) {
+                const double l = p.boff[bb + 1] - p.boff[bb];
+                if (h_svt[bb]) {
+                    f_P += 2.0 * l * l * p.L[bb];
+                    f_J += 2.0 * n * l * l;
+                }
+                if (!h_run[bb]) continue;
+                any_run = 1;
+                f_gram += 2.0 * l * l * n;
             }
-            if (!h_run[bb]) continue;
-            any_run = 1;
-            f_gram += 2.0 * l * l * n;
         }
         if (any_run) {
+            eig_seen = true;
             // Gram matrix of each block that needs a decomposition (FP64 in every
             // precision form)
             // the symmetric kernel computes the tiles on and above the diagonal
