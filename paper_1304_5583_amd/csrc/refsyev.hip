@@ -67,15 +67,22 @@ __device__ void ref_row(const RefDesc& d, int i, const DevIter* it, int gid) {
     const double* S = d.SG;
     const double* G = d.SG + L * L;
     __shared__ double red[4];
-    // Gershgorin radius from column i (S is symmetric; the column is contiguous)
-    double rs = 0.0;
-    for (int j = threadIdx.x; j < d.l; j += 256)
-        if (j != i) rs += fabs(S[j + i * L]);
-    rs = wave_sum(rs);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rs;
-    __syncthreads();
+    // Gershgorin radius from column i (S is symmetric; the column is contiguous).
+    // With the cut factor at 0 the flag needs s_ii + r below 0, which a
+    // non-negative s_ii never is: the radius is then summed only for s_ii < 0.
+    const bool need_r = i < d.l && !it->full && (d.cut[0] != 0.0 || S[i + i * L] < 0.0);
+    double r = 0.0;
+    if (need_r) {
+        double rs = 0.0;
+        for (int j = threadIdx.x; j < d.l; j += 256)
+            if (j != i) rs += fabs(S[j + i * L]);
+        rs = wave_sum(rs);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rs;
+        __syncthreads();
+        r = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();   // red is free for the next row
+    }
     if (threadIdx.x == 0) {
-        const double r = (red[0] + red[1]) + (red[2] + red[3]);
         const double tau = it->tau;
         if (i < d.l) {
             const double sii = S[i + i * L];
