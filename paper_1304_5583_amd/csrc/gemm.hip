@@ -19,17 +19,25 @@
 //     matrix (M, N or K edge) gets an offset with bit 31 set, beyond the
 //     buffer's range, and the hardware returns 0 for it: the loads are
 //     straight-line code for every tile, edges included, and the compiler
-//     waits only for the older set (vmcnt(n) instead of vmcnt(0));
+//     waits only for the older set (vmcnt(n) instead of vmcnt(0)).  With
+//     64-row tiles the offsets and the M/N edge bits are formed once per
+//     output tile and only a K-tile that reaches past K tests the K edge
+//     (2-3 % faster than testing every element of every K-tile: the products
+//     run at the chip's power limit, where fewer vector instructions per MFMA
+//     buy clock);
 //   * every load instruction of a wavefront covers whole contiguous runs: the
 //     threads walk the operand's contiguous dimension first (rows of A, k of
 //     A^T, k of B, columns of B^T);
-//   * registers -> double-buffered LDS tiles (row stride BM + 2 doubles: a
-//     stride of 16 mod 32 would make the column-wise stores of k-contiguous
-//     operands 8-way bank conflicted and measured 40 % slower);
+//   * registers -> double-buffered LDS tiles, row stride BM + 1 doubles: the
+//     16 lanes that store one column of a k-contiguous operand land in 16
+//     different bank pairs (an odd stride), and the 16 lanes of an MFMA read
+//     take 16 consecutive doubles of one row, so neither side conflicts (the
+//     bank-conflict counter reads 0; a stride of BM + 2 made those stores
+//     2-way conflicted, one of 16 mod 32 8-way and 40 % slower);
 //   * the kernel is held to 128 VGPRs (four waves per SIMD, the LDS of four
 //     workgroups per CU): at three waves per SIMD the batched 512-order
 //     products ran 17 % slower.
-// Measured on 40 products of order 512 (m = 512, n = 500, K = 512): 47 TFLOP/s,
+// Measured on 40 products of order 512 (m = 512, n = 500, K = 512), random operands: 47-48 TFLOP/s,
 // against 41 for element/vector loads one tile ahead in branches.
 #include <algorithm>
 
@@ -40,7 +48,7 @@ namespace lrr {
 
 namespace {
 
-constexpr int BN = 64, PAD = 2;
+constexpr int BN = 64, PAD = 1;
 
 constexpr int BK = 16;                         // K depth of a tile
 constexpr unsigned kRsrcWord3 = 0x00020000u;   // raw buffer resource, gfx9-family data format
@@ -130,21 +138,44 @@ __global__ __launch_bounds__(256, 4) void k_dgemm(const GemmDesc* __restrict__ d
         const unsigned astep = (unsigned)(8 * (TA ? (long)dai * lda : (long)dak * lda));
         const unsigned bstep = (unsigned)(8 * (TB ? (long)dbk * ldb : (long)dbj * ldb));
 
+        // offsets inside a K-tile's panel, the same for every K-tile; an element
+        // outside the M (N) edge carries bit 31 for the whole K loop
+        unsigned oa[NA], ob[NB];
+#pragma unroll
+        for (int v = 0; v < NA; ++v) oa[v] = (aoff + v * astep) | ((unsigned)(m0 + ai + dai * v >= M) << 31);
+#pragma unroll
+        for (int v = 0; v < NB; ++v) ob[v] = (boff + v * bstep) | ((unsigned)(n0 + bj + dbj * v >= N) << 31);
+
         double fa0[NA], fb0[NB], fa1[NA], fb1[NB];
-        // K-tile kt of both operands into registers (zeros outside the matrices)
+        // K-tile kt of both operands into registers (zeros outside the matrices);
+        // only a tile that reaches past K tests the K edge per element
         auto gload = [&](double (&fa)[NA], double (&fb)[NB], int kt) {
             const int k0 = kt * BK;
             const __amdgpu_buffer_rsrc_t ra = panel_rsrc(TA ? A + k0 + (long)m0 * lda : A + m0 + (long)k0 * lda);
             const __amdgpu_buffer_rsrc_t rb = panel_rsrc(TB ? B + n0 + (long)k0 * ldb : B + k0 + (long)n0 * ldb);
+            if (BM == 32) {
+                // short batches: per-element edge tests measured faster here
 #pragma unroll
-            for (int v = 0; v < NA; ++v) {
-                const unsigned in = (unsigned)(m0 + ai + dai * v < M) & (unsigned)(k0 + ak + dak * v < K);
-                fa[v] = buffer_ld(ra, (aoff + v * astep) | ((in ^ 1u) << 31));
-            }
+                for (int v = 0; v < NA; ++v) {
+                    const unsigned in = (unsigned)(m0 + ai + dai * v < M) & (unsigned)(k0 + ak + dak * v < K);
+                    fa[v] = buffer_ld(ra, (aoff + v * astep) | ((in ^ 1u) << 31));
+                }
 #pragma unroll
-            for (int v = 0; v < NB; ++v) {
-                const unsigned in = (unsigned)(n0 + bj + dbj * v < N) & (unsigned)(k0 + bk + dbk * v < K);
-                fb[v] = buffer_ld(rb, (boff + v * bstep) | ((in ^ 1u) << 31));
+                for (int v = 0; v < NB; ++v) {
+                    const unsigned in = (unsigned)(n0 + bj + dbj * v < N) & (unsigned)(k0 + bk + dbk * v < K);
+                    fb[v] = buffer_ld(rb, (boff + v * bstep) | ((in ^ 1u) << 31));
+                }
+            } else if (k0 + BK <= K) {
+#pragma unroll
+                for (int v = 0; v < NA; ++v) fa[v] = buffer_ld(ra, oa[v]);
+#pragma unroll
+                for (int v = 0; v < NB; ++v) fb[v] = buffer_ld(rb, ob[v]);
+            } else {
+                const int kr = K - k0;
+#pragma unroll
+                for (int v = 0; v < NA; ++v) fa[v] = buffer_ld(ra, oa[v] | ((unsigned)(ak + dak * v >= kr) << 31));
+#pragma unroll
+                for (int v = 0; v < NB; ++v) fb[v] = buffer_ld(rb, ob[v] | ((unsigned)(bk + dbk * v >= kr) << 31));
             }
         };
         auto lstore = [&](const double (&fa)[NA], const double (&fb)[NB], int buf) {
