@@ -51,6 +51,7 @@ namespace {
 constexpr int BN = 64, PAD = 1;
 
 constexpr int BK = 16;                         // K depth of a tile
+constexpr int kList = 256;                     // products listed on chip (one per thread)
 constexpr unsigned kRsrcWord3 = 0x00020000u;   // raw buffer resource, gfx9-family data format
 constexpr unsigned kRange = 0x7ffffff0u;       // num_records: offsets with bit 31 set are outside
 
@@ -80,19 +81,45 @@ __global__ __launch_bounds__(256, 4) void k_dgemm(const GemmDesc* __restrict__ d
     // double-buffered operand tiles: As[buf][k][i] = op(A)(m0+i, k0+k)
     __shared__ double As[2][BK][BM + PAD];
     __shared__ double Bs[2][BK][BN + PAD];
+    // Only the products whose block is active take part: with at most kList
+    // products every workgroup first lists the active ones, in order (one flag
+    // read per product), and the tiles below run over that list; with more, a
+    // tile of an inactive product is skipped after one descriptor read.
+    __shared__ int s_z[kList];
+    __shared__ int s_n[4];
+    const int count = total / per;
+    const bool listed = count <= kList;
+    int work = total;
+    if (listed) {
+        const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+        int act = 0;
+        if (tid < count) {
+            const int* __restrict__ a = descs[tid].active;
+            act = (a == nullptr || a[0] != 0) ? 1 : 0;
+        }
+        const unsigned long long bal = __ballot(act);
+        if (lane == 0) s_n[w] = __popcll(bal);
+        __syncthreads();
+        int off = __popcll(bal & ((1ull << lane) - 1ull));
+        for (int i = 0; i < w; ++i) off += s_n[i];
+        if (act) s_z[off] = tid;
+        work = (s_n[0] + s_n[1] + s_n[2] + s_n[3]) * per;
+        __syncthreads();
+    }
     // The grid is at most four workgroups per CU; each takes the tiles
     // blockIdx.x, blockIdx.x + gridDim.x, ...  Workgroup w runs on XCD w % 8, so
-    // the first 8 * floor(total / 8) tiles are dealt out in eight contiguous
+    // the first 8 * floor(work / 8) tiles are dealt out in eight contiguous
     // ranges, one per XCD: the tiles of one product share an L2 (3 % faster than
-    // dealing consecutive tiles to consecutive XCDs).  Within a product, row
-    // tiles run fastest.  A tile of a product whose block is not active is
-    // skipped after one descriptor read.
-    const int per_x = total >> 3;
-    for (int t0 = blockIdx.x; t0 < total; t0 += gridDim.x) {
+    // dealing consecutive tiles to consecutive XCDs), and when few blocks are
+    // active their tiles still spread over all eight XCDs.  Within a product,
+    // row tiles run fastest.
+    const int per_x = work >> 3;
+    for (int t0 = blockIdx.x; t0 < work; t0 += gridDim.x) {
         const int tile = t0 < 8 * per_x ? (t0 & 7) * per_x + (t0 >> 3) : t0;
-        const int z = tile / per, tin = tile - z * per;
+        const int zi = tile / per, tin = tile - zi * per;
+        const int z = listed ? s_z[zi] : zi;
         const GemmDesc d = descs[z];
-        if (d.active && d.active[0] == 0) continue;
+        if (!listed && d.active && d.active[0] == 0) continue;
         int tm_i, tn_i;
         if (SYM) {
             // upper-triangle index tin -> (P, Q), P <= Q, column by column
