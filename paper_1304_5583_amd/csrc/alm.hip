@@ -86,23 +86,65 @@ __global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ M,
     if (bad) atomicOr(flag, 1);
 }
 
+// Two consecutive rows of a column (16-byte access when VEC); rows at or past
+// m read as zeros and are not written.
+template <bool VEC>
+__device__ __forceinline__ void ld2(const double* __restrict__ p, int i, int m, double& a, double& b) {
+    if (VEC && i + 1 < m) {
+        const double2 x = *reinterpret_cast<const double2*>(p + i);
+        a = x.x;
+        b = x.y;
+    } else {
+        a = i < m ? p[i] : 0.0;
+        b = i + 1 < m ? p[i + 1] : 0.0;
+    }
+}
+template <bool VEC>
+__device__ __forceinline__ void st2(double* __restrict__ p, int i, int m, double a, double b) {
+    if (VEC && i + 1 < m) {
+        *reinterpret_cast<double2*>(p + i) = double2{a, b};
+    } else {
+        if (i < m) p[i] = a;
+        if (i + 1 < m) p[i + 1] = b;
+    }
+}
+
+// One wave per column, four columns per workgroup; lane l holds rows 2l and
+// 2l + 1 of every 128-row chunk (16-byte accesses when the leading dimension is
+// even).  The column's sum of squares is a fixed-order sum (per lane, then the
+// wave butterfly).
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_form_Y(const double* __restrict__ Z, const double* __restrict__ Y2,
                                                  double* __restrict__ Y, double* __restrict__ colsq,
-                                                 int n, long ld, const int* __restrict__ colblk,
+                                                 int n, long ld, int ncols, const int* __restrict__ colblk,
                                                  const int* __restrict__ active, const DevIter* it) {
-    __shared__ double red[4];
-    const int j = blockIdx.x;
+    constexpr int G = 4;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= ncols) return;
     if (!active[colblk[j]]) return;
+    const int lane = threadIdx.x & 63;
     const double mu = it->mu;
-    const long o = j * ld;
+    const long o = (long)j * ld;
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        const double y = Z[o + i] + Y2[o + i] / mu;
-        Y[o + i] = y;
-        s += y * y;
+    for (int base = 0; base < n; base += 128 * G) {
+        double z[G][2], w[G][2];
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            const int i = base + c * 128 + 2 * lane;
+            ld2<VEC>(Z + o, i, n, z[c][0], z[c][1]);
+            ld2<VEC>(Y2 + o, i, n, w[c][0], w[c][1]);
+        }
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            const int i = base + c * 128 + 2 * lane;
+            const double y0 = z[c][0] + w[c][0] / mu, y1 = z[c][1] + w[c][1] / mu;   // zeros past n
+            st2<VEC>(Y + o, i, n, y0, y1);
+            s += y0 * y0;
+            s += y1 * y1;
+        }
     }
-    s = block_sum256(s, red);
-    if (threadIdx.x == 0) colsq[j] = s;
+    s = wave_sum(s);
+    if (lane == 0) colsq[j] = s;
 }
 
 __global__ __launch_bounds__(256) void k_block_fro(const double* __restrict__ colsq,
@@ -165,24 +207,37 @@ __global__ __launch_bounds__(256) void k_zero_J(double* __restrict__ J, int n, l
 // SVT weights from the converged Gram eigenvalues: sigma = sqrt(lambda),
 // g = (1 - tau/sigma)_+ scales the eigenvector columns, h = 1/sigma on the
 // kept columns (the combine basis), rank = #{sigma > tau}.
+// One wave per eigenpair i (four per workgroup): the weight g_i scales
+// column i of W; the kept pairs of the workgroup are added to the block's rank
+// with one atomic.
 __global__ __launch_bounds__(256) void k_svt_weights(const SvtDesc* __restrict__ descs,
                                                       const DevIter* it, BlockState bs) {
+    __shared__ int kept[4];
     const SvtDesc d = descs[blockIdx.y];
     if (!d.run[0]) return;
-    const int i = blockIdx.x;
-    if (i >= d.L) return;
-    const double tau = it->tau;
-    const double lam = (i < d.l) ? d.B[i + (long)i * d.L] : 0.0;
-    const double sig = sqrt(fmax(lam, 0.0));
-    const bool keep = sig > tau;
-    const double g = keep ? 1.0 - tau / sig : 0.0;
-    if (threadIdx.x == 0) {
-        d.lam[i] = lam;
-        d.h[i] = keep ? 1.0 / sig : 0.0;
-        if (keep) atomicAdd(&bs.rank[d.block], 1);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + w;
+    int keep_i = 0;
+    if (i < d.L) {
+        const double tau = it->tau;
+        const double lam = (i < d.l) ? d.B[i + (long)i * d.L] : 0.0;
+        const double sig = sqrt(fmax(lam, 0.0));
+        const bool keep = sig > tau;
+        const double g = keep ? 1.0 - tau / sig : 0.0;
+        if (lane == 0) {
+            d.lam[i] = lam;
+            d.h[i] = keep ? 1.0 / sig : 0.0;
+        }
+        keep_i = keep ? 1 : 0;
+        const long o = (long)i * d.L;
+        for (int r = lane; r < d.L; r += 64) d.Wg[o + r] = d.W[o + r] * g;
     }
-    const long o = (long)i * d.L;
-    for (int r = threadIdx.x; r < d.L; r += 256) d.Wg[o + r] = d.W[o + r] * g;
+    if (lane == 0) kept[w] = keep_i;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int k = kept[0] + kept[1] + kept[2] + kept[3];
+        if (k) atomicAdd(&bs.rank[d.block], k);
+    }
 }
 
 // With dQ set (difference form), dQ = Q_new - Q_old is written as well.
@@ -312,26 +367,6 @@ __global__ __launch_bounds__(256) void k_estep(double* __restrict__ E, const dou
 // and 2l + 1 of every 128-row chunk (16-byte accesses when VEC, i.e. even
 // leading dimension); NCH chunks cover m <= 128 NCH.  The column norm is a
 // fixed-order sum (per lane, then the wave butterfly).
-template <bool VEC>
-__device__ __forceinline__ void ld2(const double* __restrict__ p, int i, int m, double& a, double& b) {
-    if (VEC && i + 1 < m) {
-        const double2 x = *reinterpret_cast<const double2*>(p + i);
-        a = x.x;
-        b = x.y;
-    } else {
-        a = i < m ? p[i] : 0.0;
-        b = i + 1 < m ? p[i + 1] : 0.0;
-    }
-}
-template <bool VEC>
-__device__ __forceinline__ void st2(double* __restrict__ p, int i, int m, double a, double b) {
-    if (VEC && i + 1 < m) {
-        *reinterpret_cast<double2*>(p + i) = double2{a, b};
-    } else {
-        if (i < m) p[i] = a;
-        if (i + 1 < m) p[i + 1] = b;
-    }
-}
 
 template <int NCH, bool VEC>
 __global__ __launch_bounds__(256) void k_estep_w(double* __restrict__ E, const double* __restrict__ V,
@@ -551,7 +586,12 @@ void launch_nonfinite(const double* M, long ldm, int m, int n, int* d_flag, hipS
 }
 void launch_form_Y(const double* Z, const double* Y2, double* Y, double* colsq, int n, long ld, int ncols,
                    const int* colblk, const int* active, const DevIter* it, hipStream_t s) {
-    hipLaunchKernelGGL(k_form_Y, dim3(ncols), dim3(256), 0, s, Z, Y2, Y, colsq, n, ld, colblk, active, it);
+    const dim3 grid((ncols + 3) / 4);
+    if ((ld & 1) == 0)
+        hipLaunchKernelGGL(k_form_Y<true>, grid, dim3(256), 0, s, Z, Y2, Y, colsq, n, ld, ncols, colblk, active, it);
+    else
+        hipLaunchKernelGGL(k_form_Y<false>, grid, dim3(256), 0, s, Z, Y2, Y, colsq, n, ld, ncols, colblk, active,
+                           it);
 }
 void launch_block_fro(const double* colsq, const int* boff, int t, BlockState bs, const DevIter* it,
                       hipStream_t s) {
@@ -567,7 +607,7 @@ void launch_zero_J(double* J, int n, long ld, int ncols, const int* colblk, Bloc
 }
 void launch_svt_weights(const SvtDesc* d, int count, int maxL, const DevIter* it, BlockState bs,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_svt_weights, dim3(maxL, count), dim3(256), 0, s, d, it, bs);
+    hipLaunchKernelGGL(k_svt_weights, dim3((maxL + 3) / 4, count), dim3(256), 0, s, d, it, bs);
 }
 void launch_form_QT(const double* J, const double* Y2, double* Q, double* dQ, int n, long ldn,
                     const double* X, const double* E, const double* Y1, double* T, int m, long ldm, int ncols,
