@@ -109,42 +109,26 @@ __device__ __forceinline__ void st2(double* __restrict__ p, int i, int m, double
     }
 }
 
-// One wave per column, four columns per workgroup; lane l holds rows 2l and
-// 2l + 1 of every 128-row chunk (16-byte accesses when the leading dimension is
-// even).  The column's sum of squares is a fixed-order sum (per lane, then the
-// wave butterfly).
-template <bool VEC>
+// One workgroup per column: measured faster here than one wave per column
+// with 16-byte accesses (52.5 against 55.5 us per launch on workload 4) and
+// than issuing the column's loads before the block's flag is read (54.1).
 __global__ __launch_bounds__(256) void k_form_Y(const double* __restrict__ Z, const double* __restrict__ Y2,
                                                  double* __restrict__ Y, double* __restrict__ colsq,
-                                                 int n, long ld, int ncols, const int* __restrict__ colblk,
+                                                 int n, long ld, const int* __restrict__ colblk,
                                                  const int* __restrict__ active, const DevIter* it) {
-    constexpr int G = 4;
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (j >= ncols) return;
+    __shared__ double red[4];
+    const int j = blockIdx.x;
     if (!active[colblk[j]]) return;
-    const int lane = threadIdx.x & 63;
     const double mu = it->mu;
-    const long o = (long)j * ld;
+    const long o = j * ld;
     double s = 0.0;
-    for (int base = 0; base < n; base += 128 * G) {
-        double z[G][2], w[G][2];
-#pragma unroll
-        for (int c = 0; c < G; ++c) {
-            const int i = base + c * 128 + 2 * lane;
-            ld2<VEC>(Z + o, i, n, z[c][0], z[c][1]);
-            ld2<VEC>(Y2 + o, i, n, w[c][0], w[c][1]);
-        }
-#pragma unroll
-        for (int c = 0; c < G; ++c) {
-            const int i = base + c * 128 + 2 * lane;
-            const double y0 = z[c][0] + w[c][0] / mu, y1 = z[c][1] + w[c][1] / mu;   // zeros past n
-            st2<VEC>(Y + o, i, n, y0, y1);
-            s += y0 * y0;
-            s += y1 * y1;
-        }
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double y = Z[o + i] + Y2[o + i] / mu;
+        Y[o + i] = y;
+        s += y * y;
     }
-    s = wave_sum(s);
-    if (lane == 0) colsq[j] = s;
+    s = block_sum256(s, red);
+    if (threadIdx.x == 0) colsq[j] = s;
 }
 
 __global__ __launch_bounds__(256) void k_block_fro(const double* __restrict__ colsq,
@@ -586,12 +570,7 @@ void launch_nonfinite(const double* M, long ldm, int m, int n, int* d_flag, hipS
 }
 void launch_form_Y(const double* Z, const double* Y2, double* Y, double* colsq, int n, long ld, int ncols,
                    const int* colblk, const int* active, const DevIter* it, hipStream_t s) {
-    const dim3 grid((ncols + 3) / 4);
-    if ((ld & 1) == 0)
-        hipLaunchKernelGGL(k_form_Y<true>, grid, dim3(256), 0, s, Z, Y2, Y, colsq, n, ld, ncols, colblk, active, it);
-    else
-        hipLaunchKernelGGL(k_form_Y<false>, grid, dim3(256), 0, s, Z, Y2, Y, colsq, n, ld, ncols, colblk, active,
-                           it);
+    hipLaunchKernelGGL(k_form_Y, dim3(ncols), dim3(256), 0, s, Z, Y2, Y, colsq, n, ld, colblk, active, it);
 }
 void launch_block_fro(const double* colsq, const int* boff, int t, BlockState bs, const DevIter* it,
                       hipStream_t s) {
