@@ -108,15 +108,17 @@ __global__ __launch_bounds__(256) void k_ref_E(const RefDesc* __restrict__ descs
     const RefDesc d = descs[blockIdx.y];
     if (d.run[0] == 0) return;
     const long L = d.L;
-    if ((long)blockIdx.x * 256 >= L * L) return;   // whole workgroup past the matrix
+    if (blockIdx.x >= L) return;   // no column for this workgroup
     double emax = 0.0, rdev = 0.0;
     int unres = 0;
-    // a few workgroups stride over the matrix: one atomic per workgroup for the
-    // statistics (one per 256 entries serialised on the two addresses)
-    for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < L * L; idx += (long)gridDim.x * 256) {
-        const int i = (int)(idx % L), j = (int)(idx / L);
-        const double* S = d.SG;
-        const double* G = d.SG + L * L;
+    // a few workgroups stride over the columns (rows by thread, no index
+    // division): one atomic per workgroup for the statistics (one per 256
+    // entries serialised on the two addresses)
+    const double* S = d.SG;
+    const double* G = d.SG + L * L;
+    for (int j = blockIdx.x; j < L; j += gridDim.x)
+    for (int i = threadIdx.x; i < L; i += 256) {
+        const long idx = i + (long)j * L;
         const double gij = gid ? (i == j ? 1.0 : 0.0) : G[i + j * L];
         rdev = fmax(rdev, fabs((i == j ? 1.0 : 0.0) - gij));
         double e;
